@@ -1,0 +1,11 @@
+"""Seeded synthetic inputs shared by the GPU path's tests/bench and the oracle.
+
+This package holds no arithmetic of the method: it only draws closed
+dislocation loops (segment end points and Burgers vectors).
+"""
+from .loops import (  # noqa: F401
+    WORKLOADS,
+    make_loops,
+    make_workload,
+    segment_subset,
+)
