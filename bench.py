@@ -1,0 +1,171 @@
+"""Benchmark: Lagrange-FMM force evaluation on one MI355X.
+
+One step = one dfmm_fmm_forces call (points, P2M, M2M, M2L, L2L, L2P + near
+field, force assembly) over the whole synthetic loop ensemble, inputs resident
+in HBM.  The tree is built once before timing (reported separately), the M2L
+operators are precomputed once (reported separately).
+
+Prints ONE JSON line (see the keys below).  Default workload: 1M segments
+(25,000 hexagonal loops), cubic medium (C11, C12, C44) = (1, 0.6, 0.5),
+order p = 6, depth D = 7, mixed precision.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "FMM force-eval time & segments/s at N_s=1M, rel err vs FP64 direct <=1e-4"
+PEAK_FP32_VALU = 157.3e12  # MI355X fp32 vector (256 CUs x 2.4 GHz x 256 flop/clk)
+PEAK_FP64_VALU = 78.6e12
+PEAK_HBM = 8.0e12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def hadamard_flops(tree_info, nf):
+    """Algorithmic flops of the M2L Hadamard stage: per interaction pair and
+    frequency a 6x9 complex matrix times a 9-vector (54 complex MACs = 432 flop)."""
+    return tree_info["m2l_pairs"] * nf * 54 * 8
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="cubic1m")
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--err-sample", type=int, default=200, help="segments checked against the GPU FP64 direct sum")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64-compare", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=1, help="target segments timed on the CPU oracle")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only; --gpus %d is not supported "
+              "(the multi-GPU sharding is described in DESIGN.md)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1712_07739_amd as pk
+    import synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    seg, burg, prm = synth.make_workload(args.workload)
+    ns = seg.shape[0]
+    log("workload %s: %d segments" % (args.workload, ns))
+    prec = pk.DFMM_MIXED if args.precision == "mixed" else pk.DFMM_FP64
+
+    def make_plan(precision):
+        p = pk.make_params(prm["order"], prm["depth"], prm["c11"], prm["c12"], prm["c44"], prm["core_a"],
+                           prm["box_lo"], prm["box_size"], precision=precision)
+        return pk.Plan(p)
+
+    t0 = time.perf_counter()
+    plan = make_plan(prec)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    info = plan.info()
+    log("setup %.2f s %s" % (setup_s, info))
+    tseg = torch.tensor(seg, device=dev)
+    tb = torch.tensor(burg, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tree = pk.Tree(plan, tseg)
+    torch.cuda.synchronize()
+    tree_s = time.perf_counter() - t0
+    tinfo = tree.info()
+    log("tree %.3f s: m2l pairs %d, near pairs %d" % (tree_s, tinfo["m2l_pairs"], tinfo["near_pairs"]))
+    out = torch.empty((ns, 2, 3), dtype=torch.float64, device=dev)
+    for i in range(args.warmup):
+        pk.fmm_forces(plan, tree, tseg, tb, out=out)
+        torch.cuda.synchronize()
+        log("warmup %d done" % i)
+    tree.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        pk.fmm_forces(plan, tree, tseg, tb, out=out)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    stage_ms, ncalls = tree.stage_times()
+    tree.set_timing(False)
+    ms_step = 1e3 * el / args.steps
+    log("timed %d steps: %.3f ms/step; stages (ms/step): %s" % (
+        args.steps, ms_step, {pk.STAGES[i]: round(stage_ms[i] / ncalls, 3) for i in range(pk.N_STAGES)}))
+
+    # accuracy: relative error vs the GPU FP64 direct sum on a seeded segment subset
+    sub = synth.segment_subset(ns, args.err_sample, 10000 + ns % 1000)
+    tsub = torch.tensor(sub, device=dev)
+    ref = pk.direct_forces(plan, tseg, tb, targets=tsub, fp32=False).cpu().numpy()
+    f = out.cpu().numpy()[sub]
+    err = float(np.linalg.norm(f - ref) / np.linalg.norm(ref))
+    log("rel err vs FP64 direct on %d segments: %.3e" % (len(sub), err))
+
+    # roofline of the dominant kernel (M2L Hadamard product)
+    nf = info["n_freq"]
+    had_flops = hadamard_flops(tinfo, nf)
+    had_ms = stage_ms[3] / ncalls
+    achieved = had_flops / (had_ms * 1e-3)
+    peak = PEAK_FP32_VALU if prec == pk.DFMM_MIXED else PEAK_FP64_VALU
+    roof = {"kernel": "k_hadamard (M2L in frequency space)", "bound": "alu",
+            "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak,
+            "traffic": None, "flop_per_step": had_flops, "ms_per_step": had_ms}
+    result = {
+        "metric": METRIC, "value": ns / (ms_step * 1e-3), "unit": "segments/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32" if prec == pk.DFMM_MIXED else "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n_seg": ns, "order": prm["order"], "depth": prm["depth"],
+                   "C": [prm["c11"], prm["c12"], prm["c44"]], "core_a": prm["core_a"],
+                   "precision": args.precision},
+        "rel_err_vs_fp64_direct": err, "err_sample_segments": int(len(sub)),
+        "stage_ms": {pk.STAGES[i]: stage_ms[i] / ncalls for i in range(pk.N_STAGES)},
+        "setup_s": setup_s, "build_tree_s": tree_s, "m2l_pairs": tinfo["m2l_pairs"],
+        "near_pairs": tinfo["near_pairs"], "roofline": roof,
+    }
+    del tree
+    if not args.no_fp64_compare and prec == pk.DFMM_MIXED:
+        plan64 = make_plan(pk.DFMM_FP64)
+        tree64 = pk.Tree(plan64, tseg)
+        out64 = pk.fmm_forces(plan64, tree64, tseg, tb)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        n64 = max(1, min(args.steps, 2))
+        for i in range(n64):
+            pk.fmm_forces(plan64, tree64, tseg, tb, out=out64)
+        torch.cuda.synchronize()
+        ms64 = 1e3 * (time.perf_counter() - t0) / n64
+        f64 = out64.cpu().numpy()[sub]
+        result["fp64_path"] = {"ms_per_step": ms64, "rel_err_vs_fp64_direct":
+                               float(np.linalg.norm(f64 - ref) / np.linalg.norm(ref)),
+                               "mixed_speedup": ms64 / ms_step}
+        log("fp64 FMM path: %.3f ms/step (mixed speedup %.2fx)" % (ms64, ms64 / ms_step))
+        del tree64, plan64
+    if not args.no_cpu_baseline:
+        import oracle
+
+        med = oracle.medium_from_params(prm)
+        k = max(1, args.cpu_sample)
+        tgt = synth.segment_subset(ns, k, 77)
+        t0 = time.perf_counter()
+        oracle.direct_forces(seg, burg, med, targets=tgt)
+        cpu_s = time.perf_counter() - t0
+        result["cpu_baseline"] = {
+            "value": k / cpu_s, "unit": "segments/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": "%d target segment(s) x all %d source segments (direct FP64 sum, Neumaier), %.1f s"
+                      % (k, ns, cpu_s)}
+        log("cpu oracle: %d segment(s) in %.1f s on %d threads" % (k, cpu_s, oracle.num_threads()))
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

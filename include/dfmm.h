@@ -1,0 +1,150 @@
+/*
+ * dfmm.h -- C ABI of libdfmm, a gfx950 (MI355X) implementation of the
+ * kernel-independent Lagrange fast multipole method for the stress and
+ * Peach-Koehler forces of straight dislocation segments in isotropic and
+ * cubic-anisotropic elastic media (Chen, Aubry, Oppelstrup, Arsenlis, Darve,
+ * "Fast algorithms for evaluating the stress field of dislocation lines in
+ * anisotropic elastic media").
+ *
+ * What is computed (Sec. 2, Eqs. stress, kernel, stress_discrete, stress3):
+ *   every segment i (end points x1, x2, Burgers vector b) carries n_quad
+ *   Gauss-Legendre points y_ik = x1 + (1+u_k)/2 (x2-x1) with strengths
+ *   q_ik = (omega_k/2) b (x) (x2-x1).  The stress at every point is
+ *   s(x) = sum over all points j of K(x - y_j) q_j, with the 54-component kernel
+ *   K = -eps C C dG (the sign makes a straight dislocation's stress the
+ *   textbook one) and the non-singular Green's-function derivative dG with
+ *   core radius a.  The force at the two ends of each segment is the Gauss
+ *   quadrature of (sigma.b) x (x2-x1) with linear shape functions.
+ *   dfmm_fmm_forces evaluates the sum with the Lagrange FMM (Sec. 4,
+ *   Alg. lagrange): P2M, M2M, M2L (FFT-diagonal block-Toeplitz product,
+ *   Theorem 1), L2L, L2P and the direct near field over the 27 neighbour
+ *   leaves.  dfmm_direct_forces evaluates the same sum directly.
+ *
+ * Conventions:
+ *   - Memory: every array argument marked "device" is a device pointer on
+ *     the current HIP device, owned by the caller.  seg is [n_seg][2][3]
+ *     double (x1 then x2), burgers [n_seg][3] double, forces [n][2][3]
+ *     double (force on end 1 then end 2).  The library owns plans, trees
+ *     and their workspaces.
+ *   - Streams: `stream` is a hipStream_t passed as void* (NULL = the null
+ *     stream).  All device work of a call is ordered on that stream.
+ *   - Errors: every entry point returns a dfmm_status; nothing is thrown
+ *     across the ABI.  dfmm_last_error() gives a thread-local message for
+ *     the last failing call.  On failure no output is guaranteed.
+ *   - Threads: a plan is read-only after dfmm_fmm_setup and may be shared
+ *     by concurrent calls; a tree belongs to one stream at a time.
+ */
+#ifndef DFMM_H
+#define DFMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DFMM_OK = 0,
+  DFMM_E_ARG = -1,        /* invalid argument (null pointer, size, range)       */
+  DFMM_E_NOMEM = -2,      /* device or host allocation failed                   */
+  DFMM_E_HIP = -3,        /* a HIP runtime call or kernel launch failed          */
+  DFMM_E_OUT_OF_BOX = -4, /* a quadrature point lies outside the root cube       */
+  DFMM_E_NONFINITE = -5,  /* a segment coordinate is NaN or infinite             */
+  DFMM_E_STATE = -6       /* objects that do not belong together (plan/tree)     */
+} dfmm_status;
+
+enum { DFMM_FP64 = 0, DFMM_MIXED = 1 };
+
+typedef struct dfmm_plan dfmm_plan; /* medium, order, depth, M2L spectra        */
+typedef struct dfmm_tree dfmm_tree; /* sorted points, cells, lists, workspaces   */
+
+typedef struct {
+  int order;          /* p: interpolation nodes per dimension, 2..10 (Sec. 4.1;
+                         the paper's "p-th order" interpolant has p^3 nodes)     */
+  int depth;          /* D: leaf level, 2..10; leaves are cells of side
+                         box_size / 2^D; M2L runs on levels 2..D               */
+  double c11, c12, c44; /* cubic stiffness in the crystal axes (= x, y, z).
+                         Isotropic iff 2 c44 == c11 - c12 (to 1e-12 relative):
+                         then the closed form of Eq. k_iso is used; otherwise
+                         dG comes from unit-circle quadrature (n_circle points) */
+  double core_a;      /* non-singular core radius a >= 0                         */
+  double box_lo[3];   /* lower corner of the root cube                           */
+  double box_size;    /* side of the root cube; every quadrature point must lie
+                         in [box_lo, box_lo + box_size]^3                        */
+  int n_quad;         /* Gauss-Legendre points per segment, 1..8 (usually 3)    */
+  int n_circle;       /* unit-circle quadrature points, even, 8..256 (64)       */
+  int precision;      /* DFMM_FP64: all arithmetic in double.
+                         DFMM_MIXED: P2M..L2P and the near field in float with
+                         float accumulation, near pairs closer than 2a in
+                         double, far + near combined and forces in double     */
+} dfmm_params;
+
+/* Fill *p with defaults: order 5, depth 4, isotropic mu = 1, nu = 0.3,
+ * a = 1e-3, root cube [-0.05, 1.05]^3, n_quad 3, n_circle 64, FP64. */
+void dfmm_default_params(dfmm_params* p);
+
+/* Precompute a plan (Sec. 4.1, Eq. m2l and Theorem 1): for every level 2..D
+ * the kernel on the lattice of node offsets, the 316 block-Toeplitz
+ * generators and their DFTs.  The operators depend only on the kernel, not on
+ * the segments, and are reused by every tree and every call.  Synchronous.
+ * Errors: DFMM_E_ARG for out-of-range parameters or a stiffness that is not
+ * positive definite; DFMM_E_NOMEM; DFMM_E_HIP. */
+int dfmm_fmm_setup(const dfmm_params* prm, void* stream, dfmm_plan** out);
+
+/* Build the octree of the quadrature points of seg (device, [n_seg][2][3]):
+ * Morton keys, a stable radix sort, occupied cells per level, 27-neighbour
+ * lists of the leaves and interaction lists (children of the parent's
+ * neighbours that are not neighbours; Sec. 4.3) on levels 2..D, and every
+ * workspace dfmm_fmm_forces needs.  Synchronises the stream.  n_seg >= 1.
+ * Errors: DFMM_E_NONFINITE / DFMM_E_OUT_OF_BOX for bad coordinates,
+ * DFMM_E_ARG, DFMM_E_NOMEM, DFMM_E_HIP. */
+int dfmm_build_tree(dfmm_plan* plan, const double* seg, int64_t n_seg, void* stream,
+                    dfmm_tree** out);
+
+/* Forces on all n_seg segments (forces: device [n_seg][2][3]) by the
+ * Lagrange FMM of Alg. lagrange.  seg must hold the same positions the tree
+ * was built from; burgers is device [n_seg][3].  Asynchronous on `stream`;
+ * allocates nothing.  Errors: DFMM_E_ARG, DFMM_E_STATE (tree from another
+ * plan), DFMM_E_HIP. */
+int dfmm_fmm_forces(const dfmm_plan* plan, dfmm_tree* tree, const double* seg,
+                    const double* burgers, double* forces, void* stream);
+
+/* Direct O(N^2) forces on the target segments targets[0..n_targets)
+ * (device int64 indices into seg; NULL = all segments, then n_targets must
+ * equal n_seg) from every quadrature point of every segment, Eq. stress3.
+ * forces: device [n_targets][2][3].  fp32 = 1 evaluates pairs in float with
+ * compensated float accumulation; 0 in double.  Asynchronous.
+ * Errors: DFMM_E_ARG, DFMM_E_HIP. */
+int dfmm_direct_forces(const dfmm_plan* plan, const double* seg, const double* burgers,
+                       int64_t n_seg, const int64_t* targets, int64_t n_targets,
+                       double* forces, int fp32, void* stream);
+
+/* Per-stage timing of dfmm_fmm_forces with HIP events on its stream.
+ * on = 1 starts recording (resetting the accumulators), 0 stops.  While
+ * on, every dfmm_fmm_forces call records events around each stage.
+ * dfmm_tree_stage_times synchronises the tree's last stream and writes the
+ * accumulated milliseconds per stage and the number of timed calls:
+ * ms[0..DFMM_N_STAGES).  Stages: 0 points+P2M, 1 M2M, 2 forward DFT,
+ * 3 M2L Hadamard product, 4 inverse DFT, 5 L2L, 6 near field+L2P,
+ * 7 force assembly. */
+#define DFMM_N_STAGES 8
+int dfmm_tree_set_timing(dfmm_tree* tree, int on);
+int dfmm_tree_stage_times(dfmm_tree* tree, double* ms, int* n_calls);
+
+/* JSON descriptions: parameters, M2L operator memory (Eq. mem_unif and the
+ * stored spectra), precompute time / tree sizes per level, pair counts. */
+int dfmm_plan_info(const dfmm_plan* plan, char* json, size_t cap);
+int dfmm_tree_info(const dfmm_tree* tree, char* json, size_t cap);
+
+/* NULL-safe destructors. */
+void dfmm_tree_destroy(dfmm_tree* tree);
+void dfmm_plan_destroy(dfmm_plan* plan);
+
+const char* dfmm_status_string(int status);
+const char* dfmm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DFMM_H */

@@ -333,29 +333,55 @@ static void nadd(nsum* a, double t) {
 }
 
 /* Stress s(x_i) = sum_j K(x_i - y_j) q_j, Eq. stress3, at n_t targets     */
-/* from n_s sources with 9-component strengths q[j][w*3+r].                 */
+/* from n_s sources with 9-component strengths q[j][w*3+r].  The sources   */
+/* are taken in fixed chunks of OR_CHUNK; each chunk is summed in order     */
+/* with Neumaier compensation and the chunk sums are combined in order, so  */
+/* the result does not depend on the number of threads or of targets.      */
+#define OR_CHUNK 8192
 void or_stress(int64_t n_t, const double* xt, int64_t n_s, const double* ys,
                const double* q, const double* prm, double* sigma) {
   double C[81];
   or_stiffness(prm[0], prm[1], prm[2], C);
-#pragma omp parallel for schedule(dynamic, 1)
-  for (int64_t i = 0; i < n_t; ++i) {
-    nsum acc[6];
-    memset(acc, 0, sizeof(acc));
-    for (int64_t j = 0; j < n_s; ++j) {
-      double d[3] = {xt[3 * i] - ys[3 * j], xt[3 * i + 1] - ys[3 * j + 1],
-                     xt[3 * i + 2] - ys[3 * j + 2]};
-      double D[27], K[54];
-      or_dG_medium(d, prm, D);
-      or_kernel54(D, C, K);
-      for (int ab = 0; ab < 6; ++ab) {
-        double s = 0.0;
-        for (int k = 0; k < 9; ++k) s += K[ab * 9 + k] * q[9 * j + k];
-        nadd(&acc[ab], s);
+  int64_t nch = (n_s + OR_CHUNK - 1) / OR_CHUNK;
+  if (nch < 1) nch = 1;
+  int64_t tb = (int64_t)(1 << 22) / nch; /* targets per batch: bounded scratch */
+  if (tb < 1) tb = 1;
+  nsum* part = (nsum*)malloc(sizeof(nsum) * 6 * nch * (tb < n_t ? tb : n_t));
+  for (int64_t t0 = 0; t0 < n_t; t0 += tb) {
+    int64_t nb = (n_t - t0 < tb) ? n_t - t0 : tb;
+#pragma omp parallel for schedule(dynamic, 1) collapse(2)
+    for (int64_t ii = 0; ii < nb; ++ii)
+      for (int64_t ch = 0; ch < nch; ++ch) {
+        int64_t i = t0 + ii;
+        nsum acc[6];
+        memset(acc, 0, sizeof(acc));
+        int64_t j1 = (ch + 1) * OR_CHUNK < n_s ? (ch + 1) * OR_CHUNK : n_s;
+        for (int64_t j = ch * OR_CHUNK; j < j1; ++j) {
+          double d[3] = {xt[3 * i] - ys[3 * j], xt[3 * i + 1] - ys[3 * j + 1],
+                         xt[3 * i + 2] - ys[3 * j + 2]};
+          double D[27], K[54];
+          or_dG_medium(d, prm, D);
+          or_kernel54(D, C, K);
+          for (int ab = 0; ab < 6; ++ab) {
+            double s = 0.0;
+            for (int k = 0; k < 9; ++k) s += K[ab * 9 + k] * q[9 * j + k];
+            nadd(&acc[ab], s);
+          }
+        }
+        memcpy(part + (ii * nch + ch) * 6, acc, sizeof(acc));
       }
+    for (int64_t ii = 0; ii < nb; ++ii) {
+      nsum tot[6];
+      memset(tot, 0, sizeof(tot));
+      for (int64_t ch = 0; ch < nch; ++ch)
+        for (int ab = 0; ab < 6; ++ab) {
+          nadd(&tot[ab], part[(ii * nch + ch) * 6 + ab].s);
+          nadd(&tot[ab], part[(ii * nch + ch) * 6 + ab].c);
+        }
+      for (int ab = 0; ab < 6; ++ab) sigma[6 * (t0 + ii) + ab] = tot[ab].s + tot[ab].c;
     }
-    for (int ab = 0; ab < 6; ++ab) sigma[6 * i + ab] = acc[ab].s + acc[ab].c;
   }
+  free(part);
 }
 
 /* Quadrature points y_ik = x1 + (1+u_k)/2 dS_i and strengths               */

@@ -1,0 +1,229 @@
+"""Python binding of libdfmm (the gfx950 Lagrange-FMM library for dislocation forces).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels behind the C ABI declared in include/dfmm.h.  Device memory comes from
+torch tensors (float64, on the current HIP device); the current torch stream is
+passed as the HIP stream.  The library must have been built
+(``python -m paper_1712_07739_amd.build`` or ``__graft_entry__.build()``);
+there is no fallback of any kind.
+"""
+from __future__ import annotations
+
+import ctypes
+import json
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdfmm.so")
+
+DFMM_FP64 = 0
+DFMM_MIXED = 1
+N_STAGES = 8
+STAGES = ("points+P2M", "M2M", "DFT", "M2L-Hadamard", "IDFT", "L2L", "near+L2P", "forces")
+
+ENTRY_POINTS = (
+    "dfmm_default_params", "dfmm_fmm_setup", "dfmm_build_tree", "dfmm_fmm_forces",
+    "dfmm_direct_forces", "dfmm_tree_set_timing", "dfmm_tree_stage_times", "dfmm_plan_info",
+    "dfmm_tree_info", "dfmm_tree_destroy", "dfmm_plan_destroy", "dfmm_status_string",
+    "dfmm_last_error",
+)
+
+
+class Params(ctypes.Structure):
+    """Mirror of dfmm_params."""
+
+    _fields_ = [
+        ("order", ctypes.c_int), ("depth", ctypes.c_int),
+        ("c11", ctypes.c_double), ("c12", ctypes.c_double), ("c44", ctypes.c_double),
+        ("core_a", ctypes.c_double), ("box_lo", ctypes.c_double * 3), ("box_size", ctypes.c_double),
+        ("n_quad", ctypes.c_int), ("n_circle", ctypes.c_int), ("precision", ctypes.c_int),
+    ]
+
+
+class DfmmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("dfmm status %d: %s" % (status, msg))
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load libdfmm.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libdfmm.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+    pp = ctypes.POINTER(ctypes.c_void_p)
+    L.dfmm_default_params.argtypes = [ctypes.POINTER(Params)]
+    L.dfmm_fmm_setup.argtypes = [ctypes.POINTER(Params), vp, pp]
+    L.dfmm_build_tree.argtypes = [vp, vp, i64, vp, pp]
+    L.dfmm_fmm_forces.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.dfmm_direct_forces.argtypes = [vp, vp, vp, i64, vp, i64, vp, i32, vp]
+    L.dfmm_tree_set_timing.argtypes = [vp, i32]
+    L.dfmm_tree_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)]
+    L.dfmm_plan_info.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t]
+    L.dfmm_tree_info.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t]
+    L.dfmm_tree_destroy.argtypes = [vp]
+    L.dfmm_plan_destroy.argtypes = [vp]
+    L.dfmm_status_string.argtypes = [i32]
+    L.dfmm_status_string.restype = ctypes.c_char_p
+    L.dfmm_last_error.restype = ctypes.c_char_p
+    for name in ENTRY_POINTS:
+        getattr(L, name)
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != 0:
+        L = lib()
+        raise DfmmError(rc, "%s (%s)" % (L.dfmm_status_string(rc).decode(), L.dfmm_last_error().decode()))
+
+
+def _stream(stream=None):
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_f64(t, shape, name):
+    import torch
+
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64:
+        raise TypeError("%s must be a float64 tensor on the GPU" % name)
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError("%s must have shape %s, got %s" % (name, tuple(shape), tuple(t.shape)))
+    return t.contiguous()
+
+
+def default_params():
+    p = Params()
+    lib().dfmm_default_params(ctypes.byref(p))
+    return p
+
+
+def make_params(order, depth, c11, c12, c44, core_a, box_lo, box_size, n_quad=3, n_circle=64,
+                precision=DFMM_FP64):
+    p = default_params()
+    p.order, p.depth = int(order), int(depth)
+    p.c11, p.c12, p.c44, p.core_a = float(c11), float(c12), float(c44), float(core_a)
+    for i in range(3):
+        p.box_lo[i] = float(box_lo[i])
+    p.box_size = float(box_size)
+    p.n_quad, p.n_circle, p.precision = int(n_quad), int(n_circle), int(precision)
+    return p
+
+
+class Plan:
+    """dfmm_fmm_setup: per-level M2L operator spectra for one medium/order/depth."""
+
+    def __init__(self, params: Params, stream=None):
+        self.params = params
+        self._h = ctypes.c_void_p()
+        _check(lib().dfmm_fmm_setup(ctypes.byref(params), _stream(stream), ctypes.byref(self._h)))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self):
+        buf = ctypes.create_string_buffer(4096)
+        _check(lib().dfmm_plan_info(self._h, buf, 4096))
+        return json.loads(buf.value.decode())
+
+    def close(self):
+        if self._h:
+            lib().dfmm_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Tree:
+    """dfmm_build_tree: octree + workspaces for one set of segment positions."""
+
+    def __init__(self, plan: Plan, seg, stream=None):
+        self.plan = plan
+        self.n_seg = int(seg.shape[0])
+        self._seg = _dev_f64(seg, (self.n_seg, 2, 3), "seg")
+        self._h = ctypes.c_void_p()
+        _check(lib().dfmm_build_tree(plan.handle, ctypes.c_void_p(self._seg.data_ptr()), self.n_seg,
+                                     _stream(stream), ctypes.byref(self._h)))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self):
+        buf = ctypes.create_string_buffer(1 << 16)
+        _check(lib().dfmm_tree_info(self._h, buf, 1 << 16))
+        return json.loads(buf.value.decode())
+
+    def set_timing(self, on: bool):
+        _check(lib().dfmm_tree_set_timing(self._h, 1 if on else 0))
+
+    def stage_times(self):
+        ms = (ctypes.c_double * N_STAGES)()
+        n = ctypes.c_int()
+        _check(lib().dfmm_tree_stage_times(self._h, ms, ctypes.byref(n)))
+        return list(ms), n.value
+
+    def close(self):
+        if self._h:
+            lib().dfmm_tree_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def fmm_forces(plan: Plan, tree: Tree, seg, burgers, out=None, stream=None):
+    """Lagrange-FMM end-point forces [n_seg, 2, 3] (float64, on the GPU)."""
+    import torch
+
+    n = tree.n_seg
+    seg = _dev_f64(seg, (n, 2, 3), "seg")
+    burgers = _dev_f64(burgers, (n, 3), "burgers")
+    if out is None:
+        out = torch.empty((n, 2, 3), dtype=torch.float64, device=seg.device)
+    else:
+        out = _dev_f64(out, (n, 2, 3), "out")
+    _check(lib().dfmm_fmm_forces(plan.handle, tree.handle, ctypes.c_void_p(seg.data_ptr()),
+                                 ctypes.c_void_p(burgers.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                 _stream(stream)))
+    return out
+
+
+def direct_forces(plan: Plan, seg, burgers, targets=None, fp32=False, out=None, stream=None):
+    """Direct O(N^2) end-point forces on `targets` (int64 GPU tensor, or all)."""
+    import torch
+
+    n = int(seg.shape[0])
+    seg = _dev_f64(seg, (n, 2, 3), "seg")
+    burgers = _dev_f64(burgers, (n, 3), "burgers")
+    if targets is None:
+        nt, tptr = n, ctypes.c_void_p(0)
+    else:
+        if not targets.is_cuda or targets.dtype != torch.int64:
+            raise TypeError("targets must be an int64 tensor on the GPU")
+        targets = targets.contiguous()
+        nt, tptr = int(targets.numel()), ctypes.c_void_p(targets.data_ptr())
+    if out is None:
+        out = torch.empty((nt, 2, 3), dtype=torch.float64, device=seg.device)
+    _check(lib().dfmm_direct_forces(plan.handle, ctypes.c_void_p(seg.data_ptr()),
+                                    ctypes.c_void_p(burgers.data_ptr()), n, tptr, nt,
+                                    ctypes.c_void_p(out.data_ptr()), 1 if fp32 else 0, _stream(stream)))
+    return out

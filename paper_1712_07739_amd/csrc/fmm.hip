@@ -1,0 +1,811 @@
+// Lagrange FMM evaluation (Sec. 4.3, Alg. lagrange) and the direct sum
+// (Eq. stress3) on gfx950.
+//
+// Stages of dfmm_fmm_forces, all on the caller's stream:
+//   points   quadrature points and strengths in Morton order (Eq. stress_discrete)
+//   P2M      anterpolation of the leaf points onto the p^3 leaf nodes
+//   M2M      anterpolation of children onto the parent nodes (separable)
+//   M2L      per level: DFT of the multipole weights, Hadamard product with
+//            the offset spectra summed over the interaction list (Theorem 1),
+//            inverse DFT to the p^3 local nodes
+//   L2L      interpolation of the parent's local values at the child nodes
+//   leaf     L2P at every point + the direct near field over the 27
+//            neighbour leaves
+//   forces   Gauss quadrature of (sigma.b) x dS with shape functions (1-s, s)
+#include <algorithm>
+#include <cmath>
+
+#include "internal.h"
+
+namespace dfmm {
+
+template <typename T>
+struct cplx {
+  T re, im;
+};
+
+static inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+template <typename T>
+__device__ __forceinline__ T lagr(int p, int i, T t) {
+  // ell_i(t) for nodes k/(p-1), k = 0..p-1
+  T v = T(1);
+  T tp = t * T(p - 1);
+  for (int k = 0; k < p; ++k)
+    if (k != i) v *= (tp - T(k)) / T(i - k);
+  return v;
+}
+
+// ---------------------------------------------------------------- points
+__global__ void k_gather(const double* seg, const double* burg, const uint32_t* perm, Quad qd, int64_t N,
+                         double* pts) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  uint32_t j = perm[i];
+  int64_t s = j / qd.n;
+  int k = (int)(j - s * qd.n);
+  const double* x = seg + 6 * s;
+  double dS[3] = {x[3] - x[0], x[4] - x[1], x[5] - x[2]};
+  double c = 0.5 * (1.0 + qd.u[k]), hw = 0.5 * qd.w[k];
+  for (int d = 0; d < 3; ++d) {
+    pts[d * N + i] = x[d] + c * dS[d];
+    pts[(3 + d) * N + i] = burg[3 * s + d];
+    pts[(6 + d) * N + i] = hw * dS[d];
+  }
+}
+
+__device__ __forceinline__ void cell_lo(uint32_t key, double lo0, double lo1, double lo2, double sz,
+                                        double* lo) {
+  uint32_t v[3] = {key >> 2, key >> 1, key};
+  for (int d = 0; d < 3; ++d) {
+    uint32_t x = v[d] & 0x09249249;
+    x = (x | (x >> 2)) & 0x030C30C3;
+    x = (x | (x >> 4)) & 0x0300F00F;
+    x = (x | (x >> 8)) & 0x030000FF;
+    x = (x | (x >> 16)) & 0x3ff;
+    lo[d] = (d == 0 ? lo0 : d == 1 ? lo1 : lo2) + x * sz;
+  }
+}
+
+// ------------------------------------------------------------------- P2M
+// One block per leaf; thread = node m.  Points are staged in LDS in chunks of
+// 64 with their 1D basis values and 9-component strengths b (x) t.
+template <typename T>
+__global__ void k_p2m(const double* pts, int64_t N, const int* first, const int* count, const uint32_t* key,
+                      double lo0, double lo1, double lo2, double sD, int p, T* W) {
+  extern __shared__ unsigned char shraw[];
+  T* Lb = (T*)shraw;          // [64][3][p]
+  T* qs = Lb + 64 * 3 * p;    // [64][9]
+  const int leaf = blockIdx.x, p3 = p * p * p;
+  const int f0 = first[leaf], cnt = count[leaf];
+  double lo[3];
+  cell_lo(key[leaf], lo0, lo1, lo2, sD, lo);
+  const int tid = threadIdx.x;
+  const int m1 = tid / (p * p), m2 = (tid / p) % p, m3 = tid % p;
+  T acc[9];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) acc[c] = T(0);
+  for (int c0 = 0; c0 < cnt; c0 += 64) {
+    int nc = min(64, cnt - c0);
+    for (int e = tid; e < nc * 3; e += blockDim.x) {
+      int pt = e / 3, d = e % 3;
+      T t = (T)((pts[d * N + f0 + c0 + pt] - lo[d]) / sD);
+      for (int i = 0; i < p; ++i) Lb[(pt * 3 + d) * p + i] = lagr<T>(p, i, t);
+    }
+    for (int e = tid; e < nc * 9; e += blockDim.x) {
+      int pt = e / 9, c = e % 9;
+      int64_t j = f0 + c0 + pt;
+      qs[pt * 9 + c] = (T)(pts[(3 + c / 3) * N + j] * pts[(6 + c % 3) * N + j]);
+    }
+    __syncthreads();
+    if (tid < p3) {
+      for (int pt = 0; pt < nc; ++pt) {
+        T w = Lb[(pt * 3 + 0) * p + m1] * Lb[(pt * 3 + 1) * p + m2] * Lb[(pt * 3 + 2) * p + m3];
+#pragma unroll
+        for (int c = 0; c < 9; ++c) acc[c] += w * qs[pt * 9 + c];
+      }
+    }
+    __syncthreads();
+  }
+  if (tid < p3) {
+    T* out = W + (int64_t)leaf * 9 * p3;
+#pragma unroll
+    for (int c = 0; c < 9; ++c) out[c * p3 + tid] = acc[c];
+  }
+}
+
+// ------------------------------------------------------- separable passes
+// out[g][a][b][i] = sum_m M(i, m) in[g][a][b][m] along the last axis, for the
+// three axes in turn; M(i, m) = S[bit][i][m] (anterpolation, M2M) or
+// S[bit][m][i] (interpolation, L2L).
+template <typename T, bool INTERP>
+__device__ __forceinline__ void pass_axis(const T* in, T* out, const T* S, int bit, int p, int ncomp,
+                                          int axis) {
+  const int p3 = p * p * p;
+  const int stride = axis == 2 ? 1 : axis == 1 ? p : p * p;
+  for (int e = threadIdx.x; e < ncomp * p3; e += blockDim.x) {
+    int g = e / p3, r = e % p3;
+    int i = (r / stride) % p;
+    int base = g * p3 + r - i * stride;
+    T v = T(0);
+    for (int m = 0; m < p; ++m) {
+      T c = INTERP ? S[(bit * p + m) * p + i] : S[(bit * p + i) * p + m];
+      v += c * in[base + m * stride];
+    }
+    out[e] = v;
+  }
+}
+
+// M2M: one block per parent cell.  W_child rows of the next finer level.
+template <typename T>
+__global__ void k_m2m(const int* first, const int* count, const uint32_t* ckey, const T* Wc, T* Wp,
+                      const T* Sg, int p) {
+  extern __shared__ unsigned char shraw[];
+  const int p3 = p * p * p;
+  T* A = (T*)shraw;
+  T* B = A + 9 * p3;
+  T* C = B + 9 * p3;
+  T* S = C + 9 * p3;
+  for (int e = threadIdx.x; e < 2 * p * p; e += blockDim.x) S[e] = Sg[e];
+  for (int e = threadIdx.x; e < 9 * p3; e += blockDim.x) C[e] = T(0);
+  const int par = blockIdx.x;
+  const int c0 = first[par], nc = count[par];
+  __syncthreads();
+  for (int c = c0; c < c0 + nc; ++c) {
+    uint32_t bits = ckey[c] & 7;
+    const T* src = Wc + (int64_t)c * 9 * p3;
+    for (int e = threadIdx.x; e < 9 * p3; e += blockDim.x) A[e] = src[e];
+    __syncthreads();
+    pass_axis<T, false>(A, B, S, bits & 1, p, 9, 2);
+    __syncthreads();
+    pass_axis<T, false>(B, A, S, (bits >> 1) & 1, p, 9, 1);
+    __syncthreads();
+    for (int e = threadIdx.x; e < 9 * p3; e += blockDim.x) {
+      int g = e / p3, r = e % p3;
+      int i = r / (p * p);
+      int base = g * p3 + r - i * p * p;
+      T v = T(0);
+      for (int m = 0; m < p; ++m) v += S[((bits >> 2 & 1) * p + i) * p + m] * A[base + m * p * p];
+      C[e] += v;
+    }
+    __syncthreads();
+  }
+  T* dst = Wp + (int64_t)par * 9 * p3;
+  for (int e = threadIdx.x; e < 9 * p3; e += blockDim.x) dst[e] = C[e];
+}
+
+// L2L: one block per child cell; adds the parent's interpolated local values.
+template <typename T>
+__global__ void k_l2l(const int* parent, const uint32_t* key, const T* sp, T* sc, const T* Sg, int p) {
+  extern __shared__ unsigned char shraw[];
+  const int p3 = p * p * p;
+  T* A = (T*)shraw;
+  T* B = A + 6 * p3;
+  T* S = B + 6 * p3;
+  for (int e = threadIdx.x; e < 2 * p * p; e += blockDim.x) S[e] = Sg[e];
+  const int c = blockIdx.x;
+  const uint32_t bits = key[c] & 7;
+  const T* src = sp + (int64_t)parent[c] * 6 * p3;
+  for (int e = threadIdx.x; e < 6 * p3; e += blockDim.x) A[e] = src[e];
+  __syncthreads();
+  pass_axis<T, true>(A, B, S, bits & 1, p, 6, 2);
+  __syncthreads();
+  pass_axis<T, true>(B, A, S, (bits >> 1) & 1, p, 6, 1);
+  __syncthreads();
+  T* dst = sc + (int64_t)c * 6 * p3;
+  for (int e = threadIdx.x; e < 6 * p3; e += blockDim.x) {
+    int g = e / p3, r = e % p3;
+    int i = r / (p * p);
+    int base = g * p3 + r - i * p * p;
+    T v = T(0);
+    for (int m = 0; m < p; ++m) v += S[((bits >> 2 & 1) * p + m) * p + i] * A[base + m * p * p];
+    dst[e] += v;
+  }
+}
+
+// ------------------------------------------------------------ forward DFT
+// One block per cell of a level: W[cell][9][p^3] (real) -> What[f][cell][9],
+// f = (f1 n + f2) p + f3, half spectrum in the last axis.  Components are
+// processed G at a time.
+template <typename T>
+__global__ void k_fdft(const T* W, int64_t ncell, int p, int G, const T* twg, cplx<T>* What) {
+  extern __shared__ unsigned char shraw[];
+  const int n = 2 * p - 1, p3 = p * p * p, nf = n * n * p;
+  cplx<T>* tw = (cplx<T>*)shraw;         // [n]
+  T* Wl = (T*)(tw + n);                  // [G][p^3]
+  cplx<T>* X1 = (cplx<T>*)(Wl + G * p3 + (G * p3) % 2);  // [G][p][p][p]  (m1, m2, f3)
+  cplx<T>* X2 = X1 + G * p3;             // [G][p][n][p]  (m1, f2, f3)
+  const int64_t cell = blockIdx.x;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) tw[e] = cplx<T>{twg[2 * e], twg[2 * e + 1]};
+  for (int c0 = 0; c0 < 9; c0 += G) {
+    const T* src = W + (cell * 9 + c0) * p3;
+    for (int e = threadIdx.x; e < G * p3; e += blockDim.x) Wl[e] = src[e];
+    __syncthreads();
+    for (int e = threadIdx.x; e < G * p3; e += blockDim.x) {
+      int f3 = e % p, rest = e / p;  // rest = (g, m1, m2)
+      const T* row = Wl + rest * p;
+      T re = 0, im = 0;
+      for (int m = 0; m < p; ++m) {
+        cplx<T> w = tw[(f3 * m) % n];
+        re += row[m] * w.re;
+        im += row[m] * w.im;
+      }
+      X1[e] = cplx<T>{re, im};
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < G * p * n * p; e += blockDim.x) {
+      int f3 = e % p, f2 = (e / p) % n, gm1 = e / (p * n);
+      T re = 0, im = 0;
+      for (int m = 0; m < p; ++m) {
+        cplx<T> x = X1[(gm1 * p + m) * p + f3];
+        cplx<T> w = tw[(f2 * m) % n];
+        re += x.re * w.re - x.im * w.im;
+        im += x.re * w.im + x.im * w.re;
+      }
+      X2[e] = cplx<T>{re, im};
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nf * G; e += blockDim.x) {
+      int g = e % G, f = e / G;
+      int f3 = f % p, f2 = (f / p) % n, f1 = f / (p * n);
+      T re = 0, im = 0;
+      for (int m = 0; m < p; ++m) {
+        cplx<T> x = X2[((g * p + m) * n + f2) * p + f3];
+        cplx<T> w = tw[(f1 * m) % n];
+        re += x.re * w.re - x.im * w.im;
+        im += x.re * w.im + x.im * w.re;
+      }
+      What[((int64_t)f * ncell + cell) * 9 + c0 + g] = cplx<T>{re, im};
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------ Hadamard product
+// One block per (target chunk, frequency f, row group).  The spectra of all
+// 316 offsets at frequency f (ROWS of the 6 stress rows) sit in LDS; every
+// thread owns one target cell and walks its interaction list:
+//   Shat[T][f][r] = sum_{(J, o) in I(T)} sum_k Khat_o(f)[r][k] What[f][J][k].
+template <typename T, int ROWS>
+__global__ void __launch_bounds__(1024) k_hadamard(const cplx<T>* What, const cplx<T>* Khat, const int* il_start,
+                                                   const int2* il, int64_t ncell, int nf, cplx<T>* Shat) {
+  extern __shared__ unsigned char shraw[];
+  cplx<T>* Ks = (cplx<T>*)shraw;  // [316][ROWS*9]
+  const int f = blockIdx.y;
+  const int row0 = blockIdx.z * ROWS;
+  const cplx<T>* kf = Khat + (int64_t)f * kNumOffsets * 54;
+  for (int e = threadIdx.x; e < kNumOffsets * ROWS * 9; e += blockDim.x) {
+    int o = e / (ROWS * 9), rk = e % (ROWS * 9);
+    Ks[e] = kf[o * 54 + row0 * 9 + rk];
+  }
+  __syncthreads();
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ncell) return;
+  T ar[ROWS], ai[ROWS];
+#pragma unroll
+  for (int r = 0; r < ROWS; ++r) ar[r] = ai[r] = T(0);
+  const int e0 = il_start[t], e1 = il_start[t + 1];
+  const cplx<T>* wf = What + (int64_t)f * ncell * 9;
+  for (int e = e0; e < e1; ++e) {
+    int2 jo = il[e];
+    const cplx<T>* w = wf + (int64_t)jo.x * 9;
+    cplx<T> wv[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) wv[k] = w[k];
+    const cplx<T>* K = Ks + jo.y * (ROWS * 9);
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r)
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        cplx<T> kk = K[r * 9 + k];
+        ar[r] += kk.re * wv[k].re - kk.im * wv[k].im;
+        ai[r] += kk.re * wv[k].im + kk.im * wv[k].re;
+      }
+  }
+  cplx<T>* out = Shat + (t * nf + f) * 6 + row0;
+#pragma unroll
+  for (int r = 0; r < ROWS; ++r) out[r] = cplx<T>{ar[r], ai[r]};
+}
+
+// ------------------------------------------------------------ inverse DFT
+// One block per cell: Shat[cell][f][6] -> s[cell][6][p^3] (overwrites), using
+// the Hermitian symmetry of the spectrum of a real circular convolution.
+template <typename T>
+__global__ void k_idft(const cplx<T>* Shat, int64_t ncell, int p, int G, const T* twg, T* s) {
+  extern __shared__ unsigned char shraw[];
+  const int n = 2 * p - 1, p3 = p * p * p, nf = n * n * p;
+  cplx<T>* tw = (cplx<T>*)shraw;  // conj twiddles exp(+2 pi i k/n)
+  cplx<T>* Sl = tw + n;           // [G][nf]
+  cplx<T>* Y1 = Sl + G * nf;      // [G][n(f2)][p(f3)][p(l1)]
+  cplx<T>* Y2 = Y1 + G * n * p * p;  // [G][p(f3)][p(l1)][p(l2)]
+  const int64_t cell = blockIdx.x;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) tw[e] = cplx<T>{twg[2 * e], -twg[2 * e + 1]};
+  const T scale = T(1) / T(n * n * n);
+  for (int c0 = 0; c0 < 6; c0 += G) {
+    const cplx<T>* src = Shat + cell * nf * 6;
+    for (int e = threadIdx.x; e < G * nf; e += blockDim.x) {
+      int g = e % G, f = e / G;
+      Sl[g * nf + f] = src[f * 6 + c0 + g];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < G * n * p * p; e += blockDim.x) {
+      int l1 = e % p, f3 = (e / p) % p, f2 = (e / (p * p)) % n, g = e / (p * p * n);
+      T re = 0, im = 0;
+      for (int f1 = 0; f1 < n; ++f1) {
+        cplx<T> x = Sl[g * nf + (f1 * n + f2) * p + f3];
+        cplx<T> w = tw[(f1 * l1) % n];
+        re += x.re * w.re - x.im * w.im;
+        im += x.re * w.im + x.im * w.re;
+      }
+      Y1[e] = cplx<T>{re, im};
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < G * p * p * p; e += blockDim.x) {
+      int l2 = e % p, l1 = (e / p) % p, f3 = (e / (p * p)) % p, g = e / p3;
+      T re = 0, im = 0;
+      for (int f2 = 0; f2 < n; ++f2) {
+        cplx<T> x = Y1[((g * n + f2) * p + f3) * p + l1];
+        cplx<T> w = tw[(f2 * l2) % n];
+        re += x.re * w.re - x.im * w.im;
+        im += x.re * w.im + x.im * w.re;
+      }
+      Y2[e] = cplx<T>{re, im};
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < G * p3; e += blockDim.x) {
+      int l3 = e % p, l2 = (e / p) % p, l1 = (e / (p * p)) % p, g = e / p3;
+      T re = 0;
+      for (int f3 = 0; f3 < p; ++f3) {
+        cplx<T> x = Y2[((g * p + f3) * p + l1) * p + l2];
+        cplx<T> w = tw[(f3 * l3) % n];
+        T v = x.re * w.re - x.im * w.im;
+        re += (f3 == 0 ? T(1) : T(2)) * v;
+      }
+      s[(cell * 6 + c0 + g) * p3 + (l1 * p + l2) * p + l3] = re * scale;
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------ near field + L2P (leaf)
+// One wave per leaf.  With nt <= 64 targets, S = 64/nt (rounded down to a
+// power of two) lanes share a target and split its sources; partial sums are
+// combined with xor shuffles.  In MIXED precision pairs are evaluated in float
+// (displacements formed in double) with compensated float accumulation, and
+// pairs closer than 2a in double.
+template <typename T, bool MIXED>
+__global__ void __launch_bounds__(64) k_leaf(const double* pts, int64_t N, const int* first, const int* count,
+                                             const uint32_t* key, const int* nbr, const T* s, double lo0,
+                                             double lo1, double lo2, double sD, int p, Med<T> m, Med<double> m64,
+                                             double* sig) {
+  const int leaf = blockIdx.x, lane = threadIdx.x;
+  const int t0 = first[leaf], nt = count[leaf];
+  int S = 1;
+  while (S * 2 * nt <= 64) S *= 2;
+  const int per = 64 / S;  // targets per pass
+  __shared__ int nb_first[27], nb_cnt[27];
+  if (lane < 27) {
+    int j = nbr[(int64_t)leaf * 27 + lane];
+    nb_first[lane] = j >= 0 ? first[j] : 0;
+    nb_cnt[lane] = j >= 0 ? count[j] : 0;
+  }
+  __syncthreads();
+  double lo[3];
+  cell_lo(key[leaf], lo0, lo1, lo2, sD, lo);
+  const int p3 = p * p * p;
+  const T* sl = s + (int64_t)leaf * 6 * p3;
+  const double a2x4 = 4.0 * m64.a * m64.a;
+  for (int c0 = 0; c0 < nt; c0 += per) {
+    const int ti = c0 + lane / S, slice = lane % S;
+    const bool act = (lane / S) < per && ti < nt;
+    const int64_t i = t0 + (act ? ti : 0);
+    const double xt0 = pts[i], xt1 = pts[N + i], xt2 = pts[2 * N + i];
+    T acc[6], cmp[6];
+    double acc64[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) acc[c] = cmp[c] = T(0), acc64[c] = 0.0;
+    int base = 0;
+    for (int q = 0; q < 27; ++q) {
+      const int fj = nb_first[q], cj = nb_cnt[q];
+      if (act) {
+        int jj = (slice - (base % S) + S) % S;
+        for (; jj < cj; jj += S) {
+          const int64_t j = fj + jj;
+          double d0 = xt0 - pts[j], d1 = xt1 - pts[N + j], d2 = xt2 - pts[2 * N + j];
+          if (MIXED && d0 * d0 + d1 * d1 + d2 * d2 < a2x4) {
+            double D[27], b[3], tt[3];
+            for (int c = 0; c < 3; ++c) b[c] = pts[(3 + c) * N + j], tt[c] = pts[(6 + c) * N + j];
+            dg_medium<double>(d0, d1, d2, m64, D);
+            contract_b_t<double>(D, m64.c12, m64.c44, m64.hh, b, tt, acc64);
+          } else {
+            T D[27], b[3], tt[3];
+            for (int c = 0; c < 3; ++c) b[c] = (T)pts[(3 + c) * N + j], tt[c] = (T)pts[(6 + c) * N + j];
+            dg_medium<T>((T)d0, (T)d1, (T)d2, m, D);
+            if (MIXED) {
+              T ds[6] = {0, 0, 0, 0, 0, 0};
+              contract_b_t<T>(D, m.c12, m.c44, m.hh, b, tt, ds);
+#pragma unroll
+              for (int c = 0; c < 6; ++c) {  // Kahan-compensated accumulation
+                T y = ds[c] - cmp[c];
+                T z = acc[c] + y;
+                cmp[c] = (z - acc[c]) - y;
+                acc[c] = z;
+              }
+            } else {
+              contract_b_t<T>(D, m.c12, m.c44, m.hh, b, tt, acc);
+            }
+          }
+        }
+      }
+      base += cj;
+    }
+    double tot[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) tot[c] = (double)acc[c] - (double)cmp[c] + acc64[c];
+    for (int o = S / 2; o >= 1; o >>= 1)
+#pragma unroll
+      for (int c = 0; c < 6; ++c) tot[c] += __shfl_xor(tot[c], o, 64);
+    if (act && slice == 0) {
+      // L2P: far-field stress at the point by interpolation of the leaf's local values
+      T t[3] = {(T)((xt0 - lo[0]) / sD), (T)((xt1 - lo[1]) / sD), (T)((xt2 - lo[2]) / sD)};
+      T L[3][kMaxOrder];
+      for (int d = 0; d < 3; ++d)
+        for (int k = 0; k < p; ++k) L[d][k] = lagr<T>(p, k, t[d]);
+      T far[6] = {0, 0, 0, 0, 0, 0};
+      for (int l1 = 0; l1 < p; ++l1)
+        for (int l2 = 0; l2 < p; ++l2) {
+          T w12 = L[0][l1] * L[1][l2];
+          for (int l3 = 0; l3 < p; ++l3) {
+            T w = w12 * L[2][l3];
+            int node = (l1 * p + l2) * p + l3;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) far[c] += w * sl[c * p3 + node];
+          }
+        }
+#pragma unroll
+      for (int c = 0; c < 6; ++c) sig[i * 6 + c] = tot[c] + (double)far[c];
+    }
+  }
+}
+
+// ---------------------------------------------------------------- forces
+__device__ __forceinline__ void pk_force(const double* sg, const double* b, const double* dS, double* fx) {
+  double sb0 = sg[0] * b[0] + sg[5] * b[1] + sg[4] * b[2];
+  double sb1 = sg[5] * b[0] + sg[1] * b[1] + sg[3] * b[2];
+  double sb2 = sg[4] * b[0] + sg[3] * b[1] + sg[2] * b[2];
+  fx[0] = sb1 * dS[2] - sb2 * dS[1];
+  fx[1] = sb2 * dS[0] - sb0 * dS[2];
+  fx[2] = sb0 * dS[1] - sb1 * dS[0];
+}
+
+// forces[t] for segments seg_idx(t) (= t, or targets[t]); stress of point k of
+// target t at sig[row(t, k)] with row = inv[s*nq + k] (FMM) or t*nq + k (direct).
+__global__ void k_forces(const double* seg, const double* burg, const int64_t* targets, const uint32_t* inv,
+                         const double* sig, Quad qd, int64_t nt, double* forces) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nt) return;
+  int64_t s = targets ? targets[t] : t;
+  const double* x = seg + 6 * s;
+  double dS[3] = {x[3] - x[0], x[4] - x[1], x[5] - x[2]};
+  double b[3] = {burg[3 * s], burg[3 * s + 1], burg[3 * s + 2]};
+  double f1[3] = {0, 0, 0}, f2[3] = {0, 0, 0};
+  for (int k = 0; k < qd.n; ++k) {
+    int64_t row = inv ? (int64_t)inv[s * qd.n + k] : t * qd.n + k;
+    double fx[3];
+    pk_force(sig + row * 6, b, dS, fx);
+    double sk = 0.5 * (1.0 + qd.u[k]), hw = 0.5 * qd.w[k];
+    for (int c = 0; c < 3; ++c) {
+      f1[c] += hw * (1.0 - sk) * fx[c];
+      f2[c] += hw * sk * fx[c];
+    }
+  }
+  for (int c = 0; c < 3; ++c) {
+    forces[6 * t + c] = f1[c];
+    forces[6 * t + 3 + c] = f2[c];
+  }
+}
+
+// ---------------------------------------------------------------- direct
+__global__ void k_points_plain(const double* seg, const double* burg, Quad qd, int64_t N, double* pts) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  int64_t s = j / qd.n;
+  int k = (int)(j - s * qd.n);
+  const double* x = seg + 6 * s;
+  double dS[3] = {x[3] - x[0], x[4] - x[1], x[5] - x[2]};
+  double c = 0.5 * (1.0 + qd.u[k]), hw = 0.5 * qd.w[k];
+  for (int d = 0; d < 3; ++d) {
+    pts[d * N + j] = x[d] + c * dS[d];
+    pts[(3 + d) * N + j] = burg[3 * s + d];
+    pts[(6 + d) * N + j] = hw * dS[d];
+  }
+}
+
+// Block = 256 target points x one chunk of sources (staged in LDS in tiles).
+// part[chunk][tp][6] holds the chunk's partial stress in double.
+template <bool FP32>
+__global__ void __launch_bounds__(256) k_direct(const double* pts, int64_t N, const int64_t* targets, int nq,
+                                                int64_t ntp, int64_t chunk, Med<double> m64, Med<float> m32,
+                                                double* part) {
+  __shared__ double sp[9][256];
+  const int64_t tp = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const bool act = tp < ntp;
+  int64_t src_pt = 0;
+  if (act) {
+    int64_t t = tp / nq;
+    int k = (int)(tp - t * nq);
+    src_pt = (targets ? targets[t] : t) * nq + k;
+  }
+  const double x0 = act ? pts[src_pt] : 0, x1 = act ? pts[N + src_pt] : 0, x2 = act ? pts[2 * N + src_pt] : 0;
+  const int64_t j0 = (int64_t)blockIdx.y * chunk, j1 = min(N, j0 + chunk);
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  float af[6] = {0, 0, 0, 0, 0, 0}, cf[6] = {0, 0, 0, 0, 0, 0};
+  for (int64_t jt = j0; jt < j1; jt += 256) {
+    const int nt = (int)min((int64_t)256, j1 - jt);
+    __syncthreads();
+    if (threadIdx.x < nt)
+      for (int c = 0; c < 9; ++c) sp[c][threadIdx.x] = pts[c * N + jt + threadIdx.x];
+    __syncthreads();
+    if (!act) continue;
+    for (int j = 0; j < nt; ++j) {
+      double d0 = x0 - sp[0][j], d1 = x1 - sp[1][j], d2 = x2 - sp[2][j];
+      if (FP32) {
+        float D[27], b[3] = {(float)sp[3][j], (float)sp[4][j], (float)sp[5][j]},
+                     t[3] = {(float)sp[6][j], (float)sp[7][j], (float)sp[8][j]};
+        dg_medium<float>((float)d0, (float)d1, (float)d2, m32, D);
+        float ds[6] = {0, 0, 0, 0, 0, 0};
+        contract_b_t<float>(D, m32.c12, m32.c44, m32.hh, b, t, ds);
+        for (int c = 0; c < 6; ++c) {
+          float y = ds[c] - cf[c];
+          float z = af[c] + y;
+          cf[c] = (z - af[c]) - y;
+          af[c] = z;
+        }
+      } else {
+        double D[27], b[3] = {sp[3][j], sp[4][j], sp[5][j]}, t[3] = {sp[6][j], sp[7][j], sp[8][j]};
+        dg_medium<double>(d0, d1, d2, m64, D);
+        contract_b_t<double>(D, m64.c12, m64.c44, m64.hh, b, t, acc);
+      }
+    }
+  }
+  if (act) {
+    double* o = part + ((int64_t)blockIdx.y * ntp + tp) * 6;
+    for (int c = 0; c < 6; ++c) o[c] = FP32 ? ((double)af[c] - (double)cf[c]) : acc[c];
+  }
+}
+
+__global__ void k_check_targets(const int64_t* targets, int64_t nt, int64_t nseg, int* bad) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nt && (targets[i] < 0 || targets[i] >= nseg)) atomicOr(bad, 1);
+}
+
+__global__ void k_direct_reduce(const double* part, int64_t ntp, int nchunk, double* sig) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ntp * 6) return;
+  double s = 0.0;
+  for (int c = 0; c < nchunk; ++c) s += part[(int64_t)c * ntp * 6 + i];
+  sig[i] = s;
+}
+
+// ------------------------------------------------------------ host side
+static size_t lds_fdft(int p, int G, size_t es) {
+  int n = 2 * p - 1, p3 = p * p * p;
+  return 2 * es * n + es * (G * p3 + 1) + 2 * es * (size_t)G * p3 + 2 * es * (size_t)G * p * n * p;
+}
+static size_t lds_idft(int p, int G, size_t es) {
+  int n = 2 * p - 1;
+  return 2 * es * ((size_t)n + (size_t)G * n * n * p + (size_t)G * n * p * p + (size_t)G * p * p * p);
+}
+
+struct StageTimer {
+  dfmm_tree* t;
+  hipStream_t st;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev;
+  int begin(int stage) {
+    if (!t->timing) return DFMM_OK;
+    hipEvent_t a, b;
+    DFMM_HIP(hipEventCreate(&a));
+    DFMM_HIP(hipEventCreate(&b));
+    DFMM_HIP(hipEventRecord(a, st));
+    ev.push_back({stage, {a, b}});
+    return DFMM_OK;
+  }
+  int end() {
+    if (!t->timing) return DFMM_OK;
+    DFMM_HIP(hipEventRecord(ev.back().second.second, st));
+    return DFMM_OK;
+  }
+  int finish() {
+    if (!t->timing) return DFMM_OK;
+    DFMM_HIP(hipEventSynchronize(ev.back().second.second));
+    for (auto& e : ev) {
+      float ms = 0;
+      DFMM_HIP(hipEventElapsedTime(&ms, e.second.first, e.second.second));
+      t->stage_ms[e.first] += ms;
+      hipEventDestroy(e.second.first);
+      hipEventDestroy(e.second.second);
+    }
+    t->timed_calls++;
+    return DFMM_OK;
+  }
+};
+
+#define STAGE(id, body)             \
+  do {                              \
+    int rc_ = tm.begin(id);         \
+    if (rc_) return rc_;            \
+    body;                           \
+    DFMM_LAUNCH_CHECK();            \
+    rc_ = tm.end();                 \
+    if (rc_) return rc_;            \
+  } while (0)
+
+template <typename T>
+static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const double* burg, double* forces,
+                   hipStream_t st) {
+  const int p = pl->p, p3 = p * p * p, n = pl->n, nf = pl->nf, D = pl->D;
+  const int64_t N = t->N;
+  const size_t es = sizeof(T);
+  const Tables<T>& tb = *(const Tables<T>*)(std::is_same<T, double>::value ? (const void*)&pl->t64
+                                                                          : (const void*)&pl->t32);
+  const double* lo = pl->prm.box_lo;
+  const double L = pl->prm.box_size;
+  T* W = (T*)t->W;
+  T* s = (T*)t->s;
+  cplx<T>* What = (cplx<T>*)t->What;
+  cplx<T>* Shat = (cplx<T>*)t->Shat;
+  StageTimer tm{t, st, {}};
+  const auto& LD = t->lv[D];
+  const double sD = L / std::ldexp(1.0, D);
+
+  STAGE(0, (k_gather<<<nblk(N, 256), 256, 0, st>>>(seg, burg, t->perm, pl->quad, N, t->pts)));
+  {
+    int bs = std::max(64, ((p3 + 63) / 64) * 64);
+    size_t shm = es * (64 * 3 * p + 64 * 9);
+    STAGE(0, (k_p2m<T><<<(unsigned)LD.n, bs, shm, st>>>(t->pts, N, LD.first, LD.count, LD.key, lo[0], lo[1],
+                                                           lo[2], sD, p, W + LD.off * 9 * p3)));
+  }
+  {
+    size_t shm = es * (27 * p3 + 2 * p * p);
+    for (int l = D - 1; l >= 2; --l) {
+      const auto& Lc = t->lv[l + 1];
+      const auto& Lp = t->lv[l];
+      STAGE(1, (k_m2m<T><<<(unsigned)Lp.n, 256, shm, st>>>(Lp.first, Lp.count, Lc.key, W + Lc.off * 9 * p3,
+                                                            W + Lp.off * 9 * p3, tb.S, p)));
+    }
+  }
+  int Gf = 9;
+  while (Gf > 1 && lds_fdft(p, Gf, es) > 64 * 1024) Gf = (Gf == 9) ? 3 : 1;
+  int Gi = 6;
+  while (Gi > 1 && lds_idft(p, Gi, es) > 64 * 1024) Gi = (Gi == 6) ? 3 : (Gi == 3 ? 2 : 1);
+  constexpr int ROWS = std::is_same<T, double>::value ? 3 : 6;
+  const size_t shm_h = sizeof(cplx<T>) * kNumOffsets * ROWS * 9;
+  for (int l = 2; l <= D; ++l) {
+    const auto& Lv = t->lv[l];
+    if (Lv.n == 0) continue;
+    STAGE(2, (k_fdft<T><<<(unsigned)Lv.n, 256, lds_fdft(p, Gf, es), st>>>(W + Lv.off * 9 * p3, Lv.n, p, Gf,
+                                                                         tb.tw, What)));
+    int bs = Lv.n >= 16384 ? 1024 : 256;
+    dim3 g(nblk(Lv.n, bs), nf, 6 / ROWS);
+    STAGE(3, (k_hadamard<T, ROWS><<<g, bs, shm_h, st>>>(What, (const cplx<T>*)pl->lev[l].khat, Lv.il_start,
+                                                         Lv.il, Lv.n, nf, Shat)));
+    STAGE(4, (k_idft<T><<<(unsigned)Lv.n, 256, lds_idft(p, Gi, es), st>>>(Shat, Lv.n, p, Gi, tb.tw,
+                                                                        s + Lv.off * 6 * p3)));
+  }
+  {
+    size_t shm = es * (12 * p3 + 2 * p * p);
+    for (int l = 3; l <= D; ++l) {
+      const auto& Lv = t->lv[l];
+      const auto& Lp = t->lv[l - 1];
+      STAGE(5, (k_l2l<T><<<(unsigned)Lv.n, 256, shm, st>>>(Lv.parent, Lv.key, s + Lp.off * 6 * p3,
+                                                            s + Lv.off * 6 * p3, tb.S, p)));
+    }
+  }
+  {
+    Med<T> m = pl->med<T>();
+    Med<double> m64 = pl->med<double>();
+    const bool mixed = !std::is_same<T, double>::value;
+    if (mixed)
+      STAGE(6, (k_leaf<T, true><<<(unsigned)LD.n, 64, 0, st>>>(t->pts, N, LD.first, LD.count, LD.key, t->nbr,
+                                                                s + LD.off * 6 * p3, lo[0], lo[1], lo[2], sD, p,
+                                                                m, m64, t->sig)));
+    else
+      STAGE(6, (k_leaf<T, false><<<(unsigned)LD.n, 64, 0, st>>>(t->pts, N, LD.first, LD.count, LD.key, t->nbr,
+                                                                 s + LD.off * 6 * p3, lo[0], lo[1], lo[2], sD,
+                                                                 p, m, m64, t->sig)));
+  }
+  STAGE(7, (k_forces<<<nblk(t->nseg, 128), 128, 0, st>>>(seg, burg, nullptr, t->inv, t->sig, pl->quad,
+                                                          t->nseg, forces)));
+  t->last_stream = st;
+  (void)n;
+  return tm.finish();
+}
+
+template <typename T>
+static void set_lds_attrs() {
+  static bool done = false;
+  if (done) return;
+  done = true;
+  const int mx = 160 * 1024;
+  hipFuncSetAttribute((const void*)k_hadamard<T, std::is_same<T, double>::value ? 3 : 6>,
+                      hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+  hipFuncSetAttribute((const void*)k_fdft<T>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+  hipFuncSetAttribute((const void*)k_idft<T>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+  hipFuncSetAttribute((const void*)k_m2m<T>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+  hipFuncSetAttribute((const void*)k_l2l<T>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+  hipFuncSetAttribute((const void*)k_p2m<T>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+}
+
+int fmm_forces_impl(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const double* burg, double* forces,
+                    hipStream_t st) {
+  if (pl->mixed) {
+    set_lds_attrs<float>();
+    return run_fmm<float>(pl, t, seg, burg, forces, st);
+  }
+  set_lds_attrs<double>();
+  return run_fmm<double>(pl, t, seg, burg, forces, st);
+}
+
+int direct_forces_impl(const dfmm_plan* pl, const double* seg, const double* burg, int64_t nseg,
+                       const int64_t* targets, int64_t ntgt, double* forces, int fp32, hipStream_t st) {
+  const int nq = pl->quad.n;
+  const int64_t N = nseg * nq, ntp = ntgt * nq;
+  double *pts = nullptr, *part = nullptr, *sig = nullptr;
+  const int64_t tb = (ntp + 255) / 256;
+  int64_t nchunk = std::max<int64_t>(1, std::min<int64_t>((N + 255) / 256, (4096 + tb - 1) / tb));
+  const int64_t chunk = ((N + nchunk - 1) / nchunk + 255) / 256 * 256;
+  nchunk = (N + chunk - 1) / chunk;
+  if (hipMalloc(&pts, sizeof(double) * 9 * N) != hipSuccess ||
+      hipMalloc(&part, sizeof(double) * 6 * ntp * nchunk) != hipSuccess ||
+      hipMalloc(&sig, sizeof(double) * 6 * ntp) != hipSuccess) {
+    hipFree(pts);
+    hipFree(part);
+    hipFree(sig);
+    set_error("direct_forces: cannot allocate scratch");
+    return DFMM_E_NOMEM;
+  }
+  int rc = DFMM_OK;
+  if (targets) {
+    // reject target indices outside [0, nseg) before any kernel reads through them
+    int* bad = (int*)sig;
+    int hbad = 0;
+    hipMemsetAsync(bad, 0, sizeof(int), st);
+    k_check_targets<<<nblk(ntgt, 256), 256, 0, st>>>(targets, ntgt, nseg, bad);
+    if (hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess || hbad) {
+      hipFree(pts);
+      hipFree(part);
+      hipFree(sig);
+      set_error(hbad ? "direct_forces: target index outside [0, n_seg)" : "direct_forces: HIP error");
+      return hbad ? DFMM_E_ARG : DFMM_E_HIP;
+    }
+  }
+  do {
+    k_points_plain<<<nblk(N, 256), 256, 0, st>>>(seg, burg, pl->quad, N, pts);
+    if (hipGetLastError() != hipSuccess) { rc = DFMM_E_HIP; break; }
+    dim3 g((unsigned)tb, (unsigned)nchunk);
+    if (fp32)
+      k_direct<true><<<g, 256, 0, st>>>(pts, N, targets, nq, ntp, chunk, pl->med<double>(), pl->med<float>(),
+                                       part);
+    else
+      k_direct<false><<<g, 256, 0, st>>>(pts, N, targets, nq, ntp, chunk, pl->med<double>(), pl->med<float>(),
+                                        part);
+    if (hipGetLastError() != hipSuccess) { rc = DFMM_E_HIP; break; }
+    k_direct_reduce<<<nblk(ntp * 6, 256), 256, 0, st>>>(part, ntp, (int)nchunk, sig);
+    if (hipGetLastError() != hipSuccess) { rc = DFMM_E_HIP; break; }
+    k_forces<<<nblk(ntgt, 128), 128, 0, st>>>(seg, burg, targets, nullptr, sig, pl->quad, ntgt, forces);
+    if (hipGetLastError() != hipSuccess) { rc = DFMM_E_HIP; break; }
+  } while (0);
+  if (rc) set_error("direct_forces: kernel launch failed");
+  hipError_t e = hipStreamSynchronize(st);
+  hipFree(pts);
+  hipFree(part);
+  hipFree(sig);
+  if (rc == DFMM_OK && e != hipSuccess) {
+    set_error(std::string("direct_forces: ") + hipGetErrorString(e));
+    rc = DFMM_E_HIP;
+  }
+  return rc;
+}
+
+}  // namespace dfmm

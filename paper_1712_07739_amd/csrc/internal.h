@@ -1,0 +1,140 @@
+// Internal declarations of libdfmm (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/dfmm.h"
+#include "kernel_eval.h"
+
+namespace dfmm {
+
+constexpr int kMaxOrder = 8;
+constexpr int kMaxQuad = 8;
+constexpr int kNumOffsets = 316;  // M2L offsets in [-3,3]^3 outside [-1,1]^3
+constexpr int kNumFar = 189;      // interaction-list size of an interior cell
+
+struct Quad {
+  double u[kMaxQuad], w[kMaxQuad];
+  int n;
+};
+
+// Device-resident float/double copies of the small constant tables.
+template <typename T>
+struct Tables {
+  T* S = nullptr;   // [2][p][p]: S[b][i][m] = parent basis i at child node m of octant bit b
+  T* cs = nullptr;  // circle cos/sin [nhalf][2]
+  T* tw = nullptr;  // DFT twiddles [n][2]: exp(-2 pi i k / n)
+};
+
+struct LevelTables {
+  void* khat = nullptr;  // [nf][316][54] complex (float2 or double2): DFT of the
+                         // circulant embedding of each offset's generator
+};
+
+}  // namespace dfmm
+
+struct dfmm_plan {
+  dfmm_params prm;
+  int p = 0, n = 0, nf = 0, D = 0;
+  int mixed = 0;
+  int iso = 0;
+  double mu = 0, nu = 0;  // isotropic (or Voigt) moduli
+  dfmm::Quad quad;
+  dfmm::Tables<double> t64;
+  dfmm::Tables<float> t32;
+  int* oid343 = nullptr;   // device [343]: offset (o+3) lex index -> id or -1
+  int* off316 = nullptr;   // device [316][3]: id -> offset
+  std::vector<dfmm::LevelTables> lev;  // index = level (0..D); used for 2..D
+  double setup_ms = 0;
+  size_t khat_bytes = 0;
+  int device = 0;
+  template <typename T>
+  dfmm::Med<T> med() const;
+};
+
+struct dfmm_tree {
+  const dfmm_plan* plan = nullptr;
+  int64_t nseg = 0, N = 0;
+  int D = 0;
+  // sorted points: perm[sorted] = point id (= seg*nq + k), inv[point id] = sorted
+  uint32_t* perm = nullptr;
+  uint32_t* inv = nullptr;
+  // occupied cells of one level (level-local indices), levels 2..D
+  struct Level {
+    int64_t n = 0;             // occupied cells
+    int64_t off = 0;           // first global cell index (W, s are global over levels 2..D)
+    uint32_t* key = nullptr;   // Morton key at this level, ascending
+    int* first = nullptr;      // leaves: first sorted point; others: first child (level l+1 index)
+    int* count = nullptr;      // leaves: #points; others: #children
+    int* parent = nullptr;     // parent index at level l-1 (levels 3..D)
+    int* il_start = nullptr;   // [n+1] interaction-list CSR
+    int2* il = nullptr;        // (source index at this level, offset id 0..315)
+    int64_t npairs = 0;
+  };
+  std::vector<Level> lv;
+  int64_t ncell_total = 0, max_level_cells = 0;
+  int* nbr = nullptr;            // leaves: [n][27] neighbour leaf index or -1
+  int64_t npairs = 0;            // M2L pairs over all levels
+  int64_t near_pairs = 0;        // point pairs in the near field
+  int max_leaf_pts = 0;
+  // workspaces
+  double* pts = nullptr;    // sorted point data [9][N]: x, y, z, bx, by, bz, tx, ty, tz
+  void* W = nullptr;        // [ncell_total][9][p^3]  (float or double)
+  void* s = nullptr;        // [ncell_total][6][p^3]
+  void* What = nullptr;     // [nf][max level cells][9] complex
+  void* Shat = nullptr;     // [max level cells][nf][6] complex
+  double* sig = nullptr;    // [N][6] stress at sorted points
+  size_t bytes = 0;
+  // per-stage timing
+  int timing = 0;
+  hipEvent_t ev[DFMM_N_STAGES + 1] = {};
+  double stage_ms[DFMM_N_STAGES] = {};
+  int timed_calls = 0;
+  hipStream_t last_stream = nullptr;
+};
+
+namespace dfmm {
+
+void set_error(const std::string& msg);
+
+// setup.hip
+int setup_tables(dfmm_plan* plan, hipStream_t st);
+
+// tree.hip
+int build_tree_impl(dfmm_plan* plan, const double* seg, int64_t nseg, hipStream_t st, dfmm_tree* t);
+
+// fmm.hip
+int fmm_forces_impl(const dfmm_plan* plan, dfmm_tree* t, const double* seg, const double* burg,
+                    double* forces, hipStream_t st);
+int direct_forces_impl(const dfmm_plan* plan, const double* seg, const double* burg, int64_t nseg,
+                       const int64_t* targets, int64_t ntgt, double* forces, int fp32, hipStream_t st);
+
+}  // namespace dfmm
+
+#define DFMM_HIP(call)                                                                   \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess) {                                                              \
+      dfmm::set_error(std::string(#call) + ": " + hipGetErrorString(e_));                 \
+      return DFMM_E_HIP;                                                                 \
+    }                                                                                    \
+  } while (0)
+
+#define DFMM_D2H(dst, src, bytes, st)                                                   \
+  do {                                                                                   \
+    DFMM_HIP(hipMemcpyAsync((dst), (src), (bytes), hipMemcpyDeviceToHost, (st)));        \
+    DFMM_HIP(hipStreamSynchronize(st));                                                  \
+  } while (0)
+
+#define DFMM_LAUNCH_CHECK()                                                              \
+  do {                                                                                   \
+    hipError_t e_ = hipGetLastError();                                                   \
+    if (e_ != hipSuccess) {                                                              \
+      dfmm::set_error(std::string("kernel launch: ") + hipGetErrorString(e_) + " at " +   \
+                      __FILE__ + ":" + std::to_string(__LINE__));                        \
+      return DFMM_E_HIP;                                                                 \
+    }                                                                                    \
+  } while (0)

@@ -1,0 +1,479 @@
+// Octree build (partition step of the FMM, Sec. 3 and Sec. 4.3).
+//
+// Quadrature points get 3D Morton keys of their leaf (every point is binned by
+// its own position into half-open cells; points on the upper face of the root
+// are clamped in).  A stable LSD radix sort orders (key, point id); run-length
+// encoding of the sorted keys gives the occupied leaves, and of the parent
+// keys (key >> 3) the occupied cells of each coarser level down to level 2.
+// Neighbour lists (27 cells, self included) of the leaves and interaction
+// lists (children of the parent's neighbours that are not neighbours, at most
+// 189) of every level >= 2 are found by binary search in the sorted keys.
+#include <algorithm>
+#include <cmath>
+
+#include "internal.h"
+
+namespace dfmm {
+
+// ------------------------------------------------------------------ utils
+__device__ __forceinline__ uint32_t spread3(uint32_t v) {
+  v &= 0x3ff;
+  v = (v | (v << 16)) & 0x030000FF;
+  v = (v | (v << 8)) & 0x0300F00F;
+  v = (v | (v << 4)) & 0x030C30C3;
+  v = (v | (v << 2)) & 0x09249249;
+  return v;
+}
+__device__ __forceinline__ uint32_t compact3(uint32_t v) {
+  v &= 0x09249249;
+  v = (v | (v >> 2)) & 0x030C30C3;
+  v = (v | (v >> 4)) & 0x0300F00F;
+  v = (v | (v >> 8)) & 0x030000FF;
+  v = (v | (v >> 16)) & 0x3ff;
+  return v;
+}
+// key bit 3b+2 = x_b, 3b+1 = y_b, 3b = z_b
+__device__ __forceinline__ uint32_t morton(int x, int y, int z) {
+  return (spread3(x) << 2) | (spread3(y) << 1) | spread3(z);
+}
+__device__ __forceinline__ void demorton(uint32_t k, int& x, int& y, int& z) {
+  x = compact3(k >> 2);
+  y = compact3(k >> 1);
+  z = compact3(k);
+}
+__device__ __forceinline__ int bsearch_key(const uint32_t* keys, int n, uint32_t k) {
+  int lo = 0, hi = n - 1;
+  while (lo <= hi) {
+    int mid = (lo + hi) >> 1;
+    uint32_t v = keys[mid];
+    if (v == k) return mid;
+    if (v < k) lo = mid + 1;
+    else hi = mid - 1;
+  }
+  return -1;
+}
+
+// --------------------------------------------------------------- points
+__global__ void k_make_keys(const double* seg, int64_t nseg, Quad qd, double lo0, double lo1, double lo2,
+                            double size, int D, uint32_t* keys, uint32_t* vals, int* err) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t N = nseg * qd.n;
+  if (j >= N) return;
+  int64_t i = j / qd.n;
+  int k = (int)(j - i * qd.n);
+  const double* s = seg + 6 * i;
+  double x1[3] = {s[0], s[1], s[2]}, x2[3] = {s[3], s[4], s[5]};
+  double lo[3] = {lo0, lo1, lo2};
+  int c[3];
+  int e = 0;
+  const int nside = 1 << D;
+  const double sD = size / nside;
+  for (int d = 0; d < 3; ++d) {
+    if (!isfinite(x1[d]) || !isfinite(x2[d])) e |= 1;
+    double y = x1[d] + 0.5 * (1.0 + qd.u[k]) * (x2[d] - x1[d]);
+    if (!(y >= lo[d] && y <= lo[d] + size)) e |= 2;
+    double f = floor((y - lo[d]) / sD);
+    int ci = isfinite(f) ? (int)fmin(fmax(f, 0.0), (double)(nside - 1)) : 0;
+    c[d] = ci;
+  }
+  if (e) atomicOr(err, e);
+  keys[j] = morton(c[0], c[1], c[2]);
+  vals[j] = (uint32_t)j;
+}
+
+// ----------------------------------------------------------------- scan
+constexpr int SC_T = 256, SC_I = 8, SC_TILE = SC_T * SC_I;
+
+__device__ __forceinline__ int block_excl_scan(int v, int& total) {
+  __shared__ int wsum[SC_T / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wsum[w] = x;
+  __syncthreads();
+  int pre = 0, tot = 0;
+  for (int i = 0; i < SC_T / 64; ++i) {
+    if (i < w) pre += wsum[i];
+    tot += wsum[i];
+  }
+  __syncthreads();
+  total = tot;
+  return pre + x - v;
+}
+
+__global__ void k_scan_tiles(const int* in, int* out, int64_t n, int* sums) {
+  int64_t base = (int64_t)blockIdx.x * SC_TILE + threadIdx.x * SC_I;
+  int v[SC_I], s = 0;
+#pragma unroll
+  for (int i = 0; i < SC_I; ++i) {
+    v[i] = (base + i < n) ? in[base + i] : 0;
+    s += v[i];
+  }
+  int tot;
+  int ex = block_excl_scan(s, tot);
+#pragma unroll
+  for (int i = 0; i < SC_I; ++i) {
+    if (base + i < n) out[base + i] = ex;
+    ex += v[i];
+  }
+  if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+__global__ void k_add_tile_offsets(int* out, int64_t n, const int* offs) {
+  int64_t base = (int64_t)blockIdx.x * SC_TILE;
+  int add = offs[blockIdx.x];
+  for (int i = threadIdx.x; i < SC_TILE; i += SC_T)
+    if (base + i < n) out[base + i] += add;
+}
+
+// Exclusive scan of in[0..n) into out; returns the total in *total (host).
+static int scan_excl(const int* in, int* out, int64_t n, hipStream_t st, int64_t* total) {
+  int64_t nt = (n + SC_TILE - 1) / SC_TILE;
+  int* sums = nullptr;
+  int* sums_ex = nullptr;
+  DFMM_HIP(hipMalloc(&sums, sizeof(int) * (nt + 1)));
+  DFMM_HIP(hipMalloc(&sums_ex, sizeof(int) * (nt + 1)));
+  k_scan_tiles<<<(unsigned)nt, SC_T, 0, st>>>(in, out, n, sums);
+  DFMM_LAUNCH_CHECK();
+  int64_t tot = 0;
+  int rc = DFMM_OK;
+  if (nt > 1) {
+    rc = scan_excl(sums, sums_ex, nt, st, &tot);
+    if (rc == DFMM_OK) {
+      k_add_tile_offsets<<<(unsigned)nt, SC_T, 0, st>>>(out, n, sums_ex);
+      DFMM_LAUNCH_CHECK();
+    }
+  } else {
+    int h = 0;
+    DFMM_HIP(hipMemcpyAsync(&h, sums, sizeof(int), hipMemcpyDeviceToHost, st));
+    DFMM_HIP(hipStreamSynchronize(st));
+    tot = h;
+  }
+  hipFree(sums);
+  hipFree(sums_ex);
+  *total = tot;
+  return rc;
+}
+
+// ----------------------------------------------------------- radix sort
+constexpr int RS_T = 256, RS_I = 16, RS_TILE = RS_T * RS_I;
+
+__global__ void k_rs_hist(const uint32_t* keys, int64_t n, int shift, int nblk, int* hist) {
+  __shared__ int h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  int64_t base = (int64_t)blockIdx.x * RS_TILE;
+  for (int i = threadIdx.x; i < RS_TILE; i += RS_T)
+    if (base + i < n) atomicAdd(&h[(keys[base + i] >> shift) & 255], 1);
+  __syncthreads();
+  hist[threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
+}
+
+// Stable scatter: items of a tile are ranked in index order (round, wave, lane).
+__global__ void k_rs_scatter(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
+                             int64_t n, int shift, int nblk, const int* offs) {
+  __shared__ int run[256];
+  __shared__ int wcnt[RS_T / 64][256];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  run[threadIdx.x] = offs[threadIdx.x * nblk + blockIdx.x];
+  for (int i = 0; i < RS_T / 64; ++i) wcnt[i][threadIdx.x] = 0;
+  __syncthreads();
+  int64_t base = (int64_t)blockIdx.x * RS_TILE;
+  const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+  for (int r = 0; r < RS_I; ++r) {
+    int64_t idx = base + (int64_t)r * RS_T + threadIdx.x;
+    bool valid = idx < n;
+    uint32_t k = valid ? kin[idx] : 0u;
+    uint32_t v = valid ? vin[idx] : 0u;
+    int d = (k >> shift) & 255;
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+      uint64_t m = __ballot((d >> bit) & 1);
+      peers &= ((d >> bit) & 1) ? m : ~m;
+    }
+    int rank = __popcll(peers & lt);
+    int leader = __ffsll((unsigned long long)peers) - 1;
+    if (valid && lane == leader) wcnt[w][d] = __popcll(peers);
+    __syncthreads();
+    if (valid) {
+      int pre = 0;
+      for (int i = 0; i < w; ++i) pre += wcnt[i][d];
+      int64_t pos = (int64_t)run[d] + pre + rank;
+      kout[pos] = k;
+      vout[pos] = v;
+    }
+    __syncthreads();
+    int tot = 0;
+    for (int i = 0; i < RS_T / 64; ++i) {
+      tot += wcnt[i][threadIdx.x];
+      wcnt[i][threadIdx.x] = 0;
+    }
+    run[threadIdx.x] += tot;
+    __syncthreads();
+  }
+}
+
+// Sort (keys, vals) by the low `bits` bits of keys; result in keys/vals.
+static int radix_sort(uint32_t* keys, uint32_t* vals, int64_t n, int bits, hipStream_t st) {
+  int nblk = (int)((n + RS_TILE - 1) / RS_TILE);
+  uint32_t *k2 = nullptr, *v2 = nullptr;
+  int *hist = nullptr, *offs = nullptr;
+  DFMM_HIP(hipMalloc(&k2, sizeof(uint32_t) * n));
+  DFMM_HIP(hipMalloc(&v2, sizeof(uint32_t) * n));
+  DFMM_HIP(hipMalloc(&hist, sizeof(int) * 256 * nblk));
+  DFMM_HIP(hipMalloc(&offs, sizeof(int) * 256 * nblk));
+  uint32_t *ka = keys, *va = vals, *kb = k2, *vb = v2;
+  int rc = DFMM_OK;
+  for (int shift = 0; shift < bits && rc == DFMM_OK; shift += 8) {
+    k_rs_hist<<<nblk, RS_T, 0, st>>>(ka, n, shift, nblk, hist);
+    DFMM_LAUNCH_CHECK();
+    int64_t tot;
+    rc = scan_excl(hist, offs, (int64_t)256 * nblk, st, &tot);
+    if (rc) break;
+    k_rs_scatter<<<nblk, RS_T, 0, st>>>(ka, va, kb, vb, n, shift, nblk, offs);
+    DFMM_LAUNCH_CHECK();
+    std::swap(ka, kb);
+    std::swap(va, vb);
+  }
+  if (rc == DFMM_OK && ka != keys) {
+    DFMM_HIP(hipMemcpyAsync(keys, ka, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, st));
+    DFMM_HIP(hipMemcpyAsync(vals, va, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, st));
+  }
+  DFMM_HIP(hipStreamSynchronize(st));
+  hipFree(k2);
+  hipFree(v2);
+  hipFree(hist);
+  hipFree(offs);
+  return rc;
+}
+
+// ---------------------------------------------------------------- cells
+__global__ void k_run_flags(const uint32_t* keys, int64_t n, int shift, int* flags) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  flags[i] = (i == 0 || (keys[i] >> shift) != (keys[i - 1] >> shift)) ? 1 : 0;
+}
+
+__global__ void k_run_emit(const uint32_t* keys, int64_t n, int shift, const int* flags, const int* idx,
+                           uint32_t* okey, int* ofirst, int* elem_cell) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int c = idx[i] + flags[i] - 1;
+  if (flags[i]) {
+    okey[c] = keys[i] >> shift;
+    ofirst[c] = (int)i;
+  }
+  if (elem_cell) elem_cell[i] = c;
+}
+
+__global__ void k_run_counts(const int* first, int nc, int64_t n, int* cnt) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nc) return;
+  int nx = (i + 1 < nc) ? first[i + 1] : (int)n;
+  cnt[i] = nx - first[i];
+}
+
+__global__ void k_inverse_perm(const uint32_t* perm, int64_t n, uint32_t* inv) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) inv[perm[i]] = (uint32_t)i;
+}
+
+// ---------------------------------------------------------------- lists
+__global__ void k_leaf_nbrs(const uint32_t* keys, int nc, int lvl, int* nbr) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nc) return;
+  int x, y, z;
+  demorton(keys[i], x, y, z);
+  const int ns = 1 << lvl;
+  int k = 0;
+  for (int a = -1; a <= 1; ++a)
+    for (int b = -1; b <= 1; ++b)
+      for (int c = -1; c <= 1; ++c, ++k) {
+        int X = x + a, Y = y + b, Z = z + c;
+        int r = -1;
+        if (X >= 0 && X < ns && Y >= 0 && Y < ns && Z >= 0 && Z < ns) r = bsearch_key(keys, nc, morton(X, Y, Z));
+        nbr[(int64_t)i * 27 + k] = r;
+      }
+}
+
+// count (fill == nullptr) or fill the interaction list of every cell of a level
+__global__ void k_ilist(const uint32_t* keys, int nc, int lvl, const int* oid343, const int* start, int* cnt,
+                        int2* fill) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nc) return;
+  int x, y, z;
+  demorton(keys[i], x, y, z);
+  const int ns = 1 << lvl;
+  int px = 2 * ((x >> 1) - 1), py = 2 * ((y >> 1) - 1), pz = 2 * ((z >> 1) - 1);
+  int k = 0;
+  int pos = fill ? start[i] : 0;
+  for (int a = 0; a < 6; ++a) {
+    int X = px + a;
+    if (X < 0 || X >= ns) continue;
+    for (int b = 0; b < 6; ++b) {
+      int Y = py + b;
+      if (Y < 0 || Y >= ns) continue;
+      for (int c = 0; c < 6; ++c) {
+        int Z = pz + c;
+        if (Z < 0 || Z >= ns) continue;
+        int ox = x - X, oy = y - Y, oz = z - Z;
+        if (abs(ox) <= 1 && abs(oy) <= 1 && abs(oz) <= 1) continue;
+        int r = bsearch_key(keys, nc, morton(X, Y, Z));
+        if (r < 0) continue;
+        if (fill) fill[pos++] = make_int2(r, oid343[((ox + 3) * 7 + (oy + 3)) * 7 + (oz + 3)]);
+        ++k;
+      }
+    }
+  }
+  if (!fill) cnt[i] = k;
+}
+
+static inline unsigned nb(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+int build_tree_impl(dfmm_plan* pl, const double* seg, int64_t nseg, hipStream_t st, dfmm_tree* t) {
+  const int D = pl->D, nq = pl->quad.n;
+  const int64_t N = nseg * nq;
+  if (N >= (int64_t)1 << 31) {
+    set_error("build_tree: too many quadrature points (limit 2^31)");
+    return DFMM_E_ARG;
+  }
+  t->plan = pl;
+  t->nseg = nseg;
+  t->N = N;
+  t->D = D;
+  t->lv.assign(D + 1, dfmm_tree::Level());
+  uint32_t* keys = nullptr;
+  int* err = nullptr;
+  DFMM_HIP(hipMalloc(&keys, sizeof(uint32_t) * N));
+  DFMM_HIP(hipMalloc(&t->perm, sizeof(uint32_t) * N));
+  DFMM_HIP(hipMalloc(&t->inv, sizeof(uint32_t) * N));
+  DFMM_HIP(hipMalloc(&err, sizeof(int)));
+  DFMM_HIP(hipMemsetAsync(err, 0, sizeof(int), st));
+  k_make_keys<<<nb(N, 256), 256, 0, st>>>(seg, nseg, pl->quad, pl->prm.box_lo[0], pl->prm.box_lo[1],
+                                         pl->prm.box_lo[2], pl->prm.box_size, D, keys, t->perm, err);
+  DFMM_LAUNCH_CHECK();
+  int herr = 0;
+  DFMM_HIP(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
+  DFMM_HIP(hipStreamSynchronize(st));
+  hipFree(err);
+  if (herr & 1) {
+    hipFree(keys);
+    set_error("build_tree: non-finite segment coordinate");
+    return DFMM_E_NONFINITE;
+  }
+  if (herr & 2) {
+    hipFree(keys);
+    set_error("build_tree: a quadrature point lies outside the root cube");
+    return DFMM_E_OUT_OF_BOX;
+  }
+  int rc = radix_sort(keys, t->perm, N, 3 * D, st);
+  if (rc) return rc;
+  k_inverse_perm<<<nb(N, 256), 256, 0, st>>>(t->perm, N, t->inv);
+  DFMM_LAUNCH_CHECK();
+
+  // occupied cells, level D from the points, coarser levels from their children
+  int* flags = nullptr;
+  int* idx = nullptr;
+  DFMM_HIP(hipMalloc(&flags, sizeof(int) * N));
+  DFMM_HIP(hipMalloc(&idx, sizeof(int) * N));
+  const uint32_t* in_keys = keys;
+  int64_t n_in = N;
+  for (int l = D; l >= 2; --l) {
+    int shift = (l == D) ? 0 : 3;
+    k_run_flags<<<nb(n_in, 256), 256, 0, st>>>(in_keys, n_in, shift, flags);
+    DFMM_LAUNCH_CHECK();
+    int64_t nc;
+    rc = scan_excl(flags, idx, n_in, st, &nc);
+    if (rc) return rc;
+    auto& L = t->lv[l];
+    L.n = nc;
+    DFMM_HIP(hipMalloc(&L.key, sizeof(uint32_t) * nc));
+    DFMM_HIP(hipMalloc(&L.first, sizeof(int) * nc));
+    DFMM_HIP(hipMalloc(&L.count, sizeof(int) * nc));
+    int* elem_cell = nullptr;
+    if (l < D) elem_cell = t->lv[l + 1].parent;
+    k_run_emit<<<nb(n_in, 256), 256, 0, st>>>(in_keys, n_in, shift, flags, idx, L.key, L.first, elem_cell);
+    DFMM_LAUNCH_CHECK();
+    k_run_counts<<<nb(nc, 256), 256, 0, st>>>(L.first, (int)nc, n_in, L.count);
+    DFMM_LAUNCH_CHECK();
+    if (l > 2) DFMM_HIP(hipMalloc(&L.parent, sizeof(int) * nc));
+    in_keys = L.key;
+    n_in = nc;
+  }
+  hipFree(flags);
+  hipFree(idx);
+  hipFree(keys);
+  // global cell numbering over levels 2..D
+  t->ncell_total = 0;
+  t->max_level_cells = 0;
+  for (int l = 2; l <= D; ++l) {
+    t->lv[l].off = t->ncell_total;
+    t->ncell_total += t->lv[l].n;
+    t->max_level_cells = std::max<int64_t>(t->max_level_cells, t->lv[l].n);
+  }
+  // neighbours of the leaves
+  auto& LD = t->lv[D];
+  DFMM_HIP(hipMalloc(&t->nbr, sizeof(int) * 27 * LD.n));
+  k_leaf_nbrs<<<nb(LD.n, 128), 128, 0, st>>>(LD.key, (int)LD.n, D, t->nbr);
+  DFMM_LAUNCH_CHECK();
+  // interaction lists
+  t->npairs = 0;
+  for (int l = 2; l <= D; ++l) {
+    auto& L = t->lv[l];
+    int* cnt = nullptr;
+    DFMM_HIP(hipMalloc(&cnt, sizeof(int) * (L.n + 1)));
+    DFMM_HIP(hipMalloc(&L.il_start, sizeof(int) * (L.n + 1)));
+    k_ilist<<<nb(L.n, 128), 128, 0, st>>>(L.key, (int)L.n, l, pl->oid343, nullptr, cnt, nullptr);
+    DFMM_LAUNCH_CHECK();
+    DFMM_HIP(hipMemsetAsync(cnt + L.n, 0, sizeof(int), st));
+    int64_t tot;
+    rc = scan_excl(cnt, L.il_start, L.n + 1, st, &tot);
+    if (rc) return rc;
+    int64_t pairs = tot;
+    L.npairs = pairs;
+    t->npairs += pairs;
+    DFMM_HIP(hipMalloc(&L.il, sizeof(int2) * std::max<int64_t>(pairs, 1)));
+    k_ilist<<<nb(L.n, 128), 128, 0, st>>>(L.key, (int)L.n, l, pl->oid343, L.il_start, nullptr, L.il);
+    DFMM_LAUNCH_CHECK();
+    hipFree(cnt);
+  }
+  // near-field pair count (for reporting)
+  {
+    std::vector<int> hn(27 * LD.n), hc(LD.n);
+    DFMM_D2H(hn.data(), t->nbr, sizeof(int) * hn.size(), st);
+    DFMM_D2H(hc.data(), LD.count, sizeof(int) * hc.size(), st);
+    int64_t np = 0;
+    int mx = 0;
+    for (int64_t i = 0; i < LD.n; ++i) {
+      int64_t s = 0;
+      for (int k = 0; k < 27; ++k)
+        if (hn[27 * i + k] >= 0) s += hc[hn[27 * i + k]];
+      np += s * hc[i];
+      mx = std::max(mx, hc[i]);
+    }
+    t->near_pairs = np;
+    t->max_leaf_pts = mx;
+  }
+  // workspaces
+  const int p3 = pl->p * pl->p * pl->p;
+  const size_t es = pl->mixed ? sizeof(float) : sizeof(double);
+  size_t bW = es * 9 * p3 * t->ncell_total, bS = es * 6 * p3 * t->ncell_total;
+  size_t bWh = es * 2 * 9 * (size_t)pl->nf * t->max_level_cells;
+  size_t bSh = es * 2 * 6 * (size_t)pl->nf * t->max_level_cells;
+  DFMM_HIP(hipMalloc(&t->pts, sizeof(double) * 9 * N));
+  DFMM_HIP(hipMalloc(&t->W, bW));
+  DFMM_HIP(hipMalloc(&t->s, bS));
+  DFMM_HIP(hipMalloc(&t->What, bWh));
+  DFMM_HIP(hipMalloc(&t->Shat, bSh));
+  DFMM_HIP(hipMalloc(&t->sig, sizeof(double) * 6 * N));
+  t->bytes = sizeof(double) * 15 * N + bW + bS + bWh + bSh;
+  DFMM_HIP(hipStreamSynchronize(st));
+  return DFMM_OK;
+}
+
+}  // namespace dfmm
