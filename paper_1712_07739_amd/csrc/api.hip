@@ -152,7 +152,7 @@ void dfmm_tree_destroy(dfmm_tree* t) {
   if (t->last_stream) hipStreamSynchronize(t->last_stream);
   hipFree(t->perm); hipFree(t->inv); hipFree(t->nbr);
   for (auto& L : t->lv) {
-    hipFree(L.key); hipFree(L.first); hipFree(L.count); hipFree(L.parent); hipFree(L.il_start); hipFree(L.il);
+    hipFree(L.key); hipFree(L.first); hipFree(L.count); hipFree(L.parent); hipFree(L.il_start); hipFree(L.il); hipFree(L.order);
   }
   hipFree(t->pts); hipFree(t->W); hipFree(t->s); hipFree(t->What); hipFree(t->Shat); hipFree(t->sig);
   delete t;

@@ -268,7 +268,8 @@ __global__ void k_fdft(const T* W, int64_t ncell, int p, int G, const T* twg, cp
 //   Shat[T][f][r] = sum_{(J, o) in I(T)} sum_k Khat_o(f)[r][k] What[f][J][k].
 template <typename T, int ROWS>
 __global__ void __launch_bounds__(1024) k_hadamard(const cplx<T>* What, const cplx<T>* Khat, const int* il_start,
-                                                   const int2* il, int64_t ncell, int nf, cplx<T>* Shat) {
+                                                   const int2* il, const uint32_t* order, int64_t ncell, int nf,
+                                                   cplx<T>* Shat) {
   extern __shared__ unsigned char shraw[];
   cplx<T>* Ks = (cplx<T>*)shraw;  // [316][ROWS*9]
   const int f = blockIdx.y;
@@ -279,8 +280,9 @@ __global__ void __launch_bounds__(1024) k_hadamard(const cplx<T>* What, const cp
     Ks[e] = kf[o * 54 + row0 * 9 + rk];
   }
   __syncthreads();
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= ncell) return;
+  const int64_t tt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tt >= ncell) return;
+  const int64_t t = order[tt];
   T ar[ROWS], ai[ROWS];
 #pragma unroll
   for (int r = 0; r < ROWS; ++r) ar[r] = ai[r] = T(0);
@@ -373,7 +375,7 @@ __global__ void k_idft(const cplx<T>* Shat, int64_t ncell, int p, int G, const T
 // combined with xor shuffles.  In MIXED precision pairs are evaluated in float
 // (displacements formed in double) with compensated float accumulation, and
 // pairs closer than 2a in double.
-template <typename T, bool MIXED>
+template <typename T, bool MIXED, bool ISO>
 __global__ void __launch_bounds__(64) k_leaf(const double* pts, int64_t N, const int* first, const int* count,
                                              const uint32_t* key, const int* nbr, const T* s, double lo0,
                                              double lo1, double lo2, double sD, int p, Med<T> m, Med<double> m64,
@@ -415,12 +417,12 @@ __global__ void __launch_bounds__(64) k_leaf(const double* pts, int64_t N, const
           if (MIXED && d0 * d0 + d1 * d1 + d2 * d2 < a2x4) {
             double D[27], b[3], tt[3];
             for (int c = 0; c < 3; ++c) b[c] = pts[(3 + c) * N + j], tt[c] = pts[(6 + c) * N + j];
-            dg_medium<double>(d0, d1, d2, m64, D);
+            dg_medium_t<double, ISO>(d0, d1, d2, m64, D);
             contract_b_t<double>(D, m64.c12, m64.c44, m64.hh, b, tt, acc64);
           } else {
             T D[27], b[3], tt[3];
             for (int c = 0; c < 3; ++c) b[c] = (T)pts[(3 + c) * N + j], tt[c] = (T)pts[(6 + c) * N + j];
-            dg_medium<T>((T)d0, (T)d1, (T)d2, m, D);
+            dg_medium_t<T, ISO>((T)d0, (T)d1, (T)d2, m, D);
             if (MIXED) {
               T ds[6] = {0, 0, 0, 0, 0, 0};
               contract_b_t<T>(D, m.c12, m.c44, m.hh, b, tt, ds);
@@ -523,7 +525,7 @@ __global__ void k_points_plain(const double* seg, const double* burg, Quad qd, i
 
 // Block = 256 target points x one chunk of sources (staged in LDS in tiles).
 // part[chunk][tp][6] holds the chunk's partial stress in double.
-template <bool FP32>
+template <bool FP32, bool ISO>
 __global__ void __launch_bounds__(256) k_direct(const double* pts, int64_t N, const int64_t* targets, int nq,
                                                 int64_t ntp, int64_t chunk, Med<double> m64, Med<float> m32,
                                                 double* part) {
@@ -552,7 +554,7 @@ __global__ void __launch_bounds__(256) k_direct(const double* pts, int64_t N, co
       if (FP32) {
         float D[27], b[3] = {(float)sp[3][j], (float)sp[4][j], (float)sp[5][j]},
                      t[3] = {(float)sp[6][j], (float)sp[7][j], (float)sp[8][j]};
-        dg_medium<float>((float)d0, (float)d1, (float)d2, m32, D);
+        dg_medium_t<float, ISO>((float)d0, (float)d1, (float)d2, m32, D);
         float ds[6] = {0, 0, 0, 0, 0, 0};
         contract_b_t<float>(D, m32.c12, m32.c44, m32.hh, b, t, ds);
         for (int c = 0; c < 6; ++c) {
@@ -563,7 +565,7 @@ __global__ void __launch_bounds__(256) k_direct(const double* pts, int64_t N, co
         }
       } else {
         double D[27], b[3] = {sp[3][j], sp[4][j], sp[5][j]}, t[3] = {sp[6][j], sp[7][j], sp[8][j]};
-        dg_medium<double>(d0, d1, d2, m64, D);
+        dg_medium_t<double, ISO>(d0, d1, d2, m64, D);
         contract_b_t<double>(D, m64.c12, m64.c44, m64.hh, b, t, acc);
       }
     }
@@ -688,7 +690,7 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
     int bs = Lv.n >= 16384 ? 1024 : 256;
     dim3 g(nblk(Lv.n, bs), nf, 6 / ROWS);
     STAGE(3, (k_hadamard<T, ROWS><<<g, bs, shm_h, st>>>(What, (const cplx<T>*)pl->lev[l].khat, Lv.il_start,
-                                                         Lv.il, Lv.n, nf, Shat)));
+                                                         Lv.il, Lv.order, Lv.n, nf, Shat)));
     STAGE(4, (k_idft<T><<<(unsigned)Lv.n, 256, lds_idft(p, Gi, es), st>>>(Shat, Lv.n, p, Gi, tb.tw,
                                                                         s + Lv.off * 6 * p3)));
   }
@@ -705,14 +707,18 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
     Med<T> m = pl->med<T>();
     Med<double> m64 = pl->med<double>();
     const bool mixed = !std::is_same<T, double>::value;
-    if (mixed)
-      STAGE(6, (k_leaf<T, true><<<(unsigned)LD.n, 64, 0, st>>>(t->pts, N, LD.first, LD.count, LD.key, t->nbr,
-                                                                s + LD.off * 6 * p3, lo[0], lo[1], lo[2], sD, p,
-                                                                m, m64, t->sig)));
+#define LEAF_ARGS                                                                                     \
+  t->pts, N, LD.first, LD.count, LD.key, t->nbr, s + LD.off * 6 * p3, lo[0], lo[1], lo[2], sD, p, m, m64, \
+      t->sig
+    if (mixed && pl->iso)
+      STAGE(6, (k_leaf<T, true, true><<<(unsigned)LD.n, 64, 0, st>>>(LEAF_ARGS)));
+    else if (mixed)
+      STAGE(6, (k_leaf<T, true, false><<<(unsigned)LD.n, 64, 0, st>>>(LEAF_ARGS)));
+    else if (pl->iso)
+      STAGE(6, (k_leaf<T, false, true><<<(unsigned)LD.n, 64, 0, st>>>(LEAF_ARGS)));
     else
-      STAGE(6, (k_leaf<T, false><<<(unsigned)LD.n, 64, 0, st>>>(t->pts, N, LD.first, LD.count, LD.key, t->nbr,
-                                                                 s + LD.off * 6 * p3, lo[0], lo[1], lo[2], sD,
-                                                                 p, m, m64, t->sig)));
+      STAGE(6, (k_leaf<T, false, false><<<(unsigned)LD.n, 64, 0, st>>>(LEAF_ARGS)));
+#undef LEAF_ARGS
   }
   STAGE(7, (k_forces<<<nblk(t->nseg, 128), 128, 0, st>>>(seg, burg, nullptr, t->inv, t->sig, pl->quad,
                                                           t->nseg, forces)));
@@ -784,12 +790,16 @@ int direct_forces_impl(const dfmm_plan* pl, const double* seg, const double* bur
     k_points_plain<<<nblk(N, 256), 256, 0, st>>>(seg, burg, pl->quad, N, pts);
     if (hipGetLastError() != hipSuccess) { rc = DFMM_E_HIP; break; }
     dim3 g((unsigned)tb, (unsigned)nchunk);
-    if (fp32)
-      k_direct<true><<<g, 256, 0, st>>>(pts, N, targets, nq, ntp, chunk, pl->med<double>(), pl->med<float>(),
-                                       part);
+#define DIRECT_ARGS pts, N, targets, nq, ntp, chunk, pl->med<double>(), pl->med<float>(), part
+    if (fp32 && pl->iso)
+      k_direct<true, true><<<g, 256, 0, st>>>(DIRECT_ARGS);
+    else if (fp32)
+      k_direct<true, false><<<g, 256, 0, st>>>(DIRECT_ARGS);
+    else if (pl->iso)
+      k_direct<false, true><<<g, 256, 0, st>>>(DIRECT_ARGS);
     else
-      k_direct<false><<<g, 256, 0, st>>>(pts, N, targets, nq, ntp, chunk, pl->med<double>(), pl->med<float>(),
-                                        part);
+      k_direct<false, false><<<g, 256, 0, st>>>(DIRECT_ARGS);
+#undef DIRECT_ARGS
     if (hipGetLastError() != hipSuccess) { rc = DFMM_E_HIP; break; }
     k_direct_reduce<<<nblk(ntp * 6, 256), 256, 0, st>>>(part, ntp, (int)nchunk, sig);
     if (hipGetLastError() != hipSuccess) { rc = DFMM_E_HIP; break; }

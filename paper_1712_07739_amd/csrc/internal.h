@@ -72,6 +72,7 @@ struct dfmm_tree {
     int* parent = nullptr;     // parent index at level l-1 (levels 3..D)
     int* il_start = nullptr;   // [n+1] interaction-list CSR
     int2* il = nullptr;        // (source index at this level, offset id 0..315)
+    uint32_t* order = nullptr; // targets in M2L processing order (list length buckets, then Morton)
     int64_t npairs = 0;
   };
   std::vector<Level> lv;

@@ -146,6 +146,18 @@ __device__ __forceinline__ void dg_medium(T x0, T x1, T x2, const Med<T>& m, T* 
   }
 }
 
+// dg_medium with the isotropic/anisotropic branch fixed at compile time.
+template <typename T, bool ISO>
+__device__ __forceinline__ void dg_medium_t(T x0, T x1, T x2, const Med<T>& m, T* D) {
+  if (ISO) {
+#pragma unroll
+    for (int i = 0; i < 27; ++i) D[i] = T(0);
+    dg_iso_acc(x0, x1, x2, m.mu, m.nu, m.a, T(1), D);
+  } else {
+    dg_medium(x0, x1, x2, m, D);
+  }
+}
+
 // sig[6] += stress of a source with strength b (x) t seen through dG (D).
 template <typename T>
 __device__ __forceinline__ void contract_b_t(const T* D, T c12, T c44, T hh, const T* b, const T* t,

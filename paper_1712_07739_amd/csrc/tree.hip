@@ -333,6 +333,15 @@ __global__ void k_ilist(const uint32_t* keys, int nc, int lvl, const int* oid343
   if (!fill) cnt[i] = k;
 }
 
+// key = bucket of descending list length (8 lengths per bucket), val = target
+__global__ void k_len_keys(const int* il_start, int n, uint32_t* key, uint32_t* val) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int len = il_start[i + 1] - il_start[i];
+  key[i] = (uint32_t)((kNumFar - min(len, kNumFar)) >> 3);
+  val[i] = (uint32_t)i;
+}
+
 static inline unsigned nb(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 int build_tree_impl(dfmm_plan* pl, const double* seg, int64_t nseg, hipStream_t st, dfmm_tree* t) {
@@ -440,6 +449,13 @@ int build_tree_impl(dfmm_plan* pl, const double* seg, int64_t nseg, hipStream_t 
     DFMM_HIP(hipMalloc(&L.il, sizeof(int2) * std::max<int64_t>(pairs, 1)));
     k_ilist<<<nb(L.n, 128), 128, 0, st>>>(L.key, (int)L.n, l, pl->oid343, L.il_start, nullptr, L.il);
     DFMM_LAUNCH_CHECK();
+    // processing order of the M2L targets: similar list lengths share a wave
+    uint32_t* okey = (uint32_t*)cnt;
+    DFMM_HIP(hipMalloc(&L.order, sizeof(uint32_t) * L.n));
+    k_len_keys<<<nb(L.n, 256), 256, 0, st>>>(L.il_start, (int)L.n, okey, L.order);
+    DFMM_LAUNCH_CHECK();
+    rc = radix_sort(okey, L.order, L.n, 8, st);
+    if (rc) return rc;
     hipFree(cnt);
   }
   // near-field pair count (for reporting)

@@ -1,0 +1,206 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Bars: direct sum FP64 <= 1e-12 and FP32 <= 1e-6 relative (global L2 over all
+end-point force components); GPU FMM vs the oracle's plain FMM (same
+approximation, dense M2L) <= 1e-10 in FP64; mixed precision <= 2e-5 of the
+FP64 FMM; FMM vs the direct sum <= 1e-4 at the orders the workloads use.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+BOX_LO, BOX = synth.loops.BOX_LO, synth.loops.BOX_SIZE
+ISO = synth.loops.ISO
+CUB = synth.loops.CUBIC_A25
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    import paper_1712_07739_amd as pk
+
+    assert torch.cuda.is_available()
+    pk.lib()
+    return torch, pk, torch.device("cuda:0")
+
+
+def run_fmm(env, seg, b, C, p, D, precision=0, a=1e-3):
+    torch, pk, dev = env
+    prm = pk.make_params(p, D, C[0], C[1], C[2], a, BOX_LO, BOX, precision=precision)
+    plan = pk.Plan(prm)
+    ts = torch.tensor(seg, device=dev)
+    tb = torch.tensor(b, device=dev)
+    tree = pk.Tree(plan, ts)
+    f = pk.fmm_forces(plan, tree, ts, tb).cpu().numpy()
+    return f, plan, tree
+
+
+def run_direct(env, seg, b, C, fp32=False, targets=None, a=1e-3):
+    torch, pk, dev = env
+    prm = pk.make_params(4, 3, C[0], C[1], C[2], a, BOX_LO, BOX)
+    plan = pk.Plan(prm)
+    ts = torch.tensor(seg, device=dev)
+    tb = torch.tensor(b, device=dev)
+    tt = None if targets is None else torch.tensor(np.asarray(targets, dtype=np.int64), device=dev)
+    return pk.direct_forces(plan, ts, tb, targets=tt, fp32=fp32).cpu().numpy()
+
+
+# ------------------------------------------------------------- direct sum
+@pytest.mark.parametrize("C,nloops", [(ISO, 50), (CUB, 8)])
+def test_direct_matches_oracle(env, C, nloops):
+    seg, b = synth.make_loops(nloops, 0.01, 0.05, 1)
+    med = oracle.medium(*C, 1e-3)
+    tgt = synth.segment_subset(len(seg), 150, 3)
+    ref = oracle.direct_forces(seg, b, med, targets=tgt)
+    f64 = run_direct(env, seg, b, C)
+    assert oracle.rel_err(f64[tgt], ref) <= 1e-12
+    f32 = run_direct(env, seg, b, C, fp32=True)
+    assert oracle.rel_err(f32[tgt], ref) <= 1e-6
+    # the target-list path gives the same rows as the all-targets path
+    fs = run_direct(env, seg, b, C, targets=tgt)
+    assert np.array_equal(fs, f64[tgt])
+
+
+def test_direct_rejects_bad_targets(env):
+    torch, pk, dev = env
+    seg, b = synth.make_loops(2, 0.01, 0.05, 1)
+    with pytest.raises(pk.DfmmError) as e:
+        run_direct(env, seg, b, ISO, targets=[0, len(seg)])
+    assert e.value.status == -1
+
+
+# ------------------------------------------------------------------- FMM
+@pytest.mark.parametrize("name,C,nloops,p,D", [
+    ("iso2k", ISO, 50, 4, 3),
+    ("iso-p5-D4", ISO, 30, 5, 4),
+    ("iso-p2-D2", ISO, 12, 2, 2),
+    ("iso-p3-D5", ISO, 20, 3, 5),
+    ("cubic-p4-D3", CUB, 10, 4, 3),
+    ("cubic-p6-D2", CUB, 6, 6, 2),
+])
+def test_fmm_fp64_matches_oracle_fmm(env, name, C, nloops, p, D):
+    seg, b = synth.make_loops(nloops, 0.01, 0.05, 1 if name == "iso2k" else 17)
+    med = oracle.medium(*C, 1e-3)
+    ref_fmm = oracle.fmm_forces(seg, b, med, p, D, BOX_LO, BOX)
+    f, plan, tree = run_fmm(env, seg, b, C, p, D)
+    assert oracle.rel_err(f, ref_fmm) <= 1e-10, name
+    # mixed precision against the same approximation
+    fm, _, _ = run_fmm(env, seg, b, C, p, D, precision=1)
+    assert oracle.rel_err(fm, ref_fmm) <= 2e-5, name
+
+
+def test_fmm_error_vs_direct_decreases_with_order(env):
+    seg, b = synth.make_loops(50, 0.01, 0.05, 1)
+    med = oracle.medium(*ISO, 1e-3)
+    ref = oracle.direct_forces(seg, b, med)
+    errs = [oracle.rel_err(run_fmm(env, seg, b, ISO, p, 3)[0], ref) for p in (3, 4, 5, 6, 7)]
+    for e0, e1 in zip(errs, errs[1:]):
+        assert e1 < e0 / 2
+    assert errs[2] <= 1e-4 and errs[-1] <= 5e-6
+
+
+def test_fmm_all_near_equals_direct(env):
+    seg, b = synth.make_loops(5, 0.02, 0.05, 3)
+    seg = 0.5 + 0.35 * (seg - seg.mean(axis=(0, 1)))
+    f, _, tree = run_fmm(env, seg, b, ISO, 4, 2)
+    assert tree.info()["m2l_pairs"] == 0
+    ref = run_direct(env, seg, b, ISO)
+    assert oracle.rel_err(f, ref) <= 1e-13
+
+
+# ------------------------------------------------------------ edge cases
+def test_single_segment_and_degenerate_inputs(env):
+    torch, pk, dev = env
+    seg = np.array([[[0.3, 0.3, 0.3], [0.31, 0.305, 0.3]]])
+    b = np.array([[1.0, 0.0, 0.0]]) / 1.0
+    f, _, _ = run_fmm(env, seg, b, ISO, 4, 3)
+    ref = oracle.direct_forces(seg, b, oracle.medium(*ISO, 1e-3))
+    assert np.allclose(f, ref, rtol=1e-12, atol=1e-14 * np.abs(ref).max())
+    # a zero-length segment contributes nothing and feels no force
+    seg2, b2 = synth.make_loops(3, 0.01, 0.05, 5)
+    seg2 = np.concatenate([seg2, [[[0.5, 0.5, 0.5], [0.5, 0.5, 0.5]]]])
+    b2 = np.concatenate([b2, [[0.0, 0.0, 1.0]]])
+    f2, _, _ = run_fmm(env, seg2, b2, ISO, 4, 3)
+    f1, _, _ = run_fmm(env, seg2[:-1], b2[:-1], ISO, 4, 3)
+    assert np.all(f2[-1] == 0.0)
+    assert oracle.rel_err(f2[:-1], f1) <= 1e-13
+    # points on the upper faces of the root cube
+    hi = BOX_LO[0] + BOX
+    seg3 = np.array([[[hi, hi, hi], [hi, hi - 0.01, hi]], [[BOX_LO[0], 0.2, 0.3], [BOX_LO[0], 0.21, 0.3]],
+                     [[0.4, 0.4, 0.4], [0.42, 0.4, 0.4]]])
+    b3 = np.array([[0, 0, 1.0], [0, 1.0, 0], [1.0, 0, 0]])
+    f3, _, _ = run_fmm(env, seg3, b3, ISO, 4, 3)
+    ref3 = oracle.fmm_forces(seg3, b3, oracle.medium(*ISO, 1e-3), 4, 3, BOX_LO, BOX)
+    assert oracle.rel_err(f3, ref3) <= 1e-10
+
+
+def test_errors_for_bad_coordinates(env):
+    torch, pk, dev = env
+    prm = pk.make_params(4, 3, *ISO, 1e-3, BOX_LO, BOX)
+    plan = pk.Plan(prm)
+    seg = np.array([[[0.3, 0.3, 0.3], [0.31, 0.305, 0.3]], [[1.2, 0.3, 0.3], [1.21, 0.3, 0.3]]])
+    with pytest.raises(pk.DfmmError) as e:
+        pk.Tree(plan, torch.tensor(seg, device=dev))
+    assert e.value.status == -4
+    seg[1] = [[0.3, np.nan, 0.3], [0.31, 0.3, 0.3]]
+    with pytest.raises(pk.DfmmError) as e:
+        pk.Tree(plan, torch.tensor(seg, device=dev))
+    assert e.value.status == -5
+    # a tree used with another plan
+    plan2 = pk.Plan(prm)
+    seg[1] = [[0.3, 0.3, 0.35], [0.31, 0.3, 0.35]]
+    ts = torch.tensor(seg, device=dev)
+    tree = pk.Tree(plan, ts)
+    with pytest.raises(pk.DfmmError) as e:
+        pk.fmm_forces(plan2, tree, ts, torch.zeros((2, 3), dtype=torch.float64, device=dev))
+    assert e.value.status == -6
+
+
+def test_determinism_and_stage_timing(env):
+    torch, pk, dev = env
+    seg, b = synth.make_loops(40, 0.01, 0.05, 8)
+    for prec in (0, 1):
+        f, plan, tree = run_fmm(env, seg, b, ISO, 5, 4, precision=prec)
+        ts = torch.tensor(seg, device=dev)
+        tb = torch.tensor(b, device=dev)
+        tree.set_timing(True)
+        g = pk.fmm_forces(plan, tree, ts, tb).cpu().numpy()
+        ms, n = tree.stage_times()
+        assert np.array_equal(f, g)
+        assert n == 1 and all(x >= 0 for x in ms) and ms[3] > 0 and ms[6] > 0
+
+
+# -------------------------------------------------- full-size workloads
+def _golden(name):
+    path = os.path.join(ROOT, "tests", "golden", "oracle_samples_%s.json" % name)
+    if not os.path.exists(path):
+        pytest.skip("golden file missing: " + path)
+    return json.load(open(path))
+
+
+@pytest.mark.parametrize("name,precision", [("iso200k", 0), ("iso200k", 1), ("cubic100k", 1),
+                                            ("cubic1m", 1)])
+def test_full_size_fmm_vs_oracle_samples(env, name, precision):
+    """The launch configuration the benchmark times, at the full size, against
+    the oracle's direct sum on sampled segments (values written by
+    tests/golden/make_golden.py from the oracle only)."""
+    torch, pk, dev = env
+    g = _golden(name)
+    seg, b, prm = synth.make_workload(name)
+    assert seg.shape[0] == g["n_seg"]
+    f, plan, tree = run_fmm(env, seg, b, (prm["c11"], prm["c12"], prm["c44"]), prm["order"], prm["depth"],
+                           precision=precision)
+    tgt = np.asarray(g["targets"])
+    ref = np.asarray(g["forces"])
+    err = oracle.rel_err(f[tgt], ref)
+    print("%s precision=%d: rel err vs oracle on %d segments = %.3e" % (name, precision, len(tgt), err))
+    assert err <= 1e-4
