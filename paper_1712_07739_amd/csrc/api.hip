@@ -130,7 +130,7 @@ void dfmm_plan_destroy(dfmm_plan* pl) {
   for (auto& l : pl->lev) hipFree(l.khat);
   hipFree(pl->t64.S); hipFree(pl->t64.cs); hipFree(pl->t64.tw);
   hipFree(pl->t32.S); hipFree(pl->t32.cs); hipFree(pl->t32.tw);
-  hipFree(pl->oid343); hipFree(pl->off316);
+  hipFree(pl->oid343); hipFree(pl->off158);
   delete pl;
 }
 
@@ -203,9 +203,10 @@ int dfmm_plan_info(const dfmm_plan* pl, char* json, size_t cap) {
       json, cap,
       "{\"order\": %d, \"depth\": %d, \"n_fft\": %d, \"n_freq\": %d, \"isotropic\": %d, \"mixed\": %d, "
       "\"mu\": %.17g, \"nu\": %.17g, \"mem_unif_fp64_bytes_per_level\": %.0f, "
-      "\"spectra_bytes\": %zu, \"levels_stored\": %d, \"setup_ms\": %.3f, \"n_quad\": %d, \"n_circle\": %d}",
+      "\"spectra_bytes\": %zu, \"levels_stored\": %d, \"setup_ms\": %.3f, \"n_quad\": %d, \"n_circle\": %d, "
+      "\"n_circle_float\": %d, \"float_rule_err\": %.3g}",
       p, pl->D, pl->n, pl->nf, pl->iso, pl->mixed, pl->mu, pl->nu, mem_unif, pl->khat_bytes, pl->D - 1,
-      pl->setup_ms, pl->quad.n, pl->prm.n_circle);
+      pl->setup_ms, pl->quad.n, pl->prm.n_circle, 2 * pl->nhalf32, pl->float_rule_err);
   if (w < 0 || (size_t)w >= cap) { set_error("plan_info: buffer too small"); return DFMM_E_ARG; }
   return DFMM_OK;
 }

@@ -262,51 +262,76 @@ __global__ void k_fdft(const T* W, int64_t ncell, int p, int G, const T* twg, cp
 }
 
 // ------------------------------------------------------ Hadamard product
-// One block per (target chunk, frequency f, row group).  The spectra of all
-// 316 offsets at frequency f (ROWS of the 6 stress rows) sit in LDS; every
-// thread owns one target cell and walks its interaction list:
+// One block per (window of kM2LWindow Morton-consecutive targets, frequency
+// f).  The spectra of the 158 canonical offsets at frequency f sit in LDS
+// (stride kKStride complex per offset); the spectrum of a mirrored offset -o
+// is -conj of that of o, so its contribution -conj(K) w = -conj(K conj(w)) is
+// folded into the same loop with a sign.  Every thread owns one target cell
+// and walks its interaction list:
 //   Shat[T][f][r] = sum_{(J, o) in I(T)} sum_k Khat_o(f)[r][k] What[f][J][k].
-template <typename T, int ROWS>
-__global__ void __launch_bounds__(1024) k_hadamard(const cplx<T>* What, const cplx<T>* Khat, const int* il_start,
-                                                   const int2* il, const uint32_t* order, int64_t ncell, int nf,
-                                                   cplx<T>* Shat) {
+// With many windows, blocks are remapped so that each of the 8 XCDs (blocks
+// are dispatched round-robin over them) works through a contiguous range of
+// windows at one frequency at a time: neighbouring windows share sources in
+// that XCD's L2.
+template <typename T>
+__global__ void __launch_bounds__(kM2LWindow) k_hadamard(const cplx<T>* What, const cplx<T>* Khat,
+                                                         const int* il_start, const int2* il, const uint32_t* order,
+                                                         int64_t ncell, int nf, int nwin, int remap,
+                                                         cplx<T>* Shat) {
   extern __shared__ unsigned char shraw[];
-  cplx<T>* Ks = (cplx<T>*)shraw;  // [316][ROWS*9]
-  const int f = blockIdx.y;
-  const int row0 = blockIdx.z * ROWS;
-  const cplx<T>* kf = Khat + (int64_t)f * kNumOffsets * 54;
-  for (int e = threadIdx.x; e < kNumOffsets * ROWS * 9; e += blockDim.x) {
-    int o = e / (ROWS * 9), rk = e % (ROWS * 9);
-    Ks[e] = kf[o * 54 + row0 * 9 + rk];
+  cplx<T>* Ks = (cplx<T>*)shraw;  // [158][kKStride]
+  int win, f;
+  if (remap) {
+    const int64_t L = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+    const int wx = (nwin + 7) / 8;
+    const int xcd = (int)(L % 8);
+    const int64_t k = L / 8;
+    f = (int)(k / wx);
+    win = xcd * wx + (int)(k % wx);
+    if (win >= nwin || f >= nf) return;
+  } else {
+    win = blockIdx.x;
+    f = blockIdx.y;
   }
+  const cplx<T>* kf = Khat + (int64_t)f * kNumCanon * 54;
+  for (int e = threadIdx.x; e < kNumCanon * 54; e += blockDim.x) Ks[(e / 54) * kKStride + e % 54] = kf[e];
   __syncthreads();
-  const int64_t tt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t tt = (int64_t)win * kM2LWindow + threadIdx.x;
   if (tt >= ncell) return;
   const int64_t t = order[tt];
-  T ar[ROWS], ai[ROWS];
+  T ar[6], ai[6];
 #pragma unroll
-  for (int r = 0; r < ROWS; ++r) ar[r] = ai[r] = T(0);
+  for (int r = 0; r < 6; ++r) ar[r] = ai[r] = T(0);
   const int e0 = il_start[t], e1 = il_start[t + 1];
   const cplx<T>* wf = What + (int64_t)f * ncell * 9;
   for (int e = e0; e < e1; ++e) {
-    int2 jo = il[e];
+    const int2 jo = il[e];
+    const T sg = (jo.y & 1) ? T(-1) : T(1);
     const cplx<T>* w = wf + (int64_t)jo.x * 9;
-    cplx<T> wv[9];
+    T wr[9], wi[9];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) wv[k] = w[k];
-    const cplx<T>* K = Ks + jo.y * (ROWS * 9);
+    for (int k = 0; k < 9; ++k) {
+      cplx<T> v = w[k];
+      wr[k] = v.re;
+      wi[k] = sg * v.im;
+    }
+    const cplx<T>* K = Ks + (jo.y >> 1) * kKStride;
 #pragma unroll
-    for (int r = 0; r < ROWS; ++r)
+    for (int r = 0; r < 6; ++r) {
+      T cr = T(0), ci = T(0);
 #pragma unroll
       for (int k = 0; k < 9; ++k) {
         cplx<T> kk = K[r * 9 + k];
-        ar[r] += kk.re * wv[k].re - kk.im * wv[k].im;
-        ai[r] += kk.re * wv[k].im + kk.im * wv[k].re;
+        cr += kk.re * wr[k] - kk.im * wi[k];
+        ci += kk.re * wi[k] + kk.im * wr[k];
       }
+      ar[r] += sg * cr;
+      ai[r] += ci;
+    }
   }
-  cplx<T>* out = Shat + (t * nf + f) * 6 + row0;
+  cplx<T>* out = Shat + (t * nf + f) * 6;
 #pragma unroll
-  for (int r = 0; r < ROWS; ++r) out[r] = cplx<T>{ar[r], ai[r]};
+  for (int r = 0; r < 6; ++r) out[r] = cplx<T>{ar[r], ai[r]};
 }
 
 // ------------------------------------------------------------ inverse DFT
@@ -382,10 +407,9 @@ __global__ void __launch_bounds__(64) k_leaf(const double* pts, int64_t N, const
                                              double* sig) {
   const int leaf = blockIdx.x, lane = threadIdx.x;
   const int t0 = first[leaf], nt = count[leaf];
-  int S = 1;
-  while (S * 2 * nt <= 64) S *= 2;
-  const int per = 64 / S;  // targets per pass
   __shared__ int nb_first[27], nb_cnt[27];
+  constexpr int kCloseCap = 24;
+  __shared__ int close_buf[MIXED ? kCloseCap * 64 : 1];
   if (lane < 27) {
     int j = nbr[(int64_t)leaf * 27 + lane];
     nb_first[lane] = j >= 0 ? first[j] : 0;
@@ -397,9 +421,16 @@ __global__ void __launch_bounds__(64) k_leaf(const double* pts, int64_t N, const
   const int p3 = p * p * p;
   const T* sl = s + (int64_t)leaf * 6 * p3;
   const double a2x4 = 4.0 * m64.a * m64.a;
-  for (int c0 = 0; c0 < nt; c0 += per) {
+  // Passes over the leaf's targets: 64 at a time with one lane each, then the
+  // remainder in power-of-two chunks c with S = 64/c lanes per target, so
+  // every pass keeps all 64 lanes busy.
+  for (int c0 = 0, per = 64; c0 < nt; c0 += per) {
+    const int rem = nt - c0;
+    per = 64;
+    while (per > rem) per >>= 1;
+    const int S = 64 / per;
     const int ti = c0 + lane / S, slice = lane % S;
-    const bool act = (lane / S) < per && ti < nt;
+    const bool act = ti < nt;
     const int64_t i = t0 + (act ? ti : 0);
     const double xt0 = pts[i], xt1 = pts[N + i], xt2 = pts[2 * N + i];
     T acc[6], cmp[6];
@@ -407,6 +438,7 @@ __global__ void __launch_bounds__(64) k_leaf(const double* pts, int64_t N, const
 #pragma unroll
     for (int c = 0; c < 6; ++c) acc[c] = cmp[c] = T(0), acc64[c] = 0.0;
     int base = 0;
+    int nclose = 0;
     for (int q = 0; q < 27; ++q) {
       const int fj = nb_first[q], cj = nb_cnt[q];
       if (act) {
@@ -415,10 +447,16 @@ __global__ void __launch_bounds__(64) k_leaf(const double* pts, int64_t N, const
           const int64_t j = fj + jj;
           double d0 = xt0 - pts[j], d1 = xt1 - pts[N + j], d2 = xt2 - pts[2 * N + j];
           if (MIXED && d0 * d0 + d1 * d1 + d2 * d2 < a2x4) {
-            double D[27], b[3], tt[3];
-            for (int c = 0; c < 3; ++c) b[c] = pts[(3 + c) * N + j], tt[c] = pts[(6 + c) * N + j];
-            dg_medium_t<double, ISO>(d0, d1, d2, m64, D);
-            contract_b_t<double>(D, m64.c12, m64.c44, m64.hh, b, tt, acc64);
+            // nearly coincident pair: deferred to the double-precision pass below
+            if (nclose < kCloseCap) {
+              close_buf[nclose * 64 + lane] = (int)j;
+              ++nclose;
+            } else {
+              double D[27], b[3], tt[3];
+              for (int c = 0; c < 3; ++c) b[c] = pts[(3 + c) * N + j], tt[c] = pts[(6 + c) * N + j];
+              dg_medium_t<double, ISO>(d0, d1, d2, m64, D);
+              contract_b_t<double>(D, m64.c12, m64.c44, m64.hh, b, tt, acc64);
+            }
           } else {
             T D[27], b[3], tt[3];
             for (int c = 0; c < 3; ++c) b[c] = (T)pts[(3 + c) * N + j], tt[c] = (T)pts[(6 + c) * N + j];
@@ -440,6 +478,17 @@ __global__ void __launch_bounds__(64) k_leaf(const double* pts, int64_t N, const
         }
       }
       base += cj;
+    }
+    if (MIXED) {
+      // double-precision pass over the deferred pairs (few per lane)
+      for (int k = 0; k < nclose; ++k) {
+        const int64_t j = close_buf[k * 64 + lane];
+        double d0 = xt0 - pts[j], d1 = xt1 - pts[N + j], d2 = xt2 - pts[2 * N + j];
+        double D[27], b[3], tt[3];
+        for (int c = 0; c < 3; ++c) b[c] = pts[(3 + c) * N + j], tt[c] = pts[(6 + c) * N + j];
+        dg_medium_t<double, ISO>(d0, d1, d2, m64, D);
+        contract_b_t<double>(D, m64.c12, m64.c44, m64.hh, b, tt, acc64);
+      }
     }
     double tot[6];
 #pragma unroll
@@ -680,17 +729,17 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
   while (Gf > 1 && lds_fdft(p, Gf, es) > 64 * 1024) Gf = (Gf == 9) ? 3 : 1;
   int Gi = 6;
   while (Gi > 1 && lds_idft(p, Gi, es) > 64 * 1024) Gi = (Gi == 6) ? 3 : (Gi == 3 ? 2 : 1);
-  constexpr int ROWS = std::is_same<T, double>::value ? 3 : 6;
-  const size_t shm_h = sizeof(cplx<T>) * kNumOffsets * ROWS * 9;
+  const size_t shm_h = sizeof(cplx<T>) * kNumCanon * kKStride;
   for (int l = 2; l <= D; ++l) {
     const auto& Lv = t->lv[l];
     if (Lv.n == 0) continue;
     STAGE(2, (k_fdft<T><<<(unsigned)Lv.n, 256, lds_fdft(p, Gf, es), st>>>(W + Lv.off * 9 * p3, Lv.n, p, Gf,
                                                                          tb.tw, What)));
-    int bs = Lv.n >= 16384 ? 1024 : 256;
-    dim3 g(nblk(Lv.n, bs), nf, 6 / ROWS);
-    STAGE(3, (k_hadamard<T, ROWS><<<g, bs, shm_h, st>>>(What, (const cplx<T>*)pl->lev[l].khat, Lv.il_start,
-                                                         Lv.il, Lv.order, Lv.n, nf, Shat)));
+    const int nwin = (int)((Lv.n + kM2LWindow - 1) / kM2LWindow);
+    const int remap = nwin >= 16;
+    dim3 g(remap ? 8 * ((nwin + 7) / 8) : nwin, nf);
+    STAGE(3, (k_hadamard<T><<<g, kM2LWindow, shm_h, st>>>(What, (const cplx<T>*)pl->lev[l].khat, Lv.il_start,
+                                                           Lv.il, Lv.order, Lv.n, nf, nwin, remap, Shat)));
     STAGE(4, (k_idft<T><<<(unsigned)Lv.n, 256, lds_idft(p, Gi, es), st>>>(Shat, Lv.n, p, Gi, tb.tw,
                                                                         s + Lv.off * 6 * p3)));
   }
@@ -733,8 +782,7 @@ static void set_lds_attrs() {
   if (done) return;
   done = true;
   const int mx = 160 * 1024;
-  hipFuncSetAttribute((const void*)k_hadamard<T, std::is_same<T, double>::value ? 3 : 6>,
-                      hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+  hipFuncSetAttribute((const void*)k_hadamard<T>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
   hipFuncSetAttribute((const void*)k_fdft<T>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
   hipFuncSetAttribute((const void*)k_idft<T>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
   hipFuncSetAttribute((const void*)k_m2m<T>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);

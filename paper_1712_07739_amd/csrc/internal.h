@@ -14,6 +14,10 @@ namespace dfmm {
 constexpr int kMaxOrder = 8;
 constexpr int kMaxQuad = 8;
 constexpr int kNumOffsets = 316;  // M2L offsets in [-3,3]^3 outside [-1,1]^3
+constexpr int kM2LWindow = 512;  // targets per M2L block
+constexpr int kKStride = 55;      // complex entries per offset in LDS (54 + 1 pad)
+constexpr int kNumCanon = 158;    // one of each pair (o, -o): the kernel is odd, so the
+                                  // spectrum of -o is minus the conjugate of that of o
 constexpr int kNumFar = 189;      // interaction-list size of an interior cell
 
 struct Quad {
@@ -30,8 +34,8 @@ struct Tables {
 };
 
 struct LevelTables {
-  void* khat = nullptr;  // [nf][316][54] complex (float2 or double2): DFT of the
-                         // circulant embedding of each offset's generator
+  void* khat = nullptr;  // [nf][158][54] complex (float2 or double2): DFT of the
+                         // circulant embedding of each canonical offset's generator
 };
 
 }  // namespace dfmm
@@ -42,11 +46,13 @@ struct dfmm_plan {
   int mixed = 0;
   int iso = 0;
   double mu = 0, nu = 0;  // isotropic (or Voigt) moduli
+  int nhalf32 = 0;         // circle angles on [0, pi) of the float evaluation
+  double float_rule_err = 0;
   dfmm::Quad quad;
   dfmm::Tables<double> t64;
   dfmm::Tables<float> t32;
-  int* oid343 = nullptr;   // device [343]: offset (o+3) lex index -> id or -1
-  int* off316 = nullptr;   // device [316][3]: id -> offset
+  int* oid343 = nullptr;   // device [343]: offset (o+3) lex index -> 2*canonical id + mirrored, or -1
+  int* off158 = nullptr;   // device [158][3]: canonical id -> offset
   std::vector<dfmm::LevelTables> lev;  // index = level (0..D); used for 2..D
   double setup_ms = 0;
   size_t khat_bytes = 0;
@@ -71,7 +77,7 @@ struct dfmm_tree {
     int* count = nullptr;      // leaves: #points; others: #children
     int* parent = nullptr;     // parent index at level l-1 (levels 3..D)
     int* il_start = nullptr;   // [n+1] interaction-list CSR
-    int2* il = nullptr;        // (source index at this level, offset id 0..315)
+    int2* il = nullptr;        // (source index at this level, 2*canonical offset id + mirrored)
     uint32_t* order = nullptr; // targets in M2L processing order (list length buckets, then Morton)
     int64_t npairs = 0;
   };

@@ -1,0 +1,491 @@
+// Learned surrogate for the anisotropic part of the Green's-function
+// derivative (the costly kernel evaluation of Sec. 2), trained on the GPU.
+//
+// The singular anisotropic derivative is r^-2 Phi(T) with T = x/r.  The
+// network predicts the scaled residual
+//     y(T) = c44 (Phi_circle(T) - Phi_iso[Voigt](T)) / yscale
+// for the 18 distinct components (v <= p) x q of Phi_vpq, from the features
+// (T, normalised c11, c12, c44): 6 -> 4 x 128 (SiLU) -> 18, FP32.  Training
+// samples are directions drawn by a counter-based generator with targets from
+// the FP64 circle quadrature of kernel_eval.h; forward, backward and Adam are
+// the kernels below.  A cube-map table of direction bins records, per bin,
+// the largest error of the network against the exact quadrature on a grid of
+// validation directions, relative to the largest component of Phi there; bins
+// above the tolerance keep the exact quadrature.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+
+#include "internal.h"
+#include "mlp_eval.h"
+
+namespace dfmm {
+
+static inline unsigned nb(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+// SplitMix64 (Steele, Lea, Flood 2014): counter -> 64 random bits.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__device__ __forceinline__ double u01(uint64_t bits) { return (bits >> 11) * (1.0 / 9007199254740992.0); }
+
+// Exact target y(T) (unscaled) in double for a unit direction.
+__device__ void exact_residual(const double* T, const Med<double>& m, double* y18, double* phimax) {
+  double Dc[27], Di[27];
+  for (int i = 0; i < 27; ++i) Dc[i] = Di[i] = 0.0;
+  dg_circle_acc<double>(T[0], T[1], T[2], m, 1.0, Dc);
+  dg_iso_acc<double>(T[0], T[1], T[2], m.mu, m.nu, 0.0, 1.0, Di);
+  double mx = 0.0;
+  for (int c = 0; c < 18; ++c) {
+    int pr = c / 3, q = c % 3;
+    int v = sur_pair_v(pr), p = sur_pair_p(pr);
+    int idx = (v * 3 + p) * 3 + q;
+    y18[c] = m.c44 * (Dc[idx] - Di[idx]);
+    mx = fmax(mx, fabs(m.c44 * Dc[idx]));
+  }
+  *phimax = mx;
+}
+
+__global__ void k_gen_samples(uint64_t seed, int64_t n, Med<double> m, SurFeat ft, float* X, float* Y) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint64_t r1 = splitmix64(seed ^ (2 * (uint64_t)i)), r2 = splitmix64(seed ^ (2 * (uint64_t)i + 1));
+  double z = 2.0 * u01(r1) - 1.0, ph = 2.0 * 3.14159265358979323846 * u01(r2);
+  double s = sqrt(fmax(0.0, 1.0 - z * z));
+  double T[3] = {s * cos(ph), s * sin(ph), z};
+  double y[18], pm;
+  exact_residual(T, m, y, &pm);
+  float* x = X + i * 6;
+  x[0] = (float)T[0];
+  x[1] = (float)T[1];
+  x[2] = (float)T[2];
+  x[3] = ft.f[0];
+  x[4] = ft.f[1];
+  x[5] = ft.f[2];
+  for (int c = 0; c < 18; ++c) Y[i * 18 + c] = (float)y[c];
+}
+
+__global__ void k_scale(float* Y, int64_t n, float s) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) Y[i] *= s;
+}
+
+__global__ void k_sumsq(const float* Y, int64_t n, double* part) {
+  __shared__ double sh[256];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    s += (double)Y[i] * Y[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// C[M x N] (ldc) = op(A) op(B) (+ C if acc), row-major; op(A)[m][k] = TA ? A[k*lda+m] : A[m*lda+k].
+template <bool TA, bool TB>
+__global__ void __launch_bounds__(256) k_gemm(int M, int N, int K, const float* A, int lda, const float* B, int ldb,
+                                              float* C, int ldc, int acc) {
+  __shared__ float As[16][64 + 1];
+  __shared__ float Bs[16][64 + 1];
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  float c[4][4] = {};
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    for (int e = threadIdx.x; e < 16 * 64; e += 256) {
+      int kk = e / 64, mm = e % 64;
+      int gm = m0 + mm, gk = k0 + kk;
+      As[kk][mm] = (gm < M && gk < K) ? (TA ? A[(int64_t)gk * lda + gm] : A[(int64_t)gm * lda + gk]) : 0.f;
+      int gn = n0 + mm;
+      Bs[kk][mm] = (gn < N && gk < K) ? (TB ? B[(int64_t)gn * ldb + gk] : B[(int64_t)gk * ldb + gn]) : 0.f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      float a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[kk][ty * 4 + i], b[i] = Bs[kk][tx * 4 + i];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) c[i][j] += a[i] * b[j];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      int gm = m0 + ty * 4 + i, gn = n0 + tx * 4 + j;
+      if (gm < M && gn < N) {
+        float* p = C + (int64_t)gm * ldc + gn;
+        *p = acc ? *p + c[i][j] : c[i][j];
+      }
+    }
+}
+
+// Z += b (per column); A = SiLU(Z) when act, else A = Z.
+__global__ void k_bias_act(float* Z, const float* b, int64_t rows, int cols, float* A, int act) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= rows * cols) return;
+  float z = Z[i] + b[i % cols];
+  Z[i] = z;
+  A[i] = act ? z / (1.f + expf(-z)) : z;
+}
+
+// dY = 2 (Yp - Y) / (rows*cols); per-block partial sums of the squared error.
+__global__ void k_mse(const float* Yp, const float* Y, int64_t n, float scale, float* dY, double* part) {
+  __shared__ double sh[256];
+  int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double e = 0.0;
+  if (i < n) {
+    float d = Yp[i] - Y[i];
+    dY[i] = 2.f * d * scale;
+    e = (double)d * d;
+  }
+  sh[threadIdx.x] = e;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// dZ = dA * SiLU'(Z)
+__global__ void k_silu_back(const float* dA, const float* Z, int64_t n, float* dZ) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float z = Z[i], s = 1.f / (1.f + expf(-z));
+  dZ[i] = dA[i] * s * (1.f + z * (1.f - s));
+}
+
+// db[j] = sum_i dZ[i][j] (fixed order)
+__global__ void k_colsum(const float* dZ, int rows, int cols, float* db) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= cols) return;
+  float s = 0.f;
+  for (int i = 0; i < rows; ++i) s += dZ[(int64_t)i * cols + j];
+  db[j] = s;
+}
+
+__global__ void k_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
+                       float eps, float c1, float c2) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float gi = g[i];
+  float mi = b1 * m[i] + (1.f - b1) * gi;
+  float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+__global__ void k_init_params(float* w, SurLayout L, uint64_t seed) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= L.total) return;
+  int l = 0;
+  while (l + 1 < kSurLayers && i >= L.off[l + 1]) ++l;
+  int64_t local = i - L.off[l];
+  int64_t nw = (int64_t)L.dout[l] * L.din[l];
+  if (local >= nw) {
+    w[i] = 0.f;  // bias
+    return;
+  }
+  double u = u01(splitmix64(seed ^ (0x5851F42D4C957F2Dull * (uint64_t)(i + 1))));
+  double lim = sqrt(6.0 / (L.din[l] + L.dout[l]));  // Glorot uniform
+  w[i] = (float)((2.0 * u - 1.0) * lim);
+}
+
+// Validation on the cube map: bin b = (face, i, j); nsub x nsub directions per
+// bin; err[b] = max over them of |y_net - y_exact|_inf / |c44 Phi_exact|_inf.
+__global__ void k_gate(const float* w, SurLayout L, SurFeat ft, int bins, int nsub, Med<double> m, float yscale,
+                       float* err) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t nbins = 6LL * bins * bins;
+  if (idx >= nbins * nsub * nsub) return;
+  int64_t b = idx / (nsub * nsub);
+  int s = (int)(idx % (nsub * nsub));
+  int face = (int)(b / (bins * bins)), bi = (int)((b / bins) % bins), bj = (int)(b % bins);
+  double u = -1.0 + 2.0 * (bi + (s / nsub + 0.5) / nsub) / bins;
+  double v = -1.0 + 2.0 * (bj + (s % nsub + 0.5) / nsub) / bins;
+  double T[3];
+  int ax = face >> 1;
+  double sg = (face & 1) ? -1.0 : 1.0;
+  T[ax] = sg;
+  T[(ax + 1) % 3] = u;
+  T[(ax + 2) % 3] = v;
+  double nn = 1.0 / sqrt(T[0] * T[0] + T[1] * T[1] + T[2] * T[2]);
+  for (int d = 0; d < 3; ++d) T[d] *= nn;
+  double y[18], pm;
+  exact_residual(T, m, y, &pm);
+  float x[6] = {(float)T[0], (float)T[1], (float)T[2], ft.f[0], ft.f[1], ft.f[2]};
+  float yn[18];
+  float h[2 * kSurHidden];
+  mlp_eval<1>(w, L, x, yn, h);
+  double e = 0.0;
+  for (int c = 0; c < 18; ++c) e = fmax(e, fabs((double)yn[c] * yscale - y[c]));
+  err[idx] = (float)(e / pm);
+}
+
+__global__ void k_gate_reduce(const float* err, int64_t nbins, int nsub2, float tol, unsigned char* mask,
+                              float* binerr) {
+  int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nbins) return;
+  float e = 0.f;
+  for (int s = 0; s < nsub2; ++s) e = fmaxf(e, err[b * nsub2 + s]);
+  binerr[b] = e;
+  mask[b] = e <= tol ? 1 : 0;
+}
+
+SurLayout sur_layout(int hidden) {
+  SurLayout L;
+  int dims[kSurLayers + 1] = {6, hidden, hidden, hidden, hidden, 18};
+  int64_t o = 0;
+  for (int l = 0; l < kSurLayers; ++l) {
+    L.din[l] = dims[l];
+    L.dout[l] = dims[l + 1];
+    L.off[l] = o;
+    o += (int64_t)dims[l] * dims[l + 1] + dims[l + 1];
+  }
+  L.total = o;
+  return L;
+}
+
+static int gemm(bool ta, bool tb, int M, int N, int K, const float* A, int lda, const float* B, int ldb, float* C,
+                int ldc, int acc, hipStream_t st) {
+  dim3 g(nb(N, 64), nb(M, 64));
+  if (!ta && !tb) k_gemm<false, false><<<g, 256, 0, st>>>(M, N, K, A, lda, B, ldb, C, ldc, acc);
+  else if (!ta && tb) k_gemm<false, true><<<g, 256, 0, st>>>(M, N, K, A, lda, B, ldb, C, ldc, acc);
+  else if (ta && !tb) k_gemm<true, false><<<g, 256, 0, st>>>(M, N, K, A, lda, B, ldb, C, ldc, acc);
+  else k_gemm<true, true><<<g, 256, 0, st>>>(M, N, K, A, lda, B, ldb, C, ldc, acc);
+  DFMM_LAUNCH_CHECK();
+  return DFMM_OK;
+}
+
+// Workspace for one mini-batch of B rows.
+struct MlpWork {
+  float* Z[kSurLayers] = {};
+  float* A[kSurLayers + 1] = {};  // A[0] = input rows (not owned)
+  float* dZ = nullptr;
+  float* dA = nullptr;
+  double* part = nullptr;
+  int B = 0;
+};
+
+static int work_alloc(MlpWork& w, const SurLayout& L, int B) {
+  w.B = B;
+  for (int l = 0; l < kSurLayers; ++l) {
+    DFMM_HIP(hipMalloc(&w.Z[l], sizeof(float) * (size_t)B * L.dout[l]));
+    DFMM_HIP(hipMalloc(&w.A[l + 1], sizeof(float) * (size_t)B * L.dout[l]));
+  }
+  DFMM_HIP(hipMalloc(&w.dZ, sizeof(float) * (size_t)B * kSurHidden));
+  DFMM_HIP(hipMalloc(&w.dA, sizeof(float) * (size_t)B * kSurHidden));
+  DFMM_HIP(hipMalloc(&w.part, sizeof(double) * (nb((int64_t)B * 18, 256) + 1)));
+  return DFMM_OK;
+}
+static void work_free(MlpWork& w) {
+  for (int l = 0; l < kSurLayers; ++l) {
+    hipFree(w.Z[l]);
+    hipFree(w.A[l + 1]);
+  }
+  hipFree(w.dZ);
+  hipFree(w.dA);
+  hipFree(w.part);
+}
+
+// Forward of n rows of X (A[0] = X), output in w.A[kSurLayers].
+static int forward(const float* prm, const SurLayout& L, MlpWork& w, const float* X, int n, hipStream_t st) {
+  w.A[0] = const_cast<float*>(X);
+  for (int l = 0; l < kSurLayers; ++l) {
+    const float* W = prm + L.off[l];
+    const float* b = W + (int64_t)L.dout[l] * L.din[l];
+    int rc = gemm(false, true, n, L.dout[l], L.din[l], w.A[l], L.din[l], W, L.din[l], w.Z[l], L.dout[l], 0, st);
+    if (rc) return rc;
+    k_bias_act<<<nb((int64_t)n * L.dout[l], 256), 256, 0, st>>>(w.Z[l], b, n, L.dout[l], w.A[l + 1],
+                                                                 l + 1 < kSurLayers);
+    DFMM_LAUNCH_CHECK();
+  }
+  return DFMM_OK;
+}
+
+// Loss (host, mean squared error over rows x 18) and gradient into grad.
+static int loss_grad(const float* prm, float* grad, const SurLayout& L, MlpWork& w, const float* X, const float* Y,
+                     int n, hipStream_t st, double* loss) {
+  int rc = forward(prm, L, w, X, n, st);
+  if (rc) return rc;
+  const int64_t no = (int64_t)n * 18;
+  const unsigned nbk = nb(no, 256);
+  float* dY = w.dZ;  // [n][18]
+  k_mse<<<nbk, 256, 0, st>>>(w.A[kSurLayers], Y, no, 1.f / (float)no, dY, w.part);
+  DFMM_LAUNCH_CHECK();
+  for (int l = kSurLayers - 1; l >= 0; --l) {
+    float* gW = grad + L.off[l];
+    float* gb = gW + (int64_t)L.dout[l] * L.din[l];
+    const float* W = prm + L.off[l];
+    // dW = dZ^T A_l ; db = colsum(dZ)
+    if ((rc = gemm(true, false, L.dout[l], L.din[l], n, w.dZ, L.dout[l], w.A[l], L.din[l], gW, L.din[l], 0, st)))
+      return rc;
+    k_colsum<<<nb(L.dout[l], 128), 128, 0, st>>>(w.dZ, n, L.dout[l], gb);
+    DFMM_LAUNCH_CHECK();
+    if (l > 0) {
+      // dA_l = dZ W ; dZ_{l-1} = dA_l * SiLU'(Z_{l-1})
+      if ((rc = gemm(false, false, n, L.din[l], L.dout[l], w.dZ, L.dout[l], W, L.din[l], w.dA, L.din[l], 0, st)))
+        return rc;
+      k_silu_back<<<nb((int64_t)n * L.din[l], 256), 256, 0, st>>>(w.dA, w.Z[l - 1], (int64_t)n * L.din[l], w.dZ);
+      DFMM_LAUNCH_CHECK();
+    }
+  }
+  if (loss) {
+    std::vector<double> h(nbk);
+    DFMM_D2H(h.data(), w.part, sizeof(double) * nbk, st);
+    double s = 0.0;
+    for (double x : h) s += x;
+    *loss = s / (double)no;
+  }
+  return DFMM_OK;
+}
+
+int surrogate_train(dfmm_plan* pl, const dfmm_surrogate_cfg& cfg, hipStream_t st) {
+  auto t0 = std::chrono::steady_clock::now();
+  Surrogate& S = pl->sur;
+  if (cfg.hidden != kSurHidden) {
+    set_error("surrogate: hidden width must be 128");
+    return DFMM_E_ARG;
+  }
+  if (cfg.n_samples < 1024 || cfg.batch < 64 || cfg.batch > cfg.n_samples || cfg.epochs < 1 || !(cfg.lr > 0) ||
+      cfg.bins < 1 || cfg.bins > 256 || !(cfg.tol > 0)) {
+    set_error("surrogate: invalid training configuration");
+    return DFMM_E_ARG;
+  }
+  S.L = sur_layout(cfg.hidden);
+  double c = pl->prm.c11 + pl->prm.c12 + pl->prm.c44;
+  S.ft.f[0] = (float)(pl->prm.c11 / c);
+  S.ft.f[1] = (float)(pl->prm.c12 / c);
+  S.ft.f[2] = (float)(pl->prm.c44 / c);
+  const int64_t P = S.L.total;
+  if (!S.w) {
+    DFMM_HIP(hipMalloc(&S.w, sizeof(float) * P));
+    DFMM_HIP(hipMalloc(&S.g, sizeof(float) * P));
+    DFMM_HIP(hipMalloc(&S.m, sizeof(float) * P));
+    DFMM_HIP(hipMalloc(&S.v, sizeof(float) * P));
+  }
+  k_init_params<<<nb(P, 256), 256, 0, st>>>(S.w, S.L, cfg.seed);
+  DFMM_LAUNCH_CHECK();
+  DFMM_HIP(hipMemsetAsync(S.m, 0, sizeof(float) * P, st));
+  DFMM_HIP(hipMemsetAsync(S.v, 0, sizeof(float) * P, st));
+  // samples
+  const int64_t n = cfg.n_samples;
+  float *X = nullptr, *Y = nullptr;
+  DFMM_HIP(hipMalloc(&X, sizeof(float) * 6 * n));
+  DFMM_HIP(hipMalloc(&Y, sizeof(float) * 18 * n));
+  Med<double> m = pl->med<double>();
+  k_gen_samples<<<nb(n, 128), 128, 0, st>>>(cfg.seed ^ 0xA5A5A5A5ull, n, m, S.ft, X, Y);
+  DFMM_LAUNCH_CHECK();
+  {
+    double* part = nullptr;
+    DFMM_HIP(hipMalloc(&part, sizeof(double) * 1024));
+    k_sumsq<<<1024, 256, 0, st>>>(Y, 18 * n, part);
+    std::vector<double> h(1024);
+    DFMM_D2H(h.data(), part, sizeof(double) * 1024, st);
+    hipFree(part);
+    double ss = 0;
+    for (double x : h) ss += x;
+    double rms = std::sqrt(ss / (18.0 * n));
+    S.yscale = (float)(rms > 0 ? rms : 1.0);
+    k_scale<<<nb(18 * n, 256), 256, 0, st>>>(Y, 18 * n, 1.f / S.yscale);
+    DFMM_LAUNCH_CHECK();
+  }
+  MlpWork w;
+  int rc = work_alloc(w, S.L, cfg.batch);
+  if (rc) return rc;
+  const int64_t steps_per_epoch = n / cfg.batch;
+  const int64_t total = steps_per_epoch * cfg.epochs;
+  S.loss_hist.clear();
+  int64_t step = 0;
+  for (int ep = 0; ep < cfg.epochs && rc == DFMM_OK; ++ep) {
+    double ep_loss = 0;
+    for (int64_t k = 0; k < steps_per_epoch && rc == DFMM_OK; ++k, ++step) {
+      int64_t row = ((k + (int64_t)ep * 7919) % steps_per_epoch) * cfg.batch;
+      bool want = (k == steps_per_epoch - 1);
+      double l = 0;
+      rc = loss_grad(S.w, S.g, S.L, w, X + row * 6, Y + row * 18, cfg.batch, st, want ? &l : nullptr);
+      if (rc) break;
+      double frac = (double)step / (double)std::max<int64_t>(1, total - 1);
+      float lr = (float)(cfg.lr * (0.01 + 0.99 * 0.5 * (1.0 + std::cos(M_PI * frac))));
+      float c1 = 1.f - std::pow(0.9f, (float)(step + 1)), c2 = 1.f - std::pow(0.999f, (float)(step + 1));
+      k_adam<<<nb(P, 256), 256, 0, st>>>(S.w, S.g, S.m, S.v, P, lr, 0.9f, 0.999f, 1e-8f, c1, c2);
+      if (hipGetLastError() != hipSuccess) { rc = DFMM_E_HIP; break; }
+      if (want) ep_loss = l;
+    }
+    S.loss_hist.push_back(ep_loss);
+  }
+  work_free(w);
+  hipFree(X);
+  hipFree(Y);
+  if (rc) return rc;
+  // residual gate on the cube map
+  S.bins = cfg.bins;
+  S.tol = cfg.tol;
+  const int64_t nbins = 6LL * cfg.bins * cfg.bins;
+  const int nsub = 3;
+  float *err = nullptr, *binerr = nullptr;
+  DFMM_HIP(hipMalloc(&err, sizeof(float) * nbins * nsub * nsub));
+  DFMM_HIP(hipMalloc(&binerr, sizeof(float) * nbins));
+  hipFree(S.mask);
+  DFMM_HIP(hipMalloc(&S.mask, nbins));
+  k_gate<<<nb(nbins * nsub * nsub, 64), 64, 0, st>>>(S.w, S.L, S.ft, cfg.bins, nsub, m, S.yscale, err);
+  DFMM_LAUNCH_CHECK();
+  k_gate_reduce<<<nb(nbins, 256), 256, 0, st>>>(err, nbins, nsub * nsub, (float)cfg.tol, S.mask, binerr);
+  DFMM_LAUNCH_CHECK();
+  std::vector<float> hb(nbins);
+  DFMM_D2H(hb.data(), binerr, sizeof(float) * nbins, st);
+  hipFree(err);
+  hipFree(binerr);
+  int64_t pass = 0;
+  for (float e : hb) pass += e <= cfg.tol;
+  std::vector<float> sorted(hb);
+  std::sort(sorted.begin(), sorted.end());
+  S.pass_frac = (double)pass / nbins;
+  S.max_err = sorted.back();
+  S.med_err = sorted[nbins / 2];
+  S.n_samples = n;
+  S.epochs = cfg.epochs;
+  S.trained = 1;
+  S.train_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return DFMM_OK;
+}
+
+// Test hooks: loss and gradient of the current weights on rows (X, Y) given
+// on the device, and network outputs for rows X.
+int surrogate_loss_grad(dfmm_plan* pl, const float* X, const float* Y, int64_t n, float* grad, double* loss,
+                        hipStream_t st) {
+  Surrogate& S = pl->sur;
+  MlpWork w;
+  int rc = work_alloc(w, S.L, (int)n);
+  if (rc == DFMM_OK) rc = loss_grad(S.w, grad, S.L, w, X, Y, (int)n, st, loss);
+  hipStreamSynchronize(st);
+  work_free(w);
+  return rc;
+}
+
+int surrogate_forward(const dfmm_plan* pl, const float* X, int64_t n, float* Yout, hipStream_t st) {
+  const Surrogate& S = pl->sur;
+  MlpWork w;
+  int rc = work_alloc(w, S.L, (int)n);
+  if (rc == DFMM_OK) rc = forward(S.w, S.L, w, X, (int)n, st);
+  if (rc == DFMM_OK)
+    rc = hipMemcpyAsync(Yout, w.A[kSurLayers], sizeof(float) * 18 * n, hipMemcpyDeviceToDevice, st) == hipSuccess
+             ? DFMM_OK
+             : DFMM_E_HIP;
+  hipStreamSynchronize(st);
+  work_free(w);
+  return rc;
+}
+
+}  // namespace dfmm

@@ -301,7 +301,10 @@ __global__ void k_leaf_nbrs(const uint32_t* keys, int nc, int lvl, int* nbr) {
       }
 }
 
-// count (fill == nullptr) or fill the interaction list of every cell of a level
+// Count (fill == nullptr) or fill the interaction list of every cell of a
+// level, in lexicographic order of the source cell (so neighbouring targets
+// walk their offsets in the same order).  Entry = (source, 2*canonical id +
+// mirrored).
 __global__ void k_ilist(const uint32_t* keys, int nc, int lvl, const int* oid343, const int* start, int* cnt,
                         int2* fill) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -333,12 +336,13 @@ __global__ void k_ilist(const uint32_t* keys, int nc, int lvl, const int* oid343
   if (!fill) cnt[i] = k;
 }
 
-// key = bucket of descending list length (8 lengths per bucket), val = target
+// M2L processing order: windows of kM2LWindow Morton-consecutive targets (one
+// block each, spatially compact), longest lists first inside a window.
 __global__ void k_len_keys(const int* il_start, int n, uint32_t* key, uint32_t* val) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   int len = il_start[i + 1] - il_start[i];
-  key[i] = (uint32_t)((kNumFar - min(len, kNumFar)) >> 3);
+  key[i] = ((uint32_t)(i / kM2LWindow) << 8) | (uint32_t)(kNumFar - min(len, kNumFar));
   val[i] = (uint32_t)i;
 }
 
@@ -454,7 +458,9 @@ int build_tree_impl(dfmm_plan* pl, const double* seg, int64_t nseg, hipStream_t 
     DFMM_HIP(hipMalloc(&L.order, sizeof(uint32_t) * L.n));
     k_len_keys<<<nb(L.n, 256), 256, 0, st>>>(L.il_start, (int)L.n, okey, L.order);
     DFMM_LAUNCH_CHECK();
-    rc = radix_sort(okey, L.order, L.n, 8, st);
+    int wbits = 0;
+    while (((L.n + kM2LWindow - 1) / kM2LWindow) >> wbits) ++wbits;
+    rc = radix_sort(okey, L.order, L.n, 8 + wbits, st);
     if (rc) return rc;
     hipFree(cnt);
   }
