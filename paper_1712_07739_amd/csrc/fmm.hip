@@ -266,19 +266,21 @@ __global__ void k_fdft(const T* W, int64_t ncell, int p, int G, const T* twg, cp
 // f).  The spectra of the 158 canonical offsets at frequency f sit in LDS
 // (stride kKStride complex per offset); the spectrum of a mirrored offset -o
 // is -conj of that of o, so its contribution -conj(K) w = -conj(K conj(w)) is
-// folded into the same loop with a sign.  Every thread owns one target cell
-// and walks its interaction list:
+// folded into the same loop with a sign.  Three lanes share a target, each
+// owning two of its six stress rows, and walk the target's interaction list:
 //   Shat[T][f][r] = sum_{(J, o) in I(T)} sum_k Khat_o(f)[r][k] What[f][J][k].
-// With many windows, blocks are remapped so that each of the 8 XCDs (blocks
-// are dispatched round-robin over them) works through a contiguous range of
-// windows at one frequency at a time: neighbouring windows share sources in
-// that XCD's L2.
+// Fewer distinct offsets per wave-wide LDS read (about 21 instead of 64) keep
+// bank conflicts down.  With many windows, blocks are remapped so that each
+// of the 8 XCDs (blocks are dispatched round-robin over them) works through a
+// contiguous range of windows at one frequency at a time: neighbouring windows
+// share sources in that XCD's L2.
+constexpr int kHadThreads = 3 * kM2LWindow;
 template <typename T>
-__global__ void __launch_bounds__(kM2LWindow) k_hadamard(const cplx<T>* What, const cplx<T>* Khat,
-                                                         const int* il_start, const int2* il, const uint32_t* order,
-                                                         int64_t ncell, int nf, int nwin, int remap,
-                                                         cplx<T>* Shat) {
-  extern __shared__ unsigned char shraw[];
+__global__ void __launch_bounds__(kHadThreads) k_hadamard(const cplx<T>* What, const cplx<T>* Khat,
+                                                          const int* il_start, const int2* il,
+                                                          const uint32_t* order, int64_t ncell, int nf, int nwin,
+                                                          int remap, cplx<T>* Shat) {
+  extern __shared__ __align__(16) unsigned char shraw[];
   cplx<T>* Ks = (cplx<T>*)shraw;  // [158][kKStride]
   int win, f;
   if (remap) {
@@ -296,42 +298,57 @@ __global__ void __launch_bounds__(kM2LWindow) k_hadamard(const cplx<T>* What, co
   const cplx<T>* kf = Khat + (int64_t)f * kNumCanon * 54;
   for (int e = threadIdx.x; e < kNumCanon * 54; e += blockDim.x) Ks[(e / 54) * kKStride + e % 54] = kf[e];
   __syncthreads();
-  const int64_t tt = (int64_t)win * kM2LWindow + threadIdx.x;
+  const int64_t tt = (int64_t)win * kM2LWindow + threadIdx.x / 3;
   if (tt >= ncell) return;
+  const int r0 = 2 * (threadIdx.x % 3);
   const int64_t t = order[tt];
-  T ar[6], ai[6];
-#pragma unroll
-  for (int r = 0; r < 6; ++r) ar[r] = ai[r] = T(0);
+  T ar0 = 0, ai0 = 0, ar1 = 0, ai1 = 0;
   const int e0 = il_start[t], e1 = il_start[t + 1];
   const cplx<T>* wf = What + (int64_t)f * ncell * 9;
   for (int e = e0; e < e1; ++e) {
     const int2 jo = il[e];
     const T sg = (jo.y & 1) ? T(-1) : T(1);
     const cplx<T>* w = wf + (int64_t)jo.x * 9;
-    T wr[9], wi[9];
+    // rows r0 and r0+1 of the offset's 6x9 block: 18 consecutive complex values,
+    // 16-byte aligned, read as 9 (float) or 18 (double) 16-byte LDS loads
+    cplx<T> kk[18];
+    const cplx<T>* K = Ks + (jo.y >> 1) * kKStride + r0 * 9;
+    if (sizeof(T) == 4) {
+      const float4* K4 = reinterpret_cast<const float4*>(K);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        float4 q = K4[i];
+        kk[2 * i] = cplx<T>{(T)q.x, (T)q.y};
+        kk[2 * i + 1] = cplx<T>{(T)q.z, (T)q.w};
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 18; ++i) kk[i] = K[i];
+    }
+    // complex multiply-accumulate as four fused multiply-adds each
+    T cr0 = 0, ci0 = 0, cr1 = 0, ci1 = 0;
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-      cplx<T> v = w[k];
-      wr[k] = v.re;
-      wi[k] = sg * v.im;
+      const cplx<T> v = w[k];
+      const T wr = v.re, wi = sg * v.im;
+      const cplx<T> k0 = kk[k], k1 = kk[9 + k];
+      cr0 = fma(k0.re, wr, cr0);
+      cr0 = fma(-k0.im, wi, cr0);
+      ci0 = fma(k0.re, wi, ci0);
+      ci0 = fma(k0.im, wr, ci0);
+      cr1 = fma(k1.re, wr, cr1);
+      cr1 = fma(-k1.im, wi, cr1);
+      ci1 = fma(k1.re, wi, ci1);
+      ci1 = fma(k1.im, wr, ci1);
     }
-    const cplx<T>* K = Ks + (jo.y >> 1) * kKStride;
-#pragma unroll
-    for (int r = 0; r < 6; ++r) {
-      T cr = T(0), ci = T(0);
-#pragma unroll
-      for (int k = 0; k < 9; ++k) {
-        cplx<T> kk = K[r * 9 + k];
-        cr += kk.re * wr[k] - kk.im * wi[k];
-        ci += kk.re * wi[k] + kk.im * wr[k];
-      }
-      ar[r] += sg * cr;
-      ai[r] += ci;
-    }
+    ar0 = fma(sg, cr0, ar0);
+    ai0 += ci0;
+    ar1 = fma(sg, cr1, ar1);
+    ai1 += ci1;
   }
-  cplx<T>* out = Shat + (t * nf + f) * 6;
-#pragma unroll
-  for (int r = 0; r < 6; ++r) out[r] = cplx<T>{ar[r], ai[r]};
+  cplx<T>* out = Shat + (t * nf + f) * 6 + r0;
+  out[0] = cplx<T>{ar0, ai0};
+  out[1] = cplx<T>{ar1, ai1};
 }
 
 // ------------------------------------------------------------ inverse DFT
@@ -738,7 +755,7 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
     const int nwin = (int)((Lv.n + kM2LWindow - 1) / kM2LWindow);
     const int remap = nwin >= 16;
     dim3 g(remap ? 8 * ((nwin + 7) / 8) : nwin, nf);
-    STAGE(3, (k_hadamard<T><<<g, kM2LWindow, shm_h, st>>>(What, (const cplx<T>*)pl->lev[l].khat, Lv.il_start,
+    STAGE(3, (k_hadamard<T><<<g, kHadThreads, shm_h, st>>>(What, (const cplx<T>*)pl->lev[l].khat, Lv.il_start,
                                                            Lv.il, Lv.order, Lv.n, nf, nwin, remap, Shat)));
     STAGE(4, (k_idft<T><<<(unsigned)Lv.n, 256, lds_idft(p, Gi, es), st>>>(Shat, Lv.n, p, Gi, tb.tw,
                                                                         s + Lv.off * 6 * p3)));

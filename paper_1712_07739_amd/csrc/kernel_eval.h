@@ -65,7 +65,17 @@ __device__ __forceinline__ void dg_iso_acc(T x0, T x1, T x2, T mu, T nu, T a, T 
       }
 }
 
-// D += scale * (singular anisotropic d_q G_vp) by circle quadrature.
+template <typename T>
+__device__ __forceinline__ T fast_rcp(T x) {
+  return T(1) / x;
+}
+template <>
+__device__ __forceinline__ float fast_rcp<float>(float x) {
+  return __builtin_amdgcn_rcpf(x);  // 1 ulp: ample for the float evaluation
+}
+
+// D += scale * (singular anisotropic d_q G_vp) by circle quadrature.  Only
+// the (i <= j) half of the symmetric index pair is accumulated.
 template <typename T>
 __device__ __forceinline__ void dg_circle_acc(T x0, T x1, T x2, const Med<T>& m, T scale, T* D) {
   T r2 = x0 * x0 + x1 * x1 + x2 * x2;
@@ -82,32 +92,33 @@ __device__ __forceinline__ void dg_circle_acc(T x0, T x1, T x2, const Med<T>& m,
   T n1 = T(1) / sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
   e1[0] *= n1; e1[1] *= n1; e1[2] *= n1;
   T e2[3] = {t[1] * e1[2] - t[2] * e1[1], t[2] * e1[0] - t[0] * e1[2], t[0] * e1[1] - t[1] * e1[0]};
-  const T cc = m.c12 + m.c44, hh = m.hh, c44 = m.c44;
-  T acc[27];
+  const T cc = m.c12 + m.c44, c44 = m.c44, ch = cc + m.hh;
+  const T ct[3] = {cc * t[0], cc * t[1], cc * t[2]};
+  const T dt[3] = {T(2) * ch * t[0], T(2) * ch * t[1], T(2) * ch * t[2]};
+  // symmetric pairs (i, j): 00 11 22 01 02 12
+  constexpr int PI_[6] = {0, 1, 2, 0, 0, 1}, PJ_[6] = {0, 1, 2, 1, 2, 2};
+  T acc[18];
 #pragma unroll
-  for (int i = 0; i < 27; ++i) acc[i] = T(0);
+  for (int i = 0; i < 18; ++i) acc[i] = T(0);
   for (int k = 0; k < m.nhalf; ++k) {
     T co = m.cs[2 * k], si = m.cs[2 * k + 1];
     T z[3] = {co * e1[0] + si * e2[0], co * e1[1] + si * e2[1], co * e1[2] + si * e2[2]};
-    // N = (c12 + c44) z z^T + diag(c44 + hh z_i^2)
-    T N00 = cc * z[0] * z[0] + c44 + hh * z[0] * z[0];
-    T N11 = cc * z[1] * z[1] + c44 + hh * z[1] * z[1];
-    T N22 = cc * z[2] * z[2] + c44 + hh * z[2] * z[2];
+    // N = (c12 + c44) z z^T + diag(c44 + hh z_i^2): diagonal (c12 + c44 + hh) z_i^2 + c44
+    T N00 = ch * z[0] * z[0] + c44, N11 = ch * z[1] * z[1] + c44, N22 = ch * z[2] * z[2] + c44;
     T N01 = cc * z[0] * z[1], N02 = cc * z[0] * z[2], N12 = cc * z[1] * z[2];
     T m00 = N11 * N22 - N12 * N12, m01 = N02 * N12 - N01 * N22, m02 = N01 * N12 - N02 * N11;
     T m11 = N00 * N22 - N02 * N02, m12 = N01 * N02 - N00 * N12, m22 = N00 * N11 - N01 * N01;
-    T idet = T(1) / (N00 * m00 + N01 * m01 + N02 * m02);
+    T idet = fast_rcp(N00 * m00 + N01 * m01 + N02 * m02);
     T M[9] = {m00 * idet, m01 * idet, m02 * idet, m01 * idet, m11 * idet,
               m12 * idet, m02 * idet, m12 * idet, m22 * idet};
     // A = (c12 + c44)(T z^T + z T^T) + 2 hh diag(T_i z_i)
     T A[9];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int j = 0; j < 3; ++j) A[i * 3 + j] = cc * (t[i] * z[j] + z[i] * t[j]);
-    A[0] += T(2) * hh * t[0] * z[0];
-    A[4] += T(2) * hh * t[1] * z[1];
-    A[8] += T(2) * hh * t[2] * z[2];
+    A[0] = dt[0] * z[0];
+    A[4] = dt[1] * z[1];
+    A[8] = dt[2] * z[2];
+    A[1] = A[3] = ct[0] * z[1] + z[0] * ct[1];
+    A[2] = A[6] = ct[0] * z[2] + z[0] * ct[2];
+    A[5] = A[7] = ct[1] * z[2] + z[1] * ct[2];
     T P[9];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
@@ -115,19 +126,25 @@ __device__ __forceinline__ void dg_circle_acc(T x0, T x1, T x2, const Med<T>& m,
       for (int j = 0; j < 3; ++j)
         P[i * 3 + j] = M[i * 3] * A[j] + M[i * 3 + 1] * A[3 + j] + M[i * 3 + 2] * A[6 + j];
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
+    for (int q = 0; q < 6; ++q) {
+      const int i = PI_[q], j = PJ_[q];
+      T F = P[i * 3] * M[j] + P[i * 3 + 1] * M[3 + j] + P[i * 3 + 2] * M[6 + j];
+      T Mij = M[i * 3 + j];
 #pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        T F = P[i * 3] * M[j] + P[i * 3 + 1] * M[3 + j] + P[i * 3 + 2] * M[6 + j];
-        T Mij = M[i * 3 + j];
-#pragma unroll
-        for (int s = 0; s < 3; ++s) acc[(i * 3 + j) * 3 + s] += z[s] * F - t[s] * Mij;
-      }
+      for (int s = 0; s < 3; ++s) acc[q * 3 + s] = fma(z[s], F, fma(-t[s], Mij, acc[q * 3 + s]));
+    }
   }
   // (2 pi / nphi) * 2 / (8 pi^2 r^2) with nphi = 2 nhalf
   T f = scale / (T(2) * T(3.14159265358979323846) * T(2 * m.nhalf) * r2);
 #pragma unroll
-  for (int i = 0; i < 27; ++i) D[i] += f * acc[i];
+  for (int q = 0; q < 6; ++q) {
+    const int i = PI_[q], j = PJ_[q];
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+      D[(i * 3 + j) * 3 + s] += f * acc[q * 3 + s];
+      if (i != j) D[(j * 3 + i) * 3 + s] += f * acc[q * 3 + s];
+    }
+  }
 }
 
 template <typename T>
