@@ -94,6 +94,8 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.workload == "batch64":
+        return bench_batch(args)
     seg, burg, prm = synth.make_workload(args.workload)
     configured_order = prm["order"]
     if args.order:
@@ -206,6 +208,70 @@ def main():
             "sample": "%d target segment(s) x all %d source segments (direct FP64 sum, Neumaier), %.1f s"
                       % (k, ns, cpu_s)}
         log("cpu oracle: %d segment(s) in %.1f s on %d threads" % (k, cpu_s, oracle.num_threads()))
+    print(json.dumps(result), flush=True)
+
+
+def bench_batch(args):
+    """64 independent isotropic ensembles (5k..150k segments, log-uniform), one
+    graph launch per step; depth per ensemble from the App. B autotuner."""
+    import numpy as np
+    import torch
+
+    import paper_1712_07739_amd as pk
+    import synth
+
+    dev = torch.device("cuda:0")
+    C = synth.loops.ISO
+    order = args.order or 5
+    t0 = time.perf_counter()
+    ens = synth.make_batch(64, 4)
+    sizes = [s.shape[0] for s, _ in ens]
+    log("batch: %d ensembles, %d segments in total (generated in %.1f s)" % (len(ens), sum(sizes),
+                                                                            time.perf_counter() - t0))
+    segs = [torch.tensor(s, device=dev) for s, _ in ens]
+    burgs = [torch.tensor(b, device=dev) for _, b in ens]
+    # autotune on the median ensemble: optimal leaf density, then D_i for all
+    med = int(np.argsort(sizes)[len(sizes) // 2])
+    prm = pk.make_params(order, 5, *C, synth.loops.CORE_A, synth.loops.BOX_LO, synth.loops.BOX_SIZE,
+                         precision=pk.DFMM_MIXED)
+    d_med, pred = pk.autotune_depth(prm, segs[med], burgs[med], 3, 7)
+    dens = sizes[med] / 8.0 ** d_med
+    depths = [int(min(7, max(3, round(np.log(n / dens) / np.log(8.0))))) for n in sizes]
+    log("autotuner: median ensemble %d segments -> depth %d (predicted ms %s); depths used %s"
+        % (sizes[med], d_med, {k: round(v, 2) for k, v in pred.items()},
+           {d: depths.count(d) for d in sorted(set(depths))}))
+    plans = {d: pk.Plan(pk.make_params(order, d, *C, synth.loops.CORE_A, synth.loops.BOX_LO,
+                                       synth.loops.BOX_SIZE, precision=pk.DFMM_MIXED)) for d in set(depths)}
+    trees = [pk.Tree(plans[d], s) for d, s in zip(depths, segs)]
+    outs = [torch.empty((n, 2, 3), dtype=torch.float64, device=dev) for n in sizes]
+    batch = pk.Batch([plans[d] for d in depths], trees, segs, burgs, outs, lanes=4)
+    for _ in range(args.warmup):
+        batch.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        batch.run()
+    torch.cuda.synchronize()
+    ms_step = 1e3 * (time.perf_counter() - t0) / args.steps
+    lat = np.array(batch.latencies_ms())
+    # accuracy on three ensembles against the GPU FP64 direct sum (40-segment samples)
+    errs = []
+    for i in (int(np.argmin(sizes)), med, int(np.argmax(sizes))):
+        sub = synth.segment_subset(sizes[i], 40, 20000 + i)
+        ref = pk.direct_forces(plans[depths[i]], segs[i], burgs[i], targets=torch.tensor(sub, device=dev)).cpu()
+        f = outs[i].cpu().numpy()[sub]
+        errs.append(float(np.linalg.norm(f - ref.numpy()) / np.linalg.norm(ref.numpy())))
+    result = {
+        "metric": "batched FMM force evaluation throughput, 64 ensembles of 5k-150k segments",
+        "value": sum(sizes) / (ms_step * 1e-3), "unit": "segments/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batch64", "n_ensembles": 64, "n_seg_total": int(sum(sizes)), "order": order,
+                   "medium": "isotropic", "depths": {str(d): depths.count(d) for d in sorted(set(depths))},
+                   "graph_lanes": 4},
+        "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99)),
+        "latency_ms_max": float(lat.max()), "rel_err_vs_fp64_direct_max": max(errs),
+    }
     print(json.dumps(result), flush=True)
 
 

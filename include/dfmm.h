@@ -60,7 +60,7 @@ typedef struct dfmm_plan dfmm_plan; /* medium, order, depth, M2L spectra        
 typedef struct dfmm_tree dfmm_tree; /* sorted points, cells, lists, workspaces   */
 
 typedef struct {
-  int order;          /* p: interpolation nodes per dimension, 2..10 (Sec. 4.1;
+  int order;          /* p: interpolation nodes per dimension, 2..8 (Sec. 4.1;
                          the paper's "p-th order" interpolant has p^3 nodes)     */
   int depth;          /* D: leaf level, 2..10; leaves are cells of side
                          box_size / 2^D; M2L runs on levels 2..D               */
@@ -131,6 +131,95 @@ int dfmm_direct_forces(const dfmm_plan* plan, const double* seg, const double* b
 #define DFMM_N_STAGES 8
 int dfmm_tree_set_timing(dfmm_tree* tree, int on);
 int dfmm_tree_stage_times(dfmm_tree* tree, double* ms, int* n_calls);
+
+/* ---------------------------------------------------------------------
+ * Learned surrogate for the anisotropic Green's-function derivative (the
+ * costly kernel evaluation of Sec. 2, done numerically for anisotropic
+ * media).  A network 6 -> 4 x hidden (SiLU) -> 18 maps the unit direction and
+ * the normalised (c11, c12, c44) to the 18 distinct components of
+ * c44 (Phi - Phi_iso[Voigt]) / scale, Phi_vpq = r^2 d_q G_vp (singular part).
+ * It is trained on the GPU by the library's own forward, backward and Adam
+ * kernels on directions drawn from a counter-based generator, with targets
+ * from the library's double-precision circle quadrature.  A cube map of
+ * direction bins (6 x bins x bins) records the network's largest error per
+ * bin on validation directions, relative to the largest component of Phi;
+ * bins above `tol` keep the exact quadrature. */
+typedef struct {
+  int hidden;          /* hidden width; 128                                   */
+  int epochs;          /* passes over the training samples                     */
+  int batch;           /* rows per optimisation step                           */
+  int bins;            /* cube-map bins per face edge (1..256)                 */
+  int64_t n_samples;   /* training directions                                  */
+  double lr;           /* Adam step size, cosine-decayed to 1% of it           */
+  double tol;          /* residual gate (1e-5)                                 */
+  uint64_t seed;       /* generator seed                                       */
+} dfmm_surrogate_cfg;
+
+/* Defaults: hidden 128, 2,000,000 samples, 20 epochs, batch 4096, lr 1e-3,
+ * tol 1e-5, 32 bins, seed 1. */
+void dfmm_surrogate_default_cfg(dfmm_surrogate_cfg* cfg);
+
+/* Train the surrogate of an anisotropic plan and build its residual gate.
+ * Synchronous.  Does not switch the plan to it (see dfmm_surrogate_use).
+ * Not to be called while other calls use the plan.  DFMM_E_ARG for an
+ * isotropic plan or a bad configuration. */
+int dfmm_surrogate_train(dfmm_plan* plan, const dfmm_surrogate_cfg* cfg, void* stream);
+
+/* on = 1: rebuild the plan's M2L spectra with the surrogate where its bin
+ * passes the gate (exact quadrature elsewhere) and use it in the near field
+ * of the float path; on = 0: back to the exact kernel everywhere (spectra
+ * rebuilt exactly as dfmm_fmm_setup built them).  Synchronous; trees built
+ * with the plan stay valid. */
+int dfmm_surrogate_use(dfmm_plan* plan, int on, void* stream);
+
+/* JSON: training loss per epoch, fraction of gated-in bins, max / median bin
+ * error, training time. */
+int dfmm_surrogate_info(const dfmm_plan* plan, char* json, size_t cap);
+
+/* Network parameters as float32 in layer order (W row-major [out][in], then
+ * b), host memory.  get: *n receives the count, copied if cap >= count.
+ * set: allocates the network if needed (gate cleared).  For testing and
+ * persistence. */
+int dfmm_surrogate_get_params(const dfmm_plan* plan, float* host, int64_t cap, int64_t* n);
+int dfmm_surrogate_set_params(dfmm_plan* plan, const float* host, int64_t n);
+
+/* Mean-squared loss over rows x 18 outputs and its gradient (device float
+ * [n_params]) for device rows X [n][6], Y [n][18]; and the network output
+ * Y = net(X).  Synchronous.  For gradient checks. */
+int dfmm_surrogate_loss_grad(dfmm_plan* plan, const float* X, const float* Y, int64_t n, float* grad,
+                             double* loss, void* stream);
+int dfmm_surrogate_forward(const dfmm_plan* plan, const float* X, int64_t n, float* Y, void* stream);
+
+/* ---------------------------------------------------------------------
+ * Many independent configurations in one launch.  dfmm_batch_create
+ * captures, into one HIP graph, the dfmm_fmm_forces launches of n_cfg
+ * (plan, tree, seg, burgers, forces) tuples spread over n_lanes parallel
+ * branches (configurations assigned longest-first to the least loaded
+ * branch, by estimated cost), plus a timestamp kernel after each
+ * configuration.  The device arrays are bound at creation and must stay
+ * valid; trees must not be rebuilt while the batch exists.  dfmm_batch_run
+ * launches the graph on `stream` (asynchronous).  dfmm_batch_latencies
+ * synchronises and returns, per configuration, the milliseconds from the
+ * start of the last run to the retirement of that configuration's last
+ * kernel (device wall clock).  Errors: DFMM_E_ARG, DFMM_E_STATE (a tree
+ * timing switch is on), DFMM_E_HIP. */
+typedef struct dfmm_batch dfmm_batch;
+int dfmm_batch_create(const dfmm_plan* const* plans, dfmm_tree* const* trees, const double* const* seg,
+                      const double* const* burgers, double* const* forces, int n_cfg, int n_lanes,
+                      void* stream, dfmm_batch** out);
+int dfmm_batch_run(dfmm_batch* batch, void* stream);
+int dfmm_batch_latencies(dfmm_batch* batch, double* ms, int n_cfg);
+void dfmm_batch_destroy(dfmm_batch* batch);
+
+/* Depth autotuner (App. B: near-field cost ~ C_n x near pairs, far-field
+ * cost ~ C_f x M2L translations; the optimum balances them).  Builds the
+ * tree of seg at each depth in [d_min, d_max], times one dfmm_fmm_forces at
+ * the plan's depth to measure C_n, C_f and the per-cell cost of the other
+ * stages, predicts every candidate's time from its exact pair counts and
+ * returns the fastest depth in *best (predicted ms per depth in
+ * pred_ms[d - d_min] if non-NULL).  Synchronous.  seg/burgers: device. */
+int dfmm_autotune_depth(const dfmm_params* prm, const double* seg, const double* burgers, int64_t n_seg,
+                        int d_min, int d_max, void* stream, int* best, double* pred_ms);
 
 /* JSON descriptions: parameters, M2L operator memory (Eq. mem_unif and the
  * stored spectra), precompute time / tree sizes per level, pair counts. */

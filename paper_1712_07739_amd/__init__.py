@@ -25,7 +25,10 @@ ENTRY_POINTS = (
     "dfmm_default_params", "dfmm_fmm_setup", "dfmm_build_tree", "dfmm_fmm_forces",
     "dfmm_direct_forces", "dfmm_tree_set_timing", "dfmm_tree_stage_times", "dfmm_plan_info",
     "dfmm_tree_info", "dfmm_tree_destroy", "dfmm_plan_destroy", "dfmm_status_string",
-    "dfmm_last_error",
+    "dfmm_last_error", "dfmm_surrogate_default_cfg", "dfmm_surrogate_train", "dfmm_surrogate_use",
+    "dfmm_surrogate_info", "dfmm_surrogate_get_params", "dfmm_surrogate_set_params",
+    "dfmm_surrogate_loss_grad", "dfmm_surrogate_forward", "dfmm_batch_create", "dfmm_batch_run",
+    "dfmm_batch_latencies", "dfmm_batch_destroy", "dfmm_autotune_depth",
 )
 
 
@@ -37,6 +40,16 @@ class Params(ctypes.Structure):
         ("c11", ctypes.c_double), ("c12", ctypes.c_double), ("c44", ctypes.c_double),
         ("core_a", ctypes.c_double), ("box_lo", ctypes.c_double * 3), ("box_size", ctypes.c_double),
         ("n_quad", ctypes.c_int), ("n_circle", ctypes.c_int), ("precision", ctypes.c_int),
+    ]
+
+
+class SurrogateCfg(ctypes.Structure):
+    """Mirror of dfmm_surrogate_cfg."""
+
+    _fields_ = [
+        ("hidden", ctypes.c_int), ("epochs", ctypes.c_int), ("batch", ctypes.c_int), ("bins", ctypes.c_int),
+        ("n_samples", ctypes.c_int64), ("lr", ctypes.c_double), ("tol", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
     ]
 
 
@@ -73,6 +86,20 @@ def lib():
     L.dfmm_status_string.argtypes = [i32]
     L.dfmm_status_string.restype = ctypes.c_char_p
     L.dfmm_last_error.restype = ctypes.c_char_p
+    L.dfmm_surrogate_default_cfg.argtypes = [ctypes.POINTER(SurrogateCfg)]
+    L.dfmm_surrogate_train.argtypes = [vp, ctypes.POINTER(SurrogateCfg), vp]
+    L.dfmm_surrogate_use.argtypes = [vp, i32, vp]
+    L.dfmm_surrogate_info.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t]
+    L.dfmm_surrogate_get_params.argtypes = [vp, vp, i64, ctypes.POINTER(i64)]
+    L.dfmm_surrogate_set_params.argtypes = [vp, vp, i64]
+    L.dfmm_surrogate_loss_grad.argtypes = [vp, vp, vp, i64, vp, ctypes.POINTER(ctypes.c_double), vp]
+    L.dfmm_surrogate_forward.argtypes = [vp, vp, i64, vp, vp]
+    L.dfmm_batch_create.argtypes = [vp, vp, vp, vp, vp, i32, i32, vp, pp]
+    L.dfmm_batch_run.argtypes = [vp, vp]
+    L.dfmm_batch_latencies.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i32]
+    L.dfmm_batch_destroy.argtypes = [vp]
+    L.dfmm_autotune_depth.argtypes = [ctypes.POINTER(Params), vp, vp, i64, i32, i32, vp, ctypes.POINTER(i32),
+                                      ctypes.POINTER(ctypes.c_double)]
     for name in ENTRY_POINTS:
         getattr(L, name)
     _lib = L
@@ -136,6 +163,59 @@ class Plan:
         buf = ctypes.create_string_buffer(4096)
         _check(lib().dfmm_plan_info(self._h, buf, 4096))
         return json.loads(buf.value.decode())
+
+    # ---- learned surrogate of the anisotropic kernel
+    def surrogate_train(self, stream=None, **cfg):
+        c = SurrogateCfg()
+        lib().dfmm_surrogate_default_cfg(ctypes.byref(c))
+        for k, v in cfg.items():
+            setattr(c, k, v)
+        _check(lib().dfmm_surrogate_train(self._h, ctypes.byref(c), _stream(stream)))
+        return self.surrogate_info()
+
+    def surrogate_use(self, on: bool, stream=None):
+        _check(lib().dfmm_surrogate_use(self._h, 1 if on else 0, _stream(stream)))
+
+    def surrogate_info(self):
+        buf = ctypes.create_string_buffer(1 << 16)
+        _check(lib().dfmm_surrogate_info(self._h, buf, 1 << 16))
+        return json.loads(buf.value.decode())
+
+    def surrogate_params(self):
+        import numpy as np
+
+        n = ctypes.c_int64()
+        _check(lib().dfmm_surrogate_get_params(self._h, None, 0, ctypes.byref(n)))
+        out = np.empty(n.value, dtype=np.float32)
+        _check(lib().dfmm_surrogate_get_params(self._h, ctypes.c_void_p(out.ctypes.data), n.value, ctypes.byref(n)))
+        return out
+
+    def surrogate_set_params(self, params):
+        import numpy as np
+
+        a = np.ascontiguousarray(params, dtype=np.float32)
+        _check(lib().dfmm_surrogate_set_params(self._h, ctypes.c_void_p(a.ctypes.data), a.size))
+
+    def surrogate_loss_grad(self, X, Y, stream=None):
+        """Loss and gradient for device float32 rows X [n,6], Y [n,18]."""
+        import torch
+
+        n = int(X.shape[0])
+        g = torch.empty(int(self.surrogate_params().size), dtype=torch.float32, device=X.device)
+        loss = ctypes.c_double()
+        _check(lib().dfmm_surrogate_loss_grad(self._h, ctypes.c_void_p(X.contiguous().data_ptr()),
+                                              ctypes.c_void_p(Y.contiguous().data_ptr()), n,
+                                              ctypes.c_void_p(g.data_ptr()), ctypes.byref(loss), _stream(stream)))
+        return loss.value, g
+
+    def surrogate_forward(self, X, stream=None):
+        import torch
+
+        n = int(X.shape[0])
+        Y = torch.empty((n, 18), dtype=torch.float32, device=X.device)
+        _check(lib().dfmm_surrogate_forward(self._h, ctypes.c_void_p(X.contiguous().data_ptr()), n,
+                                            ctypes.c_void_p(Y.data_ptr()), _stream(stream)))
+        return Y
 
     def close(self):
         if self._h:
@@ -227,3 +307,53 @@ def direct_forces(plan: Plan, seg, burgers, targets=None, fp32=False, out=None, 
                                     ctypes.c_void_p(burgers.data_ptr()), n, tptr, nt,
                                     ctypes.c_void_p(out.data_ptr()), 1 if fp32 else 0, _stream(stream)))
     return out
+
+
+class Batch:
+    """dfmm_batch_create: the force evaluations of many (plan, tree, seg,
+    burgers, forces) configurations captured into one HIP graph."""
+
+    def __init__(self, plans, trees, segs, burgers, forces, lanes=4, stream=None):
+        n = len(plans)
+        assert len(trees) == len(segs) == len(burgers) == len(forces) == n
+        self._keep = (plans, trees, segs, burgers, forces)
+        P = ctypes.c_void_p * n
+        self._args = (P(*[p.handle for p in plans]), P(*[t.handle for t in trees]),
+                      P(*[s.data_ptr() for s in segs]), P(*[b.data_ptr() for b in burgers]),
+                      P(*[f.data_ptr() for f in forces]))
+        self.n = n
+        self._h = ctypes.c_void_p()
+        _check(lib().dfmm_batch_create(*[ctypes.cast(a, ctypes.c_void_p) for a in self._args], n, lanes,
+                                       _stream(stream), ctypes.byref(self._h)))
+
+    def run(self, stream=None):
+        _check(lib().dfmm_batch_run(self._h, _stream(stream)))
+
+    def latencies_ms(self):
+        ms = (ctypes.c_double * self.n)()
+        _check(lib().dfmm_batch_latencies(self._h, ms, self.n))
+        return list(ms)
+
+    def close(self):
+        if self._h:
+            lib().dfmm_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune_depth(params: Params, seg, burgers, d_min=3, d_max=7, stream=None):
+    """dfmm_autotune_depth: fastest leaf depth predicted from measured near/far costs."""
+    n = int(seg.shape[0])
+    seg = _dev_f64(seg, (n, 2, 3), "seg")
+    burgers = _dev_f64(burgers, (n, 3), "burgers")
+    best = ctypes.c_int()
+    pred = (ctypes.c_double * (d_max - d_min + 1))()
+    _check(lib().dfmm_autotune_depth(ctypes.byref(params), ctypes.c_void_p(seg.data_ptr()),
+                                     ctypes.c_void_p(burgers.data_ptr()), n, d_min, d_max, _stream(stream),
+                                     ctypes.byref(best), pred))
+    return best.value, {d_min + i: pred[i] for i in range(d_max - d_min + 1)}

@@ -127,6 +127,7 @@ int dfmm_fmm_setup(const dfmm_params* prm, void* stream, dfmm_plan** out) {
 
 void dfmm_plan_destroy(dfmm_plan* pl) {
   if (!pl) return;
+  hipFree(pl->sur.w); hipFree(pl->sur.g); hipFree(pl->sur.m); hipFree(pl->sur.v); hipFree(pl->sur.mask);
   for (auto& l : pl->lev) hipFree(l.khat);
   hipFree(pl->t64.S); hipFree(pl->t64.cs); hipFree(pl->t64.tw);
   hipFree(pl->t32.S); hipFree(pl->t32.cs); hipFree(pl->t32.tw);
@@ -193,6 +194,84 @@ int dfmm_tree_stage_times(dfmm_tree* t, double* ms, int* n_calls) {
   for (int i = 0; i < DFMM_N_STAGES; ++i) ms[i] = t->stage_ms[i];
   if (n_calls) *n_calls = t->timed_calls;
   return DFMM_OK;
+}
+
+void dfmm_surrogate_default_cfg(dfmm_surrogate_cfg* c) {
+  if (!c) return;
+  c->hidden = 128;
+  c->epochs = 20;
+  c->batch = 4096;
+  c->bins = 32;
+  c->n_samples = 2000000;
+  c->lr = 1e-3;
+  c->tol = 1e-5;
+  c->seed = 1;
+}
+
+int dfmm_surrogate_train(dfmm_plan* pl, const dfmm_surrogate_cfg* cfg, void* stream) {
+  if (!pl || !cfg) { set_error("surrogate_train: null argument"); return DFMM_E_ARG; }
+  if (pl->iso) { set_error("surrogate_train: the plan's medium is isotropic (closed form)"); return DFMM_E_ARG; }
+  return surrogate_train(pl, *cfg, (hipStream_t)stream);
+}
+
+int dfmm_surrogate_use(dfmm_plan* pl, int on, void* stream) {
+  if (!pl) { set_error("surrogate_use: null plan"); return DFMM_E_ARG; }
+  if (on && (!pl->sur.trained || pl->iso)) { set_error("surrogate_use: no trained surrogate"); return DFMM_E_STATE; }
+  pl->sur.in_use = on ? 1 : 0;
+  return build_spectra(pl, (hipStream_t)stream);
+}
+
+int dfmm_surrogate_info(const dfmm_plan* pl, char* json, size_t cap) {
+  if (!pl || !json || cap == 0) { set_error("surrogate_info: invalid argument"); return DFMM_E_ARG; }
+  const Surrogate& S = pl->sur;
+  std::string s = "{\"trained\": " + std::to_string(S.trained) + ", \"in_use\": " + std::to_string(S.in_use) +
+                  ", \"n_params\": " + std::to_string(S.L.total) + ", \"n_samples\": " + std::to_string(S.n_samples) +
+                  ", \"epochs\": " + std::to_string(S.epochs) + ", \"bins\": " + std::to_string(S.bins) +
+                  ", \"tol\": " + std::to_string(S.tol) + ", \"pass_frac\": " + std::to_string(S.pass_frac) +
+                  ", \"max_bin_err\": " + std::to_string(S.max_err) + ", \"median_bin_err\": " +
+                  std::to_string(S.med_err) + ", \"yscale\": " + std::to_string(S.yscale) +
+                  ", \"train_ms\": " + std::to_string(S.train_ms) + ", \"loss\": [";
+  for (size_t i = 0; i < S.loss_hist.size(); ++i) {
+    char b[32];
+    std::snprintf(b, sizeof b, "%s%.6g", i ? ", " : "", S.loss_hist[i]);
+    s += b;
+  }
+  s += "]}";
+  if (s.size() + 1 > cap) { set_error("surrogate_info: buffer too small"); return DFMM_E_ARG; }
+  std::memcpy(json, s.c_str(), s.size() + 1);
+  return DFMM_OK;
+}
+
+int dfmm_surrogate_get_params(const dfmm_plan* pl, float* host, int64_t cap, int64_t* n) {
+  if (!pl || !n) { set_error("surrogate_get_params: null argument"); return DFMM_E_ARG; }
+  if (!pl->sur.w) { set_error("surrogate_get_params: no network"); return DFMM_E_STATE; }
+  *n = pl->sur.L.total;
+  if (host && cap >= *n) DFMM_HIP(hipMemcpy(host, pl->sur.w, sizeof(float) * (*n), hipMemcpyDeviceToHost));
+  return DFMM_OK;
+}
+
+int dfmm_surrogate_set_params(dfmm_plan* pl, const float* host, int64_t n) {
+  if (!pl || !host) { set_error("surrogate_set_params: null argument"); return DFMM_E_ARG; }
+  int rc = surrogate_alloc(pl, 1, nullptr);
+  if (rc) return rc;
+  if (n != pl->sur.L.total) { set_error("surrogate_set_params: wrong parameter count"); return DFMM_E_ARG; }
+  DFMM_HIP(hipMemcpy(pl->sur.w, host, sizeof(float) * n, hipMemcpyHostToDevice));
+  pl->sur.trained = 0;
+  pl->sur.in_use = 0;
+  return DFMM_OK;
+}
+
+int dfmm_surrogate_loss_grad(dfmm_plan* pl, const float* X, const float* Y, int64_t n, float* grad, double* loss,
+                             void* stream) {
+  if (!pl || !X || !Y || !grad || n < 1 || n > (1 << 24)) { set_error("surrogate_loss_grad: invalid argument"); return DFMM_E_ARG; }
+  if (!pl->sur.w) { set_error("surrogate_loss_grad: no network"); return DFMM_E_STATE; }
+  return surrogate_loss_grad(pl, X, Y, n, grad, loss, (hipStream_t)stream);
+}
+
+int dfmm_surrogate_forward(const dfmm_plan* pl, const float* X, int64_t n, float* Y, void* stream) {
+  if (!pl || !X || !Y || n < 1 || n > (1 << 24)) { set_error("surrogate_forward: invalid argument"); return DFMM_E_ARG; }
+  if (!pl->sur.w) { set_error("surrogate_forward: no network"); return DFMM_E_STATE; }
+  return surrogate_forward(pl, X, n, Y, (hipStream_t)stream);
 }
 
 int dfmm_plan_info(const dfmm_plan* pl, char* json, size_t cap) {

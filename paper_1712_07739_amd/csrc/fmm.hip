@@ -417,11 +417,12 @@ __global__ void k_idft(const cplx<T>* Shat, int64_t ncell, int p, int G, const T
 // combined with xor shuffles.  In MIXED precision pairs are evaluated in float
 // (displacements formed in double) with compensated float accumulation, and
 // pairs closer than 2a in double.
-template <typename T, bool MIXED, bool ISO>
+template <typename T, bool MIXED, bool ISO, bool SUR>
 __global__ void __launch_bounds__(64) k_leaf(const double* pts, int64_t N, const int* first, const int* count,
                                              const uint32_t* key, const int* nbr, const T* s, double lo0,
                                              double lo1, double lo2, double sD, int p, Med<T> m, Med<double> m64,
-                                             double* sig) {
+                                             SurDev sd, double* sig) {
+  extern __shared__ float sur_scratch[];  // [2*128][64] activations when SUR
   const int leaf = blockIdx.x, lane = threadIdx.x;
   const int t0 = first[leaf], nt = count[leaf];
   __shared__ int nb_first[27], nb_cnt[27];
@@ -477,7 +478,26 @@ __global__ void __launch_bounds__(64) k_leaf(const double* pts, int64_t N, const
           } else {
             T D[27], b[3], tt[3];
             for (int c = 0; c < 3; ++c) b[c] = (T)pts[(3 + c) * N + j], tt[c] = (T)pts[(6 + c) * N + j];
-            dg_medium_t<T, ISO>((T)d0, (T)d1, (T)d2, m, D);
+            bool net = false;
+            if constexpr (SUR) {
+              // network for the anisotropic part where its direction bin passed the gate
+              const float f0 = (float)d0, f1 = (float)d1, f2 = (float)d2;
+              const float rr = f0 * f0 + f1 * f1 + f2 * f2;
+              if (rr > 0.f) {
+                const float ir = rsqrtf(rr);
+                const float tv[3] = {f0 * ir, f1 * ir, f2 * ir};
+                if (sd.mask[sur_bin(tv, sd.bins)]) {
+#pragma unroll
+                  for (int c = 0; c < 27; ++c) D[c] = T(0);
+                  dg_iso_acc<T>((T)d0, (T)d1, (T)d2, m.mu, m.nu, m.a, T(1), D);
+                  const float q = rr / (rr + (float)m.a * (float)m.a);
+                  sur_aniso_acc<64>(sd, (float)m.c44, f0, f1, f2, q * sqrtf(q), (float*)D,
+                                    sur_scratch + lane);
+                  net = true;
+                }
+              }
+            }
+            if (!net) dg_medium_t<T, ISO>((T)d0, (T)d1, (T)d2, m, D);
             if (MIXED) {
               T ds[6] = {0, 0, 0, 0, 0, 0};
               contract_b_t<T>(D, m.c12, m.c44, m.hh, b, tt, ds);
@@ -775,15 +795,19 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
     const bool mixed = !std::is_same<T, double>::value;
 #define LEAF_ARGS                                                                                     \
   t->pts, N, LD.first, LD.count, LD.key, t->nbr, s + LD.off * 6 * p3, lo[0], lo[1], lo[2], sD, p, m, m64, \
-      t->sig
-    if (mixed && pl->iso)
-      STAGE(6, (k_leaf<T, true, true><<<(unsigned)LD.n, 64, 0, st>>>(LEAF_ARGS)));
+      sd, t->sig
+    SurDev sd = sur_dev(pl);
+    if (mixed && !pl->iso && sd.on)
+      STAGE(6, (k_leaf<T, true, false, true><<<(unsigned)LD.n, 64, sizeof(float) * 2 * kSurHidden * 64, st>>>(
+                   LEAF_ARGS)));
+    else if (mixed && pl->iso)
+      STAGE(6, (k_leaf<T, true, true, false><<<(unsigned)LD.n, 64, 0, st>>>(LEAF_ARGS)));
     else if (mixed)
-      STAGE(6, (k_leaf<T, true, false><<<(unsigned)LD.n, 64, 0, st>>>(LEAF_ARGS)));
+      STAGE(6, (k_leaf<T, true, false, false><<<(unsigned)LD.n, 64, 0, st>>>(LEAF_ARGS)));
     else if (pl->iso)
-      STAGE(6, (k_leaf<T, false, true><<<(unsigned)LD.n, 64, 0, st>>>(LEAF_ARGS)));
+      STAGE(6, (k_leaf<T, false, true, false><<<(unsigned)LD.n, 64, 0, st>>>(LEAF_ARGS)));
     else
-      STAGE(6, (k_leaf<T, false, false><<<(unsigned)LD.n, 64, 0, st>>>(LEAF_ARGS)));
+      STAGE(6, (k_leaf<T, false, false, false><<<(unsigned)LD.n, 64, 0, st>>>(LEAF_ARGS)));
 #undef LEAF_ARGS
   }
   STAGE(7, (k_forces<<<nblk(t->nseg, 128), 128, 0, st>>>(seg, burg, nullptr, t->inv, t->sig, pl->quad,
@@ -805,6 +829,11 @@ static void set_lds_attrs() {
   hipFuncSetAttribute((const void*)k_m2m<T>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
   hipFuncSetAttribute((const void*)k_l2l<T>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
   hipFuncSetAttribute((const void*)k_p2m<T>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+}
+
+void fmm_prepare(const dfmm_plan* pl) {
+  if (pl->mixed) set_lds_attrs<float>();
+  else set_lds_attrs<double>();
 }
 
 int fmm_forces_impl(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const double* burg, double* forces,

@@ -8,6 +8,7 @@
 
 #include "../../include/dfmm.h"
 #include "kernel_eval.h"
+#include "mlp_eval.h"
 
 namespace dfmm {
 
@@ -33,6 +34,24 @@ struct Tables {
   T* tw = nullptr;  // DFT twiddles [n][2]: exp(-2 pi i k / n)
 };
 
+// Trained network of the anisotropic-kernel surrogate and its residual gate.
+struct Surrogate {
+  int trained = 0, in_use = 0;
+  SurLayout L = {};
+  SurFeat ft = {};
+  float yscale = 1.f;
+  float* w = nullptr;  // parameters (device), layout SurLayout
+  float* g = nullptr;  // gradient
+  float* m = nullptr;  // Adam moments
+  float* v = nullptr;
+  unsigned char* mask = nullptr;  // [6][bins][bins]
+  int bins = 0;
+  double tol = 0, pass_frac = 0, max_err = 0, med_err = 0, train_ms = 0;
+  int64_t n_samples = 0;
+  int epochs = 0;
+  std::vector<double> loss_hist;
+};
+
 struct LevelTables {
   void* khat = nullptr;  // [nf][158][54] complex (float2 or double2): DFT of the
                          // circulant embedding of each canonical offset's generator
@@ -56,6 +75,7 @@ struct dfmm_plan {
   std::vector<dfmm::LevelTables> lev;  // index = level (0..D); used for 2..D
   double setup_ms = 0;
   size_t khat_bytes = 0;
+  dfmm::Surrogate sur;
   int device = 0;
   template <typename T>
   dfmm::Med<T> med() const;
@@ -109,11 +129,23 @@ void set_error(const std::string& msg);
 
 // setup.hip
 int setup_tables(dfmm_plan* plan, hipStream_t st);
+int build_spectra(dfmm_plan* plan, hipStream_t st);  // exact, or with the surrogate when in use
+SurDev sur_dev(const dfmm_plan* plan);
+
+// mlp.hip
+SurLayout sur_layout(int hidden);
+int surrogate_train(dfmm_plan* pl, const dfmm_surrogate_cfg& cfg, hipStream_t st);
+int surrogate_alloc(dfmm_plan* pl, uint64_t seed, hipStream_t st);
+int surrogate_loss_grad(dfmm_plan* pl, const float* X, const float* Y, int64_t n, float* grad, double* loss,
+                        hipStream_t st);
+int surrogate_forward(const dfmm_plan* pl, const float* X, int64_t n, float* Yout, hipStream_t st);
 
 // tree.hip
-int build_tree_impl(dfmm_plan* plan, const double* seg, int64_t nseg, hipStream_t st, dfmm_tree* t);
+int build_tree_impl(dfmm_plan* plan, const double* seg, int64_t nseg, hipStream_t st, dfmm_tree* t,
+                    bool workspaces = true);
 
 // fmm.hip
+void fmm_prepare(const dfmm_plan* plan);  // one-time kernel attributes (outside graph capture)
 int fmm_forces_impl(const dfmm_plan* plan, dfmm_tree* t, const double* seg, const double* burg,
                     double* forces, hipStream_t st);
 int direct_forces_impl(const dfmm_plan* plan, const double* seg, const double* burg, int64_t nseg,

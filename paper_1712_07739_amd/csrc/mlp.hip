@@ -88,21 +88,25 @@ __global__ void k_sumsq(const float* Y, int64_t n, double* part) {
 }
 
 // C[M x N] (ldc) = op(A) op(B) (+ C if acc), row-major; op(A)[m][k] = TA ? A[k*lda+m] : A[m*lda+k].
+// blockIdx.z selects a K range of length kchunk (split-K); its result goes to
+// C + z * (M * ldc) when split (acc must then be 0).
 template <bool TA, bool TB>
 __global__ void __launch_bounds__(256) k_gemm(int M, int N, int K, const float* A, int lda, const float* B, int ldb,
-                                              float* C, int ldc, int acc) {
+                                              float* C, int ldc, int acc, int kchunk) {
   __shared__ float As[16][64 + 1];
   __shared__ float Bs[16][64 + 1];
   const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
   const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  const int kb = blockIdx.z * kchunk, ke = min(K, kb + kchunk);
+  C += (int64_t)blockIdx.z * M * ldc;
   float c[4][4] = {};
-  for (int k0 = 0; k0 < K; k0 += 16) {
+  for (int k0 = kb; k0 < ke; k0 += 16) {
     for (int e = threadIdx.x; e < 16 * 64; e += 256) {
       int kk = e / 64, mm = e % 64;
       int gm = m0 + mm, gk = k0 + kk;
-      As[kk][mm] = (gm < M && gk < K) ? (TA ? A[(int64_t)gk * lda + gm] : A[(int64_t)gm * lda + gk]) : 0.f;
+      As[kk][mm] = (gm < M && gk < ke) ? (TA ? A[(int64_t)gk * lda + gm] : A[(int64_t)gm * lda + gk]) : 0.f;
       int gn = n0 + mm;
-      Bs[kk][mm] = (gn < N && gk < K) ? (TB ? B[(int64_t)gn * ldb + gk] : B[(int64_t)gk * ldb + gn]) : 0.f;
+      Bs[kk][mm] = (gn < N && gk < ke) ? (TB ? B[(int64_t)gn * ldb + gk] : B[(int64_t)gk * ldb + gn]) : 0.f;
     }
     __syncthreads();
 #pragma unroll
@@ -165,13 +169,28 @@ __global__ void k_silu_back(const float* dA, const float* Z, int64_t n, float* d
   dZ[i] = dA[i] * s * (1.f + z * (1.f - s));
 }
 
-// db[j] = sum_i dZ[i][j] (fixed order)
+// db[j] = sum_i dZ[i][j]: one block per column, fixed-order tree reduction
 __global__ void k_colsum(const float* dZ, int rows, int cols, float* db) {
-  int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= cols) return;
+  __shared__ float sh[256];
+  const int j = blockIdx.x;
   float s = 0.f;
-  for (int i = 0; i < rows; ++i) s += dZ[(int64_t)i * cols + j];
-  db[j] = s;
+  for (int i = threadIdx.x; i < rows; i += 256) s += dZ[(int64_t)i * cols + j];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) db[j] = sh[0];
+}
+
+// C[i] = sum over the S split-K partials (fixed order)
+__global__ void k_sum_parts(const float* part, int64_t n, int S, float* C) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float s = 0.f;
+  for (int k = 0; k < S; ++k) s += part[(int64_t)k * n + i];
+  C[i] = s;
 }
 
 __global__ void k_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
@@ -257,14 +276,38 @@ SurLayout sur_layout(int hidden) {
   return L;
 }
 
+// Split-K scratch for long reductions (weight gradients over the batch).
+static float* g_split = nullptr;
+static size_t g_split_n = 0;
+
 static int gemm(bool ta, bool tb, int M, int N, int K, const float* A, int lda, const float* B, int ldb, float* C,
                 int ldc, int acc, hipStream_t st) {
-  dim3 g(nb(N, 64), nb(M, 64));
-  if (!ta && !tb) k_gemm<false, false><<<g, 256, 0, st>>>(M, N, K, A, lda, B, ldb, C, ldc, acc);
-  else if (!ta && tb) k_gemm<false, true><<<g, 256, 0, st>>>(M, N, K, A, lda, B, ldb, C, ldc, acc);
-  else if (ta && !tb) k_gemm<true, false><<<g, 256, 0, st>>>(M, N, K, A, lda, B, ldb, C, ldc, acc);
-  else k_gemm<true, true><<<g, 256, 0, st>>>(M, N, K, A, lda, B, ldb, C, ldc, acc);
+  int S = 1;
+  const int tiles = (int)(nb(N, 64) * nb(M, 64));
+  if (!acc && tiles < 64 && K >= 1024) S = std::min(32, K / 256);
+  const int kchunk = ((K + S - 1) / S + 15) / 16 * 16;
+  S = (K + kchunk - 1) / kchunk;
+  float* out = C;
+  if (S > 1) {
+    size_t need = (size_t)S * M * ldc;
+    if (need > g_split_n) {
+      hipFree(g_split);
+      g_split = nullptr;
+      DFMM_HIP(hipMalloc(&g_split, sizeof(float) * need));
+      g_split_n = need;
+    }
+    out = g_split;
+  }
+  dim3 g(nb(N, 64), nb(M, 64), S);
+  if (!ta && !tb) k_gemm<false, false><<<g, 256, 0, st>>>(M, N, K, A, lda, B, ldb, out, ldc, acc, kchunk);
+  else if (!ta && tb) k_gemm<false, true><<<g, 256, 0, st>>>(M, N, K, A, lda, B, ldb, out, ldc, acc, kchunk);
+  else if (ta && !tb) k_gemm<true, false><<<g, 256, 0, st>>>(M, N, K, A, lda, B, ldb, out, ldc, acc, kchunk);
+  else k_gemm<true, true><<<g, 256, 0, st>>>(M, N, K, A, lda, B, ldb, out, ldc, acc, kchunk);
   DFMM_LAUNCH_CHECK();
+  if (S > 1) {
+    k_sum_parts<<<nb((int64_t)M * ldc, 256), 256, 0, st>>>(g_split, (int64_t)M * ldc, S, C);
+    DFMM_LAUNCH_CHECK();
+  }
   return DFMM_OK;
 }
 
@@ -331,7 +374,7 @@ static int loss_grad(const float* prm, float* grad, const SurLayout& L, MlpWork&
     // dW = dZ^T A_l ; db = colsum(dZ)
     if ((rc = gemm(true, false, L.dout[l], L.din[l], n, w.dZ, L.dout[l], w.A[l], L.din[l], gW, L.din[l], 0, st)))
       return rc;
-    k_colsum<<<nb(L.dout[l], 128), 128, 0, st>>>(w.dZ, n, L.dout[l], gb);
+    k_colsum<<<L.dout[l], 256, 0, st>>>(w.dZ, n, L.dout[l], gb);
     DFMM_LAUNCH_CHECK();
     if (l > 0) {
       // dA_l = dZ W ; dZ_{l-1} = dA_l * SiLU'(Z_{l-1})
@@ -351,19 +394,9 @@ static int loss_grad(const float* prm, float* grad, const SurLayout& L, MlpWork&
   return DFMM_OK;
 }
 
-int surrogate_train(dfmm_plan* pl, const dfmm_surrogate_cfg& cfg, hipStream_t st) {
-  auto t0 = std::chrono::steady_clock::now();
+int surrogate_alloc(dfmm_plan* pl, uint64_t seed, hipStream_t st) {
   Surrogate& S = pl->sur;
-  if (cfg.hidden != kSurHidden) {
-    set_error("surrogate: hidden width must be 128");
-    return DFMM_E_ARG;
-  }
-  if (cfg.n_samples < 1024 || cfg.batch < 64 || cfg.batch > cfg.n_samples || cfg.epochs < 1 || !(cfg.lr > 0) ||
-      cfg.bins < 1 || cfg.bins > 256 || !(cfg.tol > 0)) {
-    set_error("surrogate: invalid training configuration");
-    return DFMM_E_ARG;
-  }
-  S.L = sur_layout(cfg.hidden);
+  S.L = sur_layout(kSurHidden);
   double c = pl->prm.c11 + pl->prm.c12 + pl->prm.c44;
   S.ft.f[0] = (float)(pl->prm.c11 / c);
   S.ft.f[1] = (float)(pl->prm.c12 / c);
@@ -375,10 +408,30 @@ int surrogate_train(dfmm_plan* pl, const dfmm_surrogate_cfg& cfg, hipStream_t st
     DFMM_HIP(hipMalloc(&S.m, sizeof(float) * P));
     DFMM_HIP(hipMalloc(&S.v, sizeof(float) * P));
   }
-  k_init_params<<<nb(P, 256), 256, 0, st>>>(S.w, S.L, cfg.seed);
+  k_init_params<<<nb(P, 256), 256, 0, st>>>(S.w, S.L, seed);
   DFMM_LAUNCH_CHECK();
   DFMM_HIP(hipMemsetAsync(S.m, 0, sizeof(float) * P, st));
   DFMM_HIP(hipMemsetAsync(S.v, 0, sizeof(float) * P, st));
+  DFMM_HIP(hipStreamSynchronize(st));
+  return DFMM_OK;
+}
+
+int surrogate_train(dfmm_plan* pl, const dfmm_surrogate_cfg& cfg, hipStream_t st) {
+  auto t0 = std::chrono::steady_clock::now();
+  Surrogate& S = pl->sur;
+  if (cfg.hidden != kSurHidden) {
+    set_error("surrogate: hidden width must be 128");
+    return DFMM_E_ARG;
+  }
+  if (cfg.n_samples < 1024 || cfg.batch < 64 || cfg.batch > cfg.n_samples || cfg.epochs < 1 || !(cfg.lr > 0) ||
+      cfg.bins < 1 || cfg.bins > 256 || !(cfg.tol >= 0)) {
+    set_error("surrogate: invalid training configuration");
+    return DFMM_E_ARG;
+  }
+  int rc0 = surrogate_alloc(pl, cfg.seed, st);
+  if (rc0) return rc0;
+  S.trained = 0;
+  const int64_t P = S.L.total;
   // samples
   const int64_t n = cfg.n_samples;
   float *X = nullptr, *Y = nullptr;

@@ -348,7 +348,7 @@ __global__ void k_len_keys(const int* il_start, int n, uint32_t* key, uint32_t* 
 
 static inline unsigned nb(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
-int build_tree_impl(dfmm_plan* pl, const double* seg, int64_t nseg, hipStream_t st, dfmm_tree* t) {
+int build_tree_impl(dfmm_plan* pl, const double* seg, int64_t nseg, hipStream_t st, dfmm_tree* t, bool workspaces) {
   const int D = pl->D, nq = pl->quad.n;
   const int64_t N = nseg * nq;
   if (N >= (int64_t)1 << 31) {
@@ -480,6 +480,10 @@ int build_tree_impl(dfmm_plan* pl, const double* seg, int64_t nseg, hipStream_t 
     }
     t->near_pairs = np;
     t->max_leaf_pts = mx;
+  }
+  if (!workspaces) {
+    DFMM_HIP(hipStreamSynchronize(st));
+    return DFMM_OK;
   }
   // workspaces
   const int p3 = pl->p * pl->p * pl->p;

@@ -5,6 +5,8 @@ dislocation loops (segment end points and Burgers vectors).
 """
 from .loops import (  # noqa: F401
     WORKLOADS,
+    batch_sizes,
+    make_batch,
     make_loops,
     make_workload,
     segment_subset,

@@ -107,3 +107,15 @@ def segment_subset(n_seg: int, k: int, seed: int) -> np.ndarray:
     rng = np.random.default_rng(seed)
     k = min(k, n_seg)
     return np.sort(rng.choice(n_seg, size=k, replace=False)).astype(np.int64)
+
+
+def batch_sizes(n_cfg: int = 64, seed: int = 4, lo: int = 5000, hi: int = 150000):
+    """Segment counts of the batched ensemble: 40 * round(exp(U[ln lo, ln hi]) / 40)."""
+    rng = np.random.default_rng(seed)
+    return [int(40 * round(float(np.exp(rng.uniform(np.log(lo), np.log(hi)))) / 40)) for _ in range(n_cfg)]
+
+
+def make_batch(n_cfg: int = 64, seed: int = 4):
+    """n_cfg independent isotropic loop ensembles of log-uniform size in
+    [5000, 150000] segments, radii [0.01, 0.05], ensemble i seeded 4000 + i."""
+    return [make_loops(n // SEGS_PER_LOOP, 0.01, 0.05, 4000 + i) for i, n in enumerate(batch_sizes(n_cfg, seed))]
