@@ -234,11 +234,11 @@ def bench_batch(args):
     med = int(np.argsort(sizes)[len(sizes) // 2])
     prm = pk.make_params(order, 5, *C, synth.loops.CORE_A, synth.loops.BOX_LO, synth.loops.BOX_SIZE,
                          precision=pk.DFMM_MIXED)
-    d_med, pred = pk.autotune_depth(prm, segs[med], burgs[med], 3, 7)
+    d_med, pred, meas = pk.autotune_depth(prm, segs[med], burgs[med], 3, 7)
     dens = sizes[med] / 8.0 ** d_med
     depths = [int(min(7, max(3, round(np.log(n / dens) / np.log(8.0))))) for n in sizes]
-    log("autotuner: median ensemble %d segments -> depth %d (predicted ms %s); depths used %s"
-        % (sizes[med], d_med, {k: round(v, 2) for k, v in pred.items()},
+    log("autotuner: median ensemble %d segments -> depth %d (predicted ms %s, measured ms %s); depths used %s"
+        % (sizes[med], d_med, {k: round(v, 2) for k, v in pred.items()}, {k: round(v, 2) for k, v in meas.items()},
            {d: depths.count(d) for d in sorted(set(depths))}))
     plans = {d: pk.Plan(pk.make_params(order, d, *C, synth.loops.CORE_A, synth.loops.BOX_LO,
                                        synth.loops.BOX_SIZE, precision=pk.DFMM_MIXED)) for d in set(depths)}

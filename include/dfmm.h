@@ -214,12 +214,15 @@ void dfmm_batch_destroy(dfmm_batch* batch);
 /* Depth autotuner (App. B: near-field cost ~ C_n x near pairs, far-field
  * cost ~ C_f x M2L translations; the optimum balances them).  Builds the
  * tree of seg at each depth in [d_min, d_max], times one dfmm_fmm_forces at
- * the plan's depth to measure C_n, C_f and the per-cell cost of the other
- * stages, predicts every candidate's time from its exact pair counts and
- * returns the fastest depth in *best (predicted ms per depth in
- * pred_ms[d - d_min] if non-NULL).  Synchronous.  seg/burgers: device. */
+ * the plan's depth (prm->depth, which must lie in the range) to measure C_n,
+ * C_f and the per-cell cost of the other stages, and predicts every
+ * candidate's time from its exact pair counts (pred_ms[d - d_min] if
+ * non-NULL).  The model's fastest depth and its two neighbours are then
+ * set up and timed, and the fastest measured one is returned in *best
+ * (measured ms per depth in meas_ms[d - d_min] if non-NULL; 0 where not
+ * measured).  Synchronous; allocates.  seg/burgers: device. */
 int dfmm_autotune_depth(const dfmm_params* prm, const double* seg, const double* burgers, int64_t n_seg,
-                        int d_min, int d_max, void* stream, int* best, double* pred_ms);
+                        int d_min, int d_max, void* stream, int* best, double* pred_ms, double* meas_ms);
 
 /* JSON descriptions: parameters, M2L operator memory (Eq. mem_unif and the
  * stored spectra), precompute time / tree sizes per level, pair counts. */

@@ -99,7 +99,7 @@ def lib():
     L.dfmm_batch_latencies.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i32]
     L.dfmm_batch_destroy.argtypes = [vp]
     L.dfmm_autotune_depth.argtypes = [ctypes.POINTER(Params), vp, vp, i64, i32, i32, vp, ctypes.POINTER(i32),
-                                      ctypes.POINTER(ctypes.c_double)]
+                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     for name in ENTRY_POINTS:
         getattr(L, name)
     _lib = L
@@ -347,13 +347,18 @@ class Batch:
 
 
 def autotune_depth(params: Params, seg, burgers, d_min=3, d_max=7, stream=None):
-    """dfmm_autotune_depth: fastest leaf depth predicted from measured near/far costs."""
+    """dfmm_autotune_depth: the App. B cost model's fastest depth and its
+    neighbours are timed; returns (best depth, predicted ms per depth,
+    measured ms per timed depth)."""
     n = int(seg.shape[0])
     seg = _dev_f64(seg, (n, 2, 3), "seg")
     burgers = _dev_f64(burgers, (n, 3), "burgers")
     best = ctypes.c_int()
-    pred = (ctypes.c_double * (d_max - d_min + 1))()
+    k = d_max - d_min + 1
+    pred = (ctypes.c_double * k)()
+    meas = (ctypes.c_double * k)()
     _check(lib().dfmm_autotune_depth(ctypes.byref(params), ctypes.c_void_p(seg.data_ptr()),
                                      ctypes.c_void_p(burgers.data_ptr()), n, d_min, d_max, _stream(stream),
-                                     ctypes.byref(best), pred))
-    return best.value, {d_min + i: pred[i] for i in range(d_max - d_min + 1)}
+                                     ctypes.byref(best), pred, meas))
+    return (best.value, {d_min + i: pred[i] for i in range(k)},
+            {d_min + i: meas[i] for i in range(k) if meas[i] > 0})

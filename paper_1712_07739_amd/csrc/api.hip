@@ -155,7 +155,7 @@ void dfmm_tree_destroy(dfmm_tree* t) {
   for (auto& L : t->lv) {
     hipFree(L.key); hipFree(L.first); hipFree(L.count); hipFree(L.parent); hipFree(L.il_start); hipFree(L.il); hipFree(L.order);
   }
-  hipFree(t->pts); hipFree(t->W); hipFree(t->s); hipFree(t->What); hipFree(t->Shat); hipFree(t->sig);
+  hipFree(t->pts); hipFree(t->pleaf); hipFree(t->W); hipFree(t->s); hipFree(t->What); hipFree(t->Shat); hipFree(t->sig);
   delete t;
 }
 

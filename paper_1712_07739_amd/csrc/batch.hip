@@ -1,5 +1,6 @@
 // Many independent configurations in one graph launch, and the depth
-// autotuner built on the cost model of App. B.
+// autotuner built on the cost model of App. B (refined by measuring the
+// model's choice and its neighbours).
 #include <algorithm>
 #include <numeric>
 
@@ -38,6 +39,37 @@ static void batch_free(dfmm_batch* b) {
 }  // namespace dfmm
 
 using namespace dfmm;
+
+// Wall time (device events) of one dfmm_fmm_forces at depth d after one
+// untimed call; plan, tree and output are made and freed here.
+static int time_depth(const dfmm_params* prm, int d, const double* seg, const double* burgers, int64_t n_seg,
+                      hipStream_t st, double* ms) {
+  dfmm_params q = *prm;
+  q.depth = d;
+  dfmm_plan* pl = nullptr;
+  int rc = dfmm_fmm_setup(&q, st, &pl);
+  if (rc) return rc;
+  dfmm_tree* t = nullptr;
+  double* f = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  rc = dfmm_build_tree(pl, seg, n_seg, st, &t);
+  if (rc == DFMM_OK && hipMalloc(&f, sizeof(double) * 6 * n_seg) != hipSuccess) rc = DFMM_E_NOMEM;
+  if (rc == DFMM_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) rc = DFMM_E_HIP;
+  if (rc == DFMM_OK) rc = fmm_forces_impl(pl, t, seg, burgers, f, st);
+  if (rc == DFMM_OK && hipEventRecord(e0, st) != hipSuccess) rc = DFMM_E_HIP;
+  if (rc == DFMM_OK) rc = fmm_forces_impl(pl, t, seg, burgers, f, st);
+  if (rc == DFMM_OK && hipEventRecord(e1, st) != hipSuccess) rc = DFMM_E_HIP;
+  if (rc == DFMM_OK && hipEventSynchronize(e1) != hipSuccess) rc = DFMM_E_HIP;
+  float m = 0.f;
+  if (rc == DFMM_OK && hipEventElapsedTime(&m, e0, e1) != hipSuccess) rc = DFMM_E_HIP;
+  *ms = m;
+  if (e0) hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
+  hipFree(f);
+  dfmm_tree_destroy(t);
+  dfmm_plan_destroy(pl);
+  return rc;
+}
 
 extern "C" {
 
@@ -171,7 +203,7 @@ void dfmm_batch_destroy(dfmm_batch* b) {
 }
 
 int dfmm_autotune_depth(const dfmm_params* prm, const double* seg, const double* burgers, int64_t n_seg, int d_min,
-                        int d_max, void* stream, int* best, double* pred_ms) {
+                        int d_max, void* stream, int* best, double* pred_ms, double* meas_ms) {
   if (!prm || !seg || !burgers || !best || n_seg < 1 || d_min < 2 || d_max > 10 || d_min > d_max ||
       prm->depth < d_min || prm->depth > d_max) {
     set_error("autotune_depth: invalid argument (the plan depth must lie in [d_min, d_max])");
@@ -225,6 +257,22 @@ int dfmm_autotune_depth(const dfmm_params* prm, const double* seg, const double*
   hipFree(f);
   dfmm_tree_destroy(t0);
   dfmm_plan_destroy(pl);
+  if (meas_ms)
+    for (int d = d_min; d <= d_max; ++d) meas_ms[d - d_min] = 0.0;
+  if (rc) return rc;
+  // measurement of the model's choice and its neighbours
+  const int pick = *best;
+  double best_meas = 1e300;
+  for (int d = std::max(d_min, pick - 1); d <= std::min(d_max, pick + 1) && rc == DFMM_OK; ++d) {
+    double ms_d = 0.0;
+    rc = time_depth(prm, d, seg, burgers, n_seg, st, &ms_d);
+    if (rc) break;
+    if (meas_ms) meas_ms[d - d_min] = ms_d;
+    if (ms_d < best_meas) {
+      best_meas = ms_d;
+      *best = d;
+    }
+  }
   return rc;
 }
 

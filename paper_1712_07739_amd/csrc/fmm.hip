@@ -15,6 +15,8 @@
 #include <algorithm>
 #include <cmath>
 
+#include <utility>
+
 #include "internal.h"
 
 namespace dfmm {
@@ -204,61 +206,78 @@ __global__ void k_l2l(const int* parent, const uint32_t* key, const T* sp, T* sc
 }
 
 // ------------------------------------------------------------ forward DFT
-// One block per cell of a level: W[cell][9][p^3] (real) -> What[f][cell][9],
-// f = (f1 n + f2) p + f3, half spectrum in the last axis.  Components are
-// processed G at a time.
-template <typename T>
-__global__ void k_fdft(const T* W, int64_t ncell, int p, int G, const T* twg, cplx<T>* What) {
-  extern __shared__ unsigned char shraw[];
-  const int n = 2 * p - 1, p3 = p * p * p, nf = n * n * p;
-  cplx<T>* tw = (cplx<T>*)shraw;         // [n]
-  T* Wl = (T*)(tw + n);                  // [G][p^3]
-  cplx<T>* X1 = (cplx<T>*)(Wl + G * p3 + (G * p3) % 2);  // [G][p][p][p]  (m1, m2, f3)
-  cplx<T>* X2 = X1 + G * p3;             // [G][p][n][p]  (m1, f2, f3)
+// One block per cell of a level: W[cell][9][P^3] (real, zero-padded to n^3,
+// n = 2P - 1) -> What[f][cell][9], f = (f1 n + f2) P + f3, the half spectrum
+// in the last axis (the input is real).  Three passes of length-P to
+// length-n (or P) DFTs through LDS, G components at a time; the twiddles
+// exp(-2 pi i f m / n), f < n, m < P, are tabulated once per block.
+template <typename T, int P>
+__global__ void k_fdft(const T* W, int64_t ncell, int G, const T* twg, cplx<T>* What) {
+  constexpr int n = 2 * P - 1, p3 = P * P * P, nf = n * n * P;
+  extern __shared__ __align__(16) unsigned char shraw[];
+  cplx<T>* tm = (cplx<T>*)shraw;  // [n][P]
+  cplx<T>* X1 = tm + n * P;       // [G][P][P][P]  (m1, m2, f3)
+  T* Wl = (T*)(X1 + G * p3);      // [G][P^3]; the same space then holds
+  cplx<T>* X2 = (cplx<T>*)Wl;     // [G][P][n][P]  (m1, f2, f3)
   const int64_t cell = blockIdx.x;
-  for (int e = threadIdx.x; e < n; e += blockDim.x) tw[e] = cplx<T>{twg[2 * e], twg[2 * e + 1]};
+  for (int e = threadIdx.x; e < n * P; e += blockDim.x) {
+    const int k = ((e / P) * (e % P)) % n;
+    tm[e] = cplx<T>{twg[2 * k], twg[2 * k + 1]};
+  }
   for (int c0 = 0; c0 < 9; c0 += G) {
     const T* src = W + (cell * 9 + c0) * p3;
     for (int e = threadIdx.x; e < G * p3; e += blockDim.x) Wl[e] = src[e];
     __syncthreads();
     for (int e = threadIdx.x; e < G * p3; e += blockDim.x) {
-      int f3 = e % p, rest = e / p;  // rest = (g, m1, m2)
-      const T* row = Wl + rest * p;
+      const int f3 = e % P;
+      const T* row = Wl + (e / P) * P;
+      const cplx<T>* t = tm + f3 * P;
       T re = 0, im = 0;
-      for (int m = 0; m < p; ++m) {
-        cplx<T> w = tw[(f3 * m) % n];
-        re += row[m] * w.re;
-        im += row[m] * w.im;
+#pragma unroll
+      for (int m = 0; m < P; ++m) {
+        re = fma(row[m], t[m].re, re);
+        im = fma(row[m], t[m].im, im);
       }
       X1[e] = cplx<T>{re, im};
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < G * p * n * p; e += blockDim.x) {
-      int f3 = e % p, f2 = (e / p) % n, gm1 = e / (p * n);
+    for (int e = threadIdx.x; e < G * P * n * P; e += blockDim.x) {
+      const int f3 = e % P, f2 = (e / P) % n, gm1 = e / (P * n);
+      const cplx<T>* x = X1 + gm1 * P * P + f3;
+      const cplx<T>* t = tm + f2 * P;
       T re = 0, im = 0;
-      for (int m = 0; m < p; ++m) {
-        cplx<T> x = X1[(gm1 * p + m) * p + f3];
-        cplx<T> w = tw[(f2 * m) % n];
-        re += x.re * w.re - x.im * w.im;
-        im += x.re * w.im + x.im * w.re;
+#pragma unroll
+      for (int m = 0; m < P; ++m) {
+        const cplx<T> a = x[m * P], w = t[m];
+        re = fma(a.re, w.re, fma(-a.im, w.im, re));
+        im = fma(a.re, w.im, fma(a.im, w.re, im));
       }
       X2[e] = cplx<T>{re, im};
     }
     __syncthreads();
     for (int e = threadIdx.x; e < nf * G; e += blockDim.x) {
-      int g = e % G, f = e / G;
-      int f3 = f % p, f2 = (f / p) % n, f1 = f / (p * n);
+      const int g = e % G, f = e / G;
+      const int f3 = f % P, f2 = (f / P) % n, f1 = f / (P * n);
+      const cplx<T>* x = X2 + (g * P * n + f2) * P + f3;
+      const cplx<T>* t = tm + f1 * P;
       T re = 0, im = 0;
-      for (int m = 0; m < p; ++m) {
-        cplx<T> x = X2[((g * p + m) * n + f2) * p + f3];
-        cplx<T> w = tw[(f1 * m) % n];
-        re += x.re * w.re - x.im * w.im;
-        im += x.re * w.im + x.im * w.re;
+#pragma unroll
+      for (int m = 0; m < P; ++m) {
+        const cplx<T> a = x[m * n * P], w = t[m];
+        re = fma(a.re, w.re, fma(-a.im, w.im, re));
+        im = fma(a.re, w.im, fma(a.im, w.re, im));
       }
       What[((int64_t)f * ncell + cell) * 9 + c0 + g] = cplx<T>{re, im};
     }
     __syncthreads();
   }
+}
+
+template <int P>
+constexpr size_t lds_fdft_t(int G, size_t es) {
+  return 2 * es * (2 * P - 1) * P + 2 * es * G * P * P * P +
+         (2 * es * G * P * (2 * P - 1) * P > es * G * P * P * P ? 2 * es * G * P * (2 * P - 1) * P
+                                                                 : es * G * P * P * P);
 }
 
 // ------------------------------------------------------ Hadamard product
@@ -352,73 +371,95 @@ __global__ void __launch_bounds__(kHadThreads) k_hadamard(const cplx<T>* What, c
 }
 
 // ------------------------------------------------------------ inverse DFT
-// One block per cell: Shat[cell][f][6] -> s[cell][6][p^3] (overwrites), using
-// the Hermitian symmetry of the spectrum of a real circular convolution.
-template <typename T>
-__global__ void k_idft(const cplx<T>* Shat, int64_t ncell, int p, int G, const T* twg, T* s) {
-  extern __shared__ unsigned char shraw[];
-  const int n = 2 * p - 1, p3 = p * p * p, nf = n * n * p;
-  cplx<T>* tw = (cplx<T>*)shraw;  // conj twiddles exp(+2 pi i k/n)
-  cplx<T>* Sl = tw + n;           // [G][nf]
-  cplx<T>* Y1 = Sl + G * nf;      // [G][n(f2)][p(f3)][p(l1)]
-  cplx<T>* Y2 = Y1 + G * n * p * p;  // [G][p(f3)][p(l1)][p(l2)]
+// One block per cell: Shat[cell][f][6] -> s[cell][6][P^3] (overwrites): the
+// inverse transform of the half spectrum of a real circular convolution, of
+// which only the outputs l < P are needed (the rest is the wrap-around of the
+// embedding).  Twiddles exp(+2 pi i f l / n), f < n, l < P, in LDS.
+template <typename T, int P>
+__global__ void k_idft(const cplx<T>* Shat, int64_t ncell, int G, const T* twg, T* s) {
+  constexpr int n = 2 * P - 1, p3 = P * P * P, nf = n * n * P;
+  extern __shared__ __align__(16) unsigned char shraw[];
+  cplx<T>* tm = (cplx<T>*)shraw;  // [n][P]
+  cplx<T>* Y1 = tm + n * P;       // [G][n(f2)][P(f3)][P(l1)]
+  cplx<T>* Sl = Y1 + G * n * P * P;  // [G][nf]; the same space then holds
+  cplx<T>* Y2 = Sl;                  // [G][P(f3)][P(l1)][P(l2)]
   const int64_t cell = blockIdx.x;
-  for (int e = threadIdx.x; e < n; e += blockDim.x) tw[e] = cplx<T>{twg[2 * e], -twg[2 * e + 1]};
+  for (int e = threadIdx.x; e < n * P; e += blockDim.x) {
+    const int k = ((e / P) * (e % P)) % n;
+    tm[e] = cplx<T>{twg[2 * k], -twg[2 * k + 1]};
+  }
   const T scale = T(1) / T(n * n * n);
   for (int c0 = 0; c0 < 6; c0 += G) {
     const cplx<T>* src = Shat + cell * nf * 6;
     for (int e = threadIdx.x; e < G * nf; e += blockDim.x) {
-      int g = e % G, f = e / G;
+      const int g = e % G, f = e / G;
       Sl[g * nf + f] = src[f * 6 + c0 + g];
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < G * n * p * p; e += blockDim.x) {
-      int l1 = e % p, f3 = (e / p) % p, f2 = (e / (p * p)) % n, g = e / (p * p * n);
+    for (int e = threadIdx.x; e < G * n * P * P; e += blockDim.x) {
+      const int l1 = e % P, f3 = (e / P) % P, f2 = (e / (P * P)) % n, g = e / (P * P * n);
+      const cplx<T>* x = Sl + g * nf + f2 * P + f3;
       T re = 0, im = 0;
+#pragma unroll
       for (int f1 = 0; f1 < n; ++f1) {
-        cplx<T> x = Sl[g * nf + (f1 * n + f2) * p + f3];
-        cplx<T> w = tw[(f1 * l1) % n];
-        re += x.re * w.re - x.im * w.im;
-        im += x.re * w.im + x.im * w.re;
+        const cplx<T> a = x[f1 * n * P], w = tm[f1 * P + l1];
+        re = fma(a.re, w.re, fma(-a.im, w.im, re));
+        im = fma(a.re, w.im, fma(a.im, w.re, im));
       }
       Y1[e] = cplx<T>{re, im};
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < G * p * p * p; e += blockDim.x) {
-      int l2 = e % p, l1 = (e / p) % p, f3 = (e / (p * p)) % p, g = e / p3;
+    for (int e = threadIdx.x; e < G * p3; e += blockDim.x) {
+      const int l2 = e % P, l1 = (e / P) % P, f3 = (e / (P * P)) % P, g = e / p3;
+      const cplx<T>* x = Y1 + (g * n * P + f3) * P + l1;
       T re = 0, im = 0;
+#pragma unroll
       for (int f2 = 0; f2 < n; ++f2) {
-        cplx<T> x = Y1[((g * n + f2) * p + f3) * p + l1];
-        cplx<T> w = tw[(f2 * l2) % n];
-        re += x.re * w.re - x.im * w.im;
-        im += x.re * w.im + x.im * w.re;
+        const cplx<T> a = x[f2 * P * P], w = tm[f2 * P + l2];
+        re = fma(a.re, w.re, fma(-a.im, w.im, re));
+        im = fma(a.re, w.im, fma(a.im, w.re, im));
       }
       Y2[e] = cplx<T>{re, im};
     }
     __syncthreads();
     for (int e = threadIdx.x; e < G * p3; e += blockDim.x) {
-      int l3 = e % p, l2 = (e / p) % p, l1 = (e / (p * p)) % p, g = e / p3;
-      T re = 0;
-      for (int f3 = 0; f3 < p; ++f3) {
-        cplx<T> x = Y2[((g * p + f3) * p + l1) * p + l2];
-        cplx<T> w = tw[(f3 * l3) % n];
-        T v = x.re * w.re - x.im * w.im;
-        re += (f3 == 0 ? T(1) : T(2)) * v;
+      const int l3 = e % P, l2 = (e / P) % P, l1 = (e / (P * P)) % P, g = e / p3;
+      const cplx<T>* x = Y2 + (g * P * P + l1) * P + l2;
+      // Hermitian symmetry in the last axis: f3 = 0 once, f3 > 0 twice (real part)
+      T re = x[0].re * tm[l3].re - x[0].im * tm[l3].im;
+      T acc = 0;
+#pragma unroll
+      for (int f3 = 1; f3 < P; ++f3) {
+        const cplx<T> a = x[f3 * P * P], w = tm[f3 * P + l3];
+        acc = fma(a.re, w.re, fma(-a.im, w.im, acc));
       }
-      s[(cell * 6 + c0 + g) * p3 + (l1 * p + l2) * p + l3] = re * scale;
+      s[(cell * 6 + c0 + g) * p3 + (l1 * P + l2) * P + l3] = (re + T(2) * acc) * scale;
     }
     __syncthreads();
   }
 }
 
+template <int P>
+constexpr size_t lds_idft_t(int G, size_t es) {
+  return 2 * es * ((2 * P - 1) * P + (size_t)G * (2 * P - 1) * P * P + (size_t)G * (2 * P - 1) * (2 * P - 1) * P);
+}
+
 // ------------------------------------------------ near field + L2P (leaf)
-// One wave per leaf.  With nt <= 64 targets, S = 64/nt (rounded down to a
+// Near field.  One wave per leaf.  With nt <= 64 targets, S = 64/nt (rounded down to a
 // power of two) lanes share a target and split its sources; partial sums are
 // combined with xor shuffles.  In MIXED precision pairs are evaluated in float
 // (displacements formed in double) with compensated float accumulation, and
-// pairs closer than 2a in double.
+// pairs closer than 2a are left to k_close (double precision, run after this
+// kernel), which keeps double-precision code and its registers out of here.
+// Single precision: ask for 3 waves per SIMD (the register budget that the
+// pair evaluation fits without spilling); double precision: no constraint.
+template <typename T>
+constexpr int leaf_min_waves() {
+  return std::is_same<T, float>::value ? 3 : 1;
+}
+
 template <typename T, bool MIXED, bool ISO, bool SUR>
-__global__ void __launch_bounds__(64) k_leaf(const double* pts, int64_t N, const int* first, const int* count,
+__global__ void __launch_bounds__(64, leaf_min_waves<T>()) k_leaf(const double* pts, int64_t N, const int* first, const int* count,
                                              const uint32_t* key, const int* nbr, const T* s, double lo0,
                                              double lo1, double lo2, double sD, int p, Med<T> m, Med<double> m64,
                                              SurDev sd, double* sig) {
@@ -426,18 +467,12 @@ __global__ void __launch_bounds__(64) k_leaf(const double* pts, int64_t N, const
   const int leaf = blockIdx.x, lane = threadIdx.x;
   const int t0 = first[leaf], nt = count[leaf];
   __shared__ int nb_first[27], nb_cnt[27];
-  constexpr int kCloseCap = 24;
-  __shared__ int close_buf[MIXED ? kCloseCap * 64 : 1];
   if (lane < 27) {
     int j = nbr[(int64_t)leaf * 27 + lane];
     nb_first[lane] = j >= 0 ? first[j] : 0;
     nb_cnt[lane] = j >= 0 ? count[j] : 0;
   }
   __syncthreads();
-  double lo[3];
-  cell_lo(key[leaf], lo0, lo1, lo2, sD, lo);
-  const int p3 = p * p * p;
-  const T* sl = s + (int64_t)leaf * 6 * p3;
   const double a2x4 = 4.0 * m64.a * m64.a;
   // Passes over the leaf's targets: 64 at a time with one lane each, then the
   // remainder in power-of-two chunks c with S = 64/c lanes per target, so
@@ -452,11 +487,9 @@ __global__ void __launch_bounds__(64) k_leaf(const double* pts, int64_t N, const
     const int64_t i = t0 + (act ? ti : 0);
     const double xt0 = pts[i], xt1 = pts[N + i], xt2 = pts[2 * N + i];
     T acc[6], cmp[6];
-    double acc64[6];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) acc[c] = cmp[c] = T(0), acc64[c] = 0.0;
+    for (int c = 0; c < 6; ++c) acc[c] = cmp[c] = T(0);
     int base = 0;
-    int nclose = 0;
     for (int q = 0; q < 27; ++q) {
       const int fj = nb_first[q], cj = nb_cnt[q];
       if (act) {
@@ -465,16 +498,7 @@ __global__ void __launch_bounds__(64) k_leaf(const double* pts, int64_t N, const
           const int64_t j = fj + jj;
           double d0 = xt0 - pts[j], d1 = xt1 - pts[N + j], d2 = xt2 - pts[2 * N + j];
           if (MIXED && d0 * d0 + d1 * d1 + d2 * d2 < a2x4) {
-            // nearly coincident pair: deferred to the double-precision pass below
-            if (nclose < kCloseCap) {
-              close_buf[nclose * 64 + lane] = (int)j;
-              ++nclose;
-            } else {
-              double D[27], b[3], tt[3];
-              for (int c = 0; c < 3; ++c) b[c] = pts[(3 + c) * N + j], tt[c] = pts[(6 + c) * N + j];
-              dg_medium_t<double, ISO>(d0, d1, d2, m64, D);
-              contract_b_t<double>(D, m64.c12, m64.c44, m64.hh, b, tt, acc64);
-            }
+            // nearly coincident pair: evaluated by k_close
           } else {
             T D[27], b[3], tt[3];
             for (int c = 0; c < 3; ++c) b[c] = (T)pts[(3 + c) * N + j], tt[c] = (T)pts[(6 + c) * N + j];
@@ -516,44 +540,103 @@ __global__ void __launch_bounds__(64) k_leaf(const double* pts, int64_t N, const
       }
       base += cj;
     }
-    if (MIXED) {
-      // double-precision pass over the deferred pairs (few per lane)
-      for (int k = 0; k < nclose; ++k) {
-        const int64_t j = close_buf[k * 64 + lane];
-        double d0 = xt0 - pts[j], d1 = xt1 - pts[N + j], d2 = xt2 - pts[2 * N + j];
-        double D[27], b[3], tt[3];
-        for (int c = 0; c < 3; ++c) b[c] = pts[(3 + c) * N + j], tt[c] = pts[(6 + c) * N + j];
-        dg_medium_t<double, ISO>(d0, d1, d2, m64, D);
-        contract_b_t<double>(D, m64.c12, m64.c44, m64.hh, b, tt, acc64);
-      }
-    }
     double tot[6];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) tot[c] = (double)acc[c] - (double)cmp[c] + acc64[c];
+    for (int c = 0; c < 6; ++c) tot[c] = (double)acc[c] - (double)cmp[c];
     for (int o = S / 2; o >= 1; o >>= 1)
 #pragma unroll
       for (int c = 0; c < 6; ++c) tot[c] += __shfl_xor(tot[c], o, 64);
     if (act && slice == 0) {
-      // L2P: far-field stress at the point by interpolation of the leaf's local values
-      T t[3] = {(T)((xt0 - lo[0]) / sD), (T)((xt1 - lo[1]) / sD), (T)((xt2 - lo[2]) / sD)};
-      T L[3][kMaxOrder];
-      for (int d = 0; d < 3; ++d)
-        for (int k = 0; k < p; ++k) L[d][k] = lagr<T>(p, k, t[d]);
-      T far[6] = {0, 0, 0, 0, 0, 0};
-      for (int l1 = 0; l1 < p; ++l1)
-        for (int l2 = 0; l2 < p; ++l2) {
-          T w12 = L[0][l1] * L[1][l2];
-          for (int l3 = 0; l3 < p; ++l3) {
-            T w = w12 * L[2][l3];
-            int node = (l1 * p + l2) * p + l3;
 #pragma unroll
-            for (int c = 0; c < 6; ++c) far[c] += w * sl[c * p3 + node];
-          }
-        }
-#pragma unroll
-      for (int c = 0; c < 6; ++c) sig[i * 6 + c] = tot[c] + (double)far[c];
+      for (int c = 0; c < 6; ++c) sig[i * 6 + c] = tot[c];
     }
   }
+}
+
+// Pairs of a leaf's targets with sources closer than 2a (the near-coincident
+// pairs that the single-precision near field skips), in double precision.
+// Same wave-per-leaf layout and lane split as k_leaf, so every target sums its
+// pairs in a fixed order; the sum is added to the stress k_leaf wrote.
+template <bool ISO>
+__global__ void __launch_bounds__(64) k_close(const double* pts, int64_t N, const int* first, const int* count,
+                                              const int* nbr, Med<double> m64, double* sig) {
+  const int leaf = blockIdx.x, lane = threadIdx.x;
+  const int t0 = first[leaf], nt = count[leaf];
+  __shared__ int nb_first[27], nb_cnt[27];
+  if (lane < 27) {
+    int j = nbr[(int64_t)leaf * 27 + lane];
+    nb_first[lane] = j >= 0 ? first[j] : 0;
+    nb_cnt[lane] = j >= 0 ? count[j] : 0;
+  }
+  __syncthreads();
+  const double a2x4 = 4.0 * m64.a * m64.a;
+  for (int c0 = 0, per = 64; c0 < nt; c0 += per) {
+    const int rem = nt - c0;
+    per = 64;
+    while (per > rem) per >>= 1;
+    const int S = 64 / per;
+    const int ti = c0 + lane / S, slice = lane % S;
+    const bool act = ti < nt;
+    const int64_t i = t0 + (act ? ti : 0);
+    const double xt0 = pts[i], xt1 = pts[N + i], xt2 = pts[2 * N + i];
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    int base = 0;
+    for (int q = 0; q < 27; ++q) {
+      const int fj = nb_first[q], cj = nb_cnt[q];
+      if (act) {
+        for (int jj = (slice - (base % S) + S) % S; jj < cj; jj += S) {
+          const int64_t j = fj + jj;
+          const double d0 = xt0 - pts[j], d1 = xt1 - pts[N + j], d2 = xt2 - pts[2 * N + j];
+          if (d0 * d0 + d1 * d1 + d2 * d2 < a2x4) {
+            double D[27], b[3], tt[3];
+            for (int c = 0; c < 3; ++c) b[c] = pts[(3 + c) * N + j], tt[c] = pts[(6 + c) * N + j];
+            dg_medium_t<double, ISO>(d0, d1, d2, m64, D);
+            contract_b_t<double>(D, m64.c12, m64.c44, m64.hh, b, tt, acc);
+          }
+        }
+      }
+      base += cj;
+    }
+    for (int o = S / 2; o >= 1; o >>= 1)
+#pragma unroll
+      for (int c = 0; c < 6; ++c) acc[c] += __shfl_xor(acc[c], o, 64);
+    if (act && slice == 0) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) sig[i * 6 + c] += acc[c];
+    }
+  }
+}
+
+// L2P: far-field stress at each point by interpolation of its leaf's local
+// values (Lagrange basis on the leaf's equispaced nodes), added to the near
+// field already in sig.  One thread per point.
+template <typename T>
+__global__ void k_l2p(const double* pts, int64_t N, const int* pleaf, const uint32_t* key, const T* s, double lo0,
+                      double lo1, double lo2, double sD, int p, double* sig) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int leaf = pleaf[i];
+  double lo[3];
+  cell_lo(key[leaf], lo0, lo1, lo2, sD, lo);
+  const int p3 = p * p * p;
+  const T* sl = s + (int64_t)leaf * 6 * p3;
+  const T t[3] = {(T)((pts[i] - lo[0]) / sD), (T)((pts[N + i] - lo[1]) / sD), (T)((pts[2 * N + i] - lo[2]) / sD)};
+  T L[3][kMaxOrder];
+  for (int d = 0; d < 3; ++d)
+    for (int k = 0; k < p; ++k) L[d][k] = lagr<T>(p, k, t[d]);
+  T far[6] = {0, 0, 0, 0, 0, 0};
+  for (int l1 = 0; l1 < p; ++l1)
+    for (int l2 = 0; l2 < p; ++l2) {
+      const T w12 = L[0][l1] * L[1][l2];
+      for (int l3 = 0; l3 < p; ++l3) {
+        const T w = w12 * L[2][l3];
+        const int node = (l1 * p + l2) * p + l3;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) far[c] = fma(w, sl[c * p3 + node], far[c]);
+      }
+    }
+#pragma unroll
+  for (int c = 0; c < 6; ++c) sig[i * 6 + c] += (double)far[c];
 }
 
 // ---------------------------------------------------------------- forces
@@ -676,13 +759,50 @@ __global__ void k_direct_reduce(const double* part, int64_t ntp, int nchunk, dou
 }
 
 // ------------------------------------------------------------ host side
-static size_t lds_fdft(int p, int G, size_t es) {
-  int n = 2 * p - 1, p3 = p * p * p;
-  return 2 * es * n + es * (G * p3 + 1) + 2 * es * (size_t)G * p3 + 2 * es * (size_t)G * p * n * p;
+// DFT launches, specialised on the interpolation order.  Components per
+// round: as many as fit 80 KB of LDS (forward) or 64 KB (inverse).
+template <typename T, int P>
+static int dft_groups(bool fwd) {
+  const size_t es = sizeof(T);
+  if (fwd) {
+    for (int G : {9, 3, 1})
+      if (lds_fdft_t<P>(G, es) <= 80 * 1024) return G;
+  } else {
+    for (int G : {6, 3, 2, 1})
+      if (lds_idft_t<P>(G, es) <= 64 * 1024) return G;
+  }
+  return 1;
 }
-static size_t lds_idft(int p, int G, size_t es) {
-  int n = 2 * p - 1;
-  return 2 * es * ((size_t)n + (size_t)G * n * n * p + (size_t)G * n * p * p + (size_t)G * p * p * p);
+
+template <typename T, int P>
+static void dft_launch(bool fwd, unsigned blocks, const void* in, int64_t ncell, const T* tw, void* out,
+                       hipStream_t st) {
+  const int G = dft_groups<T, P>(fwd);
+  if (fwd)
+    k_fdft<T, P><<<blocks, 256, lds_fdft_t<P>(G, sizeof(T)), st>>>((const T*)in, ncell, G, tw, (cplx<T>*)out);
+  else
+    k_idft<T, P><<<blocks, 256, lds_idft_t<P>(G, sizeof(T)), st>>>((const cplx<T>*)in, ncell, G, tw, (T*)out);
+}
+
+template <typename T>
+static void dft(int p, bool fwd, unsigned blocks, const void* in, int64_t ncell, const T* tw, void* out,
+                hipStream_t st) {
+  switch (p) {
+    case 2: dft_launch<T, 2>(fwd, blocks, in, ncell, tw, out, st); break;
+    case 3: dft_launch<T, 3>(fwd, blocks, in, ncell, tw, out, st); break;
+    case 4: dft_launch<T, 4>(fwd, blocks, in, ncell, tw, out, st); break;
+    case 5: dft_launch<T, 5>(fwd, blocks, in, ncell, tw, out, st); break;
+    case 6: dft_launch<T, 6>(fwd, blocks, in, ncell, tw, out, st); break;
+    case 7: dft_launch<T, 7>(fwd, blocks, in, ncell, tw, out, st); break;
+    default: dft_launch<T, 8>(fwd, blocks, in, ncell, tw, out, st); break;
+  }
+}
+
+template <typename T, int... Ps>
+static void dft_lds_attrs(std::integer_sequence<int, Ps...>) {
+  const int mx = 160 * 1024;
+  ((void)hipFuncSetAttribute((const void*)k_fdft<T, Ps + 2>, hipFuncAttributeMaxDynamicSharedMemorySize, mx), ...);
+  ((void)hipFuncSetAttribute((const void*)k_idft<T, Ps + 2>, hipFuncAttributeMaxDynamicSharedMemorySize, mx), ...);
 }
 
 struct StageTimer {
@@ -762,23 +882,17 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
                                                             W + Lp.off * 9 * p3, tb.S, p)));
     }
   }
-  int Gf = 9;
-  while (Gf > 1 && lds_fdft(p, Gf, es) > 64 * 1024) Gf = (Gf == 9) ? 3 : 1;
-  int Gi = 6;
-  while (Gi > 1 && lds_idft(p, Gi, es) > 64 * 1024) Gi = (Gi == 6) ? 3 : (Gi == 3 ? 2 : 1);
   const size_t shm_h = sizeof(cplx<T>) * kNumCanon * kKStride;
   for (int l = 2; l <= D; ++l) {
     const auto& Lv = t->lv[l];
     if (Lv.n == 0) continue;
-    STAGE(2, (k_fdft<T><<<(unsigned)Lv.n, 256, lds_fdft(p, Gf, es), st>>>(W + Lv.off * 9 * p3, Lv.n, p, Gf,
-                                                                         tb.tw, What)));
+    STAGE(2, dft<T>(p, true, (unsigned)Lv.n, W + Lv.off * 9 * p3, Lv.n, tb.tw, What, st));
     const int nwin = (int)((Lv.n + kM2LWindow - 1) / kM2LWindow);
     const int remap = nwin >= 16;
     dim3 g(remap ? 8 * ((nwin + 7) / 8) : nwin, nf);
     STAGE(3, (k_hadamard<T><<<g, kHadThreads, shm_h, st>>>(What, (const cplx<T>*)pl->lev[l].khat, Lv.il_start,
                                                            Lv.il, Lv.order, Lv.n, nf, nwin, remap, Shat)));
-    STAGE(4, (k_idft<T><<<(unsigned)Lv.n, 256, lds_idft(p, Gi, es), st>>>(Shat, Lv.n, p, Gi, tb.tw,
-                                                                        s + Lv.off * 6 * p3)));
+    STAGE(4, dft<T>(p, false, (unsigned)Lv.n, Shat, Lv.n, tb.tw, s + Lv.off * 6 * p3, st));
   }
   {
     size_t shm = es * (12 * p3 + 2 * p * p);
@@ -809,6 +923,12 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
     else
       STAGE(6, (k_leaf<T, false, false, false><<<(unsigned)LD.n, 64, 0, st>>>(LEAF_ARGS)));
 #undef LEAF_ARGS
+    if (mixed && pl->iso)
+      STAGE(6, (k_close<true><<<(unsigned)LD.n, 64, 0, st>>>(t->pts, N, LD.first, LD.count, t->nbr, m64, t->sig)));
+    else if (mixed)
+      STAGE(6, (k_close<false><<<(unsigned)LD.n, 64, 0, st>>>(t->pts, N, LD.first, LD.count, t->nbr, m64, t->sig)));
+    STAGE(6, (k_l2p<T><<<nblk(N, 256), 256, 0, st>>>(t->pts, N, t->pleaf, LD.key, s + LD.off * 6 * p3, lo[0], lo[1],
+                                                     lo[2], sD, p, t->sig)));
   }
   STAGE(7, (k_forces<<<nblk(t->nseg, 128), 128, 0, st>>>(seg, burg, nullptr, t->inv, t->sig, pl->quad,
                                                           t->nseg, forces)));
@@ -824,8 +944,7 @@ static void set_lds_attrs() {
   done = true;
   const int mx = 160 * 1024;
   hipFuncSetAttribute((const void*)k_hadamard<T>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-  hipFuncSetAttribute((const void*)k_fdft<T>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-  hipFuncSetAttribute((const void*)k_idft<T>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+  dft_lds_attrs<T>(std::make_integer_sequence<int, kMaxOrder - 1>{});
   hipFuncSetAttribute((const void*)k_m2m<T>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
   hipFuncSetAttribute((const void*)k_l2l<T>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
   hipFuncSetAttribute((const void*)k_p2m<T>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);

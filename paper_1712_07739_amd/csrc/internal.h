@@ -104,6 +104,7 @@ struct dfmm_tree {
   std::vector<Level> lv;
   int64_t ncell_total = 0, max_level_cells = 0;
   int* nbr = nullptr;            // leaves: [n][27] neighbour leaf index or -1
+  int* pleaf = nullptr;          // [N] leaf of each sorted point
   int64_t npairs = 0;            // M2L pairs over all levels
   int64_t near_pairs = 0;        // point pairs in the near field
   int max_leaf_pts = 0;

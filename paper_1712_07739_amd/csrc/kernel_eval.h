@@ -100,6 +100,7 @@ __device__ __forceinline__ void dg_circle_acc(T x0, T x1, T x2, const Med<T>& m,
   T acc[18];
 #pragma unroll
   for (int i = 0; i < 18; ++i) acc[i] = T(0);
+#pragma unroll 1
   for (int k = 0; k < m.nhalf; ++k) {
     T co = m.cs[2 * k], si = m.cs[2 * k + 1];
     T z[3] = {co * e1[0] + si * e2[0], co * e1[1] + si * e2[1], co * e1[2] + si * e2[2]};
@@ -151,16 +152,19 @@ template <typename T>
 __device__ __forceinline__ void dg_medium(T x0, T x1, T x2, const Med<T>& m, T* D) {
 #pragma unroll
   for (int i = 0; i < 27; ++i) D[i] = T(0);
-  dg_iso_acc(x0, x1, x2, m.mu, m.nu, m.a, T(1), D);
+  // the circle rule first, while D is still zero (keeps D out of the
+  // registers live across the angle loop), then the closed-form terms
+  T damp = T(0);
   if (!m.iso) {
     T r2 = x0 * x0 + x1 * x1 + x2 * x2;
     if (r2 > T(0)) {
       T q = r2 / (r2 + m.a * m.a);
-      T damp = q * sqrt(q);
+      damp = q * sqrt(q);
       dg_circle_acc(x0, x1, x2, m, damp, D);
-      dg_iso_acc(x0, x1, x2, m.mu, m.nu, T(0), -damp, D);
     }
   }
+  dg_iso_acc(x0, x1, x2, m.mu, m.nu, m.a, T(1), D);
+  if (damp != T(0)) dg_iso_acc(x0, x1, x2, m.mu, m.nu, T(0), -damp, D);
 }
 
 // dg_medium with the isotropic/anisotropic branch fixed at compile time.

@@ -283,6 +283,12 @@ __global__ void k_inverse_perm(const uint32_t* perm, int64_t n, uint32_t* inv) {
   if (i < n) inv[perm[i]] = (uint32_t)i;
 }
 
+__global__ void k_point_leaf(const int* first, const int* count, int nleaf, int* pleaf) {
+  const int leaf = blockIdx.x;
+  if (leaf >= nleaf) return;
+  for (int k = threadIdx.x; k < count[leaf]; k += blockDim.x) pleaf[first[leaf] + k] = leaf;
+}
+
 // ---------------------------------------------------------------- lists
 __global__ void k_leaf_nbrs(const uint32_t* keys, int nc, int lvl, int* nbr) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -337,11 +343,21 @@ __global__ void k_ilist(const uint32_t* keys, int nc, int lvl, const int* oid343
 }
 
 // M2L processing order: windows of kM2LWindow Morton-consecutive targets (one
-// block each, spatially compact), longest lists first inside a window.
-__global__ void k_len_keys(const int* il_start, int n, uint32_t* key, uint32_t* val) {
+// block each, spatially compact), longest lists first inside a window.  The
+// length that orders a target is the longest list among its siblings, so that
+// siblings (which draw on the same source cells, in the same lexicographic
+// order) stay next to each other in a wave.
+__global__ void k_sib_len(const int* il_start, const int* parent, int n, int* pmax) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  int len = il_start[i + 1] - il_start[i];
+  atomicMax(&pmax[parent[i]], il_start[i + 1] - il_start[i]);
+}
+
+__global__ void k_len_keys(const int* il_start, const int* parent, const int* pmax, int n, uint32_t* key,
+                           uint32_t* val) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int len = parent ? pmax[parent[i]] : il_start[i + 1] - il_start[i];
   key[i] = ((uint32_t)(i / kM2LWindow) << 8) | (uint32_t)(kNumFar - min(len, kNumFar));
   val[i] = (uint32_t)i;
 }
@@ -456,11 +472,19 @@ int build_tree_impl(dfmm_plan* pl, const double* seg, int64_t nseg, hipStream_t 
     // processing order of the M2L targets: similar list lengths share a wave
     uint32_t* okey = (uint32_t*)cnt;
     DFMM_HIP(hipMalloc(&L.order, sizeof(uint32_t) * L.n));
-    k_len_keys<<<nb(L.n, 256), 256, 0, st>>>(L.il_start, (int)L.n, okey, L.order);
+    int* pmax = nullptr;
+    if (l > 2) {
+      DFMM_HIP(hipMalloc(&pmax, sizeof(int) * t->lv[l - 1].n));
+      DFMM_HIP(hipMemsetAsync(pmax, 0, sizeof(int) * t->lv[l - 1].n, st));
+      k_sib_len<<<nb(L.n, 256), 256, 0, st>>>(L.il_start, L.parent, (int)L.n, pmax);
+      DFMM_LAUNCH_CHECK();
+    }
+    k_len_keys<<<nb(L.n, 256), 256, 0, st>>>(L.il_start, pmax ? L.parent : nullptr, pmax, (int)L.n, okey, L.order);
     DFMM_LAUNCH_CHECK();
     int wbits = 0;
     while (((L.n + kM2LWindow - 1) / kM2LWindow) >> wbits) ++wbits;
     rc = radix_sort(okey, L.order, L.n, 8 + wbits, st);
+    hipFree(pmax);
     if (rc) return rc;
     hipFree(cnt);
   }
@@ -492,12 +516,15 @@ int build_tree_impl(dfmm_plan* pl, const double* seg, int64_t nseg, hipStream_t 
   size_t bWh = es * 2 * 9 * (size_t)pl->nf * t->max_level_cells;
   size_t bSh = es * 2 * 6 * (size_t)pl->nf * t->max_level_cells;
   DFMM_HIP(hipMalloc(&t->pts, sizeof(double) * 9 * N));
+  DFMM_HIP(hipMalloc(&t->pleaf, sizeof(int) * N));
+  k_point_leaf<<<(unsigned)LD.n, 64, 0, st>>>(LD.first, LD.count, (int)LD.n, t->pleaf);
+  DFMM_LAUNCH_CHECK();
   DFMM_HIP(hipMalloc(&t->W, bW));
   DFMM_HIP(hipMalloc(&t->s, bS));
   DFMM_HIP(hipMalloc(&t->What, bWh));
   DFMM_HIP(hipMalloc(&t->Shat, bSh));
   DFMM_HIP(hipMalloc(&t->sig, sizeof(double) * 6 * N));
-  t->bytes = sizeof(double) * 15 * N + bW + bS + bWh + bSh;
+  t->bytes = sizeof(double) * 15 * N + sizeof(int) * N + bW + bS + bWh + bSh;
   DFMM_HIP(hipStreamSynchronize(st));
   return DFMM_OK;
 }

@@ -52,15 +52,37 @@ def test_batched_graph_equals_individual_calls_on_every_replay(env):
     batch.close()
 
 
+def _measured_ms(pk, torch, prm_args, d, ts, tb, reps=3):
+    import time
+
+    plan = pk.Plan(pk.make_params(*prm_args[:1], d, *prm_args[1:], precision=1))
+    tree = pk.Tree(plan, ts)
+    out = torch.empty((ts.shape[0], 2, 3), dtype=torch.float64, device=ts.device)
+    pk.fmm_forces(plan, tree, ts, tb, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        pk.fmm_forces(plan, tree, ts, tb, out=out)
+    torch.cuda.synchronize()
+    return 1e3 * (time.perf_counter() - t0) / reps
+
+
 def test_depth_autotuner(env):
+    """App. B model: the prediction's minimum is the model's pick; the returned
+    depth (the fastest of the timed candidates) is within 25% of the fastest
+    depth measured independently over the whole range."""
     torch, pk, dev = env
-    best = {}
     for nl in (40, 800):
         seg, b = synth.make_loops(nl, 0.01, 0.05, 77)
+        ts, tb = torch.tensor(seg, device=dev), torch.tensor(b, device=dev)
         prm = pk.make_params(5, 4, *ISO, 1e-3, BOX_LO, BOX, precision=1)
-        d, pred = pk.autotune_depth(prm, torch.tensor(seg, device=dev), torch.tensor(b, device=dev), 2, 6)
-        print("segments %d: depth %d, predicted ms %s" % (nl * 40, d, {k: round(v, 3) for k, v in pred.items()}))
+        d, pred, meas = pk.autotune_depth(prm, ts, tb, 2, 6)
+        print("segments %d: depth %d, predicted ms %s, measured ms %s" % (
+            nl * 40, d, {k: round(v, 3) for k, v in pred.items()}, {k: round(v, 3) for k, v in meas.items()}))
         assert 2 <= d <= 6 and all(v > 0 for v in pred.values())
-        assert pred[d] == min(pred.values())
-        best[nl] = d
-    assert best[800] >= best[40]  # more segments, finer leaves (App. B: N_c grows with N_s)
+        pick = min(pred, key=pred.get)
+        assert set(meas) <= {pick - 1, pick, pick + 1} and pick in meas and d in meas
+        assert meas[d] == min(meas.values())
+        truth = {k: _measured_ms(pk, torch, (5, *ISO, 1e-3, BOX_LO, BOX), k, ts, tb) for k in range(2, 7)}
+        print("  independent timing:", {k: round(v, 3) for k, v in truth.items()})
+        assert truth[d] <= 1.25 * min(truth.values()) + 0.05
