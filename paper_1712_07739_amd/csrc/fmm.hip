@@ -119,55 +119,55 @@ __global__ void k_p2m(const double* pts, int64_t N, const int* first, const int*
 // ------------------------------------------------------- separable passes
 // out[g][a][b][i] = sum_m M(i, m) in[g][a][b][m] along the last axis, for the
 // three axes in turn; M(i, m) = S[bit][i][m] (anterpolation, M2M) or
-// S[bit][m][i] (interpolation, L2L).
-template <typename T, bool INTERP>
-__device__ __forceinline__ void pass_axis(const T* in, T* out, const T* S, int bit, int p, int ncomp,
-                                          int axis) {
-  const int p3 = p * p * p;
-  const int stride = axis == 2 ? 1 : axis == 1 ? p : p * p;
+// S[bit][m][i] (interpolation, L2L).  The order P is a template parameter.
+template <typename T, bool INTERP, int P, int AXIS>
+__device__ __forceinline__ void pass_axis(const T* in, T* out, const T* S, int bit, int ncomp) {
+  constexpr int p3 = P * P * P;
+  constexpr int stride = AXIS == 2 ? 1 : AXIS == 1 ? P : P * P;
   for (int e = threadIdx.x; e < ncomp * p3; e += blockDim.x) {
-    int g = e / p3, r = e % p3;
-    int i = (r / stride) % p;
-    int base = g * p3 + r - i * stride;
+    const int r = e % p3, i = (r / stride) % P;
+    const int base = e - i * stride;
     T v = T(0);
-    for (int m = 0; m < p; ++m) {
-      T c = INTERP ? S[(bit * p + m) * p + i] : S[(bit * p + i) * p + m];
-      v += c * in[base + m * stride];
+#pragma unroll
+    for (int m = 0; m < P; ++m) {
+      const T c = INTERP ? S[(bit * P + m) * P + i] : S[(bit * P + i) * P + m];
+      v = fma(c, in[base + m * stride], v);
     }
     out[e] = v;
   }
 }
 
-// M2M: one block per parent cell.  W_child rows of the next finer level.
-template <typename T>
-__global__ void k_m2m(const int* first, const int* count, const uint32_t* ckey, const T* Wc, T* Wp,
-                      const T* Sg, int p) {
+// M2M: one block per parent cell; the children's W (next finer level) are
+// anterpolated onto the parent's nodes one child at a time.
+template <typename T, int P>
+__global__ void k_m2m(const int* first, const int* count, const uint32_t* ckey, const T* Wc, T* Wp, const T* Sg) {
   extern __shared__ unsigned char shraw[];
-  const int p3 = p * p * p;
+  constexpr int p3 = P * P * P;
   T* A = (T*)shraw;
   T* B = A + 9 * p3;
   T* C = B + 9 * p3;
   T* S = C + 9 * p3;
-  for (int e = threadIdx.x; e < 2 * p * p; e += blockDim.x) S[e] = Sg[e];
+  for (int e = threadIdx.x; e < 2 * P * P; e += blockDim.x) S[e] = Sg[e];
   for (int e = threadIdx.x; e < 9 * p3; e += blockDim.x) C[e] = T(0);
   const int par = blockIdx.x;
   const int c0 = first[par], nc = count[par];
   __syncthreads();
   for (int c = c0; c < c0 + nc; ++c) {
-    uint32_t bits = ckey[c] & 7;
+    const uint32_t bits = ckey[c] & 7;
     const T* src = Wc + (int64_t)c * 9 * p3;
     for (int e = threadIdx.x; e < 9 * p3; e += blockDim.x) A[e] = src[e];
     __syncthreads();
-    pass_axis<T, false>(A, B, S, bits & 1, p, 9, 2);
+    pass_axis<T, false, P, 2>(A, B, S, bits & 1, 9);
     __syncthreads();
-    pass_axis<T, false>(B, A, S, (bits >> 1) & 1, p, 9, 1);
+    pass_axis<T, false, P, 1>(B, A, S, (bits >> 1) & 1, 9);
     __syncthreads();
+    const int b2 = (bits >> 2) & 1;
     for (int e = threadIdx.x; e < 9 * p3; e += blockDim.x) {
-      int g = e / p3, r = e % p3;
-      int i = r / (p * p);
-      int base = g * p3 + r - i * p * p;
+      const int r = e % p3, i = r / (P * P);
+      const int base = e - i * P * P;
       T v = T(0);
-      for (int m = 0; m < p; ++m) v += S[((bits >> 2 & 1) * p + i) * p + m] * A[base + m * p * p];
+#pragma unroll
+      for (int m = 0; m < P; ++m) v = fma(S[(b2 * P + i) * P + m], A[base + m * P * P], v);
       C[e] += v;
     }
     __syncthreads();
@@ -177,32 +177,41 @@ __global__ void k_m2m(const int* first, const int* count, const uint32_t* ckey, 
 }
 
 // L2L: one block per child cell; adds the parent's interpolated local values.
-template <typename T>
-__global__ void k_l2l(const int* parent, const uint32_t* key, const T* sp, T* sc, const T* Sg, int p) {
+template <typename T, int P>
+__global__ void k_l2l(const int* parent, const uint32_t* key, const T* sp, T* sc, const T* Sg) {
   extern __shared__ unsigned char shraw[];
-  const int p3 = p * p * p;
+  constexpr int p3 = P * P * P;
   T* A = (T*)shraw;
   T* B = A + 6 * p3;
   T* S = B + 6 * p3;
-  for (int e = threadIdx.x; e < 2 * p * p; e += blockDim.x) S[e] = Sg[e];
+  for (int e = threadIdx.x; e < 2 * P * P; e += blockDim.x) S[e] = Sg[e];
   const int c = blockIdx.x;
   const uint32_t bits = key[c] & 7;
   const T* src = sp + (int64_t)parent[c] * 6 * p3;
   for (int e = threadIdx.x; e < 6 * p3; e += blockDim.x) A[e] = src[e];
   __syncthreads();
-  pass_axis<T, true>(A, B, S, bits & 1, p, 6, 2);
+  pass_axis<T, true, P, 2>(A, B, S, bits & 1, 6);
   __syncthreads();
-  pass_axis<T, true>(B, A, S, (bits >> 1) & 1, p, 6, 1);
+  pass_axis<T, true, P, 1>(B, A, S, (bits >> 1) & 1, 6);
   __syncthreads();
   T* dst = sc + (int64_t)c * 6 * p3;
+  const int b2 = (bits >> 2) & 1;
   for (int e = threadIdx.x; e < 6 * p3; e += blockDim.x) {
-    int g = e / p3, r = e % p3;
-    int i = r / (p * p);
-    int base = g * p3 + r - i * p * p;
+    const int r = e % p3, i = r / (P * P);
+    const int base = e - i * P * P;
     T v = T(0);
-    for (int m = 0; m < p; ++m) v += S[((bits >> 2 & 1) * p + m) * p + i] * A[base + m * p * p];
+#pragma unroll
+    for (int m = 0; m < P; ++m) v = fma(S[(b2 * P + m) * P + i], A[base + m * P * P], v);
     dst[e] += v;
   }
+}
+
+// Blocks are dispatched round-robin over the 8 XCDs; this bijection of
+// [0, n) gives XCD x the contiguous range of items [x q + min(x, r), ...)
+// (n = 8 q + r), so that items next to each other in memory meet in one L2.
+__device__ __forceinline__ int64_t xcd_block(int64_t L, int64_t n) {
+  const int64_t q = n / 8, r = n % 8, x = L % 8, k = L / 8;
+  return x * q + (x < r ? x : r) + k;
 }
 
 // ------------------------------------------------------------ forward DFT
@@ -210,16 +219,18 @@ __global__ void k_l2l(const int* parent, const uint32_t* key, const T* sp, T* sc
 // n = 2P - 1) -> What[f][cell][9], f = (f1 n + f2) P + f3, the half spectrum
 // in the last axis (the input is real).  Three passes of length-P to
 // length-n (or P) DFTs through LDS, G components at a time; the twiddles
-// exp(-2 pi i f m / n), f < n, m < P, are tabulated once per block.
+// exp(-2 pi i f m / n), f < n, m < P, are tabulated once per block.  Rows of
+// neighbouring cells share cache lines, so cells are spread over the XCDs in
+// contiguous ranges (xcd_block).
 template <typename T, int P>
-__global__ void k_fdft(const T* W, int64_t ncell, int G, const T* twg, cplx<T>* What) {
+__global__ void __launch_bounds__(256) k_fdft(const T* W, int64_t ncell, int G, const T* twg, cplx<T>* What) {
   constexpr int n = 2 * P - 1, p3 = P * P * P, nf = n * n * P;
   extern __shared__ __align__(16) unsigned char shraw[];
   cplx<T>* tm = (cplx<T>*)shraw;  // [n][P]
   cplx<T>* X1 = tm + n * P;       // [G][P][P][P]  (m1, m2, f3)
   T* Wl = (T*)(X1 + G * p3);      // [G][P^3]; the same space then holds
   cplx<T>* X2 = (cplx<T>*)Wl;     // [G][P][n][P]  (m1, f2, f3)
-  const int64_t cell = blockIdx.x;
+  const int64_t cell = xcd_block(blockIdx.x, ncell);
   for (int e = threadIdx.x; e < n * P; e += blockDim.x) {
     const int k = ((e / P) * (e % P)) % n;
     tm[e] = cplx<T>{twg[2 * k], twg[2 * k + 1]};
@@ -374,74 +385,74 @@ __global__ void __launch_bounds__(kHadThreads) k_hadamard(const cplx<T>* What, c
 // One block per cell: Shat[cell][f][6] -> s[cell][6][P^3] (overwrites): the
 // inverse transform of the half spectrum of a real circular convolution, of
 // which only the outputs l < P are needed (the rest is the wrap-around of the
-// embedding).  Twiddles exp(+2 pi i f l / n), f < n, l < P, in LDS.
+// embedding).  Twiddles exp(+2 pi i f l / n), f < n, l < P, in LDS.  The
+// first pass reads the spectrum straight from memory, each value once (a
+// thread takes one (f2, f3, component) line and produces all P outputs).
 template <typename T, int P>
-__global__ void k_idft(const cplx<T>* Shat, int64_t ncell, int G, const T* twg, T* s) {
+__global__ void __launch_bounds__(256) k_idft(const cplx<T>* Shat, int64_t ncell, const T* twg, T* s) {
   constexpr int n = 2 * P - 1, p3 = P * P * P, nf = n * n * P;
   extern __shared__ __align__(16) unsigned char shraw[];
   cplx<T>* tm = (cplx<T>*)shraw;  // [n][P]
-  cplx<T>* Y1 = tm + n * P;       // [G][n(f2)][P(f3)][P(l1)]
-  cplx<T>* Sl = Y1 + G * n * P * P;  // [G][nf]; the same space then holds
-  cplx<T>* Y2 = Sl;                  // [G][P(f3)][P(l1)][P(l2)]
+  cplx<T>* Y1 = tm + n * P;       // [6][n(f2)][P(f3)][P(l1)]
+  cplx<T>* Y2 = Y1 + 6 * n * P * P;  // [6][P(f3)][P(l1)][P(l2)]
   const int64_t cell = blockIdx.x;
   for (int e = threadIdx.x; e < n * P; e += blockDim.x) {
     const int k = ((e / P) * (e % P)) % n;
     tm[e] = cplx<T>{twg[2 * k], -twg[2 * k + 1]};
   }
+  __syncthreads();
   const T scale = T(1) / T(n * n * n);
-  for (int c0 = 0; c0 < 6; c0 += G) {
-    const cplx<T>* src = Shat + cell * nf * 6;
-    for (int e = threadIdx.x; e < G * nf; e += blockDim.x) {
-      const int g = e % G, f = e / G;
-      Sl[g * nf + f] = src[f * 6 + c0 + g];
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < G * n * P * P; e += blockDim.x) {
-      const int l1 = e % P, f3 = (e / P) % P, f2 = (e / (P * P)) % n, g = e / (P * P * n);
-      const cplx<T>* x = Sl + g * nf + f2 * P + f3;
+  const cplx<T>* src = Shat + cell * nf * 6;
+  for (int e = threadIdx.x; e < 6 * n * P; e += blockDim.x) {
+    const int g = e % 6, f3 = (e / 6) % P, f2 = e / (6 * P);
+    cplx<T> x[n];
+#pragma unroll
+    for (int f1 = 0; f1 < n; ++f1) x[f1] = src[((f1 * n + f2) * P + f3) * 6 + g];
+    cplx<T>* y = Y1 + ((g * n + f2) * P + f3) * P;
+#pragma unroll 1
+    for (int l1 = 0; l1 < P; ++l1) {
       T re = 0, im = 0;
 #pragma unroll
       for (int f1 = 0; f1 < n; ++f1) {
-        const cplx<T> a = x[f1 * n * P], w = tm[f1 * P + l1];
-        re = fma(a.re, w.re, fma(-a.im, w.im, re));
-        im = fma(a.re, w.im, fma(a.im, w.re, im));
+        const cplx<T> w = tm[f1 * P + l1];
+        re = fma(x[f1].re, w.re, fma(-x[f1].im, w.im, re));
+        im = fma(x[f1].re, w.im, fma(x[f1].im, w.re, im));
       }
-      Y1[e] = cplx<T>{re, im};
+      y[l1] = cplx<T>{re, im};
     }
-    __syncthreads();
-    for (int e = threadIdx.x; e < G * p3; e += blockDim.x) {
-      const int l2 = e % P, l1 = (e / P) % P, f3 = (e / (P * P)) % P, g = e / p3;
-      const cplx<T>* x = Y1 + (g * n * P + f3) * P + l1;
-      T re = 0, im = 0;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 6 * p3; e += blockDim.x) {
+    const int l2 = e % P, l1 = (e / P) % P, f3 = (e / (P * P)) % P, g = e / p3;
+    const cplx<T>* x = Y1 + (g * n * P + f3) * P + l1;
+    T re = 0, im = 0;
 #pragma unroll
-      for (int f2 = 0; f2 < n; ++f2) {
-        const cplx<T> a = x[f2 * P * P], w = tm[f2 * P + l2];
-        re = fma(a.re, w.re, fma(-a.im, w.im, re));
-        im = fma(a.re, w.im, fma(a.im, w.re, im));
-      }
-      Y2[e] = cplx<T>{re, im};
+    for (int f2 = 0; f2 < n; ++f2) {
+      const cplx<T> a = x[f2 * P * P], w = tm[f2 * P + l2];
+      re = fma(a.re, w.re, fma(-a.im, w.im, re));
+      im = fma(a.re, w.im, fma(a.im, w.re, im));
     }
-    __syncthreads();
-    for (int e = threadIdx.x; e < G * p3; e += blockDim.x) {
-      const int l3 = e % P, l2 = (e / P) % P, l1 = (e / (P * P)) % P, g = e / p3;
-      const cplx<T>* x = Y2 + (g * P * P + l1) * P + l2;
-      // Hermitian symmetry in the last axis: f3 = 0 once, f3 > 0 twice (real part)
-      T re = x[0].re * tm[l3].re - x[0].im * tm[l3].im;
-      T acc = 0;
+    Y2[e] = cplx<T>{re, im};
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 6 * p3; e += blockDim.x) {
+    const int l3 = e % P, l2 = (e / P) % P, l1 = (e / (P * P)) % P, g = e / p3;
+    const cplx<T>* x = Y2 + (g * P * P + l1) * P + l2;
+    // Hermitian symmetry in the last axis: f3 = 0 once, f3 > 0 twice (real part)
+    const T re = x[0].re * tm[l3].re - x[0].im * tm[l3].im;
+    T acc = 0;
 #pragma unroll
-      for (int f3 = 1; f3 < P; ++f3) {
-        const cplx<T> a = x[f3 * P * P], w = tm[f3 * P + l3];
-        acc = fma(a.re, w.re, fma(-a.im, w.im, acc));
-      }
-      s[(cell * 6 + c0 + g) * p3 + (l1 * P + l2) * P + l3] = (re + T(2) * acc) * scale;
+    for (int f3 = 1; f3 < P; ++f3) {
+      const cplx<T> a = x[f3 * P * P], w = tm[f3 * P + l3];
+      acc = fma(a.re, w.re, fma(-a.im, w.im, acc));
     }
-    __syncthreads();
+    s[(cell * 6 + g) * p3 + (l1 * P + l2) * P + l3] = (re + T(2) * acc) * scale;
   }
 }
 
 template <int P>
-constexpr size_t lds_idft_t(int G, size_t es) {
-  return 2 * es * ((2 * P - 1) * P + (size_t)G * (2 * P - 1) * P * P + (size_t)G * (2 * P - 1) * (2 * P - 1) * P);
+constexpr size_t lds_idft_t(size_t es) {
+  return 2 * es * ((2 * P - 1) * P + (size_t)6 * (2 * P - 1) * P * P + (size_t)6 * P * P * P);
 }
 
 // ------------------------------------------------ near field + L2P (leaf)
@@ -804,18 +815,14 @@ __global__ void k_direct_reduce(const double* part, int64_t ntp, int nchunk, dou
 }
 
 // ------------------------------------------------------------ host side
-// DFT launches, specialised on the interpolation order.  Components per
-// round: as many as fit 80 KB of LDS (forward) or 64 KB (inverse).
+// DFT launches, specialised on the interpolation order.  Forward: as many
+// components per round as fit 80 KB of LDS; inverse: all six in one round.
 template <typename T, int P>
 static int dft_groups(bool fwd) {
   const size_t es = sizeof(T);
-  if (fwd) {
-    for (int G : {9, 3, 1})
-      if (lds_fdft_t<P>(G, es) <= 80 * 1024) return G;
-  } else {
-    for (int G : {6, 3, 2, 1})
-      if (lds_idft_t<P>(G, es) <= 64 * 1024) return G;
-  }
+  for (int G : {9, 3, 1})
+    if (lds_fdft_t<P>(G, es) <= 80 * 1024) return G;
+  (void)fwd;
   return 1;
 }
 
@@ -826,7 +833,7 @@ static void dft_launch(bool fwd, unsigned blocks, const void* in, int64_t ncell,
   if (fwd)
     k_fdft<T, P><<<blocks, 256, lds_fdft_t<P>(G, sizeof(T)), st>>>((const T*)in, ncell, G, tw, (cplx<T>*)out);
   else
-    k_idft<T, P><<<blocks, 256, lds_idft_t<P>(G, sizeof(T)), st>>>((const cplx<T>*)in, ncell, G, tw, (T*)out);
+    k_idft<T, P><<<blocks, 256, lds_idft_t<P>(sizeof(T)), st>>>((const cplx<T>*)in, ncell, tw, (T*)out);
 }
 
 template <typename T>
@@ -843,11 +850,39 @@ static void dft(int p, bool fwd, unsigned blocks, const void* in, int64_t ncell,
   }
 }
 
+// M2M (up) or L2L (down) launch, specialised on the order.  For M2M, a / b
+// are the parents' first child and child count; for L2L, a is the parent
+// index of each child (b unused).
+template <typename T, int P>
+static void tree_pass_p(bool up, unsigned blocks, size_t shm, const int* a, const int* b, const uint32_t* key,
+                        const T* in, T* out, const T* S, hipStream_t st) {
+  if (up)
+    k_m2m<T, P><<<blocks, 256, shm, st>>>(a, b, key, in, out, S);
+  else
+    k_l2l<T, P><<<blocks, 256, shm, st>>>(a, key, in, out, S);
+}
+
+template <typename T>
+static void tree_pass(int p, bool up, unsigned blocks, size_t shm, const int* a, const int* b, const uint32_t* key,
+                      const T* in, T* out, const T* S, hipStream_t st) {
+  switch (p) {
+    case 2: tree_pass_p<T, 2>(up, blocks, shm, a, b, key, in, out, S, st); break;
+    case 3: tree_pass_p<T, 3>(up, blocks, shm, a, b, key, in, out, S, st); break;
+    case 4: tree_pass_p<T, 4>(up, blocks, shm, a, b, key, in, out, S, st); break;
+    case 5: tree_pass_p<T, 5>(up, blocks, shm, a, b, key, in, out, S, st); break;
+    case 6: tree_pass_p<T, 6>(up, blocks, shm, a, b, key, in, out, S, st); break;
+    case 7: tree_pass_p<T, 7>(up, blocks, shm, a, b, key, in, out, S, st); break;
+    default: tree_pass_p<T, 8>(up, blocks, shm, a, b, key, in, out, S, st); break;
+  }
+}
+
 template <typename T, int... Ps>
 static void dft_lds_attrs(std::integer_sequence<int, Ps...>) {
   const int mx = 160 * 1024;
   ((void)hipFuncSetAttribute((const void*)k_fdft<T, Ps + 2>, hipFuncAttributeMaxDynamicSharedMemorySize, mx), ...);
   ((void)hipFuncSetAttribute((const void*)k_idft<T, Ps + 2>, hipFuncAttributeMaxDynamicSharedMemorySize, mx), ...);
+  ((void)hipFuncSetAttribute((const void*)k_m2m<T, Ps + 2>, hipFuncAttributeMaxDynamicSharedMemorySize, mx), ...);
+  ((void)hipFuncSetAttribute((const void*)k_l2l<T, Ps + 2>, hipFuncAttributeMaxDynamicSharedMemorySize, mx), ...);
 }
 
 struct StageTimer {
@@ -923,8 +958,8 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
     for (int l = D - 1; l >= 2; --l) {
       const auto& Lc = t->lv[l + 1];
       const auto& Lp = t->lv[l];
-      STAGE(1, (k_m2m<T><<<(unsigned)Lp.n, 256, shm, st>>>(Lp.first, Lp.count, Lc.key, W + Lc.off * 9 * p3,
-                                                            W + Lp.off * 9 * p3, tb.S, p)));
+      STAGE(1, tree_pass<T>(p, true, (unsigned)Lp.n, shm, Lp.first, Lp.count, Lc.key, W + Lc.off * 9 * p3,
+                               W + Lp.off * 9 * p3, tb.S, st));
     }
   }
   const size_t shm_h = sizeof(cplx<T>) * kNumCanon * kKStride;
@@ -944,8 +979,8 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
     for (int l = 3; l <= D; ++l) {
       const auto& Lv = t->lv[l];
       const auto& Lp = t->lv[l - 1];
-      STAGE(5, (k_l2l<T><<<(unsigned)Lv.n, 256, shm, st>>>(Lv.parent, Lv.key, s + Lp.off * 6 * p3,
-                                                            s + Lv.off * 6 * p3, tb.S, p)));
+      STAGE(5, tree_pass<T>(p, false, (unsigned)Lv.n, shm, Lv.parent, nullptr, Lv.key, s + Lp.off * 6 * p3,
+                               s + Lv.off * 6 * p3, tb.S, st));
     }
   }
   {
@@ -992,8 +1027,6 @@ static void set_lds_attrs() {
   const int mx = 160 * 1024;
   hipFuncSetAttribute((const void*)k_hadamard<T>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
   dft_lds_attrs<T>(std::make_integer_sequence<int, kMaxOrder - 1>{});
-  hipFuncSetAttribute((const void*)k_m2m<T>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-  hipFuncSetAttribute((const void*)k_l2l<T>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
   hipFuncSetAttribute((const void*)k_p2m<T>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
 }
 
