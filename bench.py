@@ -67,6 +67,8 @@ def main():
     ap.add_argument("--err-sample", type=int, default=200, help="segments checked against the GPU FP64 direct sum")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true",
+                    help="cubic media: skip training the anisotropic-kernel network (it is used where its gate passes)")
     ap.add_argument("--cpu-sample", type=int, default=1, help="target segments timed on the CPU oracle")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run 3 plain device copies of MIB MiB (calibrates HBM byte counters) and exit")
@@ -119,6 +121,20 @@ def main():
     setup_s = time.perf_counter() - t0
     info = plan.info()
     log("setup %.2f s %s" % (setup_s, info))
+    sur = None
+    cubic = abs(2 * prm["c44"] - (prm["c11"] - prm["c12"])) > 1e-12
+    if cubic and prec == pk.DFMM_MIXED and not args.no_surrogate:
+        # the learned surrogate of the anisotropic kernel: 2M samples, residual gate 1e-5,
+        # the exact quadrature wherever a direction bin fails the gate
+        t0 = time.perf_counter()
+        sinfo = plan.surrogate_train(n_samples=1 << 21, tol=1e-5, seed=5)
+        plan.surrogate_use(True)
+        torch.cuda.synchronize()
+        sur = {k: sinfo[k] for k in ("n_params", "n_samples", "epochs", "bins", "tol", "pass_frac",
+                                      "median_bin_err", "max_bin_err", "train_ms")}
+        sur["loss_first_last"] = [sinfo["loss"][0], sinfo["loss"][-1]]
+        sur["setup_s"] = time.perf_counter() - t0
+        log("surrogate: %s" % sur)
     tseg = torch.tensor(seg, device=dev)
     tb = torch.tensor(burg, device=dev)
     torch.cuda.synchronize()
@@ -173,7 +189,10 @@ def main():
                    "precision": args.precision, "configured_order": configured_order},
         "rel_err_vs_fp64_direct": err, "err_sample_segments": int(len(sub)),
         "stage_ms": {pk.STAGES[i]: stage_ms[i] / ncalls for i in range(pk.N_STAGES)},
-        "setup_s": setup_s, "build_tree_s": tree_s, "m2l_pairs": tinfo["m2l_pairs"],
+        "setup_s": setup_s, "build_tree_s": tree_s,
+        "plan": {k: info[k] for k in ("n_freq", "n_circle", "n_circle_float", "float_rule_err", "spectra_bytes")
+                 if k in info},
+        "surrogate": sur, "m2l_pairs": tinfo["m2l_pairs"],
         "near_pairs": tinfo["near_pairs"], "roofline": roof,
     }
     del tree
