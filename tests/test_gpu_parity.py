@@ -117,6 +117,38 @@ def test_fmm_all_near_equals_direct(env):
     assert oracle.rel_err(f, ref) <= 1e-13
 
 
+@pytest.mark.parametrize("C", [ISO, CUB])
+def test_single_precision_path_with_close_pairs_only(env, C):
+    """One loop of radius 2e-4: every pair of its 120 points is closer than
+    2a = 2e-3, so the single-precision path's near field is entirely the
+    double-precision close-pair kernel and must equal the FP64 direct sum."""
+    seg, b = synth.make_loops(1, 2e-4, 2e-4, 11)
+    seg = seg - seg.mean(axis=(0, 1)) + 0.5
+    f, _, tree = run_fmm(env, seg, b, C, 4, 2, precision=1)
+    assert tree.info()["m2l_pairs"] == 0
+    ref = oracle.direct_forces(seg, b, oracle.medium(*C, 1e-3))
+    assert oracle.rel_err(f, ref) <= 1e-11
+
+
+def test_dense_cluster_of_close_pairs(env):
+    """20 tiny loops packed into a 3e-3 cube (about a thousand close partners
+    per point): the close-pair buffer fills and is evaluated many times per
+    wave.  All pairs are near; single vs FP64 path vs the oracle."""
+    rng = np.random.default_rng(12)
+    segs, bs = [], []
+    for k in range(20):
+        s1, b1 = synth.make_loops(1, 1e-4, 4e-4, 100 + k)
+        segs.append(s1 - s1.mean(axis=(0, 1)) + 0.5 + rng.uniform(-1.5e-3, 1.5e-3, size=3))
+        bs.append(b1)
+    seg, b = np.concatenate(segs), np.concatenate(bs)
+    ref = oracle.direct_forces(seg, b, oracle.medium(*CUB, 1e-3))
+    f64, _, tree = run_fmm(env, seg, b, CUB, 4, 4, precision=0)
+    assert tree.info()["m2l_pairs"] == 0
+    f32, _, _ = run_fmm(env, seg, b, CUB, 4, 4, precision=1)
+    assert oracle.rel_err(f64, ref) <= 1e-12
+    assert oracle.rel_err(f32, ref) <= 2e-5
+
+
 # ------------------------------------------------------------ edge cases
 def test_single_segment_and_degenerate_inputs(env):
     torch, pk, dev = env
