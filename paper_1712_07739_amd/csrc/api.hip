@@ -151,6 +151,12 @@ int dfmm_build_tree(dfmm_plan* plan, const double* seg, int64_t n_seg, void* str
 void dfmm_tree_destroy(dfmm_tree* t) {
   if (!t) return;
   if (t->last_stream) hipStreamSynchronize(t->last_stream);
+  if (t->side) {
+    hipStreamSynchronize(t->side);
+    hipStreamDestroy(t->side);
+  }
+  if (t->fork) hipEventDestroy(t->fork);
+  if (t->join) hipEventDestroy(t->join);
   hipFree(t->perm); hipFree(t->inv); hipFree(t->nbr);
   for (auto& L : t->lv) {
     hipFree(L.key); hipFree(L.first); hipFree(L.count); hipFree(L.parent); hipFree(L.il_start); hipFree(L.il); hipFree(L.order);

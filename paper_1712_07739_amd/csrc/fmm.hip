@@ -947,6 +947,46 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
   const double sD = L / std::ldexp(1.0, D);
 
   STAGE(0, (k_gather<<<nblk(N, 256), 256, 0, st>>>(seg, burg, t->perm, pl->quad, N, t->pts)));
+  // The near field needs only the gathered points: it runs on the tree's
+  // second stream beside P2M..L2L, unless stages are being timed one by one
+  // or the caller's stream is being captured into a graph (there the near
+  // field stays on the capturing stream; a batch overlaps its configurations
+  // across its own lanes instead).
+  hipStream_t nst = st;
+  hipStreamCaptureStatus capture = hipStreamCaptureStatusNone;
+  DFMM_HIP(hipStreamIsCapturing(st, &capture));
+  if (!t->timing && t->side && capture == hipStreamCaptureStatusNone) {
+    DFMM_HIP(hipEventRecord(t->fork, st));
+    DFMM_HIP(hipStreamWaitEvent(t->side, t->fork, 0));
+    nst = t->side;
+  }
+  {
+    Med<T> m = pl->med<T>();
+    Med<double> m64 = pl->med<double>();
+    const bool mixed = !std::is_same<T, double>::value;
+#define LEAF_ARGS                                                                                     \
+  t->pts, N, LD.first, LD.count, LD.key, t->nbr, s + LD.off * 6 * p3, lo[0], lo[1], lo[2], sD, p, m, m64, \
+      sd, t->sig
+    SurDev sd = sur_dev(pl);
+    if (mixed && !pl->iso && sd.on)
+      STAGE(6, (k_leaf<T, true, false, true><<<(unsigned)LD.n, 64, sizeof(float) * 2 * kSurHidden * 64, nst>>>(
+                   LEAF_ARGS)));
+    else if (mixed && pl->iso)
+      STAGE(6, (k_leaf<T, true, true, false><<<(unsigned)LD.n, 64, 0, nst>>>(LEAF_ARGS)));
+    else if (mixed)
+      STAGE(6, (k_leaf<T, true, false, false><<<(unsigned)LD.n, 64, 0, nst>>>(LEAF_ARGS)));
+    else if (pl->iso)
+      STAGE(6, (k_leaf<T, false, true, false><<<(unsigned)LD.n, 64, 0, nst>>>(LEAF_ARGS)));
+    else
+      STAGE(6, (k_leaf<T, false, false, false><<<(unsigned)LD.n, 64, 0, nst>>>(LEAF_ARGS)));
+#undef LEAF_ARGS
+    if (mixed && pl->iso)
+      STAGE(6, (k_close<true><<<(unsigned)LD.n, 64, 0, nst>>>(t->pts, N, LD.first, LD.count, LD.key, t->nbr, lo[0],
+                                                            lo[1], lo[2], sD, m64, t->sig)));
+    else if (mixed)
+      STAGE(6, (k_close<false><<<(unsigned)LD.n, 64, 0, nst>>>(t->pts, N, LD.first, LD.count, LD.key, t->nbr, lo[0],
+                                                             lo[1], lo[2], sD, m64, t->sig)));
+  }
   {
     int bs = std::max(64, ((p3 + 63) / 64) * 64);
     size_t shm = es * (64 * 3 * p + 64 * 9);
@@ -983,32 +1023,11 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
                                s + Lv.off * 6 * p3, tb.S, st));
     }
   }
+  if (nst != st) {
+    DFMM_HIP(hipEventRecord(t->join, nst));
+    DFMM_HIP(hipStreamWaitEvent(st, t->join, 0));
+  }
   {
-    Med<T> m = pl->med<T>();
-    Med<double> m64 = pl->med<double>();
-    const bool mixed = !std::is_same<T, double>::value;
-#define LEAF_ARGS                                                                                     \
-  t->pts, N, LD.first, LD.count, LD.key, t->nbr, s + LD.off * 6 * p3, lo[0], lo[1], lo[2], sD, p, m, m64, \
-      sd, t->sig
-    SurDev sd = sur_dev(pl);
-    if (mixed && !pl->iso && sd.on)
-      STAGE(6, (k_leaf<T, true, false, true><<<(unsigned)LD.n, 64, sizeof(float) * 2 * kSurHidden * 64, st>>>(
-                   LEAF_ARGS)));
-    else if (mixed && pl->iso)
-      STAGE(6, (k_leaf<T, true, true, false><<<(unsigned)LD.n, 64, 0, st>>>(LEAF_ARGS)));
-    else if (mixed)
-      STAGE(6, (k_leaf<T, true, false, false><<<(unsigned)LD.n, 64, 0, st>>>(LEAF_ARGS)));
-    else if (pl->iso)
-      STAGE(6, (k_leaf<T, false, true, false><<<(unsigned)LD.n, 64, 0, st>>>(LEAF_ARGS)));
-    else
-      STAGE(6, (k_leaf<T, false, false, false><<<(unsigned)LD.n, 64, 0, st>>>(LEAF_ARGS)));
-#undef LEAF_ARGS
-    if (mixed && pl->iso)
-      STAGE(6, (k_close<true><<<(unsigned)LD.n, 64, 0, st>>>(t->pts, N, LD.first, LD.count, LD.key, t->nbr, lo[0],
-                                                            lo[1], lo[2], sD, m64, t->sig)));
-    else if (mixed)
-      STAGE(6, (k_close<false><<<(unsigned)LD.n, 64, 0, st>>>(t->pts, N, LD.first, LD.count, LD.key, t->nbr, lo[0],
-                                                             lo[1], lo[2], sD, m64, t->sig)));
     STAGE(6, (k_l2p<T><<<nblk(N, 256), 256, 0, st>>>(t->pts, N, t->pleaf, LD.key, s + LD.off * 6 * p3, lo[0], lo[1],
                                                      lo[2], sD, p, t->sig)));
   }

@@ -122,6 +122,10 @@ struct dfmm_tree {
   double stage_ms[DFMM_N_STAGES] = {};
   int timed_calls = 0;
   hipStream_t last_stream = nullptr;
+  // second stream for the near field, which runs beside the far-field
+  // pipeline (fork after the point gather, join before L2P)
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
 };
 
 namespace dfmm {

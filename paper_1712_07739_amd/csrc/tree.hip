@@ -515,6 +515,9 @@ int build_tree_impl(dfmm_plan* pl, const double* seg, int64_t nseg, hipStream_t 
   size_t bW = es * 9 * p3 * t->ncell_total, bS = es * 6 * p3 * t->ncell_total;
   size_t bWh = es * 2 * 9 * (size_t)pl->nf * t->max_level_cells;
   size_t bSh = es * 2 * 6 * (size_t)pl->nf * t->max_level_cells;
+  DFMM_HIP(hipStreamCreateWithFlags(&t->side, hipStreamNonBlocking));
+  DFMM_HIP(hipEventCreateWithFlags(&t->fork, hipEventDisableTiming));
+  DFMM_HIP(hipEventCreateWithFlags(&t->join, hipEventDisableTiming));
   DFMM_HIP(hipMalloc(&t->pts, sizeof(double) * 9 * N));
   DFMM_HIP(hipMalloc(&t->pleaf, sizeof(int) * N));
   k_point_leaf<<<(unsigned)LD.n, 64, 0, st>>>(LD.first, LD.count, (int)LD.n, t->pleaf);
