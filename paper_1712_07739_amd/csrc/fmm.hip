@@ -470,10 +470,9 @@ constexpr int leaf_min_waves() {
 }
 
 template <typename T, bool MIXED, bool ISO, bool SUR>
-__global__ void __launch_bounds__(64, leaf_min_waves<T>()) k_leaf(const double* pts, int64_t N, const int* first, const int* count,
-                                             const uint32_t* key, const int* nbr, const T* s, double lo0,
-                                             double lo1, double lo2, double sD, int p, Med<T> m, Med<double> m64,
-                                             SurDev sd, double* sig) {
+__global__ void __launch_bounds__(64, leaf_min_waves<T>())
+    k_leaf(const double* pts, int64_t N, const int* first, const int* count, const int* nbr, Med<T> m,
+           Med<double> m64, SurDev sd, double* sig) {
   extern __shared__ float sur_scratch[];  // [2*128][64] activations when SUR
   const int leaf = blockIdx.x, lane = threadIdx.x;
   const int t0 = first[leaf], nt = count[leaf];
@@ -666,33 +665,57 @@ __global__ void __launch_bounds__(64) k_close(const double* pts, int64_t N, cons
 // L2P: far-field stress at each point by interpolation of its leaf's local
 // values (Lagrange basis on the leaf's equispaced nodes), added to the near
 // field already in sig.  One thread per point.
-template <typename T>
+template <typename T, int P>
 __global__ void k_l2p(const double* pts, int64_t N, const int* pleaf, const uint32_t* key, const T* s, double lo0,
-                      double lo1, double lo2, double sD, int p, double* sig) {
+                      double lo1, double lo2, double sD, double* sig) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
   const int leaf = pleaf[i];
   double lo[3];
   cell_lo(key[leaf], lo0, lo1, lo2, sD, lo);
-  const int p3 = p * p * p;
+  constexpr int p3 = P * P * P;
   const T* sl = s + (int64_t)leaf * 6 * p3;
   const T t[3] = {(T)((pts[i] - lo[0]) / sD), (T)((pts[N + i] - lo[1]) / sD), (T)((pts[2 * N + i] - lo[2]) / sD)};
-  T L[3][kMaxOrder];
-  for (int d = 0; d < 3; ++d)
-    for (int k = 0; k < p; ++k) L[d][k] = lagr<T>(p, k, t[d]);
+  T L1[P], L2[P];  // the first axis' basis value is formed inside its (rolled) loop
+#pragma unroll
+  for (int k = 0; k < P; ++k) {
+    L1[k] = lagr<T>(P, k, t[1]);
+    L2[k] = lagr<T>(P, k, t[2]);
+  }
   T far[6] = {0, 0, 0, 0, 0, 0};
-  for (int l1 = 0; l1 < p; ++l1)
-    for (int l2 = 0; l2 < p; ++l2) {
-      const T w12 = L[0][l1] * L[1][l2];
-      for (int l3 = 0; l3 < p; ++l3) {
-        const T w = w12 * L[2][l3];
-        const int node = (l1 * p + l2) * p + l3;
+  for (int l1 = 0; l1 < P; ++l1) {
+    const T L0 = lagr<T>(P, l1, t[0]);
+#pragma unroll
+    for (int l2 = 0; l2 < P; ++l2) {
+      const T w12 = L0 * L1[l2];
+#pragma unroll
+      for (int l3 = 0; l3 < P; ++l3) {
+        const T w = w12 * L2[l3];
+        const int node = (l1 * P + l2) * P + l3;
 #pragma unroll
         for (int c = 0; c < 6; ++c) far[c] = fma(w, sl[c * p3 + node], far[c]);
       }
     }
+  }
 #pragma unroll
   for (int c = 0; c < 6; ++c) sig[i * 6 + c] += (double)far[c];
+}
+
+template <typename T>
+static void l2p_launch(int p, int64_t N, const double* pts, const int* pleaf, const uint32_t* key, const T* s,
+                       const double* lo, double sD, double* sig, hipStream_t st) {
+  const unsigned blocks = (unsigned)((N + 255) / 256);
+#define L2P(P_) k_l2p<T, P_><<<blocks, 256, 0, st>>>(pts, N, pleaf, key, s, lo[0], lo[1], lo[2], sD, sig)
+  switch (p) {
+    case 2: L2P(2); break;
+    case 3: L2P(3); break;
+    case 4: L2P(4); break;
+    case 5: L2P(5); break;
+    case 6: L2P(6); break;
+    case 7: L2P(7); break;
+    default: L2P(8); break;
+  }
+#undef L2P
 }
 
 // ---------------------------------------------------------------- forces
@@ -963,29 +986,29 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
   {
     Med<T> m = pl->med<T>();
     Med<double> m64 = pl->med<double>();
-    const bool mixed = !std::is_same<T, double>::value;
-#define LEAF_ARGS                                                                                     \
-  t->pts, N, LD.first, LD.count, LD.key, t->nbr, s + LD.off * 6 * p3, lo[0], lo[1], lo[2], sD, p, m, m64, \
-      sd, t->sig
+#define LEAF_ARGS t->pts, N, LD.first, LD.count, t->nbr, m, m64, sd, t->sig
     SurDev sd = sur_dev(pl);
-    if (mixed && !pl->iso && sd.on)
-      STAGE(6, (k_leaf<T, true, false, true><<<(unsigned)LD.n, 64, sizeof(float) * 2 * kSurHidden * 64, nst>>>(
-                   LEAF_ARGS)));
-    else if (mixed && pl->iso)
-      STAGE(6, (k_leaf<T, true, true, false><<<(unsigned)LD.n, 64, 0, nst>>>(LEAF_ARGS)));
-    else if (mixed)
-      STAGE(6, (k_leaf<T, true, false, false><<<(unsigned)LD.n, 64, 0, nst>>>(LEAF_ARGS)));
-    else if (pl->iso)
-      STAGE(6, (k_leaf<T, false, true, false><<<(unsigned)LD.n, 64, 0, nst>>>(LEAF_ARGS)));
-    else
-      STAGE(6, (k_leaf<T, false, false, false><<<(unsigned)LD.n, 64, 0, nst>>>(LEAF_ARGS)));
+    if constexpr (std::is_same<T, float>::value) {
+      if (!pl->iso && sd.on)
+        STAGE(6, (k_leaf<T, true, false, true><<<(unsigned)LD.n, 64, sizeof(float) * 2 * kSurHidden * 64, nst>>>(
+                     LEAF_ARGS)));
+      else if (pl->iso)
+        STAGE(6, (k_leaf<T, true, true, false><<<(unsigned)LD.n, 64, 0, nst>>>(LEAF_ARGS)));
+      else
+        STAGE(6, (k_leaf<T, true, false, false><<<(unsigned)LD.n, 64, 0, nst>>>(LEAF_ARGS)));
+      if (pl->iso)
+        STAGE(6, (k_close<true><<<(unsigned)LD.n, 64, 0, nst>>>(t->pts, N, LD.first, LD.count, LD.key, t->nbr,
+                                                              lo[0], lo[1], lo[2], sD, m64, t->sig)));
+      else
+        STAGE(6, (k_close<false><<<(unsigned)LD.n, 64, 0, nst>>>(t->pts, N, LD.first, LD.count, LD.key, t->nbr,
+                                                               lo[0], lo[1], lo[2], sD, m64, t->sig)));
+    } else {
+      if (pl->iso)
+        STAGE(6, (k_leaf<T, false, true, false><<<(unsigned)LD.n, 64, 0, nst>>>(LEAF_ARGS)));
+      else
+        STAGE(6, (k_leaf<T, false, false, false><<<(unsigned)LD.n, 64, 0, nst>>>(LEAF_ARGS)));
+    }
 #undef LEAF_ARGS
-    if (mixed && pl->iso)
-      STAGE(6, (k_close<true><<<(unsigned)LD.n, 64, 0, nst>>>(t->pts, N, LD.first, LD.count, LD.key, t->nbr, lo[0],
-                                                            lo[1], lo[2], sD, m64, t->sig)));
-    else if (mixed)
-      STAGE(6, (k_close<false><<<(unsigned)LD.n, 64, 0, nst>>>(t->pts, N, LD.first, LD.count, LD.key, t->nbr, lo[0],
-                                                             lo[1], lo[2], sD, m64, t->sig)));
   }
   {
     int bs = std::max(64, ((p3 + 63) / 64) * 64);
@@ -1028,8 +1051,7 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
     DFMM_HIP(hipStreamWaitEvent(st, t->join, 0));
   }
   {
-    STAGE(6, (k_l2p<T><<<nblk(N, 256), 256, 0, st>>>(t->pts, N, t->pleaf, LD.key, s + LD.off * 6 * p3, lo[0], lo[1],
-                                                     lo[2], sD, p, t->sig)));
+    STAGE(6, l2p_launch<T>(p, N, t->pts, t->pleaf, LD.key, s + LD.off * 6 * p3, lo, sD, t->sig, st));
   }
   STAGE(7, (k_forces<<<nblk(t->nseg, 128), 128, 0, st>>>(seg, burg, nullptr, t->inv, t->sig, pl->quad,
                                                           t->nseg, forces)));
