@@ -292,26 +292,31 @@ constexpr size_t lds_fdft_t(int G, size_t es) {
 }
 
 // ------------------------------------------------------ Hadamard product
-// One block per (window of kM2LWindow Morton-consecutive targets, frequency
-// f).  The spectra of the 158 canonical offsets at frequency f sit in LDS
-// (stride kKStride complex per offset); the spectrum of a mirrored offset -o
-// is -conj of that of o, so its contribution -conj(K) w = -conj(K conj(w)) is
-// folded into the same loop with a sign.  Three lanes share a target, each
-// owning two of its six stress rows, and walk the target's interaction list:
+// One block per (window of kM2LWindowF Morton-consecutive targets, frequency
+// f).  The spectra of the 158 canonical offsets at frequency f sit in LDS;
+// the spectrum of a mirrored offset -o is -conj of that of o, so its
+// contribution -conj(K) w = -conj(K conj(w)) is folded into the same loop
+// with a sign.  Two lanes share a target, each owning three of its six stress
+// rows, and walk the target's interaction list:
 //   Shat[T][f][r] = sum_{(J, o) in I(T)} sum_k Khat_o(f)[r][k] What[f][J][k].
-// Fewer distinct offsets per wave-wide LDS read (about 21 instead of 64) keep
-// bank conflicts down.  With many windows, blocks are remapped so that each
+// (Two lanes rather than three: every lane loads the source's nine values,
+// and that load traffic is one of the limits together with the LDS reads of
+// the spectra and the multiply-adds.)  Each offset's spectrum is stored as two
+// halves of 28 complex values (rows 0-2 and rows 3-5, 27 values each, padded
+// to 16-byte alignment).  With many windows, blocks are remapped so that each
 // of the 8 XCDs (blocks are dispatched round-robin over them) works through a
-// contiguous range of windows at one frequency at a time: neighbouring windows
-// share sources in that XCD's L2.
-constexpr int kHadThreads = 3 * kM2LWindow;
+// contiguous range of windows at one frequency at a time: neighbouring
+// windows share sources in that XCD's L2.
+constexpr int kHadThreads = 2 * kM2LWindowF;
+constexpr int kKHalf = 28;  // complex per half-spectrum in LDS
+
 template <typename T>
 __global__ void __launch_bounds__(kHadThreads) k_hadamard(const cplx<T>* What, const cplx<T>* Khat,
                                                           const int* il_start, const int2* il,
                                                           const uint32_t* order, int64_t ncell, int nf, int nwin,
                                                           int remap, cplx<T>* Shat) {
   extern __shared__ __align__(16) unsigned char shraw[];
-  cplx<T>* Ks = (cplx<T>*)shraw;  // [158][kKStride]
+  cplx<T>* Ks = (cplx<T>*)shraw;  // [158][2][kKHalf]
   int win, f;
   if (remap) {
     const int64_t L = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
@@ -326,9 +331,98 @@ __global__ void __launch_bounds__(kHadThreads) k_hadamard(const cplx<T>* What, c
     f = blockIdx.y;
   }
   const cplx<T>* kf = Khat + (int64_t)f * kNumCanon * 54;
-  for (int e = threadIdx.x; e < kNumCanon * 54; e += blockDim.x) Ks[(e / 54) * kKStride + e % 54] = kf[e];
+  for (int e = threadIdx.x; e < kNumCanon * 2 * kKHalf; e += blockDim.x) {
+    const int cls = e / (2 * kKHalf), rem = e - cls * 2 * kKHalf, half = rem / kKHalf, idx = rem - half * kKHalf;
+    Ks[e] = idx < 27 ? kf[cls * 54 + half * 27 + idx] : cplx<T>{T(0), T(0)};
+  }
   __syncthreads();
-  const int64_t tt = (int64_t)win * kM2LWindow + threadIdx.x / 3;
+  const int64_t tt = (int64_t)win * kM2LWindowF + threadIdx.x / 2;
+  if (tt >= ncell) return;
+  const int h = threadIdx.x & 1;
+  const int64_t t = order[tt];
+  T ar[3] = {0, 0, 0}, ai[3] = {0, 0, 0};
+  const int e0 = il_start[t], e1 = il_start[t + 1];
+  const cplx<T>* wf = What + (int64_t)f * ncell * 9;
+  for (int e = e0; e < e1; ++e) {
+    const int2 jo = il[e];
+    const T sg = (jo.y & 1) ? T(-1) : T(1);
+    const cplx<T>* w = wf + (int64_t)jo.x * 9;
+    T wr[9], wi[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const cplx<T> v = w[k];
+      wr[k] = v.re;
+      wi[k] = sg * v.im;
+    }
+    const cplx<T>* K = Ks + (jo.y >> 1) * 2 * kKHalf + h * kKHalf;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      // row r of this lane's half: 9 complex values, read as 16-byte words
+      T kr[10], ki[10];
+      if constexpr (sizeof(T) == 4) {
+        const float4* K4 = reinterpret_cast<const float4*>(K + r * 9 - (r & 1));
+        // rows start at complex 0, 9, 18: odd rows start 8 bytes into a 16-byte word
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+          const float4 q = K4[i];
+          kr[2 * i] = q.x;
+          ki[2 * i] = q.y;
+          kr[2 * i + 1] = q.z;
+          ki[2 * i + 1] = q.w;
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+          kr[i] = K[r * 9 + i].re;
+          ki[i] = K[r * 9 + i].im;
+        }
+      }
+      const int o = (sizeof(T) == 4) ? (r & 1) : 0;
+      T cr = 0, ci = 0;
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        cr = fma(kr[o + k], wr[k], cr);
+        cr = fma(-ki[o + k], wi[k], cr);
+        ci = fma(kr[o + k], wi[k], ci);
+        ci = fma(ki[o + k], wr[k], ci);
+      }
+      ar[r] = fma(sg, cr, ar[r]);
+      ai[r] += ci;
+    }
+  }
+  cplx<T>* out = Shat + (t * nf + f) * 6 + 3 * h;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) out[r] = cplx<T>{ar[r], ai[r]};
+}
+
+constexpr int kKStride3 = 54;  // complex per offset in LDS for the three-lane kernel
+// Double precision keeps three lanes per target (two rows each): with twice
+// the bytes per value its LDS and register budget favour the shorter rows.
+constexpr int kHad3Threads = 3 * kM2LWindowD;
+template <typename T>
+__global__ void __launch_bounds__(kHad3Threads) k_hadamard3(const cplx<T>* What, const cplx<T>* Khat,
+                                                          const int* il_start, const int2* il,
+                                                          const uint32_t* order, int64_t ncell, int nf, int nwin,
+                                                          int remap, cplx<T>* Shat) {
+  extern __shared__ __align__(16) unsigned char shraw[];
+  cplx<T>* Ks = (cplx<T>*)shraw;  // [158][kKStride3]
+  int win, f;
+  if (remap) {
+    const int64_t L = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+    const int wx = (nwin + 7) / 8;
+    const int xcd = (int)(L % 8);
+    const int64_t k = L / 8;
+    f = (int)(k / wx);
+    win = xcd * wx + (int)(k % wx);
+    if (win >= nwin || f >= nf) return;
+  } else {
+    win = blockIdx.x;
+    f = blockIdx.y;
+  }
+  const cplx<T>* kf = Khat + (int64_t)f * kNumCanon * 54;
+  for (int e = threadIdx.x; e < kNumCanon * 54; e += blockDim.x) Ks[(e / 54) * kKStride3 + e % 54] = kf[e];
+  __syncthreads();
+  const int64_t tt = (int64_t)win * kM2LWindowD + threadIdx.x / 3;
   if (tt >= ncell) return;
   const int r0 = 2 * (threadIdx.x % 3);
   const int64_t t = order[tt];
@@ -342,7 +436,7 @@ __global__ void __launch_bounds__(kHadThreads) k_hadamard(const cplx<T>* What, c
     // rows r0 and r0+1 of the offset's 6x9 block: 18 consecutive complex values,
     // 16-byte aligned, read as 9 (float) or 18 (double) 16-byte LDS loads
     cplx<T> kk[18];
-    const cplx<T>* K = Ks + (jo.y >> 1) * kKStride + r0 * 9;
+    const cplx<T>* K = Ks + (jo.y >> 1) * kKStride3 + r0 * 9;
     if (sizeof(T) == 4) {
       const float4* K4 = reinterpret_cast<const float4*>(K);
 #pragma unroll
@@ -1025,16 +1119,21 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
                                W + Lp.off * 9 * p3, tb.S, st));
     }
   }
-  const size_t shm_h = sizeof(cplx<T>) * kNumCanon * kKStride;
+  const size_t shm_h = sizeof(cplx<T>) * kNumCanon * 2 * kKHalf;
   for (int l = 2; l <= D; ++l) {
     const auto& Lv = t->lv[l];
     if (Lv.n == 0) continue;
     STAGE(2, dft<T>(p, true, (unsigned)Lv.n, W + Lv.off * 9 * p3, Lv.n, tb.tw, What, st));
-    const int nwin = (int)((Lv.n + kM2LWindow - 1) / kM2LWindow);
+    const int wsz = m2l_window(pl->mixed);
+    const int nwin = (int)((Lv.n + wsz - 1) / wsz);
     const int remap = nwin >= 16;
     dim3 g(remap ? 8 * ((nwin + 7) / 8) : nwin, nf);
-    STAGE(3, (k_hadamard<T><<<g, kHadThreads, shm_h, st>>>(What, (const cplx<T>*)pl->lev[l].khat, Lv.il_start,
-                                                           Lv.il, Lv.order, Lv.n, nf, nwin, remap, Shat)));
+    if constexpr (std::is_same<T, float>::value)
+      STAGE(3, (k_hadamard<T><<<g, kHadThreads, shm_h, st>>>(What, (const cplx<T>*)pl->lev[l].khat, Lv.il_start,
+                                                             Lv.il, Lv.order, Lv.n, nf, nwin, remap, Shat)));
+    else
+      STAGE(3, (k_hadamard3<T><<<g, kHad3Threads, sizeof(cplx<T>) * kNumCanon * kKStride3, st>>>(
+                   What, (const cplx<T>*)pl->lev[l].khat, Lv.il_start, Lv.il, Lv.order, Lv.n, nf, nwin, remap, Shat)));
     STAGE(4, dft<T>(p, false, (unsigned)Lv.n, Shat, Lv.n, tb.tw, s + Lv.off * 6 * p3, st));
   }
   {
@@ -1067,6 +1166,7 @@ static void set_lds_attrs() {
   done = true;
   const int mx = 160 * 1024;
   hipFuncSetAttribute((const void*)k_hadamard<T>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+  hipFuncSetAttribute((const void*)k_hadamard3<T>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
   dft_lds_attrs<T>(std::make_integer_sequence<int, kMaxOrder - 1>{});
   hipFuncSetAttribute((const void*)k_p2m<T>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
 }

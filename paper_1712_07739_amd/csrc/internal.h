@@ -15,8 +15,11 @@ namespace dfmm {
 constexpr int kMaxOrder = 8;
 constexpr int kMaxQuad = 8;
 constexpr int kNumOffsets = 316;  // M2L offsets in [-3,3]^3 outside [-1,1]^3
-constexpr int kM2LWindow = 256;  // targets per M2L block
-constexpr int kKStride = 54;      // complex entries per offset in LDS (27 x 16 bytes in float: odd bank step)
+// Targets per M2L block (one window of Morton-consecutive targets): two lanes
+// per target in single precision, three in double, 768 threads either way.
+constexpr int kM2LWindowF = 384;
+constexpr int kM2LWindowD = 256;
+inline int m2l_window(bool mixed) { return mixed ? kM2LWindowF : kM2LWindowD; }
 constexpr int kNumCanon = 158;    // one of each pair (o, -o): the kernel is odd, so the
                                   // spectrum of -o is minus the conjugate of that of o
 constexpr int kNumFar = 189;      // interaction-list size of an interior cell

@@ -342,7 +342,7 @@ __global__ void k_ilist(const uint32_t* keys, int nc, int lvl, const int* oid343
   if (!fill) cnt[i] = k;
 }
 
-// M2L processing order: windows of kM2LWindow Morton-consecutive targets (one
+// M2L processing order: windows of `win` Morton-consecutive targets (one
 // block each, spatially compact), longest lists first inside a window.  The
 // length that orders a target is the longest list among its siblings, so that
 // siblings (which draw on the same source cells, in the same lexicographic
@@ -353,12 +353,12 @@ __global__ void k_sib_len(const int* il_start, const int* parent, int n, int* pm
   atomicMax(&pmax[parent[i]], il_start[i + 1] - il_start[i]);
 }
 
-__global__ void k_len_keys(const int* il_start, const int* parent, const int* pmax, int n, uint32_t* key,
+__global__ void k_len_keys(const int* il_start, const int* parent, const int* pmax, int n, int win, uint32_t* key,
                            uint32_t* val) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int len = parent ? pmax[parent[i]] : il_start[i + 1] - il_start[i];
-  key[i] = ((uint32_t)(i / kM2LWindow) << 8) | (uint32_t)(kNumFar - min(len, kNumFar));
+  key[i] = ((uint32_t)(i / win) << 8) | (uint32_t)(kNumFar - min(len, kNumFar));
   val[i] = (uint32_t)i;
 }
 
@@ -479,10 +479,12 @@ int build_tree_impl(dfmm_plan* pl, const double* seg, int64_t nseg, hipStream_t 
       k_sib_len<<<nb(L.n, 256), 256, 0, st>>>(L.il_start, L.parent, (int)L.n, pmax);
       DFMM_LAUNCH_CHECK();
     }
-    k_len_keys<<<nb(L.n, 256), 256, 0, st>>>(L.il_start, pmax ? L.parent : nullptr, pmax, (int)L.n, okey, L.order);
+    const int win = m2l_window(pl->mixed);
+    k_len_keys<<<nb(L.n, 256), 256, 0, st>>>(L.il_start, pmax ? L.parent : nullptr, pmax, (int)L.n, win, okey,
+                                             L.order);
     DFMM_LAUNCH_CHECK();
     int wbits = 0;
-    while (((L.n + kM2LWindow - 1) / kM2LWindow) >> wbits) ++wbits;
+    while (((L.n + win - 1) / win) >> wbits) ++wbits;
     rc = radix_sort(okey, L.order, L.n, 8 + wbits, st);
     hipFree(pmax);
     if (rc) return rc;
