@@ -299,24 +299,30 @@ constexpr size_t lds_fdft_t(int G, size_t es) {
 // with a sign.  Two lanes share a target, each owning three of its six stress
 // rows, and walk the target's interaction list:
 //   Shat[T][f][r] = sum_{(J, o) in I(T)} sum_k Khat_o(f)[r][k] What[f][J][k].
-// (Two lanes rather than three: every lane loads the source's nine values,
-// and that load traffic is one of the limits together with the LDS reads of
-// the spectra and the multiply-adds.)  Each offset's spectrum is stored as two
-// halves of 28 complex values (rows 0-2 and rows 3-5, 27 values each, padded
-// to 16-byte alignment).  With many windows, blocks are remapped so that each
-// of the 8 XCDs (blocks are dispatched round-robin over them) works through a
-// contiguous range of windows at one frequency at a time: neighbouring
-// windows share sources in that XCD's L2.
+// The load of the source's nine values is one of the kernel's limits (with
+// the LDS reads of the spectra and the multiply-adds), so the two lanes of a
+// target split it: lane h loads components 4h..4h+4 and the halves are
+// swapped between neighbouring lanes with a DPP move.  A lane then holds ten
+// slots, own values then its partner's, with component 4 twice; its spectrum
+// rows are stored in LDS in the same slot order, with a zero in the repeated
+// slot (30 complex per half, rows of 10, 16-byte aligned).  With many windows,
+// blocks are remapped so that each of the 8 XCDs (blocks are dispatched
+// round-robin over them) works through a contiguous range of windows at one
+// frequency at a time: neighbouring windows share sources in that XCD's L2.
 constexpr int kHadThreads = 2 * kM2LWindowF;
-constexpr int kKHalf = 28;  // complex per half-spectrum in LDS
+constexpr int kKHalf = 30;  // complex per half-spectrum in LDS (3 rows x 10 slots)
 
-template <typename T>
-__global__ void __launch_bounds__(kHadThreads) k_hadamard(const cplx<T>* What, const cplx<T>* Khat,
+// Component in slot s (0..9) of lane h of a target pair, or -1 for the repeat.
+__host__ __device__ constexpr int had_slot_comp(int h, int s) {
+  return h == 0 ? (s < 5 ? s : (s == 5 ? -1 : s - 1)) : (s < 5 ? s + 4 : (s < 9 ? s - 5 : -1));
+}
+
+__global__ void __launch_bounds__(kHadThreads) k_hadamard(const cplx<float>* What, const cplx<float>* Khat,
                                                           const int* il_start, const int2* il,
                                                           const uint32_t* order, int64_t ncell, int nf, int nwin,
-                                                          int remap, cplx<T>* Shat) {
+                                                          int remap, cplx<float>* Shat) {
   extern __shared__ __align__(16) unsigned char shraw[];
-  cplx<T>* Ks = (cplx<T>*)shraw;  // [158][2][kKHalf]
+  cplx<float>* Ks = (cplx<float>*)shraw;  // [158][2][kKHalf]
   int win, f;
   if (remap) {
     const int64_t L = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
@@ -330,69 +336,60 @@ __global__ void __launch_bounds__(kHadThreads) k_hadamard(const cplx<T>* What, c
     win = blockIdx.x;
     f = blockIdx.y;
   }
-  const cplx<T>* kf = Khat + (int64_t)f * kNumCanon * 54;
+  const cplx<float>* kf = Khat + (int64_t)f * kNumCanon * 54;
   for (int e = threadIdx.x; e < kNumCanon * 2 * kKHalf; e += blockDim.x) {
     const int cls = e / (2 * kKHalf), rem = e - cls * 2 * kKHalf, half = rem / kKHalf, idx = rem - half * kKHalf;
-    Ks[e] = idx < 27 ? kf[cls * 54 + half * 27 + idx] : cplx<T>{T(0), T(0)};
+    const int row = idx / 10, k = had_slot_comp(half, idx % 10);
+    Ks[e] = k >= 0 ? kf[cls * 54 + (half * 3 + row) * 9 + k] : cplx<float>{0.f, 0.f};
   }
   __syncthreads();
   const int64_t tt = (int64_t)win * kM2LWindowF + threadIdx.x / 2;
-  if (tt >= ncell) return;
+  if (tt >= ncell) return;  // both lanes of a target leave together
   const int h = threadIdx.x & 1;
   const int64_t t = order[tt];
-  T ar[3] = {0, 0, 0}, ai[3] = {0, 0, 0};
+  float ar[3] = {0.f, 0.f, 0.f}, ai[3] = {0.f, 0.f, 0.f};
   const int e0 = il_start[t], e1 = il_start[t + 1];
-  const cplx<T>* wf = What + (int64_t)f * ncell * 9;
-  for (int e = e0; e < e1; ++e) {
+  const cplx<float>* wf = What + (int64_t)f * ncell * 9;
+  for (int e = e0; e < e1; ++e) {  // the two lanes of a target run the same iterations
     const int2 jo = il[e];
-    const T sg = (jo.y & 1) ? T(-1) : T(1);
-    const cplx<T>* w = wf + (int64_t)jo.x * 9;
-    T wr[9], wi[9];
+    const float sg = (jo.y & 1) ? -1.f : 1.f;
+    const cplx<float>* w = wf + (int64_t)jo.x * 9 + 4 * h;
+    float wr[10], wi[10];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      const cplx<T> v = w[k];
+    for (int k = 0; k < 5; ++k) {
+      const cplx<float> v = w[k];
       wr[k] = v.re;
       wi[k] = sg * v.im;
     }
-    const cplx<T>* K = Ks + (jo.y >> 1) * 2 * kKHalf + h * kKHalf;
+    // swap halves with the neighbouring lane (quad permutation 1, 0, 3, 2)
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      wr[5 + k] = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(wr[k]), 0xB1, 0xF, 0xF, false));
+      wi[5 + k] = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(wi[k]), 0xB1, 0xF, 0xF, false));
+    }
+    const float4* K4 = reinterpret_cast<const float4*>(Ks + (jo.y >> 1) * 2 * kKHalf + h * kKHalf);
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
-      // row r of this lane's half: 9 complex values, read as 16-byte words
-      T kr[10], ki[10];
-      if constexpr (sizeof(T) == 4) {
-        const float4* K4 = reinterpret_cast<const float4*>(K + r * 9 - (r & 1));
-        // rows start at complex 0, 9, 18: odd rows start 8 bytes into a 16-byte word
+      float cr = 0.f, ci = 0.f;
 #pragma unroll
-        for (int i = 0; i < 5; ++i) {
-          const float4 q = K4[i];
-          kr[2 * i] = q.x;
-          ki[2 * i] = q.y;
-          kr[2 * i + 1] = q.z;
-          ki[2 * i + 1] = q.w;
-        }
-      } else {
-#pragma unroll
-        for (int i = 0; i < 9; ++i) {
-          kr[i] = K[r * 9 + i].re;
-          ki[i] = K[r * 9 + i].im;
-        }
-      }
-      const int o = (sizeof(T) == 4) ? (r & 1) : 0;
-      T cr = 0, ci = 0;
-#pragma unroll
-      for (int k = 0; k < 9; ++k) {
-        cr = fma(kr[o + k], wr[k], cr);
-        cr = fma(-ki[o + k], wi[k], cr);
-        ci = fma(kr[o + k], wi[k], ci);
-        ci = fma(ki[o + k], wr[k], ci);
+      for (int i = 0; i < 5; ++i) {
+        const float4 q = K4[r * 5 + i];  // slots 2i, 2i+1 of row r
+        cr = fma(q.x, wr[2 * i], cr);
+        cr = fma(-q.y, wi[2 * i], cr);
+        ci = fma(q.x, wi[2 * i], ci);
+        ci = fma(q.y, wr[2 * i], ci);
+        cr = fma(q.z, wr[2 * i + 1], cr);
+        cr = fma(-q.w, wi[2 * i + 1], cr);
+        ci = fma(q.z, wi[2 * i + 1], ci);
+        ci = fma(q.w, wr[2 * i + 1], ci);
       }
       ar[r] = fma(sg, cr, ar[r]);
       ai[r] += ci;
     }
   }
-  cplx<T>* out = Shat + (t * nf + f) * 6 + 3 * h;
+  cplx<float>* out = Shat + (t * nf + f) * 6 + 3 * h;
 #pragma unroll
-  for (int r = 0; r < 3; ++r) out[r] = cplx<T>{ar[r], ai[r]};
+  for (int r = 0; r < 3; ++r) out[r] = cplx<float>{ar[r], ai[r]};
 }
 
 constexpr int kKStride3 = 54;  // complex per offset in LDS for the three-lane kernel
@@ -1119,7 +1116,6 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
                                W + Lp.off * 9 * p3, tb.S, st));
     }
   }
-  const size_t shm_h = sizeof(cplx<T>) * kNumCanon * 2 * kKHalf;
   for (int l = 2; l <= D; ++l) {
     const auto& Lv = t->lv[l];
     if (Lv.n == 0) continue;
@@ -1129,8 +1125,9 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
     const int remap = nwin >= 16;
     dim3 g(remap ? 8 * ((nwin + 7) / 8) : nwin, nf);
     if constexpr (std::is_same<T, float>::value)
-      STAGE(3, (k_hadamard<T><<<g, kHadThreads, shm_h, st>>>(What, (const cplx<T>*)pl->lev[l].khat, Lv.il_start,
-                                                             Lv.il, Lv.order, Lv.n, nf, nwin, remap, Shat)));
+      STAGE(3, (k_hadamard<<<g, kHadThreads, sizeof(cplx<float>) * kNumCanon * 2 * kKHalf, st>>>(
+                   What, (const cplx<float>*)pl->lev[l].khat, Lv.il_start, Lv.il, Lv.order, Lv.n, nf, nwin, remap,
+                   Shat)));
     else
       STAGE(3, (k_hadamard3<T><<<g, kHad3Threads, sizeof(cplx<T>) * kNumCanon * kKStride3, st>>>(
                    What, (const cplx<T>*)pl->lev[l].khat, Lv.il_start, Lv.il, Lv.order, Lv.n, nf, nwin, remap, Shat)));
@@ -1165,7 +1162,7 @@ static void set_lds_attrs() {
   if (done) return;
   done = true;
   const int mx = 160 * 1024;
-  hipFuncSetAttribute((const void*)k_hadamard<T>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+  hipFuncSetAttribute((const void*)k_hadamard, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
   hipFuncSetAttribute((const void*)k_hadamard3<T>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
   dft_lds_attrs<T>(std::make_integer_sequence<int, kMaxOrder - 1>{});
   hipFuncSetAttribute((const void*)k_p2m<T>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
