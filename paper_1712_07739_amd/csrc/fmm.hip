@@ -301,28 +301,24 @@ constexpr size_t lds_fdft_t(int G, size_t es) {
 //   Shat[T][f][r] = sum_{(J, o) in I(T)} sum_k Khat_o(f)[r][k] What[f][J][k].
 // The load of the source's nine values is one of the kernel's limits (with
 // the LDS reads of the spectra and the multiply-adds), so the two lanes of a
-// target split it: lane h loads components 4h..4h+4 and the halves are
-// swapped between neighbouring lanes with a DPP move.  A lane then holds ten
-// slots, own values then its partner's, with component 4 twice; its spectrum
-// rows are stored in LDS in the same slot order, with a zero in the repeated
-// slot (30 complex per half, rows of 10, 16-byte aligned).  With many windows,
-// blocks are remapped so that each of the 8 XCDs (blocks are dispatched
-// round-robin over them) works through a contiguous range of windows at one
-// frequency at a time: neighbouring windows share sources in that XCD's L2.
+// target split it: lane h loads components 4h..4h+3 and component 8, and the
+// four-value halves are swapped between neighbouring lanes with a DPP move.
+// Each lane then holds the nine components in its own slot order, the order
+// in which the spectra are stored (had_slot_of), and the block's copy of them
+// into LDS is a straight copy.  With many windows, blocks are remapped so that
+// each of the 8 XCDs (blocks are dispatched round-robin over them) works
+// through a contiguous range of windows at one frequency at a time:
+// neighbouring windows share sources in that XCD's L2.
+// The spectra take 70.8 KB of LDS per block, so two blocks share a CU: four
+// waves per SIMD, which leaves the software pipeline of the list walk the
+// ~105 registers it needs.
 constexpr int kHadThreads = 2 * kM2LWindowF;
-constexpr int kKHalf = 30;  // complex per half-spectrum in LDS (3 rows x 10 slots)
 
-// Component in slot s (0..9) of lane h of a target pair, or -1 for the repeat.
-__host__ __device__ constexpr int had_slot_comp(int h, int s) {
-  return h == 0 ? (s < 5 ? s : (s == 5 ? -1 : s - 1)) : (s < 5 ? s + 4 : (s < 9 ? s - 5 : -1));
-}
-
-__global__ void __launch_bounds__(kHadThreads) k_hadamard(const cplx<float>* What, const cplx<float>* Khat,
-                                                          const int* il_start, const int2* il,
-                                                          const uint32_t* order, int64_t ncell, int nf, int nwin,
-                                                          int remap, cplx<float>* Shat) {
+__global__ void __launch_bounds__(kHadThreads) __attribute__((amdgpu_waves_per_eu(4, 4)))
+k_hadamard(const cplx<float>* What, const cplx<float>* Khat, const int* il_start, const int2* il,
+           const uint32_t* order, int64_t ncell, int nf, int nwin, int remap, cplx<float>* Shat) {
   extern __shared__ __align__(16) unsigned char shraw[];
-  cplx<float>* Ks = (cplx<float>*)shraw;  // [158][2][kKHalf]
+  float4* Ks4 = (float4*)shraw;  // [158][2][kKHalfF] complex
   int win, f;
   if (remap) {
     const int64_t L = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
@@ -336,12 +332,8 @@ __global__ void __launch_bounds__(kHadThreads) k_hadamard(const cplx<float>* Wha
     win = blockIdx.x;
     f = blockIdx.y;
   }
-  const cplx<float>* kf = Khat + (int64_t)f * kNumCanon * 54;
-  for (int e = threadIdx.x; e < kNumCanon * 2 * kKHalf; e += blockDim.x) {
-    const int cls = e / (2 * kKHalf), rem = e - cls * 2 * kKHalf, half = rem / kKHalf, idx = rem - half * kKHalf;
-    const int row = idx / 10, k = had_slot_comp(half, idx % 10);
-    Ks[e] = k >= 0 ? kf[cls * 54 + (half * 3 + row) * 9 + k] : cplx<float>{0.f, 0.f};
-  }
+  const float4* kf = reinterpret_cast<const float4*>(Khat + (int64_t)f * kNumCanon * kKOffsetF);
+  for (int e = threadIdx.x; e < kNumCanon * kKOffsetF / 2; e += blockDim.x) Ks4[e] = kf[e];
   __syncthreads();
   const int64_t tt = (int64_t)win * kM2LWindowF + threadIdx.x / 2;
   if (tt >= ncell) return;  // both lanes of a target leave together
@@ -349,42 +341,103 @@ __global__ void __launch_bounds__(kHadThreads) k_hadamard(const cplx<float>* Wha
   const int64_t t = order[tt];
   float ar[3] = {0.f, 0.f, 0.f}, ai[3] = {0.f, 0.f, 0.f};
   const int e0 = il_start[t], e1 = il_start[t + 1];
-  const cplx<float>* wf = What + (int64_t)f * ncell * 9;
-  for (int e = e0; e < e1; ++e) {  // the two lanes of a target run the same iterations
-    const int2 jo = il[e];
-    const float sg = (jo.y & 1) ? -1.f : 1.f;
-    const cplx<float>* w = wf + (int64_t)jo.x * 9 + 4 * h;
-    float wr[10], wi[10];
+  // Byte offsets within one frequency's source slice and within a level's
+  // list are 32-bit (the host checks that both fit), so the loads take a
+  // uniform base and one offset register.
+  const char* wfb = reinterpret_cast<const char*>(What + (int64_t)f * ncell * 9);
+  const char* ilb = reinterpret_cast<const char*>(il);
+  const uint32_t hoff = 32u * (uint32_t)h;
+  auto entry = [&](int e) { return *reinterpret_cast<const int2*>(ilb + 8u * (uint32_t)e); };
+  // Software pipeline over the list with two source buffers, A and B: the
+  // values of the next entry and the index after it are loaded while the
+  // current entry is computed.  Indices are clamped to the last entry, so
+  // every load stays in bounds; the two buffers are used alternately (no
+  // copies, so no wait on loads still in flight).
+  typedef float f4a8 __attribute__((ext_vector_type(4), aligned(8)));
+  auto load_src = [&](int2 j, cplx<float>* v) {
+    const uint32_t o = 72u * (uint32_t)j.x;
+    const f4a8 x = *reinterpret_cast<const f4a8*>(wfb + o + hoff);
+    const f4a8 y = *reinterpret_cast<const f4a8*>(wfb + o + hoff + 16u);
+    const float2 z = *reinterpret_cast<const float2*>(wfb + o + 64u);
+    v[0] = {x.x, x.y};
+    v[1] = {x.z, x.w};
+    v[2] = {y.x, y.y};
+    v[3] = {y.z, y.w};
+    v[4] = {z.x, z.y};
+  };
+  auto pair = [&](int2 j, const cplx<float>* v, bool valid) {
+    const float sg = (j.y & 1) ? -1.f : 1.f;
+    const float use = valid ? 1.f : 0.f;
+    float wr[9], wi[9];
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
-      const cplx<float> v = w[k];
-      wr[k] = v.re;
-      wi[k] = sg * v.im;
+      wr[k] = v[k].re;
+      wi[k] = sg * v[k].im;
     }
     // swap halves with the neighbouring lane (quad permutation 1, 0, 3, 2)
 #pragma unroll
-    for (int k = 0; k < 5; ++k) {
+    for (int k = 0; k < 4; ++k) {
       wr[5 + k] = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(wr[k]), 0xB1, 0xF, 0xF, false));
       wi[5 + k] = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(wi[k]), 0xB1, 0xF, 0xF, false));
     }
-    const float4* K4 = reinterpret_cast<const float4*>(Ks + (jo.y >> 1) * 2 * kKHalf + h * kKHalf);
+    // the lane's 27 complex spectrum entries: 13 float4 and one float2
+    const float4* K4 = Ks4 + ((j.y >> 1) * kKOffsetF + h * kKHalfF) / 2;
+    float kk[54];
+#pragma unroll
+    for (int i = 0; i < 13; ++i) {
+      const float4 q = K4[i];
+      kk[4 * i] = q.x;
+      kk[4 * i + 1] = q.y;
+      kk[4 * i + 2] = q.z;
+      kk[4 * i + 3] = q.w;
+    }
+    {
+      const float2 q = reinterpret_cast<const float2*>(K4)[26];
+      kk[52] = q.x;
+      kk[53] = q.y;
+    }
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
       float cr = 0.f, ci = 0.f;
 #pragma unroll
-      for (int i = 0; i < 5; ++i) {
-        const float4 q = K4[r * 5 + i];  // slots 2i, 2i+1 of row r
-        cr = fma(q.x, wr[2 * i], cr);
-        cr = fma(-q.y, wi[2 * i], cr);
-        ci = fma(q.x, wi[2 * i], ci);
-        ci = fma(q.y, wr[2 * i], ci);
-        cr = fma(q.z, wr[2 * i + 1], cr);
-        cr = fma(-q.w, wi[2 * i + 1], cr);
-        ci = fma(q.z, wi[2 * i + 1], ci);
-        ci = fma(q.w, wr[2 * i + 1], ci);
+      for (int s = 0; s < 9; ++s) {
+        const float kr = kk[2 * (9 * r + s)], ki = kk[2 * (9 * r + s) + 1];
+        cr = fma(kr, wr[s], cr);
+        cr = fma(-ki, wi[s], cr);
+        ci = fma(kr, wi[s], ci);
+        ci = fma(ki, wr[s], ci);
       }
-      ar[r] = fma(sg, cr, ar[r]);
-      ai[r] += ci;
+      ar[r] = fma(sg * use, cr, ar[r]);
+      ai[r] = fma(use, ci, ai[r]);
+    }
+  };
+  if (e0 < e1) {
+    cplx<float> va[5], vb[5];
+    int2 ja = entry(e0);
+    int2 jb = entry(min(e0 + 1, e1 - 1));
+    load_src(ja, va);
+    // Two entries per iteration in one straight block (no exit between the
+    // loads and their use, so the loads stay ahead of the arithmetic); an odd
+    // list computes its last entry twice and weighs the copy by zero.  The two
+    // lanes of a target run the same iterations.
+    for (int e = e0; e < e1; e += 2) {
+      const int2 jna = entry(min(e + 2, e1 - 1));
+      const int2 jnb = entry(min(e + 3, e1 - 1));
+      load_src(jb, vb);
+      __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the arithmetic
+      pair(ja, va, true);
+      __builtin_amdgcn_sched_barrier(0);
+      load_src(jna, va);
+      __builtin_amdgcn_sched_barrier(0);
+      pair(jb, vb, e + 1 < e1);
+      ja = jna;
+      jb = jnb;
+      // Values carried into the next iteration pass through an empty asm
+      // statement: it keeps the compiler from folding them back into loads at
+      // the top of the loop (which would undo the pipeline).
+      asm volatile("" : "+v"(ja.x), "+v"(ja.y), "+v"(jb.x), "+v"(jb.y));
+#pragma unroll
+      for (int k = 0; k < 5; ++k) asm volatile("" : "+v"(va[k].re), "+v"(va[k].im));
     }
   }
   cplx<float>* out = Shat + (t * nf + f) * 6 + 3 * h;
@@ -1125,7 +1178,7 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
     const int remap = nwin >= 16;
     dim3 g(remap ? 8 * ((nwin + 7) / 8) : nwin, nf);
     if constexpr (std::is_same<T, float>::value)
-      STAGE(3, (k_hadamard<<<g, kHadThreads, sizeof(cplx<float>) * kNumCanon * 2 * kKHalf, st>>>(
+      STAGE(3, (k_hadamard<<<g, kHadThreads, sizeof(cplx<float>) * kNumCanon * kKOffsetF, st>>>(
                    What, (const cplx<float>*)pl->lev[l].khat, Lv.il_start, Lv.il, Lv.order, Lv.n, nf, nwin, remap,
                    Shat)));
     else

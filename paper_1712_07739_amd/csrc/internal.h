@@ -16,13 +16,27 @@ constexpr int kMaxOrder = 8;
 constexpr int kMaxQuad = 8;
 constexpr int kNumOffsets = 316;  // M2L offsets in [-3,3]^3 outside [-1,1]^3
 // Targets per M2L block (one window of Morton-consecutive targets): two lanes
-// per target in single precision, three in double, 768 threads either way.
-constexpr int kM2LWindowF = 384;
+// per target in single precision (512 threads), three in double (768).  Both
+// are whole multiples of four waves, so a CU's four SIMDs get equal shares.
+constexpr int kM2LWindowF = 256;
 constexpr int kM2LWindowD = 256;
 inline int m2l_window(bool mixed) { return mixed ? kM2LWindowF : kM2LWindowD; }
 constexpr int kNumCanon = 158;    // one of each pair (o, -o): the kernel is odd, so the
                                   // spectrum of -o is minus the conjugate of that of o
 constexpr int kNumFar = 189;      // interaction-list size of an interior cell
+
+// Single-precision spectra are stored in the order in which the M2L Hadamard
+// kernel reads them.  Two lanes share a target; lane h owns stress rows
+// 3h..3h+2 and loads source components 4h..4h+3 and 8, then receives the
+// partner's four components by a lane swap.  Its nine slots hold components
+//   slot 0..3: 4h..4h+3,  slot 4: 8,  slot 5..8: 4(1-h)..4(1-h)+3.
+// Per frequency and canonical offset: [2 halves][3 rows][9 slots] complex,
+// each half padded to kKHalfF entries (16-byte aligned; the pad is zero).
+constexpr int kKHalfF = 28;
+constexpr int kKOffsetF = 2 * kKHalfF;
+__host__ __device__ constexpr int had_slot_of(int h, int k) {
+  return k == 8 ? 4 : ((k >> 2) == h ? k - 4 * h : 5 + k - 4 * (1 - h));
+}
 
 struct Quad {
   double u[kMaxQuad], w[kMaxQuad];
@@ -56,8 +70,9 @@ struct Surrogate {
 };
 
 struct LevelTables {
-  void* khat = nullptr;  // [nf][158][54] complex (float2 or double2): DFT of the
-                         // circulant embedding of each canonical offset's generator
+  void* khat = nullptr;  // DFT of the circulant embedding of each canonical offset's
+                         // generator: double [nf][158][54] complex (row-major 6 x 9);
+                         // float [nf][158][kKOffsetF] complex in slot order
 };
 
 }  // namespace dfmm

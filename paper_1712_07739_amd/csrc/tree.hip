@@ -464,6 +464,13 @@ int build_tree_impl(dfmm_plan* pl, const double* seg, int64_t nseg, hipStream_t 
     rc = scan_excl(cnt, L.il_start, L.n + 1, st, &tot);
     if (rc) return rc;
     int64_t pairs = tot;
+    // The M2L kernels address a level's list and one frequency's slice of the
+    // source spectra (9 complex per cell) with 32-bit byte offsets.
+    if (pairs * (int64_t)sizeof(int2) >= ((int64_t)1 << 32) || L.n * 9 * 16 >= ((int64_t)1 << 32)) {
+      hipFree(cnt);
+      set_error("build_tree: a level's interaction list or cell count exceeds the M2L kernels' 32-bit offsets");
+      return DFMM_E_ARG;
+    }
     L.npairs = pairs;
     t->npairs += pairs;
     DFMM_HIP(hipMalloc(&L.il, sizeof(int2) * std::max<int64_t>(pairs, 1)));
