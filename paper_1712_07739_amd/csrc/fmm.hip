@@ -309,7 +309,7 @@ constexpr size_t lds_fdft_t(int G, size_t es) {
 // each of the 8 XCDs (blocks are dispatched round-robin over them) works
 // through a contiguous range of windows at one frequency at a time:
 // neighbouring windows share sources in that XCD's L2.
-// The spectra take 70.8 KB of LDS per block, so two blocks share a CU: four
+// The spectra take 73.3 KB of LDS per block, so two blocks share a CU: four
 // waves per SIMD, which leaves the software pipeline of the list walk the
 // ~105 registers it needs.
 constexpr int kHadThreads = 2 * kM2LWindowF;

@@ -31,9 +31,12 @@ constexpr int kNumFar = 189;      // interaction-list size of an interior cell
 // partner's four components by a lane swap.  Its nine slots hold components
 //   slot 0..3: 4h..4h+3,  slot 4: 8,  slot 5..8: 4(1-h)..4(1-h)+3.
 // Per frequency and canonical offset: [2 halves][3 rows][9 slots] complex,
-// each half padded to kKHalfF entries (16-byte aligned; the pad is zero).
+// each half padded to kKHalfF entries (16-byte aligned; the pads are zero).
+// An offset takes 29 16-byte units: lanes read the spectra of unrelated
+// offsets at once, and an odd stride spreads those reads evenly over the LDS
+// banks (an even one leaves half of them idle and doubles up the rest).
 constexpr int kKHalfF = 28;
-constexpr int kKOffsetF = 2 * kKHalfF;
+constexpr int kKOffsetF = 2 * kKHalfF + 2;
 __host__ __device__ constexpr int had_slot_of(int h, int k) {
   return k == 8 ? 4 : ((k >> 2) == h ? k - 4 * h : 5 + k - 4 * (1 - h));
 }
