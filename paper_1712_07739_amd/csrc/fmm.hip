@@ -313,9 +313,11 @@ constexpr size_t lds_fdft_t(int G, size_t es) {
 // waves per SIMD, which leaves the software pipeline of the list walk the
 // ~105 registers it needs.
 constexpr int kHadThreads = 2 * kM2LWindowF;
+static_assert(kM2LWindowF % kWaveTargets == 0 && 2 * kWaveTargets == 64,
+              "a wave holds kWaveTargets targets, two lanes each");
 
 __global__ void __launch_bounds__(kHadThreads) __attribute__((amdgpu_waves_per_eu(4, 4)))
-k_hadamard(const cplx<float>* What, const cplx<float>* Khat, const int* il_start, const int2* il,
+k_hadamard(const cplx<float>* What, const cplx<float>* Khat, const int* lenq, const int* wbase, const int2* ilw,
            const uint32_t* order, int64_t ncell, int nf, int nwin, int remap, cplx<float>* Shat) {
   extern __shared__ __align__(16) unsigned char shraw[];
   float4* Ks4 = (float4*)shraw;  // [158][2][kKHalfF] complex
@@ -339,40 +341,42 @@ k_hadamard(const cplx<float>* What, const cplx<float>* Khat, const int* il_start
   if (tt >= ncell) return;  // both lanes of a target leave together
   const int h = threadIdx.x & 1;
   const int64_t t = order[tt];
+  const int len = lenq[tt];
   float ar[3] = {0.f, 0.f, 0.f}, ai[3] = {0.f, 0.f, 0.f};
-  const int e0 = il_start[t], e1 = il_start[t + 1];
-  // Byte offsets within one frequency's source slice and within a level's
-  // list are 32-bit (the host checks that both fit), so the loads take a
-  // uniform base and one offset register.
+  // List entries hold byte offsets: the source's row within one frequency's
+  // slice of the source spectra (32-bit: the host checks that the slice and
+  // the lists fit), and the offset's spectra in LDS with the mirror flag in
+  // bit 0.  The wave's 32 targets have their entries of one step side by side
+  // (one pair of cache lines per load).  Loads take a uniform base and one
+  // offset register.
   const char* wfb = reinterpret_cast<const char*>(What + (int64_t)f * ncell * 9);
-  const char* ilb = reinterpret_cast<const char*>(il);
+  const char* ilb = reinterpret_cast<const char*>(ilw);
+  constexpr uint32_t kStep = kWaveTargets * sizeof(int2);  // bytes per step of a wave's block
+  const char* kb = reinterpret_cast<const char*>(shraw) + h * (kKHalfF * 8);
   const uint32_t hoff = 32u * (uint32_t)h;
-  auto entry = [&](int e) { return *reinterpret_cast<const int2*>(ilb + 8u * (uint32_t)e); };
-  // Software pipeline over the list with two source buffers, A and B: the
-  // values of the next entry and the index after it are loaded while the
-  // current entry is computed.  Indices are clamped to the last entry, so
-  // every load stays in bounds; the two buffers are used alternately (no
-  // copies, so no wait on loads still in flight).
+  auto entry = [&](uint32_t eb) { return *reinterpret_cast<const int2*>(ilb + eb); };
   typedef float f4a8 __attribute__((ext_vector_type(4), aligned(8)));
   auto load_src = [&](int2 j, cplx<float>* v) {
-    const uint32_t o = 72u * (uint32_t)j.x;
-    const f4a8 x = *reinterpret_cast<const f4a8*>(wfb + o + hoff);
-    const f4a8 y = *reinterpret_cast<const f4a8*>(wfb + o + hoff + 16u);
-    const float2 z = *reinterpret_cast<const float2*>(wfb + o + 64u);
+    const uint32_t o = (uint32_t)j.x;
+    const f4a8 x = *reinterpret_cast<const f4a8*>(wfb + (o + hoff));
+    const f4a8 y = *reinterpret_cast<const f4a8*>(wfb + (o + hoff) + 16);
+    const float2 z = *reinterpret_cast<const float2*>(wfb + o + 64);
     v[0] = {x.x, x.y};
     v[1] = {x.z, x.w};
     v[2] = {y.x, y.y};
     v[3] = {y.z, y.w};
     v[4] = {z.x, z.y};
   };
-  auto pair = [&](int2 j, const cplx<float>* v, bool valid) {
-    const float sg = (j.y & 1) ? -1.f : 1.f;
-    const float use = valid ? 1.f : 0.f;
+  auto pair = [&](int2 j, const cplx<float>* v, float use) {
+    // mirrored offset: conjugate the source values (sign bit of the imaginary
+    // parts) and negate the real part of the result
+    const uint32_t sgb = ((uint32_t)j.y & 1u) << 31;
+    const float sg = __uint_as_float(0x3f800000u | sgb) * use;
     float wr[9], wi[9];
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
       wr[k] = v[k].re;
-      wi[k] = sg * v[k].im;
+      wi[k] = __uint_as_float(__float_as_uint(v[k].im) ^ sgb);
     }
     // swap halves with the neighbouring lane (quad permutation 1, 0, 3, 2)
 #pragma unroll
@@ -381,7 +385,7 @@ k_hadamard(const cplx<float>* What, const cplx<float>* Khat, const int* il_start
       wi[5 + k] = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(wi[k]), 0xB1, 0xF, 0xF, false));
     }
     // the lane's 27 complex spectrum entries: 13 float4 and one float2
-    const float4* K4 = Ks4 + ((j.y >> 1) * kKOffsetF + h * kKHalfF) / 2;
+    const float4* K4 = reinterpret_cast<const float4*>(kb + ((uint32_t)j.y & ~1u));
     float kk[54];
 #pragma unroll
     for (int i = 0; i < 13; ++i) {
@@ -407,29 +411,33 @@ k_hadamard(const cplx<float>* What, const cplx<float>* Khat, const int* il_start
         ci = fma(kr, wi[s], ci);
         ci = fma(ki, wr[s], ci);
       }
-      ar[r] = fma(sg * use, cr, ar[r]);
+      ar[r] = fma(sg, cr, ar[r]);
       ai[r] = fma(use, ci, ai[r]);
     }
   };
-  if (e0 < e1) {
+  // Software pipeline over the list with two source buffers, A and B: the
+  // values of the next entry and the entries after it are loaded while the
+  // current entry is computed.  Entries up to three past the end of the list
+  // are read (the zero padding of the wave's block: valid offsets); the extra
+  // entry of an odd list is weighed by zero.  The two buffers are used
+  // alternately (no copies, so no wait on loads still in flight), and each
+  // iteration is one straight block (no exit between the loads and their
+  // use).  The two lanes of a target run the same iterations.
+  if (len > 0) {
     cplx<float> va[5], vb[5];
-    int2 ja = entry(e0);
-    int2 jb = entry(min(e0 + 1, e1 - 1));
+    uint32_t eb = kStep * (uint32_t)wbase[tt / kWaveTargets] + sizeof(int2) * (uint32_t)(tt % kWaveTargets);
+    int2 ja = entry(eb), jb = entry(eb + kStep);
     load_src(ja, va);
-    // Two entries per iteration in one straight block (no exit between the
-    // loads and their use, so the loads stay ahead of the arithmetic); an odd
-    // list computes its last entry twice and weighs the copy by zero.  The two
-    // lanes of a target run the same iterations.
-    for (int e = e0; e < e1; e += 2) {
-      const int2 jna = entry(min(e + 2, e1 - 1));
-      const int2 jnb = entry(min(e + 3, e1 - 1));
+    for (int e = 0; e < len; e += 2, eb += 2 * kStep) {
+      const int2 jna = entry(eb + 2 * kStep);
+      const int2 jnb = entry(eb + 3 * kStep);
       load_src(jb, vb);
       __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the arithmetic
-      pair(ja, va, true);
+      pair(ja, va, 1.f);
       __builtin_amdgcn_sched_barrier(0);
       load_src(jna, va);
       __builtin_amdgcn_sched_barrier(0);
-      pair(jb, vb, e + 1 < e1);
+      pair(jb, vb, e + 1 < len ? 1.f : 0.f);
       ja = jna;
       jb = jnb;
       // Values carried into the next iteration pass through an empty asm
@@ -1179,8 +1187,8 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
     dim3 g(remap ? 8 * ((nwin + 7) / 8) : nwin, nf);
     if constexpr (std::is_same<T, float>::value)
       STAGE(3, (k_hadamard<<<g, kHadThreads, sizeof(cplx<float>) * kNumCanon * kKOffsetF, st>>>(
-                   What, (const cplx<float>*)pl->lev[l].khat, Lv.il_start, Lv.il, Lv.order, Lv.n, nf, nwin, remap,
-                   Shat)));
+                   What, (const cplx<float>*)pl->lev[l].khat, Lv.lenq, Lv.wbase, Lv.ilw, Lv.order, Lv.n, nf, nwin,
+                   remap, Shat)));
     else
       STAGE(3, (k_hadamard3<T><<<g, kHad3Threads, sizeof(cplx<T>) * kNumCanon * kKStride3, st>>>(
                    What, (const cplx<T>*)pl->lev[l].khat, Lv.il_start, Lv.il, Lv.order, Lv.n, nf, nwin, remap, Shat)));

@@ -40,6 +40,11 @@ constexpr int kKOffsetF = 2 * kKHalfF + 2;
 __host__ __device__ constexpr int had_slot_of(int h, int k) {
   return k == 8 ? 4 : ((k >> 2) == h ? k - 4 * h : 5 + k - 4 * (1 - h));
 }
+// The single-precision M2L kernel walks the lists of 32 consecutive targets
+// of the processing order in one wave; their entries are stored step-major per
+// wave (see Level::ilw), and entries up to kIlwPad past a list's end are read.
+constexpr int kWaveTargets = 32;
+constexpr int kIlwPad = 3;
 
 struct Quad {
   double u[kMaxQuad], w[kMaxQuad];
@@ -118,8 +123,18 @@ struct dfmm_tree {
     int* count = nullptr;      // leaves: #points; others: #children
     int* parent = nullptr;     // parent index at level l-1 (levels 3..D)
     int* il_start = nullptr;   // [n+1] interaction-list CSR
-    int2* il = nullptr;        // (source index at this level, 2*canonical offset id + mirrored)
+    int2* il = nullptr;        // (source index at this level, 2*canonical offset id + mirrored);
+                               // double-precision plans only
     uint32_t* order = nullptr; // targets in M2L processing order (list length buckets, then Morton)
+    // Single-precision plans: the lists laid out for the M2L kernel, one block
+    // per wave of kWaveTargets consecutive targets of the processing order.
+    // Entry s of the target in slot k of wave w is ilw[kWaveTargets *
+    // (wbase[w] + s) + k], as byte offsets (72 * source, kKOffsetF * 8 * id +
+    // mirrored); a block has the wave's longest list + kIlwPad steps, the
+    // unused entries zero (valid offsets).
+    int2* ilw = nullptr;
+    int* wbase = nullptr;      // [waves + 1] first step of each wave's block
+    int* lenq = nullptr;       // [n] list length by processing position
     int64_t npairs = 0;
   };
   std::vector<Level> lv;

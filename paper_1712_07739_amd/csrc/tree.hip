@@ -362,6 +362,34 @@ __global__ void k_len_keys(const int* il_start, const int* parent, const int* pm
   val[i] = (uint32_t)i;
 }
 
+// Single-precision plans: per wave of kWaveTargets consecutive targets of the
+// processing order, the longest list (+ the prefetch pad), and each target's
+// list length by processing position.
+__global__ void k_wave_len(const uint32_t* order, const int* il_start, int n, int* lenq, int* wlen) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  const uint32_t t = order[q];
+  const int len = il_start[t + 1] - il_start[t];
+  lenq[q] = len;
+  atomicMax(&wlen[q / kWaveTargets], len + kIlwPad);
+}
+
+// Copy each target's list into its wave's block, step-major, as the byte
+// offsets the M2L kernel uses (the source's row in one frequency's slice of
+// the source spectra, the offset's spectra in LDS), the mirror flag in bit 0.
+__global__ void k_il_wave(const uint32_t* order, const int* il_start, const int2* il, const int* wbase, int n,
+                          int2* ilw) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  const uint32_t t = order[q];
+  const int b = il_start[t], len = il_start[t + 1] - b;
+  int2* dst = ilw + (int64_t)kWaveTargets * wbase[q / kWaveTargets] + q % kWaveTargets;
+  for (int i = 0; i < len; ++i) {
+    const int2 v = il[b + i];
+    dst[(int64_t)kWaveTargets * i] = make_int2(v.x * 72, (v.y >> 1) * (kKOffsetF * 8) + (v.y & 1));
+  }
+}
+
 static inline unsigned nb(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 int build_tree_impl(dfmm_plan* pl, const double* seg, int64_t nseg, hipStream_t st, dfmm_tree* t, bool workspaces) {
@@ -495,6 +523,31 @@ int build_tree_impl(dfmm_plan* pl, const double* seg, int64_t nseg, hipStream_t 
     rc = radix_sort(okey, L.order, L.n, 8 + wbits, st);
     hipFree(pmax);
     if (rc) return rc;
+    if (pl->mixed) {  // the wave-blocked lists of the single-precision M2L kernel
+      const int64_t nw = (L.n + kWaveTargets - 1) / kWaveTargets;
+      int* wlen = nullptr;
+      DFMM_HIP(hipMalloc(&wlen, sizeof(int) * (nw + 1)));
+      DFMM_HIP(hipMemsetAsync(wlen, 0, sizeof(int) * (nw + 1), st));
+      DFMM_HIP(hipMalloc(&L.lenq, sizeof(int) * L.n));
+      DFMM_HIP(hipMalloc(&L.wbase, sizeof(int) * (nw + 1)));
+      k_wave_len<<<nb(L.n, 256), 256, 0, st>>>(L.order, L.il_start, (int)L.n, L.lenq, wlen);
+      DFMM_LAUNCH_CHECK();
+      int64_t steps = 0;
+      rc = scan_excl(wlen, L.wbase, nw + 1, st, &steps);
+      hipFree(wlen);
+      if (rc) return rc;
+      if (steps * kWaveTargets * (int64_t)sizeof(int2) >= ((int64_t)1 << 32)) {
+        set_error("build_tree: a level's M2L lists exceed the kernel's 32-bit offsets");
+        return DFMM_E_ARG;
+      }
+      DFMM_HIP(hipMalloc(&L.ilw, sizeof(int2) * kWaveTargets * std::max<int64_t>(steps, 1)));
+      DFMM_HIP(hipMemsetAsync(L.ilw, 0, sizeof(int2) * kWaveTargets * std::max<int64_t>(steps, 1), st));
+      k_il_wave<<<nb(L.n, 128), 128, 0, st>>>(L.order, L.il_start, L.il, L.wbase, (int)L.n, L.ilw);
+      DFMM_LAUNCH_CHECK();
+      DFMM_HIP(hipStreamSynchronize(st));
+      hipFree(L.il);
+      L.il = nullptr;
+    }
     hipFree(cnt);
   }
   // near-field pair count (for reporting)
