@@ -150,7 +150,8 @@ int dfmm_build_tree(dfmm_plan* plan, const double* seg, int64_t n_seg, void* str
 
 void dfmm_tree_destroy(dfmm_tree* t) {
   if (!t) return;
-  if (t->last_stream) hipStreamSynchronize(t->last_stream);
+  if (t->done_set) hipEventSynchronize(t->done);
+  if (t->done) hipEventDestroy(t->done);
   if (t->side) {
     hipStreamSynchronize(t->side);
     hipStreamDestroy(t->side);
@@ -197,7 +198,7 @@ int dfmm_tree_set_timing(dfmm_tree* t, int on) {
 
 int dfmm_tree_stage_times(dfmm_tree* t, double* ms, int* n_calls) {
   if (!t || !ms) { set_error("tree_stage_times: null argument"); return DFMM_E_ARG; }
-  if (t->last_stream) DFMM_HIP(hipStreamSynchronize(t->last_stream));
+  if (t->done_set) DFMM_HIP(hipEventSynchronize(t->done));
   for (int i = 0; i < DFMM_N_STAGES; ++i) ms[i] = t->stage_ms[i];
   if (n_calls) *n_calls = t->timed_calls;
   return DFMM_OK;

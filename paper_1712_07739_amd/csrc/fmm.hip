@@ -1212,7 +1212,10 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
   }
   STAGE(7, (k_forces<<<nblk(t->nseg, 128), 128, 0, st>>>(seg, burg, nullptr, t->inv, t->sig, pl->quad,
                                                           t->nseg, forces)));
-  t->last_stream = st;
+  if (capture == hipStreamCaptureStatusNone && t->done) {
+    DFMM_HIP(hipEventRecord(t->done, st));
+    t->done_set = true;
+  }
   (void)n;
   return tm.finish();
 }

@@ -157,7 +157,11 @@ struct dfmm_tree {
   hipEvent_t ev[DFMM_N_STAGES + 1] = {};
   double stage_ms[DFMM_N_STAGES] = {};
   int timed_calls = 0;
-  hipStream_t last_stream = nullptr;
+  // recorded at the end of every call that is not being captured into a
+  // graph: destroy and the query calls wait on it (an event the tree owns,
+  // valid whatever becomes of the caller's streams)
+  hipEvent_t done = nullptr;
+  bool done_set = false;
   // second stream for the near field, which runs beside the far-field
   // pipeline (fork after the point gather, join before L2P)
   hipStream_t side = nullptr;

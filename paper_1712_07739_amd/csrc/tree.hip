@@ -580,6 +580,7 @@ int build_tree_impl(dfmm_plan* pl, const double* seg, int64_t nseg, hipStream_t 
   DFMM_HIP(hipStreamCreateWithFlags(&t->side, hipStreamNonBlocking));
   DFMM_HIP(hipEventCreateWithFlags(&t->fork, hipEventDisableTiming));
   DFMM_HIP(hipEventCreateWithFlags(&t->join, hipEventDisableTiming));
+  DFMM_HIP(hipEventCreateWithFlags(&t->done, hipEventDisableTiming));
   DFMM_HIP(hipMalloc(&t->pts, sizeof(double) * 9 * N));
   DFMM_HIP(hipMalloc(&t->pleaf, sizeof(int) * N));
   k_point_leaf<<<(unsigned)LD.n, 64, 0, st>>>(LD.first, LD.count, (int)LD.n, t->pleaf);

@@ -49,7 +49,14 @@ def test_batched_graph_equals_individual_calls_on_every_replay(env):
     p, tree, ts, tb, out, ref, seg, b = cfg[2]
     ref_o = oracle.fmm_forces(seg, b, oracle.medium(*ISO, 1e-3), 4, 4, BOX_LO, BOX)
     assert oracle.rel_err(out.cpu().numpy(), ref_o) <= 2e-5
+    # The batch's streams go with it; the trees it captured stay usable and
+    # are destroyed afterwards without touching those streams.
     batch.close()
+    again = pk.fmm_forces(p, tree, ts, tb).cpu().numpy()
+    assert np.array_equal(again, ref)
+    for c in cfg:
+        c[1].info()
+        c[1].close()
 
 
 def _measured_ms(pk, torch, prm_args, d, ts, tb, reps=3):
