@@ -218,67 +218,82 @@ __device__ __forceinline__ int64_t xcd_block(int64_t L, int64_t n) {
 // One block per cell of a level: W[cell][9][P^3] (real, zero-padded to n^3,
 // n = 2P - 1) -> What[f][cell][9], f = (f1 n + f2) P + f3, the half spectrum
 // in the last axis (the input is real).  Three passes of length-P to
-// length-n (or P) DFTs through LDS, G components at a time; the twiddles
-// exp(-2 pi i f m / n), f < n, m < P, are tabulated once per block.  Rows of
+// length-n (or P) DFTs, G components at a time.  A thread takes one input
+// line of a pass, holds its P values in registers and produces all of the
+// line's outputs, so each value is read once; the twiddles
+// exp(-2 pi i k / n), k < n, are read once into (scalar) registers, and the
+// fully unrolled loops index them with constants.  The first pass reads W
+// straight from memory; the intermediate lines go through LDS.  Rows of
 // neighbouring cells share cache lines, so cells are spread over the XCDs in
 // contiguous ranges (xcd_block).
+template <typename T>
+__device__ __forceinline__ void cmac(const cplx<T>& a, T c, T s, T& re, T& im) {
+  re = fma(a.re, c, fma(-a.im, s, re));
+  im = fma(a.re, s, fma(a.im, c, im));
+}
+
 template <typename T, int P>
-__global__ void __launch_bounds__(256) k_fdft(const T* W, int64_t ncell, int G, const T* twg, cplx<T>* What) {
-  constexpr int n = 2 * P - 1, p3 = P * P * P, nf = n * n * P;
+__global__ void __launch_bounds__(256) k_fdft(const T* __restrict__ W, int64_t ncell, int G,
+                                              const T* __restrict__ twg, cplx<T>* __restrict__ What) {
+  constexpr int n = 2 * P - 1, p3 = P * P * P;
   extern __shared__ __align__(16) unsigned char shraw[];
-  cplx<T>* tm = (cplx<T>*)shraw;  // [n][P]
-  cplx<T>* X1 = tm + n * P;       // [G][P][P][P]  (m1, m2, f3)
-  T* Wl = (T*)(X1 + G * p3);      // [G][P^3]; the same space then holds
-  cplx<T>* X2 = (cplx<T>*)Wl;     // [G][P][n][P]  (m1, f2, f3)
-  const int64_t cell = xcd_block(blockIdx.x, ncell);
-  for (int e = threadIdx.x; e < n * P; e += blockDim.x) {
-    const int k = ((e / P) * (e % P)) % n;
-    tm[e] = cplx<T>{twg[2 * k], twg[2 * k + 1]};
+  cplx<T>* X1 = (cplx<T>*)shraw;  // [G][P][P][P]  (g, m1, m2, f3)
+  cplx<T>* X2 = X1 + G * p3;      // [G][P][n][P]  (g, m1, f2, f3)
+  T c[n], s[n];
+#pragma unroll
+  for (int k = 0; k < n; ++k) {
+    c[k] = twg[2 * k];
+    s[k] = twg[2 * k + 1];
   }
+  const int64_t cell = xcd_block(blockIdx.x, ncell);
   for (int c0 = 0; c0 < 9; c0 += G) {
     const T* src = W + (cell * 9 + c0) * p3;
-    for (int e = threadIdx.x; e < G * p3; e += blockDim.x) Wl[e] = src[e];
-    __syncthreads();
-    for (int e = threadIdx.x; e < G * p3; e += blockDim.x) {
-      const int f3 = e % P;
-      const T* row = Wl + (e / P) * P;
-      const cplx<T>* t = tm + f3 * P;
-      T re = 0, im = 0;
+    // along the last axis: P real values -> P half-spectrum values
+    for (int it = threadIdx.x; it < G * P * P; it += blockDim.x) {
+      T x[P];
 #pragma unroll
-      for (int m = 0; m < P; ++m) {
-        re = fma(row[m], t[m].re, re);
-        im = fma(row[m], t[m].im, im);
+      for (int m = 0; m < P; ++m) x[m] = src[it * P + m];
+#pragma unroll
+      for (int f = 0; f < P; ++f) {
+        T re = 0, im = 0;
+#pragma unroll
+        for (int m = 0; m < P; ++m) {
+          re = fma(x[m], c[(f * m) % n], re);
+          im = fma(x[m], s[(f * m) % n], im);
+        }
+        X1[it * P + f] = cplx<T>{re, im};
       }
-      X1[e] = cplx<T>{re, im};
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < G * P * n * P; e += blockDim.x) {
-      const int f3 = e % P, f2 = (e / P) % n, gm1 = e / (P * n);
-      const cplx<T>* x = X1 + gm1 * P * P + f3;
-      const cplx<T>* t = tm + f2 * P;
-      T re = 0, im = 0;
+    // along the middle axis: P -> n
+    for (int it = threadIdx.x; it < G * P * P; it += blockDim.x) {
+      const int f3 = it % P, gm = it / P;
+      cplx<T> x[P];
 #pragma unroll
-      for (int m = 0; m < P; ++m) {
-        const cplx<T> a = x[m * P], w = t[m];
-        re = fma(a.re, w.re, fma(-a.im, w.im, re));
-        im = fma(a.re, w.im, fma(a.im, w.re, im));
+      for (int m = 0; m < P; ++m) x[m] = X1[(gm * P + m) * P + f3];
+#pragma unroll
+      for (int f = 0; f < n; ++f) {
+        T re = 0, im = 0;
+#pragma unroll
+        for (int m = 0; m < P; ++m) cmac(x[m], c[(f * m) % n], s[(f * m) % n], re, im);
+        X2[(gm * n + f) * P + f3] = cplx<T>{re, im};
       }
-      X2[e] = cplx<T>{re, im};
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < nf * G; e += blockDim.x) {
-      const int g = e % G, f = e / G;
-      const int f3 = f % P, f2 = (f / P) % n, f1 = f / (P * n);
-      const cplx<T>* x = X2 + (g * P * n + f2) * P + f3;
-      const cplx<T>* t = tm + f1 * P;
-      T re = 0, im = 0;
+    // along the first axis: P -> n, into What (the G components of a
+    // frequency are neighbours in memory, so they are neighbouring lanes)
+    for (int it = threadIdx.x; it < G * n * P; it += blockDim.x) {
+      const int g = it % G, r = it / G;  // r = f2 P + f3
+      cplx<T> x[P];
 #pragma unroll
-      for (int m = 0; m < P; ++m) {
-        const cplx<T> a = x[m * n * P], w = t[m];
-        re = fma(a.re, w.re, fma(-a.im, w.im, re));
-        im = fma(a.re, w.im, fma(a.im, w.re, im));
+      for (int m = 0; m < P; ++m) x[m] = X2[(g * P + m) * n * P + r];
+#pragma unroll
+      for (int f = 0; f < n; ++f) {
+        T re = 0, im = 0;
+#pragma unroll
+        for (int m = 0; m < P; ++m) cmac(x[m], c[(f * m) % n], s[(f * m) % n], re, im);
+        What[((int64_t)(f * n * P + r) * ncell + cell) * 9 + c0 + g] = cplx<T>{re, im};
       }
-      What[((int64_t)f * ncell + cell) * 9 + c0 + g] = cplx<T>{re, im};
     }
     __syncthreads();
   }
@@ -286,9 +301,7 @@ __global__ void __launch_bounds__(256) k_fdft(const T* W, int64_t ncell, int G, 
 
 template <int P>
 constexpr size_t lds_fdft_t(int G, size_t es) {
-  return 2 * es * (2 * P - 1) * P + 2 * es * G * P * P * P +
-         (2 * es * G * P * (2 * P - 1) * P > es * G * P * P * P ? 2 * es * G * P * (2 * P - 1) * P
-                                                                 : es * G * P * P * P);
+  return 2 * es * (size_t)G * (P * P * P + P * (2 * P - 1) * P);
 }
 
 // ------------------------------------------------------ Hadamard product
@@ -991,12 +1004,12 @@ __global__ void k_direct_reduce(const double* part, int64_t ntp, int nchunk, dou
 
 // ------------------------------------------------------------ host side
 // DFT launches, specialised on the interpolation order.  Forward: as many
-// components per round as fit 80 KB of LDS; inverse: all six in one round.
+// components per round as fit the LDS; inverse: all six in one round.
 template <typename T, int P>
 static int dft_groups(bool fwd) {
   const size_t es = sizeof(T);
   for (int G : {9, 3, 1})
-    if (lds_fdft_t<P>(G, es) <= 80 * 1024) return G;
+    if (lds_fdft_t<P>(G, es) <= 160 * 1024) return G;
   (void)fwd;
   return 1;
 }
