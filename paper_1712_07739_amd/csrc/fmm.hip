@@ -550,74 +550,77 @@ __global__ void __launch_bounds__(kHad3Threads) k_hadamard3(const cplx<T>* What,
 // One block per cell: Shat[cell][f][6] -> s[cell][6][P^3] (overwrites): the
 // inverse transform of the half spectrum of a real circular convolution, of
 // which only the outputs l < P are needed (the rest is the wrap-around of the
-// embedding).  Twiddles exp(+2 pi i f l / n), f < n, l < P, in LDS.  The
-// first pass reads the spectrum straight from memory, each value once (a
-// thread takes one (f2, f3, component) line and produces all P outputs).
+// embedding).  As in the forward transform, a thread takes one line of a
+// pass in registers and produces all of its P outputs, with the twiddles
+// exp(+2 pi i k / n) in scalar registers.  The first pass reads the spectrum
+// straight from memory, each value once; the last pass uses the Hermitian
+// symmetry of the last axis (f3 = 0 once, f3 > 0 twice, real part).
 template <typename T, int P>
-__global__ void __launch_bounds__(256) k_idft(const cplx<T>* Shat, int64_t ncell, const T* twg, T* s) {
+__global__ void __launch_bounds__(256) k_idft(const cplx<T>* __restrict__ Shat, int64_t ncell,
+                                              const T* __restrict__ twg, T* __restrict__ s) {
   constexpr int n = 2 * P - 1, p3 = P * P * P, nf = n * n * P;
   extern __shared__ __align__(16) unsigned char shraw[];
-  cplx<T>* tm = (cplx<T>*)shraw;  // [n][P]
-  cplx<T>* Y1 = tm + n * P;       // [6][n(f2)][P(f3)][P(l1)]
+  cplx<T>* Y1 = (cplx<T>*)shraw;     // [6][n(f2)][P(f3)][P(l1)]
   cplx<T>* Y2 = Y1 + 6 * n * P * P;  // [6][P(f3)][P(l1)][P(l2)]
-  const int64_t cell = blockIdx.x;
-  for (int e = threadIdx.x; e < n * P; e += blockDim.x) {
-    const int k = ((e / P) * (e % P)) % n;
-    tm[e] = cplx<T>{twg[2 * k], -twg[2 * k + 1]};
+  T c[n], sn[n];  // exp(+2 pi i k / n) = c[k] + i sn[k]
+#pragma unroll
+  for (int k = 0; k < n; ++k) {
+    c[k] = twg[2 * k];
+    sn[k] = -twg[2 * k + 1];
   }
-  __syncthreads();
+  const int64_t cell = blockIdx.x;
   const T scale = T(1) / T(n * n * n);
   const cplx<T>* src = Shat + cell * nf * 6;
-  for (int e = threadIdx.x; e < 6 * n * P; e += blockDim.x) {
-    const int g = e % 6, f3 = (e / 6) % P, f2 = e / (6 * P);
+  // along the first axis: n -> P
+  for (int it = threadIdx.x; it < 6 * n * P; it += blockDim.x) {
+    const int g = it % 6, r = it / 6;  // r = f2 P + f3
     cplx<T> x[n];
 #pragma unroll
-    for (int f1 = 0; f1 < n; ++f1) x[f1] = src[((f1 * n + f2) * P + f3) * 6 + g];
-    cplx<T>* y = Y1 + ((g * n + f2) * P + f3) * P;
-#pragma unroll 1
-    for (int l1 = 0; l1 < P; ++l1) {
+    for (int f = 0; f < n; ++f) x[f] = src[(f * n * P + r) * 6 + g];
+#pragma unroll
+    for (int l = 0; l < P; ++l) {
       T re = 0, im = 0;
 #pragma unroll
-      for (int f1 = 0; f1 < n; ++f1) {
-        const cplx<T> w = tm[f1 * P + l1];
-        re = fma(x[f1].re, w.re, fma(-x[f1].im, w.im, re));
-        im = fma(x[f1].re, w.im, fma(x[f1].im, w.re, im));
-      }
-      y[l1] = cplx<T>{re, im};
+      for (int f = 0; f < n; ++f) cmac(x[f], c[(f * l) % n], sn[(f * l) % n], re, im);
+      Y1[(g * n * P + r) * P + l] = cplx<T>{re, im};
     }
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < 6 * p3; e += blockDim.x) {
-    const int l2 = e % P, l1 = (e / P) % P, f3 = (e / (P * P)) % P, g = e / p3;
-    const cplx<T>* x = Y1 + (g * n * P + f3) * P + l1;
-    T re = 0, im = 0;
+  // along the middle axis: n -> P
+  for (int it = threadIdx.x; it < 6 * P * P; it += blockDim.x) {
+    const int l1 = it % P, f3 = (it / P) % P, g = it / (P * P);
+    cplx<T> x[n];
 #pragma unroll
-    for (int f2 = 0; f2 < n; ++f2) {
-      const cplx<T> a = x[f2 * P * P], w = tm[f2 * P + l2];
-      re = fma(a.re, w.re, fma(-a.im, w.im, re));
-      im = fma(a.re, w.im, fma(a.im, w.re, im));
+    for (int f = 0; f < n; ++f) x[f] = Y1[((g * n + f) * P + f3) * P + l1];
+#pragma unroll
+    for (int l = 0; l < P; ++l) {
+      T re = 0, im = 0;
+#pragma unroll
+      for (int f = 0; f < n; ++f) cmac(x[f], c[(f * l) % n], sn[(f * l) % n], re, im);
+      Y2[((g * P + f3) * P + l1) * P + l] = cplx<T>{re, im};
     }
-    Y2[e] = cplx<T>{re, im};
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < 6 * p3; e += blockDim.x) {
-    const int l3 = e % P, l2 = (e / P) % P, l1 = (e / (P * P)) % P, g = e / p3;
-    const cplx<T>* x = Y2 + (g * P * P + l1) * P + l2;
-    // Hermitian symmetry in the last axis: f3 = 0 once, f3 > 0 twice (real part)
-    const T re = x[0].re * tm[l3].re - x[0].im * tm[l3].im;
-    T acc = 0;
+  // along the last axis: half spectrum (P) -> P real outputs
+  for (int it = threadIdx.x; it < 6 * P * P; it += blockDim.x) {
+    const int l2 = it % P, l1 = (it / P) % P, g = it / (P * P);
+    cplx<T> x[P];
 #pragma unroll
-    for (int f3 = 1; f3 < P; ++f3) {
-      const cplx<T> a = x[f3 * P * P], w = tm[f3 * P + l3];
-      acc = fma(a.re, w.re, fma(-a.im, w.im, acc));
+    for (int f = 0; f < P; ++f) x[f] = Y2[((g * P + f) * P + l1) * P + l2];
+    T* out = s + (cell * 6 + g) * p3 + (l1 * P + l2) * P;
+#pragma unroll
+    for (int l = 0; l < P; ++l) {
+      T acc = 0;
+#pragma unroll
+      for (int f = 1; f < P; ++f) acc = fma(x[f].re, c[(f * l) % n], fma(-x[f].im, sn[(f * l) % n], acc));
+      out[l] = (x[0].re + T(2) * acc) * scale;
     }
-    s[(cell * 6 + g) * p3 + (l1 * P + l2) * P + l3] = (re + T(2) * acc) * scale;
   }
 }
 
 template <int P>
 constexpr size_t lds_idft_t(size_t es) {
-  return 2 * es * ((2 * P - 1) * P + (size_t)6 * (2 * P - 1) * P * P + (size_t)6 * P * P * P);
+  return 2 * es * ((size_t)6 * (2 * P - 1) * P * P + (size_t)6 * P * P * P);
 }
 
 // ------------------------------------------------ near field + L2P (leaf)
