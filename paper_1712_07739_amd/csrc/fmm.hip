@@ -117,59 +117,59 @@ __global__ void k_p2m(const double* pts, int64_t N, const int* first, const int*
 }
 
 // ------------------------------------------------------- separable passes
-// out[g][a][b][i] = sum_m M(i, m) in[g][a][b][m] along the last axis, for the
+// out[g][a][b][i] = sum_m M(i, m) in[g][a][b][m] along one axis, for the
 // three axes in turn; M(i, m) = S[bit][i][m] (anterpolation, M2M) or
-// S[bit][m][i] (interpolation, L2L).  The order P is a template parameter.
-template <typename T, bool INTERP, int P, int AXIS>
-__device__ __forceinline__ void pass_axis(const T* in, T* out, const T* S, int bit, int ncomp) {
+// S[bit][m][i] (interpolation, L2L).  A thread takes one line along the axis:
+// its P values in registers, all P outputs.  The bit is the same for the
+// whole block, so the matrix entries are uniform loads (scalar registers).
+// ACC adds the result to out.
+template <typename T, bool INTERP, bool ACC, int P, int AXIS>
+__device__ __forceinline__ void pass_axis(const T* in, T* out, const T* __restrict__ S, int bit, int ncomp) {
   constexpr int p3 = P * P * P;
   constexpr int stride = AXIS == 2 ? 1 : AXIS == 1 ? P : P * P;
-  for (int e = threadIdx.x; e < ncomp * p3; e += blockDim.x) {
-    const int r = e % p3, i = (r / stride) % P;
-    const int base = e - i * stride;
-    T v = T(0);
+  const T* Sb = S + bit * P * P;
+  for (int L = threadIdx.x; L < ncomp * P * P; L += blockDim.x) {
+    const int g = L / (P * P), q = L % (P * P);
+    const int base = g * p3 + (AXIS == 2 ? q * P : AXIS == 1 ? (q / P) * P * P + q % P : q);
+    T x[P];
 #pragma unroll
-    for (int m = 0; m < P; ++m) {
-      const T c = INTERP ? S[(bit * P + m) * P + i] : S[(bit * P + i) * P + m];
-      v = fma(c, in[base + m * stride], v);
+    for (int m = 0; m < P; ++m) x[m] = in[base + m * stride];
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      T v = T(0);
+#pragma unroll
+      for (int m = 0; m < P; ++m) v = fma(INTERP ? Sb[m * P + i] : Sb[i * P + m], x[m], v);
+      if (ACC)
+        out[base + i * stride] += v;
+      else
+        out[base + i * stride] = v;
     }
-    out[e] = v;
   }
 }
 
 // M2M: one block per parent cell; the children's W (next finer level) are
 // anterpolated onto the parent's nodes one child at a time.
 template <typename T, int P>
-__global__ void k_m2m(const int* first, const int* count, const uint32_t* ckey, const T* Wc, T* Wp, const T* Sg) {
+__global__ void k_m2m(const int* first, const int* count, const uint32_t* ckey, const T* Wc, T* Wp,
+                      const T* __restrict__ Sg) {
   extern __shared__ unsigned char shraw[];
   constexpr int p3 = P * P * P;
   T* A = (T*)shraw;
   T* B = A + 9 * p3;
   T* C = B + 9 * p3;
-  T* S = C + 9 * p3;
-  for (int e = threadIdx.x; e < 2 * P * P; e += blockDim.x) S[e] = Sg[e];
   for (int e = threadIdx.x; e < 9 * p3; e += blockDim.x) C[e] = T(0);
   const int par = blockIdx.x;
   const int c0 = first[par], nc = count[par];
-  __syncthreads();
   for (int c = c0; c < c0 + nc; ++c) {
     const uint32_t bits = ckey[c] & 7;
     const T* src = Wc + (int64_t)c * 9 * p3;
     for (int e = threadIdx.x; e < 9 * p3; e += blockDim.x) A[e] = src[e];
     __syncthreads();
-    pass_axis<T, false, P, 2>(A, B, S, bits & 1, 9);
+    pass_axis<T, false, false, P, 2>(A, B, Sg, bits & 1, 9);
     __syncthreads();
-    pass_axis<T, false, P, 1>(B, A, S, (bits >> 1) & 1, 9);
+    pass_axis<T, false, false, P, 1>(B, A, Sg, (bits >> 1) & 1, 9);
     __syncthreads();
-    const int b2 = (bits >> 2) & 1;
-    for (int e = threadIdx.x; e < 9 * p3; e += blockDim.x) {
-      const int r = e % p3, i = r / (P * P);
-      const int base = e - i * P * P;
-      T v = T(0);
-#pragma unroll
-      for (int m = 0; m < P; ++m) v = fma(S[(b2 * P + i) * P + m], A[base + m * P * P], v);
-      C[e] += v;
-    }
+    pass_axis<T, false, true, P, 0>(A, C, Sg, (bits >> 2) & 1, 9);
     __syncthreads();
   }
   T* dst = Wp + (int64_t)par * 9 * p3;
@@ -178,32 +178,22 @@ __global__ void k_m2m(const int* first, const int* count, const uint32_t* ckey, 
 
 // L2L: one block per child cell; adds the parent's interpolated local values.
 template <typename T, int P>
-__global__ void k_l2l(const int* parent, const uint32_t* key, const T* sp, T* sc, const T* Sg) {
+__global__ void k_l2l(const int* parent, const uint32_t* key, const T* sp, T* sc, const T* __restrict__ Sg) {
   extern __shared__ unsigned char shraw[];
   constexpr int p3 = P * P * P;
   T* A = (T*)shraw;
   T* B = A + 6 * p3;
-  T* S = B + 6 * p3;
-  for (int e = threadIdx.x; e < 2 * P * P; e += blockDim.x) S[e] = Sg[e];
   const int c = blockIdx.x;
   const uint32_t bits = key[c] & 7;
   const T* src = sp + (int64_t)parent[c] * 6 * p3;
   for (int e = threadIdx.x; e < 6 * p3; e += blockDim.x) A[e] = src[e];
   __syncthreads();
-  pass_axis<T, true, P, 2>(A, B, S, bits & 1, 6);
+  pass_axis<T, true, false, P, 2>(A, B, Sg, bits & 1, 6);
   __syncthreads();
-  pass_axis<T, true, P, 1>(B, A, S, (bits >> 1) & 1, 6);
+  pass_axis<T, true, false, P, 1>(B, A, Sg, (bits >> 1) & 1, 6);
   __syncthreads();
   T* dst = sc + (int64_t)c * 6 * p3;
-  const int b2 = (bits >> 2) & 1;
-  for (int e = threadIdx.x; e < 6 * p3; e += blockDim.x) {
-    const int r = e % p3, i = r / (P * P);
-    const int base = e - i * P * P;
-    T v = T(0);
-#pragma unroll
-    for (int m = 0; m < P; ++m) v = fma(S[(b2 * P + m) * P + i], A[base + m * P * P], v);
-    dst[e] += v;
-  }
+  pass_axis<T, true, true, P, 0>(A, dst, Sg, (bits >> 2) & 1, 6);
 }
 
 // Blocks are dispatched round-robin over the 8 XCDs; this bijection of
@@ -1185,7 +1175,7 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
                                                            lo[2], sD, p, W + LD.off * 9 * p3)));
   }
   {
-    size_t shm = es * (27 * p3 + 2 * p * p);
+    size_t shm = es * 27 * p3;
     for (int l = D - 1; l >= 2; --l) {
       const auto& Lc = t->lv[l + 1];
       const auto& Lp = t->lv[l];
@@ -1211,7 +1201,7 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
     STAGE(4, dft<T>(p, false, (unsigned)Lv.n, Shat, Lv.n, tb.tw, s + Lv.off * 6 * p3, st));
   }
   {
-    size_t shm = es * (12 * p3 + 2 * p * p);
+    size_t shm = es * 12 * p3;
     for (int l = 3; l <= D; ++l) {
       const auto& Lv = t->lv[l];
       const auto& Lp = t->lv[l - 1];
