@@ -46,13 +46,12 @@ __global__ void k_gather(const double* seg, const double* burg, const uint32_t* 
   uint32_t j = perm[i];
   int64_t s = j / qd.n;
   int k = (int)(j - s * qd.n);
-  const double* x = seg + 6 * s;
-  double dS[3] = {x[3] - x[0], x[4] - x[1], x[5] - x[2]};
-  double c = 0.5 * (1.0 + qd.u[k]), hw = 0.5 * qd.w[k];
+  double x[3], t[3];
+  quad_point(seg, s, k, qd, x, t);
   for (int d = 0; d < 3; ++d) {
-    pts[d * N + i] = x[d] + c * dS[d];
+    pts[d * N + i] = x[d];
     pts[(3 + d) * N + i] = burg[3 * s + d];
-    pts[(6 + d) * N + i] = hw * dS[d];
+    pts[(6 + d) * N + i] = t[d];
   }
 }
 
@@ -721,103 +720,37 @@ __global__ void __launch_bounds__(64, leaf_min_waves<T>())
   }
 }
 
-// Pairs of a leaf's targets with sources closer than 2a (the near-coincident
-// pairs that the single-precision near field skips), in double precision.
-// One wave per leaf, one lane per target (64 at a time).  A neighbour leaf is
-// only searched if its box comes within 2a of the target (usually the
-// target's own leaf alone).  Lanes append the close pairs they find to a
-// buffer in LDS (one pair per lane per round, in lane order); a full buffer
-// is evaluated by all 64 lanes together (the double-precision kernel is long,
-// and close pairs are sparse, so evaluating them where they are found would
-// leave most lanes idle), then every target adds its entries in buffer order,
-// which fixes each target's summation order.  The sum is added to the stress
-// k_leaf wrote.
-constexpr int kCloseBuf = 256;
-
+// The near-coincident pairs (closer than 2a) that the single-precision near
+// field skips, in double precision.  The tree holds them per target point, in
+// the order the near field visits its sources.  One thread per pair writes
+// the pair's stress; then one thread per target adds its pairs in that order
+// (a fixed summation order) to the stress k_leaf wrote.
 template <bool ISO>
-__global__ void __launch_bounds__(64) k_close(const double* pts, int64_t N, const int* first, const int* count,
-                                              const uint32_t* key, const int* nbr, double lo0, double lo1,
-                                              double lo2, double sD, Med<double> m64, double* sig) {
-  const int leaf = blockIdx.x, lane = threadIdx.x;
-  const int t0 = first[leaf], nt = count[leaf];
-  __shared__ int nb_first[27], nb_cnt[27];
-  __shared__ int bsrc[kCloseBuf];
-  __shared__ int btgt[kCloseBuf];
-  __shared__ double bval[kCloseBuf][6];
-  if (lane < 27) {
-    int j = nbr[(int64_t)leaf * 27 + lane];
-    nb_first[lane] = j >= 0 ? first[j] : 0;
-    nb_cnt[lane] = j >= 0 ? count[j] : 0;
-  }
-  __syncthreads();
-  const double a2x4 = 4.0 * m64.a * m64.a;
-  double lo[3];
-  cell_lo(key[leaf], lo0, lo1, lo2, sD, lo);
-  for (int c0 = 0; c0 < nt; c0 += 64) {
-    const bool act = c0 + lane < nt;
-    const int64_t i = t0 + (act ? c0 + lane : 0);
-    const double xt0 = pts[i], xt1 = pts[N + i], xt2 = pts[2 * N + i];
-    const double r0 = xt0 - lo[0], r1 = xt1 - lo[1], r2 = xt2 - lo[2];
-    const double dlo[3] = {r0 * r0, r1 * r1, r2 * r2};
-    const double dhi[3] = {(sD - r0) * (sD - r0), (sD - r1) * (sD - r1), (sD - r2) * (sD - r2)};
-    double acc[6] = {0, 0, 0, 0, 0, 0};
-    // scan state of this lane: neighbour q, source jj within it
-    int q = act ? 0 : 27, jj = 0;
-    int n = 0;  // pairs in the buffer (wave-uniform)
-    while (true) {
-      // advance to this lane's next close pair, if any
-      int found = -1;
-      while (q < 27 && found < 0) {
-        const int oq0 = q / 9 - 1, oq1 = q / 3 % 3 - 1, oq2 = q % 3 - 1;
-        const double gap = (oq0 < 0 ? dlo[0] : oq0 > 0 ? dhi[0] : 0.0) + (oq1 < 0 ? dlo[1] : oq1 > 0 ? dhi[1] : 0.0) +
-                           (oq2 < 0 ? dlo[2] : oq2 > 0 ? dhi[2] : 0.0);
-        const int cj = nb_cnt[q];
-        if (gap >= a2x4 || jj >= cj) {
-          ++q;
-          jj = 0;
-          continue;
-        }
-        const int64_t j = nb_first[q] + jj;
-        ++jj;
-        const double d0 = xt0 - pts[j], d1 = xt1 - pts[N + j], d2 = xt2 - pts[2 * N + j];
-        if (d0 * d0 + d1 * d1 + d2 * d2 < a2x4) found = (int)j;
-      }
-      const uint64_t mask = __ballot(found >= 0);
-      if (found >= 0) {
-        const int pos = n + __popcll(mask & ((1ull << lane) - 1ull));
-        bsrc[pos] = found;
-        btgt[pos] = lane;
-      }
-      n += __popcll(mask);
-      const bool more = __ballot(q < 27) != 0;
-      if (n > kCloseBuf - 64 || (!more && n > 0)) {
-        __syncthreads();
-        for (int k = lane; k < n; k += 64) {
-          const int64_t it = t0 + c0 + btgt[k], j = bsrc[k];
-          const double d0 = pts[it] - pts[j], d1 = pts[N + it] - pts[N + j], d2 = pts[2 * N + it] - pts[2 * N + j];
-          double D[27], bb[3], tt[3], v[6] = {0, 0, 0, 0, 0, 0};
-          for (int c = 0; c < 3; ++c) bb[c] = pts[(3 + c) * N + j], tt[c] = pts[(6 + c) * N + j];
-          dg_medium_t<double, ISO>(d0, d1, d2, m64, D);
-          contract_b_t<double>(D, m64.c12, m64.c44, m64.hh, bb, tt, v);
+__global__ void __launch_bounds__(64) k_close_eval(const double* pts, int64_t N, const int2* cpair, int64_t nclose,
+                                                   Med<double> m64, double* cval) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nclose) return;
+  const int2 pr = cpair[k];
+  const int64_t it = pr.x, j = pr.y;
+  const double d0 = pts[it] - pts[j], d1 = pts[N + it] - pts[N + j], d2 = pts[2 * N + it] - pts[2 * N + j];
+  double D[27], bb[3], tt[3], v[6] = {0, 0, 0, 0, 0, 0};
+  for (int c = 0; c < 3; ++c) bb[c] = pts[(3 + c) * N + j], tt[c] = pts[(6 + c) * N + j];
+  dg_medium_t<double, ISO>(d0, d1, d2, m64, D);
+  contract_b_t<double>(D, m64.c12, m64.c44, m64.hh, bb, tt, v);
 #pragma unroll
-          for (int c = 0; c < 6; ++c) bval[k][c] = v[c];
-        }
-        __syncthreads();
-        for (int k = 0; k < n; ++k)
-          if (btgt[k] == lane) {
+  for (int c = 0; c < 6; ++c) cval[k * 6 + c] = v[c];
+}
+
+__global__ void k_close_sum(const int* cstart, int64_t N, const double* cval, double* sig) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (int k = cstart[i]; k < cstart[i + 1]; ++k)
 #pragma unroll
-            for (int c = 0; c < 6; ++c) acc[c] += bval[k][c];
-          }
-        __syncthreads();
-        n = 0;
-      }
-      if (!more) break;
-    }
-    if (act) {
+    for (int c = 0; c < 6; ++c) acc[c] += cval[(int64_t)k * 6 + c];
+  if (cstart[i + 1] > cstart[i])
 #pragma unroll
-      for (int c = 0; c < 6; ++c) sig[i * 6 + c] += acc[c];
-    }
-  }
+    for (int c = 0; c < 6; ++c) sig[i * 6 + c] += acc[c];
 }
 
 // L2P: far-field stress at each point by interpolation of its leaf's local
@@ -1154,12 +1087,15 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
         STAGE(6, (k_leaf<T, true, true, false><<<(unsigned)LD.n, 64, 0, nst>>>(LEAF_ARGS)));
       else
         STAGE(6, (k_leaf<T, true, false, false><<<(unsigned)LD.n, 64, 0, nst>>>(LEAF_ARGS)));
-      if (pl->iso)
-        STAGE(6, (k_close<true><<<(unsigned)LD.n, 64, 0, nst>>>(t->pts, N, LD.first, LD.count, LD.key, t->nbr,
-                                                              lo[0], lo[1], lo[2], sD, m64, t->sig)));
-      else
-        STAGE(6, (k_close<false><<<(unsigned)LD.n, 64, 0, nst>>>(t->pts, N, LD.first, LD.count, LD.key, t->nbr,
-                                                               lo[0], lo[1], lo[2], sD, m64, t->sig)));
+      if (t->nclose > 0) {
+        if (pl->iso)
+          STAGE(6, (k_close_eval<true><<<nblk(t->nclose, 64), 64, 0, nst>>>(t->pts, N, t->cpair, t->nclose, m64,
+                                                                            t->cval)));
+        else
+          STAGE(6, (k_close_eval<false><<<nblk(t->nclose, 64), 64, 0, nst>>>(t->pts, N, t->cpair, t->nclose, m64,
+                                                                             t->cval)));
+        STAGE(6, (k_close_sum<<<nblk(N, 256), 256, 0, nst>>>(t->cstart, N, t->cval, t->sig)));
+      }
     } else {
       if (pl->iso)
         STAGE(6, (k_leaf<T, false, true, false><<<(unsigned)LD.n, 64, 0, nst>>>(LEAF_ARGS)));

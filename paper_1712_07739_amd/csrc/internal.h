@@ -51,6 +51,22 @@ struct Quad {
   int n;
 };
 
+// Quadrature point k of segment s: position x = x1 + (1 + u_k)/2 (x2 - x1)
+// and weight vector t = (w_k / 2)(x2 - x1).  The tree build (which finds the
+// near-coincident pairs) and every force call (which skips them in the
+// single-precision near field) form the positions with this one function,
+// with explicit fused multiply-adds, so both see the same bits.
+__device__ __forceinline__ void quad_point(const double* seg, int64_t s, int k, const Quad& qd, double* x,
+                                           double* t) {
+  const double* p = seg + 6 * s;
+  const double c = 0.5 * (1.0 + qd.u[k]), hw = 0.5 * qd.w[k];
+  for (int d = 0; d < 3; ++d) {
+    const double dS = p[3 + d] - p[d];
+    x[d] = fma(c, dS, p[d]);
+    t[d] = hw * dS;
+  }
+}
+
 // Device-resident float/double copies of the small constant tables.
 template <typename T>
 struct Tables {
@@ -157,6 +173,13 @@ struct dfmm_tree {
   hipEvent_t ev[DFMM_N_STAGES + 1] = {};
   double stage_ms[DFMM_N_STAGES] = {};
   int timed_calls = 0;
+  // Single-precision plans: the near-coincident pairs (closer than 2a, left
+  // to a double-precision pass), found once per tree.  Per sorted target
+  // point, the CSR of its sources in the order the near field visits them.
+  int64_t nclose = 0;
+  int* cstart = nullptr;   // [N + 1]
+  int2* cpair = nullptr;   // [nclose] (target, source), sorted point indices
+  double* cval = nullptr;  // [nclose][6] per-pair stress, written by every call
   // recorded at the end of every call that is not being captured into a
   // graph: destroy and the query calls wait on it (an event the tree owns,
   // valid whatever becomes of the caller's streams)

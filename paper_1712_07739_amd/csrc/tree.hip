@@ -390,6 +390,62 @@ __global__ void k_il_wave(const uint32_t* order, const int* il_start, const int2
   }
 }
 
+// Positions of the sorted points (rows 0..2 of the points array), formed as
+// the force call's gather forms them.
+__global__ void k_gather_pos(const double* seg, const uint32_t* perm, Quad qd, int64_t N, double* pts) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const uint32_t j = perm[i];
+  const int64_t s = j / qd.n;
+  double x[3], t[3];
+  quad_point(seg, s, (int)(j - s * qd.n), qd, x, t);
+  for (int d = 0; d < 3; ++d) pts[d * N + i] = x[d];
+}
+
+// Near-coincident pairs of each sorted target point: the sources closer than
+// 2a in its leaf's 27 neighbour leaves, in the order the near field visits
+// them (neighbour by neighbour, then by sorted index).  A neighbour leaf is
+// skipped only if its box lies at least 2a from the target (with a relative
+// margin of 1e-9 against rounding).  FILL = false counts, true writes.
+template <bool FILL>
+__global__ void k_close_find(const double* pts, int64_t N, const int* pleaf, const int* first, const int* count,
+                             const uint32_t* key, const int* nbr, double lo0, double lo1, double lo2, double sD,
+                             double a2x4, int* cnt, const int* cstart, int2* cpair) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int leaf = pleaf[i];
+  int cx, cy, cz;
+  demorton(key[leaf], cx, cy, cz);
+  const double x0 = pts[i], x1 = pts[N + i], x2 = pts[2 * N + i];
+  const double r[3] = {x0 - (lo0 + cx * sD), x1 - (lo1 + cy * sD), x2 - (lo2 + cz * sD)};
+  const double lim = a2x4 * (1.0 + 1e-9);
+  int c = 0;
+  int64_t w = FILL ? cstart[i] : 0;
+  for (int q = 0; q < 27; ++q) {
+    const int o[3] = {q / 9 - 1, q / 3 % 3 - 1, q % 3 - 1};
+    double gap = 0.0;
+    for (int d = 0; d < 3; ++d)
+      if (o[d] < 0)
+        gap += r[d] * r[d];
+      else if (o[d] > 0)
+        gap += (sD - r[d]) * (sD - r[d]);
+    const int nl = nbr[(int64_t)leaf * 27 + q];
+    if (nl < 0 || gap >= lim) continue;
+    const int f = first[nl], n = count[nl];
+    for (int jj = 0; jj < n; ++jj) {
+      const int64_t j = f + jj;
+      const double d0 = x0 - pts[j], d1 = x1 - pts[N + j], d2 = x2 - pts[2 * N + j];
+      if (d0 * d0 + d1 * d1 + d2 * d2 < a2x4) {
+        if (FILL)
+          cpair[w++] = make_int2((int)i, (int)j);
+        else
+          ++c;
+      }
+    }
+  }
+  if (!FILL) cnt[i] = c;
+}
+
 static inline unsigned nb(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 int build_tree_impl(dfmm_plan* pl, const double* seg, int64_t nseg, hipStream_t st, dfmm_tree* t, bool workspaces) {
@@ -590,7 +646,35 @@ int build_tree_impl(dfmm_plan* pl, const double* seg, int64_t nseg, hipStream_t 
   DFMM_HIP(hipMalloc(&t->What, bWh));
   DFMM_HIP(hipMalloc(&t->Shat, bSh));
   DFMM_HIP(hipMalloc(&t->sig, sizeof(double) * 6 * N));
-  t->bytes = sizeof(double) * 15 * N + sizeof(int) * N + bW + bS + bWh + bSh;
+  if (pl->mixed) {  // the near-coincident pairs, evaluated in double by every call
+    const double sD = pl->prm.box_size / (double)(1 << D);
+    const double a2x4 = 4.0 * pl->prm.core_a * pl->prm.core_a;
+    k_gather_pos<<<nb(N, 256), 256, 0, st>>>(seg, t->perm, pl->quad, N, t->pts);
+    DFMM_LAUNCH_CHECK();
+    int* cnt = nullptr;
+    DFMM_HIP(hipMalloc(&cnt, sizeof(int) * (N + 1)));
+    DFMM_HIP(hipMemsetAsync(cnt + N, 0, sizeof(int), st));
+    k_close_find<false><<<nb(N, 128), 128, 0, st>>>(t->pts, N, t->pleaf, LD.first, LD.count, LD.key, t->nbr,
+                                                   pl->prm.box_lo[0], pl->prm.box_lo[1], pl->prm.box_lo[2], sD,
+                                                   a2x4, cnt, nullptr, nullptr);
+    DFMM_LAUNCH_CHECK();
+    DFMM_HIP(hipMalloc(&t->cstart, sizeof(int) * (N + 1)));
+    rc = scan_excl(cnt, t->cstart, N + 1, st, &t->nclose);
+    hipFree(cnt);
+    if (rc) return rc;
+    if (t->nclose >= ((int64_t)1 << 31)) {
+      set_error("build_tree: too many near-coincident pairs (limit 2^31)");
+      return DFMM_E_ARG;
+    }
+    DFMM_HIP(hipMalloc(&t->cpair, sizeof(int2) * std::max<int64_t>(t->nclose, 1)));
+    DFMM_HIP(hipMalloc(&t->cval, sizeof(double) * 6 * std::max<int64_t>(t->nclose, 1)));
+    k_close_find<true><<<nb(N, 128), 128, 0, st>>>(t->pts, N, t->pleaf, LD.first, LD.count, LD.key, t->nbr,
+                                                  pl->prm.box_lo[0], pl->prm.box_lo[1], pl->prm.box_lo[2], sD,
+                                                  a2x4, nullptr, t->cstart, t->cpair);
+    DFMM_LAUNCH_CHECK();
+  }
+  t->bytes = sizeof(double) * 15 * N + sizeof(int) * N + bW + bS + bWh + bSh +
+             (sizeof(int2) + 6 * sizeof(double)) * t->nclose + (t->cstart ? sizeof(int) * (N + 1) : 0);
   DFMM_HIP(hipStreamSynchronize(st));
   return DFMM_OK;
 }
