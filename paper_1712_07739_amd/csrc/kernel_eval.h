@@ -97,9 +97,13 @@ __device__ __forceinline__ void dg_circle_acc(T x0, T x1, T x2, const Med<T>& m,
   const T dt[3] = {T(2) * ch * t[0], T(2) * ch * t[1], T(2) * ch * t[2]};
   // symmetric pairs (i, j): 00 11 22 01 02 12
   constexpr int PI_[6] = {0, 1, 2, 0, 0, 1}, PJ_[6] = {0, 1, 2, 1, 2, 2};
-  T acc[18];
+  // z = cos(phi) e1 + sin(phi) e2 and T are fixed vectors times scalars, so
+  // the sums of z_s F_ij and T_s M_ij are formed as sum cos F_ij, sum sin F_ij
+  // and sum M_ij (18 accumulations per angle instead of 36), and the vectors
+  // are applied once after the loop.
+  T acc_c[6], acc_s[6], acc_m[6];
 #pragma unroll
-  for (int i = 0; i < 18; ++i) acc[i] = T(0);
+  for (int i = 0; i < 6; ++i) acc_c[i] = acc_s[i] = acc_m[i] = T(0);
 #pragma unroll 1
   for (int k = 0; k < m.nhalf; ++k) {
     T co = m.cs[2 * k], si = m.cs[2 * k + 1];
@@ -130,11 +134,16 @@ __device__ __forceinline__ void dg_circle_acc(T x0, T x1, T x2, const Med<T>& m,
     for (int q = 0; q < 6; ++q) {
       const int i = PI_[q], j = PJ_[q];
       T F = P[i * 3] * M[j] + P[i * 3 + 1] * M[3 + j] + P[i * 3 + 2] * M[6 + j];
-      T Mij = M[i * 3 + j];
-#pragma unroll
-      for (int s = 0; s < 3; ++s) acc[q * 3 + s] = fma(z[s], F, fma(-t[s], Mij, acc[q * 3 + s]));
+      acc_c[q] = fma(co, F, acc_c[q]);
+      acc_s[q] = fma(si, F, acc_s[q]);
+      acc_m[q] += M[i * 3 + j];
     }
   }
+  T acc[18];
+#pragma unroll
+  for (int q = 0; q < 6; ++q)
+#pragma unroll
+    for (int s = 0; s < 3; ++s) acc[q * 3 + s] = e1[s] * acc_c[q] + e2[s] * acc_s[q] - t[s] * acc_m[q];
   // (2 pi / nphi) * 2 / (8 pi^2 r^2) with nphi = 2 nhalf
   T f = scale / (T(2) * T(3.14159265358979323846) * T(2 * m.nhalf) * r2);
 #pragma unroll
