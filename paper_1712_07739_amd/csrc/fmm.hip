@@ -455,15 +455,24 @@ k_hadamard(const cplx<float>* What, const cplx<float>* Khat, const int* lenq, co
   for (int r = 0; r < 3; ++r) out[r] = cplx<float>{ar[r], ai[r]};
 }
 
-constexpr int kKStride3 = 54;  // complex per offset in LDS for the three-lane kernel
+// Per offset 55 complex in LDS (54 used): an odd number of 16-byte units, so
+// that the lanes' reads of unrelated offsets spread over the LDS banks.
+constexpr int kKStride3 = 55;
 // Double precision keeps three lanes per target (two rows each): with twice
 // the bytes per value its LDS and register budget favour the shorter rows.
+// Each lane loads the source's whole row.  The next list entry is loaded one
+// step ahead (carried through an empty asm statement, which keeps the
+// compiler from turning it back into a load at the top of the loop), so a
+// step's source loads do not wait on its index; the index past the end of
+// the list is clamped to its last entry.  (Prefetching the source values as
+// well, with two buffers, needs 168 registers and spills.)
 constexpr int kHad3Threads = 3 * kM2LWindowD;
 template <typename T>
 __global__ void __launch_bounds__(kHad3Threads) k_hadamard3(const cplx<T>* What, const cplx<T>* Khat,
                                                           const int* il_start, const int2* il,
                                                           const uint32_t* order, int64_t ncell, int nf, int nwin,
                                                           int remap, cplx<T>* Shat) {
+  static_assert(sizeof(T) == 8, "the three-lane kernel is the double-precision one");
   extern __shared__ __align__(16) unsigned char shraw[];
   cplx<T>* Ks = (cplx<T>*)shraw;  // [158][kKStride3]
   int win, f;
@@ -489,32 +498,24 @@ __global__ void __launch_bounds__(kHad3Threads) k_hadamard3(const cplx<T>* What,
   T ar0 = 0, ai0 = 0, ar1 = 0, ai1 = 0;
   const int e0 = il_start[t], e1 = il_start[t + 1];
   const cplx<T>* wf = What + (int64_t)f * ncell * 9;
-  for (int e = e0; e < e1; ++e) {
-    const int2 jo = il[e];
-    const T sg = (jo.y & 1) ? T(-1) : T(1);
-    const cplx<T>* w = wf + (int64_t)jo.x * 9;
-    // rows r0 and r0+1 of the offset's 6x9 block: 18 consecutive complex values,
-    // 16-byte aligned, read as 9 (float) or 18 (double) 16-byte LDS loads
+  auto load_src = [&](int2 j, cplx<T>* v) {
+    const cplx<T>* w = wf + (int64_t)j.x * 9;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) v[k] = w[k];
+  };
+  auto pair = [&](int2 j, const cplx<T>* v, T use) {
+    const T sg = ((j.y & 1) ? T(-1) : T(1)) * use;
+    // rows r0 and r0+1 of the offset's 6x9 block: 18 consecutive complex values
+    const cplx<T>* K = Ks + (j.y >> 1) * kKStride3 + r0 * 9;
     cplx<T> kk[18];
-    const cplx<T>* K = Ks + (jo.y >> 1) * kKStride3 + r0 * 9;
-    if (sizeof(T) == 4) {
-      const float4* K4 = reinterpret_cast<const float4*>(K);
 #pragma unroll
-      for (int i = 0; i < 9; ++i) {
-        float4 q = K4[i];
-        kk[2 * i] = cplx<T>{(T)q.x, (T)q.y};
-        kk[2 * i + 1] = cplx<T>{(T)q.z, (T)q.w};
-      }
-    } else {
-#pragma unroll
-      for (int i = 0; i < 18; ++i) kk[i] = K[i];
-    }
+    for (int i = 0; i < 18; ++i) kk[i] = K[i];
     // complex multiply-accumulate as four fused multiply-adds each
     T cr0 = 0, ci0 = 0, cr1 = 0, ci1 = 0;
+    const T sw = (j.y & 1) ? T(-1) : T(1);
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-      const cplx<T> v = w[k];
-      const T wr = v.re, wi = sg * v.im;
+      const T wr = v[k].re, wi = sw * v[k].im;
       const cplx<T> k0 = kk[k], k1 = kk[9 + k];
       cr0 = fma(k0.re, wr, cr0);
       cr0 = fma(-k0.im, wi, cr0);
@@ -526,9 +527,20 @@ __global__ void __launch_bounds__(kHad3Threads) k_hadamard3(const cplx<T>* What,
       ci1 = fma(k1.im, wr, ci1);
     }
     ar0 = fma(sg, cr0, ar0);
-    ai0 += ci0;
+    ai0 = fma(use, ci0, ai0);
     ar1 = fma(sg, cr1, ar1);
-    ai1 += ci1;
+    ai1 = fma(use, ci1, ai1);
+  };
+  if (e0 < e1) {  // the three lanes of a target run the same iterations
+    int2 jo = il[e0];
+    for (int e = e0; e < e1; ++e) {
+      const int2 jn = il[min(e + 1, e1 - 1)];
+      cplx<T> v[9];
+      load_src(jo, v);
+      pair(jo, v, T(1));
+      jo = jn;
+      asm volatile("" : "+v"(jo.x), "+v"(jo.y));
+    }
   }
   cplx<T>* out = Shat + (t * nf + f) * 6 + r0;
   out[0] = cplx<T>{ar0, ai0};
@@ -617,7 +629,7 @@ constexpr size_t lds_idft_t(size_t es) {
 // power of two) lanes share a target and split its sources; partial sums are
 // combined with xor shuffles.  In MIXED precision pairs are evaluated in float
 // (displacements formed in double) with compensated float accumulation, and
-// pairs closer than 2a are left to k_close (double precision, run after this
+// pairs closer than 2a are left to k_close_eval (double precision, run after this
 // kernel), which keeps double-precision code and its registers out of here.
 // Single precision: ask for 3 waves per SIMD (the register budget that the
 // pair evaluation fits without spilling); double precision: no constraint.
@@ -665,7 +677,7 @@ __global__ void __launch_bounds__(64, leaf_min_waves<T>())
           const int64_t j = fj + jj;
           double d0 = xt0 - pts[j], d1 = xt1 - pts[N + j], d2 = xt2 - pts[2 * N + j];
           if (MIXED && d0 * d0 + d1 * d1 + d2 * d2 < a2x4) {
-            // nearly coincident pair: evaluated by k_close
+            // nearly coincident pair: evaluated by k_close_eval
           } else {
             T D[27], b[3], tt[3];
             for (int c = 0; c < 3; ++c) b[c] = (T)pts[(3 + c) * N + j], tt[c] = (T)pts[(6 + c) * N + j];
@@ -1169,7 +1181,7 @@ static void set_lds_attrs() {
   done = true;
   const int mx = 160 * 1024;
   hipFuncSetAttribute((const void*)k_hadamard, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-  hipFuncSetAttribute((const void*)k_hadamard3<T>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+  hipFuncSetAttribute((const void*)k_hadamard3<double>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
   dft_lds_attrs<T>(std::make_integer_sequence<int, kMaxOrder - 1>{});
   hipFuncSetAttribute((const void*)k_p2m<T>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
 }
