@@ -311,14 +311,13 @@ constexpr size_t lds_fdft_t(int G, size_t es) {
 // each of the 8 XCDs (blocks are dispatched round-robin over them) works
 // through a contiguous range of windows at one frequency at a time:
 // neighbouring windows share sources in that XCD's L2.
-// The spectra take 73.3 KB of LDS per block, so two blocks share a CU: four
-// waves per SIMD, which leaves the software pipeline of the list walk the
-// ~105 registers it needs.
+// The spectra take 73.3 KB of LDS per block, so two blocks (384 targets,
+// twelve waves each) share a CU: six waves per SIMD.
 constexpr int kHadThreads = 2 * kM2LWindowF;
 static_assert(kM2LWindowF % kWaveTargets == 0 && 2 * kWaveTargets == 64,
               "a wave holds kWaveTargets targets, two lanes each");
 
-__global__ void __launch_bounds__(kHadThreads) __attribute__((amdgpu_waves_per_eu(4, 4)))
+__global__ void __launch_bounds__(kHadThreads) __attribute__((amdgpu_waves_per_eu(6, 6)))
 k_hadamard(const cplx<float>* What, const cplx<float>* Khat, const int* lenq, const int* wbase, const int2* ilw,
            const uint32_t* order, int64_t ncell, int nf, int nwin, int remap, cplx<float>* Shat) {
   extern __shared__ __align__(16) unsigned char shraw[];
@@ -369,11 +368,11 @@ k_hadamard(const cplx<float>* What, const cplx<float>* Khat, const int* lenq, co
     v[3] = {y.z, y.w};
     v[4] = {z.x, z.y};
   };
-  auto pair = [&](int2 j, const cplx<float>* v, float use) {
+  auto pair = [&](int2 j, const cplx<float>* v) {
     // mirrored offset: conjugate the source values (sign bit of the imaginary
     // parts) and negate the real part of the result
     const uint32_t sgb = ((uint32_t)j.y & 1u) << 31;
-    const float sg = __uint_as_float(0x3f800000u | sgb) * use;
+    const float sg = __uint_as_float(0x3f800000u | sgb);
     float wr[9], wi[9];
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
@@ -414,40 +413,27 @@ k_hadamard(const cplx<float>* What, const cplx<float>* Khat, const int* lenq, co
         ci = fma(ki, wr[s], ci);
       }
       ar[r] = fma(sg, cr, ar[r]);
-      ai[r] = fma(use, ci, ai[r]);
+      ai[r] += ci;
     }
   };
-  // Software pipeline over the list with two source buffers, A and B: the
-  // values of the next entry and the entries after it are loaded while the
-  // current entry is computed.  Entries up to three past the end of the list
-  // are read (the zero padding of the wave's block: valid offsets); the extra
-  // entry of an odd list is weighed by zero.  The two buffers are used
-  // alternately (no copies, so no wait on loads still in flight), and each
-  // iteration is one straight block (no exit between the loads and their
-  // use).  The two lanes of a target run the same iterations.
+  // The next list entry is loaded one step ahead (carried through an empty
+  // asm statement, which keeps the compiler from turning it back into a load
+  // at the top of the loop), so a step's source loads do not wait on its
+  // index; the entry after a list's end is the zero padding of the wave's
+  // block.  This needs few registers (76), which leaves room for six waves
+  // per SIMD; prefetching the source values as well (two buffers, 105
+  // registers, four waves per SIMD) was 4% slower.  The two lanes of a target
+  // run the same iterations.
   if (len > 0) {
-    cplx<float> va[5], vb[5];
     uint32_t eb = kStep * (uint32_t)wbase[tt / kWaveTargets] + sizeof(int2) * (uint32_t)(tt % kWaveTargets);
-    int2 ja = entry(eb), jb = entry(eb + kStep);
-    load_src(ja, va);
-    for (int e = 0; e < len; e += 2, eb += 2 * kStep) {
-      const int2 jna = entry(eb + 2 * kStep);
-      const int2 jnb = entry(eb + 3 * kStep);
-      load_src(jb, vb);
-      __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the arithmetic
-      pair(ja, va, 1.f);
-      __builtin_amdgcn_sched_barrier(0);
-      load_src(jna, va);
-      __builtin_amdgcn_sched_barrier(0);
-      pair(jb, vb, e + 1 < len ? 1.f : 0.f);
-      ja = jna;
-      jb = jnb;
-      // Values carried into the next iteration pass through an empty asm
-      // statement: it keeps the compiler from folding them back into loads at
-      // the top of the loop (which would undo the pipeline).
-      asm volatile("" : "+v"(ja.x), "+v"(ja.y), "+v"(jb.x), "+v"(jb.y));
-#pragma unroll
-      for (int k = 0; k < 5; ++k) asm volatile("" : "+v"(va[k].re), "+v"(va[k].im));
+    int2 jo = entry(eb);
+    for (int e = 0; e < len; ++e, eb += kStep) {
+      const int2 jn = entry(eb + kStep);
+      cplx<float> v[5];
+      load_src(jo, v);
+      pair(jo, v);
+      jo = jn;
+      asm volatile("" : "+v"(jo.x), "+v"(jo.y));
     }
   }
   cplx<float>* out = Shat + (t * nf + f) * 6 + 3 * h;

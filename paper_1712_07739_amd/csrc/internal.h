@@ -16,9 +16,9 @@ constexpr int kMaxOrder = 8;
 constexpr int kMaxQuad = 8;
 constexpr int kNumOffsets = 316;  // M2L offsets in [-3,3]^3 outside [-1,1]^3
 // Targets per M2L block (one window of Morton-consecutive targets): two lanes
-// per target in single precision (512 threads), three in double (768).  Both
-// are whole multiples of four waves, so a CU's four SIMDs get equal shares.
-constexpr int kM2LWindowF = 256;
+// per target in single precision, three in double, 768 threads either way (a
+// whole multiple of four waves, so a CU's four SIMDs get equal shares).
+constexpr int kM2LWindowF = 384;
 constexpr int kM2LWindowD = 256;
 inline int m2l_window(bool mixed) { return mixed ? kM2LWindowF : kM2LWindowD; }
 constexpr int kNumCanon = 158;    // one of each pair (o, -o): the kernel is odd, so the
@@ -42,9 +42,9 @@ __host__ __device__ constexpr int had_slot_of(int h, int k) {
 }
 // The single-precision M2L kernel walks the lists of 32 consecutive targets
 // of the processing order in one wave; their entries are stored step-major per
-// wave (see Level::ilw), and entries up to kIlwPad past a list's end are read.
+// wave (see Level::ilw), and the entry after a list's end is read.
 constexpr int kWaveTargets = 32;
-constexpr int kIlwPad = 3;
+constexpr int kIlwPad = 1;
 
 struct Quad {
   double u[kMaxQuad], w[kMaxQuad];
