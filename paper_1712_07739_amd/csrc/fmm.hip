@@ -718,6 +718,135 @@ __global__ void __launch_bounds__(64, leaf_min_waves<T>())
   }
 }
 
+// Symmetric near field (single precision, cubic medium).  The kernel's
+// derivative is odd, dG(-x) = -dG(x), so one evaluation per unordered pair of
+// points serves both directions: sigma_i += K(x_i - x_j) q_j and
+// sigma_j += K(x_j - x_i) q_i = -(the contraction of the same dG with q_i).
+// One wave per unordered pair of neighbouring leaves {A, B}: B = A + o with o
+// the neighbour offsets q = 13..26 (q = 13: the leaf with itself, pairs
+// i < j).  Lane = point pair (i in A, j in B); pairs closer than 2a are left
+// to k_close_eval.  Each round of 64 pairs is reduced in LDS in a fixed order
+// (a target of A sums its consecutive lanes, a target of B its lanes at
+// stride |B|) into compensated float sums, and the block writes one partial
+// per (target, neighbour slot): slot q for the targets of A, slot 26 - q (the
+// offset of A seen from B) for those of B.  k_near_sum then adds a target's
+// 27 slots in slot order, so every sum has a fixed order.
+__device__ __forceinline__ void kadd(float& s, float& c, float x) {
+  const float y = x - c;
+  const float z = s + y;
+  c = (z - s) - y;
+  s = z;
+}
+
+// BIG = false takes the leaf pairs with at most 64 points on each side (LDS
+// for 64 accumulators per side, so LDS does not limit occupancy); BIG = true
+// takes the others, with accumulators for the largest leaf (lmax).
+template <bool BIG>
+__global__ void __launch_bounds__(64, 3)
+    k_leaf_sym(const double* pts, int64_t N, const int* first, const int* count, const int* nbr, Med<float> m,
+               double a2x4, int lmax, float* part) {
+  extern __shared__ float symsh[];
+  const int A = blockIdx.x, q = 13 + blockIdx.y, lane = threadIdx.x;
+  const int B = nbr[(int64_t)A * 27 + q];
+  if (B < 0) return;
+  const bool self = q == 13;
+  const int fa = first[A], na = count[A], fb = first[B], nb = count[B];
+  if ((na > 64 || nb > 64) != BIG) return;
+  if (!BIG) lmax = 64;
+  float* accA = symsh;              // [lmax][6]
+  float* cmpA = accA + lmax * 6;
+  float* accB = cmpA + lmax * 6;
+  float* cmpB = accB + lmax * 6;
+  float* vij = cmpB + lmax * 6;     // [64][6] contributions to A's targets
+  float* vji = vij + 64 * 6;        // [64][6] contributions to B's targets
+  for (int e = lane; e < lmax * 6; e += 64) accA[e] = cmpA[e] = accB[e] = cmpB[e] = 0.f;
+  __syncthreads();
+  const int npair = na * nb;
+  for (int p0 = 0; p0 < npair; p0 += 64) {
+    const int p = p0 + lane;
+    const int i = p / nb, j = p - (p / nb) * nb;
+    float fi[6] = {0, 0, 0, 0, 0, 0}, fj[6] = {0, 0, 0, 0, 0, 0};
+    if (p < npair && (!self || i < j)) {
+      const int64_t gi = fa + i, gj = fb + j;
+      const double d0 = pts[gi] - pts[gj], d1 = pts[N + gi] - pts[N + gj], d2 = pts[2 * N + gi] - pts[2 * N + gj];
+      if (d0 * d0 + d1 * d1 + d2 * d2 >= a2x4) {
+        float D[27], bj[3], tj[3], bi[3], ti[3];
+        for (int c = 0; c < 3; ++c) {
+          bj[c] = (float)pts[(3 + c) * N + gj], tj[c] = (float)pts[(6 + c) * N + gj];
+          bi[c] = (float)pts[(3 + c) * N + gi], ti[c] = (float)pts[(6 + c) * N + gi];
+        }
+        dg_medium_t<float, false>((float)d0, (float)d1, (float)d2, m, D);
+        contract_b_t<float>(D, m.c12, m.c44, m.hh, bj, tj, fi);
+        contract_b_t<float>(D, m.c12, m.c44, m.hh, bi, ti, fj);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      vij[lane * 6 + c] = fi[c];
+      vji[lane * 6 + c] = -fj[c];  // dG(x_j - x_i) = -dG(x_i - x_j)
+    }
+    __syncthreads();
+    const int pend = min(p0 + 64, npair);
+    // the running sums go through registers (one LDS read and write each per
+    // round, not one per term)
+    for (int ii = lane; ii < na; ii += 64) {  // A's target ii: lanes ii*nb .. ii*nb + nb - 1
+      const int lo = max(ii * nb, p0), hi = min(ii * nb + nb, pend);
+      if (lo >= hi) continue;
+      float sa[6], ca[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) sa[c] = accA[ii * 6 + c], ca[c] = cmpA[ii * 6 + c];
+      for (int r = lo; r < hi; ++r)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) kadd(sa[c], ca[c], vij[(r - p0) * 6 + c]);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) accA[ii * 6 + c] = sa[c], cmpA[ii * 6 + c] = ca[c];
+    }
+    for (int jj = lane; jj < nb; jj += 64) {  // B's target jj: lanes with p % nb == jj, in order
+      const int r0 = p0 + ((jj - p0 % nb) % nb + nb) % nb;
+      if (r0 >= pend) continue;
+      float sb[6], cb[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) sb[c] = accB[jj * 6 + c], cb[c] = cmpB[jj * 6 + c];
+      for (int r = r0; r < pend; r += nb)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) kadd(sb[c], cb[c], vji[(r - p0) * 6 + c]);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) accB[jj * 6 + c] = sb[c], cmpB[jj * 6 + c] = cb[c];
+    }
+    __syncthreads();
+  }
+  for (int ii = lane; ii < na; ii += 64)
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      double v = (double)accA[ii * 6 + c] - (double)cmpA[ii * 6 + c];
+      if (self) v += (double)accB[ii * 6 + c] - (double)cmpB[ii * 6 + c];
+      part[((int64_t)(fa + ii) * 27 + q) * 6 + c] = (float)v;
+    }
+  if (!self)
+    for (int jj = lane; jj < nb; jj += 64)
+#pragma unroll
+      for (int c = 0; c < 6; ++c)
+        part[((int64_t)(fb + jj) * 27 + (26 - q)) * 6 + c] =
+            (float)((double)accB[jj * 6 + c] - (double)cmpB[jj * 6 + c]);
+}
+
+// Near-field stress of each point: its 27 neighbour-slot partials in slot
+// order (slots of absent neighbour leaves are skipped).
+__global__ void k_near_sum(const float* part, int64_t N, const int* pleaf, const int* nbr, double* sig) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int leaf = pleaf[i];
+  double tot[6] = {0, 0, 0, 0, 0, 0};
+  for (int q = 0; q < 27; ++q)
+    if (nbr[(int64_t)leaf * 27 + q] >= 0)
+#pragma unroll
+      for (int c = 0; c < 6; ++c) tot[c] += (double)part[(i * 27 + q) * 6 + c];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) sig[i * 6 + c] = tot[c];
+}
+
+inline size_t sym_lds(int lmax) { return sizeof(float) * (24 * (size_t)lmax + 2 * 64 * 6); }
+
 // The near-coincident pairs (closer than 2a) that the single-precision near
 // field skips, in double precision.  The tree holds them per target point, in
 // the order the near field visits its sources.  One thread per pair writes
@@ -1083,8 +1212,18 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
                      LEAF_ARGS)));
       else if (pl->iso)
         STAGE(6, (k_leaf<T, true, true, false><<<(unsigned)LD.n, 64, 0, nst>>>(LEAF_ARGS)));
+      else if (t->part) {
+        const double a2x4 = 4.0 * m64.a * m64.a;
+        STAGE(6, (k_leaf_sym<false><<<dim3((unsigned)LD.n, 14), 64, sym_lds(64), nst>>>(
+                     t->pts, N, LD.first, LD.count, t->nbr, m, a2x4, 64, t->part)));
+        if (t->max_leaf_pts > 64)
+          STAGE(6, (k_leaf_sym<true><<<dim3((unsigned)LD.n, 14), 64, sym_lds(t->max_leaf_pts), nst>>>(
+                       t->pts, N, LD.first, LD.count, t->nbr, m, a2x4, t->max_leaf_pts, t->part)));
+      }
       else
         STAGE(6, (k_leaf<T, true, false, false><<<(unsigned)LD.n, 64, 0, nst>>>(LEAF_ARGS)));
+      if (!pl->iso && !sd.on && t->part)
+        STAGE(6, (k_near_sum<<<nblk(N, 256), 256, 0, nst>>>(t->part, N, t->pleaf, t->nbr, t->sig)));
       if (t->nclose > 0) {
         if (pl->iso)
           STAGE(6, (k_close_eval<true><<<nblk(t->nclose, 64), 64, 0, nst>>>(t->pts, N, t->cpair, t->nclose, m64,
@@ -1168,6 +1307,7 @@ static void set_lds_attrs() {
   const int mx = 160 * 1024;
   hipFuncSetAttribute((const void*)k_hadamard, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
   hipFuncSetAttribute((const void*)k_hadamard3<double>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+  hipFuncSetAttribute((const void*)k_leaf_sym<true>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
   dft_lds_attrs<T>(std::make_integer_sequence<int, kMaxOrder - 1>{});
   hipFuncSetAttribute((const void*)k_p2m<T>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
 }

@@ -43,6 +43,9 @@ __host__ __device__ constexpr int had_slot_of(int h, int k) {
 // The single-precision M2L kernel walks the lists of 32 consecutive targets
 // of the processing order in one wave; their entries are stored step-major per
 // wave (see Level::ilw), and the entry after a list's end is read.
+// Largest leaf (points) for the symmetric near field (its LDS holds four
+// accumulators per point); trees with larger leaves use the one-sided kernel.
+constexpr int kSymMaxLeaf = 1024;
 constexpr int kWaveTargets = 32;
 constexpr int kIlwPad = 1;
 
@@ -167,6 +170,8 @@ struct dfmm_tree {
   void* What = nullptr;     // [nf][max level cells][9] complex
   void* Shat = nullptr;     // [max level cells][nf][6] complex
   double* sig = nullptr;    // [N][6] stress at sorted points
+  float* part = nullptr;    // single precision, cubic medium: [N][27][6] near-field partial per
+                            // neighbour slot (the symmetric near field)
   size_t bytes = 0;
   // per-stage timing
   int timing = 0;

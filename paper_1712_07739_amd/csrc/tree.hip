@@ -646,6 +646,8 @@ int build_tree_impl(dfmm_plan* pl, const double* seg, int64_t nseg, hipStream_t 
   DFMM_HIP(hipMalloc(&t->What, bWh));
   DFMM_HIP(hipMalloc(&t->Shat, bSh));
   DFMM_HIP(hipMalloc(&t->sig, sizeof(double) * 6 * N));
+  if (pl->mixed && !pl->iso && t->max_leaf_pts <= kSymMaxLeaf)
+    DFMM_HIP(hipMalloc(&t->part, sizeof(float) * 27 * 6 * N));
   if (pl->mixed) {  // the near-coincident pairs, evaluated in double by every call
     const double sD = pl->prm.box_size / (double)(1 << D);
     const double a2x4 = 4.0 * pl->prm.core_a * pl->prm.core_a;
@@ -674,7 +676,8 @@ int build_tree_impl(dfmm_plan* pl, const double* seg, int64_t nseg, hipStream_t 
     DFMM_LAUNCH_CHECK();
   }
   t->bytes = sizeof(double) * 15 * N + sizeof(int) * N + bW + bS + bWh + bSh +
-             (sizeof(int2) + 6 * sizeof(double)) * t->nclose + (t->cstart ? sizeof(int) * (N + 1) : 0);
+             (sizeof(int2) + 6 * sizeof(double)) * t->nclose + (t->cstart ? sizeof(int) * (N + 1) : 0) +
+             (t->part ? sizeof(float) * 27 * 6 * N : 0);
   DFMM_HIP(hipStreamSynchronize(st));
   return DFMM_OK;
 }
