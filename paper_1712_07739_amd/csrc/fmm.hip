@@ -849,23 +849,32 @@ inline size_t sym_lds(int lmax) { return sizeof(float) * (24 * (size_t)lmax + 2 
 
 // The near-coincident pairs (closer than 2a) that the single-precision near
 // field skips, in double precision.  The tree holds them per target point, in
-// the order the near field visits its sources.  One thread per pair writes
-// the pair's stress; then one thread per target adds its pairs in that order
-// (a fixed summation order) to the stress k_leaf wrote.
+// the order the near field visits its sources, and as unordered pairs with
+// their two list entries.  One thread per unordered pair evaluates the
+// kernel derivative once (it is odd: dG(x_j - x_i) = -dG(x_i - x_j)) and
+// writes the stress of both list entries; then one thread per target adds
+// its entries in list order (a fixed summation order) to the near field.
 template <bool ISO>
-__global__ void __launch_bounds__(64) k_close_eval(const double* pts, int64_t N, const int2* cpair, int64_t nclose,
-                                                   Med<double> m64, double* cval) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= nclose) return;
-  const int2 pr = cpair[k];
+__global__ void __launch_bounds__(64) k_close_eval(const double* pts, int64_t N, const int2* cpair,
+                                                   const int2* cuni, int64_t nuni, Med<double> m64, double* cval) {
+  const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= nuni) return;
+  const int2 ks = cuni[u];
+  const int2 pr = cpair[ks.x];
   const int64_t it = pr.x, j = pr.y;
   const double d0 = pts[it] - pts[j], d1 = pts[N + it] - pts[N + j], d2 = pts[2 * N + it] - pts[2 * N + j];
-  double D[27], bb[3], tt[3], v[6] = {0, 0, 0, 0, 0, 0};
-  for (int c = 0; c < 3; ++c) bb[c] = pts[(3 + c) * N + j], tt[c] = pts[(6 + c) * N + j];
+  double D[27], bb[3], tt[3], v[6] = {0, 0, 0, 0, 0, 0}, w[6] = {0, 0, 0, 0, 0, 0};
   dg_medium_t<double, ISO>(d0, d1, d2, m64, D);
+  for (int c = 0; c < 3; ++c) bb[c] = pts[(3 + c) * N + j], tt[c] = pts[(6 + c) * N + j];
   contract_b_t<double>(D, m64.c12, m64.c44, m64.hh, bb, tt, v);
 #pragma unroll
-  for (int c = 0; c < 6; ++c) cval[k * 6 + c] = v[c];
+  for (int c = 0; c < 6; ++c) cval[(int64_t)ks.x * 6 + c] = v[c];
+  if (ks.y >= 0) {
+    for (int c = 0; c < 3; ++c) bb[c] = pts[(3 + c) * N + it], tt[c] = pts[(6 + c) * N + it];
+    contract_b_t<double>(D, m64.c12, m64.c44, m64.hh, bb, tt, w);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) cval[(int64_t)ks.y * 6 + c] = -w[c];
+  }
 }
 
 __global__ void k_close_sum(const int* cstart, int64_t N, const double* cval, double* sig) {
@@ -1226,11 +1235,11 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
         STAGE(6, (k_near_sum<<<nblk(N, 256), 256, 0, nst>>>(t->part, N, t->pleaf, t->nbr, t->sig)));
       if (t->nclose > 0) {
         if (pl->iso)
-          STAGE(6, (k_close_eval<true><<<nblk(t->nclose, 64), 64, 0, nst>>>(t->pts, N, t->cpair, t->nclose, m64,
-                                                                            t->cval)));
+          STAGE(6, (k_close_eval<true><<<nblk(t->nuni, 64), 64, 0, nst>>>(t->pts, N, t->cpair, t->cuni, t->nuni,
+                                                                          m64, t->cval)));
         else
-          STAGE(6, (k_close_eval<false><<<nblk(t->nclose, 64), 64, 0, nst>>>(t->pts, N, t->cpair, t->nclose, m64,
-                                                                             t->cval)));
+          STAGE(6, (k_close_eval<false><<<nblk(t->nuni, 64), 64, 0, nst>>>(t->pts, N, t->cpair, t->cuni, t->nuni,
+                                                                           m64, t->cval)));
         STAGE(6, (k_close_sum<<<nblk(N, 256), 256, 0, nst>>>(t->cstart, N, t->cval, t->sig)));
       }
     } else {

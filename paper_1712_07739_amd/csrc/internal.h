@@ -185,6 +185,8 @@ struct dfmm_tree {
   int* cstart = nullptr;   // [N + 1]
   int2* cpair = nullptr;   // [nclose] (target, source), sorted point indices
   double* cval = nullptr;  // [nclose][6] per-pair stress, written by every call
+  int64_t nuni = 0;
+  int2* cuni = nullptr;     // [nuni] unordered pairs: (entry (i, j) with i < j, entry (j, i))
   // recorded at the end of every call that is not being captured into a
   // graph: destroy and the query calls wait on it (an event the tree owns,
   // valid whatever becomes of the caller's streams)

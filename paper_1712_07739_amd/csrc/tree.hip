@@ -403,8 +403,9 @@ __global__ void k_gather_pos(const double* seg, const uint32_t* perm, Quad qd, i
 }
 
 // Near-coincident pairs of each sorted target point: the sources closer than
-// 2a in its leaf's 27 neighbour leaves, in the order the near field visits
-// them (neighbour by neighbour, then by sorted index).  A neighbour leaf is
+// 2a in its leaf's 27 neighbour leaves (the point itself excluded: its own
+// term is zero), in the order the near field visits them (neighbour by
+// neighbour, then by sorted index).  A neighbour leaf is
 // skipped only if its box lies at least 2a from the target (with a relative
 // margin of 1e-9 against rounding).  FILL = false counts, true writes.
 template <bool FILL>
@@ -435,7 +436,7 @@ __global__ void k_close_find(const double* pts, int64_t N, const int* pleaf, con
     for (int jj = 0; jj < n; ++jj) {
       const int64_t j = f + jj;
       const double d0 = x0 - pts[j], d1 = x1 - pts[N + j], d2 = x2 - pts[2 * N + j];
-      if (d0 * d0 + d1 * d1 + d2 * d2 < a2x4) {
+      if (j != i && d0 * d0 + d1 * d1 + d2 * d2 < a2x4) {  // a point's own pair is zero (odd kernel)
         if (FILL)
           cpair[w++] = make_int2((int)i, (int)j);
         else
@@ -444,6 +445,28 @@ __global__ void k_close_find(const double* pts, int64_t N, const int* pleaf, con
     }
   }
   if (!FILL) cnt[i] = c;
+}
+
+// The close pairs are symmetric ((i, j) listed iff (j, i) is).  One thread
+// per listed pair with i < j finds the mirror entry (j, i) in j's list; the
+// pair is then evaluated once for both directions (flag pass, then fill).
+__global__ void k_close_uni(const int2* cpair, const int* cstart, int64_t nclose, const int* upos, int* flag,
+                            int2* cuni) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nclose) return;
+  const int2 pr = cpair[k];
+  if (!cuni) {
+    flag[k] = pr.x < pr.y ? 1 : 0;
+    return;
+  }
+  if (pr.x >= pr.y) return;
+  int mk = -1;
+  for (int r = cstart[pr.y]; r < cstart[pr.y + 1]; ++r)
+    if (cpair[r].y == pr.x) {
+      mk = r;
+      break;
+    }
+  cuni[upos[k]] = make_int2((int)k, mk);
 }
 
 static inline unsigned nb(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
@@ -674,9 +697,37 @@ int build_tree_impl(dfmm_plan* pl, const double* seg, int64_t nseg, hipStream_t 
                                                   pl->prm.box_lo[0], pl->prm.box_lo[1], pl->prm.box_lo[2], sD,
                                                   a2x4, nullptr, t->cstart, t->cpair);
     DFMM_LAUNCH_CHECK();
+    if (t->nclose > 0) {  // the unordered pairs with their two list entries
+      int *flag = nullptr, *upos = nullptr;
+      DFMM_HIP(hipMalloc(&flag, sizeof(int) * (t->nclose + 1)));
+      DFMM_HIP(hipMalloc(&upos, sizeof(int) * (t->nclose + 1)));
+      DFMM_HIP(hipMemsetAsync(flag + t->nclose, 0, sizeof(int), st));
+      k_close_uni<<<nb(t->nclose, 256), 256, 0, st>>>(t->cpair, t->cstart, t->nclose, nullptr, flag, nullptr);
+      DFMM_LAUNCH_CHECK();
+      rc = scan_excl(flag, upos, t->nclose + 1, st, &t->nuni);
+      if (rc == DFMM_OK && hipMalloc(&t->cuni, sizeof(int2) * std::max<int64_t>(t->nuni, 1)) != hipSuccess)
+        rc = DFMM_E_NOMEM;
+      if (rc == DFMM_OK) {
+        k_close_uni<<<nb(t->nclose, 256), 256, 0, st>>>(t->cpair, t->cstart, t->nclose, upos, nullptr, t->cuni);
+        DFMM_LAUNCH_CHECK();
+        DFMM_HIP(hipStreamSynchronize(st));
+      }
+      hipFree(flag);
+      hipFree(upos);
+      if (rc) {
+        set_error("build_tree: cannot allocate the close-pair tables");
+        return rc;
+      }
+      if (2 * t->nuni != t->nclose) {  // the lists are symmetric by construction
+        set_error("build_tree: the near-coincident pair lists are not symmetric");
+        return DFMM_E_STATE;
+      }
+      DFMM_HIP(hipMemsetAsync(t->cval, 0, sizeof(double) * 6 * t->nclose, st));
+    }
   }
   t->bytes = sizeof(double) * 15 * N + sizeof(int) * N + bW + bS + bWh + bSh +
-             (sizeof(int2) + 6 * sizeof(double)) * t->nclose + (t->cstart ? sizeof(int) * (N + 1) : 0) +
+             (sizeof(int2) + 6 * sizeof(double)) * t->nclose + sizeof(int2) * t->nuni +
+             (t->cstart ? sizeof(int) * (N + 1) : 0) +
              (t->part ? sizeof(float) * 27 * 6 * N : 0);
   DFMM_HIP(hipStreamSynchronize(st));
   return DFMM_OK;
