@@ -204,6 +204,7 @@ __device__ __forceinline__ int64_t xcd_block(int64_t L, int64_t n) {
 }
 
 // ------------------------------------------------------------ forward DFT
+constexpr int kDftThreads = 512;  // threads per block of the DFT kernels
 // One block per cell of a level: W[cell][9][P^3] (real, zero-padded to n^3,
 // n = 2P - 1) -> What[f][cell][9], f = (f1 n + f2) P + f3, the half spectrum
 // in the last axis (the input is real).  Three passes of length-P to
@@ -222,7 +223,7 @@ __device__ __forceinline__ void cmac(const cplx<T>& a, T c, T s, T& re, T& im) {
 }
 
 template <typename T, int P>
-__global__ void __launch_bounds__(256) k_fdft(const T* __restrict__ W, int64_t ncell, int G,
+__global__ void __launch_bounds__(kDftThreads) k_fdft(const T* __restrict__ W, int64_t ncell, int G,
                                               const T* __restrict__ twg, cplx<T>* __restrict__ What) {
   constexpr int n = 2 * P - 1, p3 = P * P * P;
   extern __shared__ __align__(16) unsigned char shraw[];
@@ -543,7 +544,7 @@ __global__ void __launch_bounds__(kHad3Threads) k_hadamard3(const cplx<T>* What,
 // straight from memory, each value once; the last pass uses the Hermitian
 // symmetry of the last axis (f3 = 0 once, f3 > 0 twice, real part).
 template <typename T, int P>
-__global__ void __launch_bounds__(256) k_idft(const cplx<T>* __restrict__ Shat, int64_t ncell,
+__global__ void __launch_bounds__(kDftThreads) k_idft(const cplx<T>* __restrict__ Shat, int64_t ncell,
                                               const T* __restrict__ twg, T* __restrict__ s) {
   constexpr int n = 2 * P - 1, p3 = P * P * P, nf = n * n * P;
   extern __shared__ __align__(16) unsigned char shraw[];
@@ -1081,9 +1082,9 @@ static void dft_launch(bool fwd, unsigned blocks, const void* in, int64_t ncell,
                        hipStream_t st) {
   const int G = dft_groups<T, P>(fwd);
   if (fwd)
-    k_fdft<T, P><<<blocks, 256, lds_fdft_t<P>(G, sizeof(T)), st>>>((const T*)in, ncell, G, tw, (cplx<T>*)out);
+    k_fdft<T, P><<<blocks, kDftThreads, lds_fdft_t<P>(G, sizeof(T)), st>>>((const T*)in, ncell, G, tw, (cplx<T>*)out);
   else
-    k_idft<T, P><<<blocks, 256, lds_idft_t<P>(sizeof(T)), st>>>((const cplx<T>*)in, ncell, tw, (T*)out);
+    k_idft<T, P><<<blocks, kDftThreads, lds_idft_t<P>(sizeof(T)), st>>>((const cplx<T>*)in, ncell, tw, (T*)out);
 }
 
 template <typename T>
