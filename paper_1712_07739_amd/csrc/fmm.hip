@@ -788,31 +788,25 @@ __global__ void __launch_bounds__(64, 3)
     }
     __syncthreads();
     const int pend = min(p0 + 64, npair);
-    // the running sums go through registers (one LDS read and write each per
-    // round, not one per term)
-    for (int ii = lane; ii < na; ii += 64) {  // A's target ii: lanes ii*nb .. ii*nb + nb - 1
+    // one lane per (target, component); the running sum goes through
+    // registers (one LDS read and write per round, not one per term)
+    for (int w = lane; w < na * 6; w += 64) {  // A's target ii: lanes ii*nb .. ii*nb + nb - 1
+      const int ii = w / 6, c = w - ii * 6;
       const int lo = max(ii * nb, p0), hi = min(ii * nb + nb, pend);
       if (lo >= hi) continue;
-      float sa[6], ca[6];
-#pragma unroll
-      for (int c = 0; c < 6; ++c) sa[c] = accA[ii * 6 + c], ca[c] = cmpA[ii * 6 + c];
-      for (int r = lo; r < hi; ++r)
-#pragma unroll
-        for (int c = 0; c < 6; ++c) kadd(sa[c], ca[c], vij[(r - p0) * 6 + c]);
-#pragma unroll
-      for (int c = 0; c < 6; ++c) accA[ii * 6 + c] = sa[c], cmpA[ii * 6 + c] = ca[c];
+      float sa = accA[w], ca = cmpA[w];
+      for (int r = lo; r < hi; ++r) kadd(sa, ca, vij[(r - p0) * 6 + c]);
+      accA[w] = sa;
+      cmpA[w] = ca;
     }
-    for (int jj = lane; jj < nb; jj += 64) {  // B's target jj: lanes with p % nb == jj, in order
+    for (int w = lane; w < nb * 6; w += 64) {  // B's target jj: lanes with p % nb == jj, in order
+      const int jj = w / 6, c = w - jj * 6;
       const int r0 = p0 + ((jj - p0 % nb) % nb + nb) % nb;
       if (r0 >= pend) continue;
-      float sb[6], cb[6];
-#pragma unroll
-      for (int c = 0; c < 6; ++c) sb[c] = accB[jj * 6 + c], cb[c] = cmpB[jj * 6 + c];
-      for (int r = r0; r < pend; r += nb)
-#pragma unroll
-        for (int c = 0; c < 6; ++c) kadd(sb[c], cb[c], vji[(r - p0) * 6 + c]);
-#pragma unroll
-      for (int c = 0; c < 6; ++c) accB[jj * 6 + c] = sb[c], cmpB[jj * 6 + c] = cb[c];
+      float sb = accB[w], cb = cmpB[w];
+      for (int r = r0; r < pend; r += nb) kadd(sb, cb, vji[(r - p0) * 6 + c]);
+      accB[w] = sb;
+      cmpB[w] = cb;
     }
     __syncthreads();
   }
