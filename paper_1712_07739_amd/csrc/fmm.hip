@@ -719,22 +719,24 @@ __global__ void __launch_bounds__(64, leaf_min_waves<T>())
   }
 }
 
-// Symmetric near field (single precision, cubic medium).  The kernel's
+// Symmetric near field (cubic medium; single precision, and double precision
+// in the FP64 path, where no pair is left out).  The kernel's
 // derivative is odd, dG(-x) = -dG(x), so one evaluation per unordered pair of
 // points serves both directions: sigma_i += K(x_i - x_j) q_j and
 // sigma_j += K(x_j - x_i) q_i = -(the contraction of the same dG with q_i).
 // One wave per unordered pair of neighbouring leaves {A, B}: B = A + o with o
 // the neighbour offsets q = 13..26 (q = 13: the leaf with itself, pairs
-// i < j).  Lane = point pair (i in A, j in B); pairs closer than 2a are left
-// to k_close_eval.  Each round of 64 pairs is reduced in LDS in a fixed order
-// (a target of A sums its consecutive lanes, a target of B its lanes at
-// stride |B|) into compensated float sums, and the block writes one partial
+// i < j).  Lane = point pair (i in A, j in B); in single precision, pairs
+// closer than 2a are left to k_close_eval.  Each round of 64 pairs is reduced
+// in LDS in a fixed order (a target of A sums its consecutive lanes, a target
+// of B its lanes at stride |B|) into compensated sums, and the block writes one partial
 // per (target, neighbour slot): slot q for the targets of A, slot 26 - q (the
 // offset of A seen from B) for those of B.  k_near_sum then adds a target's
 // 27 slots in slot order, so every sum has a fixed order.
-__device__ __forceinline__ void kadd(float& s, float& c, float x) {
-  const float y = x - c;
-  const float z = s + y;
+template <typename T>
+__device__ __forceinline__ void kadd(T& s, T& c, T x) {
+  const T y = x - c;
+  const T z = s + y;
   c = (z - s) - y;
   s = z;
 }
@@ -742,11 +744,17 @@ __device__ __forceinline__ void kadd(float& s, float& c, float x) {
 // BIG = false takes the leaf pairs with at most 64 points on each side (LDS
 // for 64 accumulators per side, so LDS does not limit occupancy); BIG = true
 // takes the others, with accumulators for the largest leaf (lmax).
-template <bool BIG>
-__global__ void __launch_bounds__(64, 3)
-    k_leaf_sym(const double* pts, int64_t N, const int* first, const int* count, const int* nbr, Med<float> m,
-               double a2x4, int lmax, float* part) {
-  extern __shared__ float symsh[];
+template <typename T>
+constexpr int sym_min_waves() {
+  return sizeof(T) == 4 ? 3 : 1;
+}
+
+template <typename T, bool MIXED, bool BIG>
+__global__ void __launch_bounds__(64, sym_min_waves<T>())
+    k_leaf_sym(const double* pts, int64_t N, const int* first, const int* count, const int* nbr, Med<T> m,
+               double a2x4, int lmax, T* part) {
+  extern __shared__ __align__(16) unsigned char symraw[];
+  T* symsh = reinterpret_cast<T*>(symraw);
   const int A = blockIdx.x, q = 13 + blockIdx.y, lane = threadIdx.x;
   const int B = nbr[(int64_t)A * 27 + q];
   if (B < 0) return;
@@ -754,31 +762,31 @@ __global__ void __launch_bounds__(64, 3)
   const int fa = first[A], na = count[A], fb = first[B], nb = count[B];
   if ((na > 64 || nb > 64) != BIG) return;
   if (!BIG) lmax = 64;
-  float* accA = symsh;              // [lmax][6]
-  float* cmpA = accA + lmax * 6;
-  float* accB = cmpA + lmax * 6;
-  float* cmpB = accB + lmax * 6;
-  float* vij = cmpB + lmax * 6;     // [64][6] contributions to A's targets
-  float* vji = vij + 64 * 6;        // [64][6] contributions to B's targets
-  for (int e = lane; e < lmax * 6; e += 64) accA[e] = cmpA[e] = accB[e] = cmpB[e] = 0.f;
+  T* accA = symsh;              // [lmax][6]
+  T* cmpA = accA + lmax * 6;
+  T* accB = cmpA + lmax * 6;
+  T* cmpB = accB + lmax * 6;
+  T* vij = cmpB + lmax * 6;     // [64][6] contributions to A's targets
+  T* vji = vij + 64 * 6;        // [64][6] contributions to B's targets
+  for (int e = lane; e < lmax * 6; e += 64) accA[e] = cmpA[e] = accB[e] = cmpB[e] = T(0);
   __syncthreads();
   const int npair = na * nb;
   for (int p0 = 0; p0 < npair; p0 += 64) {
     const int p = p0 + lane;
     const int i = p / nb, j = p - (p / nb) * nb;
-    float fi[6] = {0, 0, 0, 0, 0, 0}, fj[6] = {0, 0, 0, 0, 0, 0};
+    T fi[6] = {0, 0, 0, 0, 0, 0}, fj[6] = {0, 0, 0, 0, 0, 0};
     if (p < npair && (!self || i < j)) {
       const int64_t gi = fa + i, gj = fb + j;
       const double d0 = pts[gi] - pts[gj], d1 = pts[N + gi] - pts[N + gj], d2 = pts[2 * N + gi] - pts[2 * N + gj];
-      if (d0 * d0 + d1 * d1 + d2 * d2 >= a2x4) {
-        float D[27], bj[3], tj[3], bi[3], ti[3];
+      if (!MIXED || d0 * d0 + d1 * d1 + d2 * d2 >= a2x4) {
+        T D[27], bj[3], tj[3], bi[3], ti[3];
         for (int c = 0; c < 3; ++c) {
-          bj[c] = (float)pts[(3 + c) * N + gj], tj[c] = (float)pts[(6 + c) * N + gj];
-          bi[c] = (float)pts[(3 + c) * N + gi], ti[c] = (float)pts[(6 + c) * N + gi];
+          bj[c] = (T)pts[(3 + c) * N + gj], tj[c] = (T)pts[(6 + c) * N + gj];
+          bi[c] = (T)pts[(3 + c) * N + gi], ti[c] = (T)pts[(6 + c) * N + gi];
         }
-        dg_medium_t<float, false>((float)d0, (float)d1, (float)d2, m, D);
-        contract_b_t<float>(D, m.c12, m.c44, m.hh, bj, tj, fi);
-        contract_b_t<float>(D, m.c12, m.c44, m.hh, bi, ti, fj);
+        dg_medium_t<T, false>((T)d0, (T)d1, (T)d2, m, D);
+        contract_b_t<T>(D, m.c12, m.c44, m.hh, bj, tj, fi);
+        contract_b_t<T>(D, m.c12, m.c44, m.hh, bi, ti, fj);
       }
     }
 #pragma unroll
@@ -794,7 +802,7 @@ __global__ void __launch_bounds__(64, 3)
       const int ii = w / 6, c = w - ii * 6;
       const int lo = max(ii * nb, p0), hi = min(ii * nb + nb, pend);
       if (lo >= hi) continue;
-      float sa = accA[w], ca = cmpA[w];
+      T sa = accA[w], ca = cmpA[w];
       for (int r = lo; r < hi; ++r) kadd(sa, ca, vij[(r - p0) * 6 + c]);
       accA[w] = sa;
       cmpA[w] = ca;
@@ -803,7 +811,7 @@ __global__ void __launch_bounds__(64, 3)
       const int jj = w / 6, c = w - jj * 6;
       const int r0 = p0 + ((jj - p0 % nb) % nb + nb) % nb;
       if (r0 >= pend) continue;
-      float sb = accB[w], cb = cmpB[w];
+      T sb = accB[w], cb = cmpB[w];
       for (int r = r0; r < pend; r += nb) kadd(sb, cb, vji[(r - p0) * 6 + c]);
       accB[w] = sb;
       cmpB[w] = cb;
@@ -815,19 +823,20 @@ __global__ void __launch_bounds__(64, 3)
     for (int c = 0; c < 6; ++c) {
       double v = (double)accA[ii * 6 + c] - (double)cmpA[ii * 6 + c];
       if (self) v += (double)accB[ii * 6 + c] - (double)cmpB[ii * 6 + c];
-      part[((int64_t)(fa + ii) * 27 + q) * 6 + c] = (float)v;
+      part[((int64_t)(fa + ii) * 27 + q) * 6 + c] = (T)v;
     }
   if (!self)
     for (int jj = lane; jj < nb; jj += 64)
 #pragma unroll
       for (int c = 0; c < 6; ++c)
         part[((int64_t)(fb + jj) * 27 + (26 - q)) * 6 + c] =
-            (float)((double)accB[jj * 6 + c] - (double)cmpB[jj * 6 + c]);
+            (T)((double)accB[jj * 6 + c] - (double)cmpB[jj * 6 + c]);
 }
 
 // Near-field stress of each point: its 27 neighbour-slot partials in slot
 // order (slots of absent neighbour leaves are skipped).
-__global__ void k_near_sum(const float* part, int64_t N, const int* pleaf, const int* nbr, double* sig) {
+template <typename T>
+__global__ void k_near_sum(const T* part, int64_t N, const int* pleaf, const int* nbr, double* sig) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
   const int leaf = pleaf[i];
@@ -840,7 +849,8 @@ __global__ void k_near_sum(const float* part, int64_t N, const int* pleaf, const
   for (int c = 0; c < 6; ++c) sig[i * 6 + c] = tot[c];
 }
 
-inline size_t sym_lds(int lmax) { return sizeof(float) * (24 * (size_t)lmax + 2 * 64 * 6); }
+template <typename T>
+inline size_t sym_lds(int lmax) { return sizeof(T) * (24 * (size_t)lmax + 2 * 64 * 6); }
 
 // The near-coincident pairs (closer than 2a) that the single-precision near
 // field skips, in double precision.  The tree holds them per target point, in
@@ -1218,16 +1228,16 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
         STAGE(6, (k_leaf<T, true, true, false><<<(unsigned)LD.n, 64, 0, nst>>>(LEAF_ARGS)));
       else if (t->part) {
         const double a2x4 = 4.0 * m64.a * m64.a;
-        STAGE(6, (k_leaf_sym<false><<<dim3((unsigned)LD.n, 14), 64, sym_lds(64), nst>>>(
-                     t->pts, N, LD.first, LD.count, t->nbr, m, a2x4, 64, t->part)));
+        STAGE(6, (k_leaf_sym<T, true, false><<<dim3((unsigned)LD.n, 14), 64, sym_lds<T>(64), nst>>>(
+                     t->pts, N, LD.first, LD.count, t->nbr, m, a2x4, 64, (T*)t->part)));
         if (t->max_leaf_pts > 64)
-          STAGE(6, (k_leaf_sym<true><<<dim3((unsigned)LD.n, 14), 64, sym_lds(t->max_leaf_pts), nst>>>(
-                       t->pts, N, LD.first, LD.count, t->nbr, m, a2x4, t->max_leaf_pts, t->part)));
+          STAGE(6, (k_leaf_sym<T, true, true><<<dim3((unsigned)LD.n, 14), 64, sym_lds<T>(t->max_leaf_pts), nst>>>(
+                       t->pts, N, LD.first, LD.count, t->nbr, m, a2x4, t->max_leaf_pts, (T*)t->part)));
       }
       else
         STAGE(6, (k_leaf<T, true, false, false><<<(unsigned)LD.n, 64, 0, nst>>>(LEAF_ARGS)));
       if (!pl->iso && !sd.on && t->part)
-        STAGE(6, (k_near_sum<<<nblk(N, 256), 256, 0, nst>>>(t->part, N, t->pleaf, t->nbr, t->sig)));
+        STAGE(6, (k_near_sum<T><<<nblk(N, 256), 256, 0, nst>>>((const T*)t->part, N, t->pleaf, t->nbr, t->sig)));
       if (t->nclose > 0) {
         if (pl->iso)
           STAGE(6, (k_close_eval<true><<<nblk(t->nuni, 64), 64, 0, nst>>>(t->pts, N, t->cpair, t->cuni, t->nuni,
@@ -1238,10 +1248,18 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
         STAGE(6, (k_close_sum<<<nblk(N, 256), 256, 0, nst>>>(t->cstart, N, t->cval, t->sig)));
       }
     } else {
-      if (pl->iso)
+      if (pl->iso) {
         STAGE(6, (k_leaf<T, false, true, false><<<(unsigned)LD.n, 64, 0, nst>>>(LEAF_ARGS)));
-      else
+      } else if (t->part) {
+        STAGE(6, (k_leaf_sym<T, false, false><<<dim3((unsigned)LD.n, 14), 64, sym_lds<T>(64), nst>>>(
+                     t->pts, N, LD.first, LD.count, t->nbr, m, 0.0, 64, (T*)t->part)));
+        if (t->max_leaf_pts > 64)
+          STAGE(6, (k_leaf_sym<T, false, true><<<dim3((unsigned)LD.n, 14), 64, sym_lds<T>(t->max_leaf_pts), nst>>>(
+                       t->pts, N, LD.first, LD.count, t->nbr, m, 0.0, t->max_leaf_pts, (T*)t->part)));
+        STAGE(6, (k_near_sum<T><<<nblk(N, 256), 256, 0, nst>>>((const T*)t->part, N, t->pleaf, t->nbr, t->sig)));
+      } else {
         STAGE(6, (k_leaf<T, false, false, false><<<(unsigned)LD.n, 64, 0, nst>>>(LEAF_ARGS)));
+      }
     }
 #undef LEAF_ARGS
   }
@@ -1311,7 +1329,8 @@ static void set_lds_attrs() {
   const int mx = 160 * 1024;
   hipFuncSetAttribute((const void*)k_hadamard, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
   hipFuncSetAttribute((const void*)k_hadamard3<double>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-  hipFuncSetAttribute((const void*)k_leaf_sym<true>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+  hipFuncSetAttribute((const void*)k_leaf_sym<T, sizeof(T) == 4, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                      mx);
   dft_lds_attrs<T>(std::make_integer_sequence<int, kMaxOrder - 1>{});
   hipFuncSetAttribute((const void*)k_p2m<T>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
 }

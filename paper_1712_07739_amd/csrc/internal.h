@@ -45,7 +45,8 @@ __host__ __device__ constexpr int had_slot_of(int h, int k) {
 // wave (see Level::ilw), and the entry after a list's end is read.
 // Largest leaf (points) for the symmetric near field (its LDS holds four
 // accumulators per point); trees with larger leaves use the one-sided kernel.
-constexpr int kSymMaxLeaf = 1024;
+constexpr int kSymMaxLeaf = 1024;  // single precision
+constexpr int kSymMaxLeafD = 768;  // double precision
 constexpr int kWaveTargets = 32;
 constexpr int kIlwPad = 1;
 
@@ -170,7 +171,7 @@ struct dfmm_tree {
   void* What = nullptr;     // [nf][max level cells][9] complex
   void* Shat = nullptr;     // [max level cells][nf][6] complex
   double* sig = nullptr;    // [N][6] stress at sorted points
-  float* part = nullptr;    // single precision, cubic medium: [N][27][6] near-field partial per
+  void* part = nullptr;     // cubic medium: [N][27][6] near-field partial (float or double) per
                             // neighbour slot (the symmetric near field)
   size_t bytes = 0;
   // per-stage timing

@@ -669,8 +669,9 @@ int build_tree_impl(dfmm_plan* pl, const double* seg, int64_t nseg, hipStream_t 
   DFMM_HIP(hipMalloc(&t->What, bWh));
   DFMM_HIP(hipMalloc(&t->Shat, bSh));
   DFMM_HIP(hipMalloc(&t->sig, sizeof(double) * 6 * N));
-  if (pl->mixed && !pl->iso && t->max_leaf_pts <= kSymMaxLeaf)
-    DFMM_HIP(hipMalloc(&t->part, sizeof(float) * 27 * 6 * N));
+  const size_t part_es = pl->mixed ? sizeof(float) : sizeof(double);
+  if (!pl->iso && t->max_leaf_pts <= (pl->mixed ? kSymMaxLeaf : kSymMaxLeafD))
+    DFMM_HIP(hipMalloc(&t->part, part_es * 27 * 6 * N));
   if (pl->mixed) {  // the near-coincident pairs, evaluated in double by every call
     const double sD = pl->prm.box_size / (double)(1 << D);
     const double a2x4 = 4.0 * pl->prm.core_a * pl->prm.core_a;
@@ -728,7 +729,7 @@ int build_tree_impl(dfmm_plan* pl, const double* seg, int64_t nseg, hipStream_t 
   t->bytes = sizeof(double) * 15 * N + sizeof(int) * N + bW + bS + bWh + bSh +
              (sizeof(int2) + 6 * sizeof(double)) * t->nclose + sizeof(int2) * t->nuni +
              (t->cstart ? sizeof(int) * (N + 1) : 0) +
-             (t->part ? sizeof(float) * 27 * 6 * N : 0);
+             (t->part ? part_es * 27 * 6 * N : 0);
   DFMM_HIP(hipStreamSynchronize(st));
   return DFMM_OK;
 }

@@ -150,10 +150,10 @@ def test_dense_cluster_of_close_pairs(env):
 
 
 def test_symmetric_near_field_small_and_large_leaves(env):
-    """Cubic single-precision near field, one kernel evaluation per unordered
-    pair: a shallow tree puts whole loops in one leaf (more than 64 points:
-    the launch for large leaves) beside small leaves (64 or fewer), and the
-    forces must match the oracle's FMM and the FP64 path."""
+    """Cubic near field with one kernel evaluation per unordered pair, in
+    single and in double precision: a shallow tree puts whole loops in one
+    leaf (more than 64 points: the launch for large leaves) beside small
+    leaves (64 or fewer), and both paths must match the oracle's FMM."""
     seg, b = synth.make_loops(12, 0.01, 0.04, 23)
     med = oracle.medium(*CUB, 1e-3)
     f32, _, tree = run_fmm(env, seg, b, CUB, 4, 3, precision=1)
@@ -161,7 +161,9 @@ def test_symmetric_near_field_small_and_large_leaves(env):
     assert 64 < info["max_leaf_points"] <= 1024
     ref = oracle.fmm_forces(seg, b, med, 4, 3, BOX_LO, BOX)
     assert oracle.rel_err(f32, ref) <= 2e-5
-    f64, _, _ = run_fmm(env, seg, b, CUB, 4, 3, precision=0)
+    f64, _, tree64 = run_fmm(env, seg, b, CUB, 4, 3, precision=0)
+    assert tree64.info()["max_leaf_points"] <= 768
+    assert oracle.rel_err(f64, ref) <= 1e-10
     assert oracle.rel_err(f32, f64) <= 2e-5
 
 
