@@ -69,7 +69,7 @@ def main():
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true",
                     help="cubic media: skip training the anisotropic-kernel network (it is used where its gate passes)")
-    ap.add_argument("--cpu-sample", type=int, default=1, help="target segments timed on the CPU oracle")
+    ap.add_argument("--cpu-sample", type=int, default=3, help="target segments timed on the CPU oracle")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run 3 plain device copies of MIB MiB (calibrates HBM byte counters) and exit")
     args = ap.parse_args()
