@@ -216,10 +216,37 @@ constexpr int kDftThreads = 512;  // threads per block of the DFT kernels
 // straight from memory; the intermediate lines go through LDS.  Rows of
 // neighbouring cells share cache lines, so cells are spread over the XCDs in
 // contiguous ranges (xcd_block).
-template <typename T>
-__device__ __forceinline__ void cmac(const cplx<T>& a, T c, T s, T& re, T& im) {
-  re = fma(a.re, c, fma(-a.im, s, re));
-  im = fma(a.re, s, fma(a.im, c, im));
+// One line of a complex pass, P inputs -> all n = 2P - 1 outputs.  Outputs f
+// and n - f use conjugate twiddles, so with A = sum re(x) c, B = sum im(x) s,
+// C = sum re(x) s and D = sum im(x) c, X[f] = (A - B, C + D) and
+// X[n - f] = (A + B, D - C): four multiply-adds per input for two outputs.
+// Output 0 is the plain sum.  put(f, value) stores output f.
+template <typename T, int P, typename Put>
+__device__ __forceinline__ void dft_line_pairs(const cplx<T>* x, const T* c, const T* s, Put put) {
+  constexpr int n = 2 * P - 1;
+  {
+    T re = x[0].re, im = x[0].im;
+#pragma unroll
+    for (int m = 1; m < P; ++m) {
+      re += x[m].re;
+      im += x[m].im;
+    }
+    put(0, cplx<T>{re, im});
+  }
+#pragma unroll
+  for (int f = 1; f < P; ++f) {
+    T A = x[0].re, B = 0, C = 0, D = x[0].im;
+#pragma unroll
+    for (int m = 1; m < P; ++m) {
+      const T cc = c[(f * m) % n], ss = s[(f * m) % n];
+      A = fma(x[m].re, cc, A);
+      B = fma(x[m].im, ss, B);
+      C = fma(x[m].re, ss, C);
+      D = fma(x[m].im, cc, D);
+    }
+    put(f, cplx<T>{A - B, C + D});
+    put(n - f, cplx<T>{A + B, D - C});
+  }
 }
 
 template <typename T, int P>
@@ -261,13 +288,7 @@ __global__ void __launch_bounds__(kDftThreads) k_fdft(const T* __restrict__ W, i
       cplx<T> x[P];
 #pragma unroll
       for (int m = 0; m < P; ++m) x[m] = X1[(gm * P + m) * P + f3];
-#pragma unroll
-      for (int f = 0; f < n; ++f) {
-        T re = 0, im = 0;
-#pragma unroll
-        for (int m = 0; m < P; ++m) cmac(x[m], c[(f * m) % n], s[(f * m) % n], re, im);
-        X2[(gm * n + f) * P + f3] = cplx<T>{re, im};
-      }
+      dft_line_pairs<T, P>(x, c, s, [&](int f, cplx<T> v) { X2[(gm * n + f) * P + f3] = v; });
     }
     __syncthreads();
     // along the first axis: P -> n, into What (the G components of a
@@ -277,13 +298,8 @@ __global__ void __launch_bounds__(kDftThreads) k_fdft(const T* __restrict__ W, i
       cplx<T> x[P];
 #pragma unroll
       for (int m = 0; m < P; ++m) x[m] = X2[(g * P + m) * n * P + r];
-#pragma unroll
-      for (int f = 0; f < n; ++f) {
-        T re = 0, im = 0;
-#pragma unroll
-        for (int m = 0; m < P; ++m) cmac(x[m], c[(f * m) % n], s[(f * m) % n], re, im);
-        What[((int64_t)(f * n * P + r) * ncell + cell) * 9 + c0 + g] = cplx<T>{re, im};
-      }
+      dft_line_pairs<T, P>(x, c, s,
+                           [&](int f, cplx<T> v) { What[((int64_t)(f * n * P + r) * ncell + cell) * 9 + c0 + g] = v; });
     }
     __syncthreads();
   }
@@ -543,6 +559,33 @@ __global__ void __launch_bounds__(kHad3Threads) k_hadamard3(const cplx<T>* What,
 // exp(+2 pi i k / n) in scalar registers.  The first pass reads the spectrum
 // straight from memory, each value once; the last pass uses the Hermitian
 // symmetry of the last axis (f3 = 0 once, f3 > 0 twice, real part).
+// One line of an inverse complex pass, n = 2P - 1 inputs -> the first P
+// outputs, with twiddles c + i sn = exp(+2 pi i k / n).  Inputs f and n - f
+// have conjugate twiddles, so they enter as u = x[f] + x[n - f] (times c) and
+// v = x[f] - x[n - f] (times i sn): four multiply-adds per input pair and
+// output.  put(l, value) stores output l.
+template <typename T, int P, typename Put>
+__device__ __forceinline__ void idft_line_pairs(const cplx<T>* x, const T* c, const T* sn, Put put) {
+  constexpr int n = 2 * P - 1;
+  cplx<T> u[P], v[P];
+#pragma unroll
+  for (int f = 1; f < P; ++f) {
+    u[f] = cplx<T>{x[f].re + x[n - f].re, x[f].im + x[n - f].im};
+    v[f] = cplx<T>{x[f].re - x[n - f].re, x[f].im - x[n - f].im};
+  }
+#pragma unroll
+  for (int l = 0; l < P; ++l) {
+    T re = x[0].re, im = x[0].im;
+#pragma unroll
+    for (int f = 1; f < P; ++f) {
+      const T cc = c[(f * l) % n], ss = sn[(f * l) % n];
+      re = fma(u[f].re, cc, fma(-v[f].im, ss, re));
+      im = fma(u[f].im, cc, fma(v[f].re, ss, im));
+    }
+    put(l, cplx<T>{re, im});
+  }
+}
+
 template <typename T, int P>
 __global__ void __launch_bounds__(kDftThreads) k_idft(const cplx<T>* __restrict__ Shat, int64_t ncell,
                                               const T* __restrict__ twg, T* __restrict__ s) {
@@ -565,13 +608,7 @@ __global__ void __launch_bounds__(kDftThreads) k_idft(const cplx<T>* __restrict_
     cplx<T> x[n];
 #pragma unroll
     for (int f = 0; f < n; ++f) x[f] = src[(f * n * P + r) * 6 + g];
-#pragma unroll
-    for (int l = 0; l < P; ++l) {
-      T re = 0, im = 0;
-#pragma unroll
-      for (int f = 0; f < n; ++f) cmac(x[f], c[(f * l) % n], sn[(f * l) % n], re, im);
-      Y1[(g * n * P + r) * P + l] = cplx<T>{re, im};
-    }
+    idft_line_pairs<T, P>(x, c, sn, [&](int l, cplx<T> v) { Y1[(g * n * P + r) * P + l] = v; });
   }
   __syncthreads();
   // along the middle axis: n -> P
@@ -580,13 +617,7 @@ __global__ void __launch_bounds__(kDftThreads) k_idft(const cplx<T>* __restrict_
     cplx<T> x[n];
 #pragma unroll
     for (int f = 0; f < n; ++f) x[f] = Y1[((g * n + f) * P + f3) * P + l1];
-#pragma unroll
-    for (int l = 0; l < P; ++l) {
-      T re = 0, im = 0;
-#pragma unroll
-      for (int f = 0; f < n; ++f) cmac(x[f], c[(f * l) % n], sn[(f * l) % n], re, im);
-      Y2[((g * P + f3) * P + l1) * P + l] = cplx<T>{re, im};
-    }
+    idft_line_pairs<T, P>(x, c, sn, [&](int l, cplx<T> v) { Y2[((g * P + f3) * P + l1) * P + l] = v; });
   }
   __syncthreads();
   // along the last axis: half spectrum (P) -> P real outputs
