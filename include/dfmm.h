@@ -97,8 +97,10 @@ int dfmm_fmm_setup(const dfmm_params* prm, void* stream, dfmm_plan** out);
  * lists of the leaves and interaction lists (children of the parent's
  * neighbours that are not neighbours; Sec. 4.3) on levels 2..D, and every
  * workspace dfmm_fmm_forces needs.  Synchronises the stream.  n_seg >= 1.
+ * With DFMM_MIXED a level may hold at most 2^23 - 1 occupied cells (the M2L
+ * list entries are 32-bit words).
  * Errors: DFMM_E_NONFINITE / DFMM_E_OUT_OF_BOX for bad coordinates,
- * DFMM_E_ARG, DFMM_E_NOMEM, DFMM_E_HIP. */
+ * DFMM_E_ARG (also for the cell limit), DFMM_E_NOMEM, DFMM_E_HIP. */
 int dfmm_build_tree(dfmm_plan* plan, const double* seg, int64_t n_seg, void* stream,
                     dfmm_tree** out);
 

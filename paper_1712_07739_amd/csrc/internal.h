@@ -149,10 +149,10 @@ struct dfmm_tree {
     // Single-precision plans: the lists laid out for the M2L kernel, one block
     // per wave of kWaveTargets consecutive targets of the processing order.
     // Entry s of the target in slot k of wave w is ilw[kWaveTargets *
-    // (wbase[w] + s) + k], as byte offsets (72 * source, kKOffsetF * 8 * id +
-    // mirrored); a block has the wave's longest list + kIlwPad steps, the
-    // unused entries zero (valid offsets).
-    int2* ilw = nullptr;
+    // (wbase[w] + s) + k] = source | id << 23 | mirrored << 31 (cells < 2^23);
+    // a block has the wave's longest list + kIlwPad steps, the unused entries
+    // zero (a valid entry).
+    uint32_t* ilw = nullptr;
     int* wbase = nullptr;      // [waves + 1] first step of each wave's block
     int* lenq = nullptr;       // [n] list length by processing position
     int64_t npairs = 0;

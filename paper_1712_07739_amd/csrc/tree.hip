@@ -374,19 +374,19 @@ __global__ void k_wave_len(const uint32_t* order, const int* il_start, int n, in
   atomicMax(&wlen[q / kWaveTargets], len + kIlwPad);
 }
 
-// Copy each target's list into its wave's block, step-major, as the byte
-// offsets the M2L kernel uses (the source's row in one frequency's slice of
-// the source spectra, the offset's spectra in LDS), the mirror flag in bit 0.
+// Copy each target's list into its wave's block, step-major, one 32-bit word
+// per entry: source cell in bits 0..22, canonical offset in bits 23..30,
+// mirror flag in bit 31.
 __global__ void k_il_wave(const uint32_t* order, const int* il_start, const int2* il, const int* wbase, int n,
-                          int2* ilw) {
+                          uint32_t* ilw) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= n) return;
   const uint32_t t = order[q];
   const int b = il_start[t], len = il_start[t + 1] - b;
-  int2* dst = ilw + (int64_t)kWaveTargets * wbase[q / kWaveTargets] + q % kWaveTargets;
+  uint32_t* dst = ilw + (int64_t)kWaveTargets * wbase[q / kWaveTargets] + q % kWaveTargets;
   for (int i = 0; i < len; ++i) {
     const int2 v = il[b + i];
-    dst[(int64_t)kWaveTargets * i] = make_int2(v.x * 72, (v.y >> 1) * (kKOffsetF * 8) + (v.y & 1));
+    dst[(int64_t)kWaveTargets * i] = (uint32_t)v.x | ((uint32_t)(v.y >> 1) << 23) | ((uint32_t)(v.y & 1) << 31);
   }
 }
 
@@ -615,12 +615,12 @@ int build_tree_impl(dfmm_plan* pl, const double* seg, int64_t nseg, hipStream_t 
       rc = scan_excl(wlen, L.wbase, nw + 1, st, &steps);
       hipFree(wlen);
       if (rc) return rc;
-      if (steps * kWaveTargets * (int64_t)sizeof(int2) >= ((int64_t)1 << 32)) {
-        set_error("build_tree: a level's M2L lists exceed the kernel's 32-bit offsets");
+      if (steps * kWaveTargets * (int64_t)sizeof(uint32_t) >= ((int64_t)1 << 32) || L.n >= ((int64_t)1 << 23)) {
+        set_error("build_tree: a level's M2L lists exceed the kernel's 32-bit offsets, or the level has 2^23 or more cells");
         return DFMM_E_ARG;
       }
-      DFMM_HIP(hipMalloc(&L.ilw, sizeof(int2) * kWaveTargets * std::max<int64_t>(steps, 1)));
-      DFMM_HIP(hipMemsetAsync(L.ilw, 0, sizeof(int2) * kWaveTargets * std::max<int64_t>(steps, 1), st));
+      DFMM_HIP(hipMalloc(&L.ilw, sizeof(uint32_t) * kWaveTargets * std::max<int64_t>(steps, 1)));
+      DFMM_HIP(hipMemsetAsync(L.ilw, 0, sizeof(uint32_t) * kWaveTargets * std::max<int64_t>(steps, 1), st));
       k_il_wave<<<nb(L.n, 128), 128, 0, st>>>(L.order, L.il_start, L.il, L.wbase, (int)L.n, L.ilw);
       DFMM_LAUNCH_CHECK();
       DFMM_HIP(hipStreamSynchronize(st));
