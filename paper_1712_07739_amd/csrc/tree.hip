@@ -390,6 +390,71 @@ __global__ void k_il_wave(const uint32_t* order, const int* il_start, const int2
   }
 }
 
+// Order of the entries inside each list, for the LDS banks of the M2L kernel.
+// A 16-byte LDS read is served 16 lanes at a time, and in the kernel those
+// lanes are the two lanes of each of 8 consecutive targets of a wave, which at
+// one step read the spectra of 8 unrelated offsets: lane h of a target with
+// offset id c reads 16-byte unit 29 c + 14 h + i (29 units per offset, lane 1
+// from unit 14), bank group (29 c + 14 h + i) mod 16.  Reads of one address are a broadcast; reads of different
+// addresses in one bank group are served one after another.  So step by step,
+// each group of 8 targets picks, per target, an entry of its remaining list
+// whose two bank groups are free or already taken by the same offset (the same
+// offset first, then the earliest such entry, else the earliest entry).  This
+// only permutes each target's list: 228 -> 208.6 ms of M2L on 1M segments,
+// for about 6 ms of tree build.  One wave per group of 8 targets.
+__global__ void k_il_bank(const int* lenq, const int* wbase, int64_t n, int64_t ngroups, uint32_t* ilw) {
+  __shared__ uint32_t ent[8][kNumFar + 1];
+  __shared__ int used[16];
+  const int64_t G = blockIdx.x;
+  if (G >= ngroups) return;
+  static_assert(kWaveTargets % 8 == 0, "groups of 8 targets per wave");
+  constexpr int kGroups = kWaveTargets / 8;
+  constexpr int kUnits = kKOffsetF / 2, kHalf = kKHalfF / 2;  // 16-byte units per offset, lane 1's start
+  const int64_t w = G / kGroups;
+  const int p = (int)(G % kGroups), lane = threadIdx.x;
+  const int64_t base = (int64_t)kWaveTargets * wbase[w];
+  int len[8];
+  int maxlen = 0;
+  for (int j = 0; j < 8; ++j) {
+    const int64_t q = w * kWaveTargets + 8 * p + j;
+    len[j] = q < n ? lenq[q] : 0;
+    maxlen = max(maxlen, len[j]);
+    for (int s = lane; s < len[j]; s += 64) ent[j][s] = ilw[base + (int64_t)kWaveTargets * s + 8 * p + j];
+  }
+  __syncthreads();
+  for (int s = 0; s < maxlen; ++s) {
+    if (lane < 16) used[lane] = -1;
+    __syncthreads();
+    for (int j = 0; j < 8; ++j) {
+      if (s >= len[j]) continue;
+      int best = -1;  // key: priority * 256 + (255 - offset from s)
+      for (int c = s + lane; c < len[j]; c += 64) {
+        const int code = (int)((ent[j][c] >> 23) & 0xFFu);
+        const int g0 = (kUnits * code) & 15, g1 = (g0 + kHalf) & 15;
+        const int u0 = used[g0], u1 = used[g1];
+        int pr = 0;
+        if ((u0 == -1 || u0 == code) && (u1 == -1 || u1 == code)) pr = (u0 == code) ? 2 : 1;
+        best = max(best, pr * 256 + (255 - (c - s)));
+      }
+      for (int o = 32; o > 0; o >>= 1) best = max(best, __shfl_xor(best, o));
+      const int pick = s + (255 - (best & 255));
+      __syncthreads();
+      if (lane == 0) {
+        const uint32_t e = ent[j][pick];
+        ent[j][pick] = ent[j][s];
+        ent[j][s] = e;
+        const int code = (int)((e >> 23) & 0xFFu);
+        const int g0 = (kUnits * code) & 15;
+        used[g0] = code;
+        used[(g0 + kHalf) & 15] = code;
+      }
+      __syncthreads();
+    }
+  }
+  for (int j = 0; j < 8; ++j)
+    for (int s = lane; s < len[j]; s += 64) ilw[base + (int64_t)kWaveTargets * s + 8 * p + j] = ent[j][s];
+}
+
 // Positions of the sorted points (rows 0..2 of the points array), formed as
 // the force call's gather forms them.
 __global__ void k_gather_pos(const double* seg, const uint32_t* perm, Quad qd, int64_t N, double* pts) {
@@ -623,6 +688,11 @@ int build_tree_impl(dfmm_plan* pl, const double* seg, int64_t nseg, hipStream_t 
       DFMM_HIP(hipMemsetAsync(L.ilw, 0, sizeof(uint32_t) * kWaveTargets * std::max<int64_t>(steps, 1), st));
       k_il_wave<<<nb(L.n, 128), 128, 0, st>>>(L.order, L.il_start, L.il, L.wbase, (int)L.n, L.ilw);
       DFMM_LAUNCH_CHECK();
+      {
+        const int64_t ng = nw * (kWaveTargets / 8);
+        k_il_bank<<<(unsigned)ng, 64, 0, st>>>(L.lenq, L.wbase, L.n, ng, L.ilw);
+        DFMM_LAUNCH_CHECK();
+      }
       DFMM_HIP(hipStreamSynchronize(st));
       hipFree(L.il);
       L.il = nullptr;
