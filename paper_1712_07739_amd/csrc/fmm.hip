@@ -802,12 +802,27 @@ __global__ void __launch_bounds__(64, sym_min_waves<T>())
   T* vji = vij + 64 * 6;        // [64][6] contributions to B's targets
   for (int e = lane; e < lmax * 6; e += 64) accA[e] = cmpA[e] = accB[e] = cmpB[e] = T(0);
   __syncthreads();
-  const int npair = na * nb;
+  // With the leaf itself only the pairs i < j are enumerated, row by row:
+  // row i holds (i, i+1 .. na-1) and starts at pair row0(i).
+  const int npair = self ? na * (na - 1) / 2 : na * nb;
+  auto row0 = [&](int i) { return i * na - i * (i + 1) / 2; };
+  int ic = 0, rlo = 0, rhi = 0;  // this lane's row; rows of the round's first and last pair
   for (int p0 = 0; p0 < npair; p0 += 64) {
     const int p = p0 + lane;
-    const int i = p / nb, j = p - (p / nb) * nb;
+    int i, j;
+    if (self) {
+      while (ic + 1 < na && row0(ic + 1) <= p) ++ic;
+      while (rlo + 1 < na && row0(rlo + 1) <= p0) ++rlo;
+      const int plast = min(p0 + 63, npair - 1);
+      while (rhi + 1 < na && row0(rhi + 1) <= plast) ++rhi;
+      i = ic;
+      j = i + 1 + (p - row0(i));
+    } else {
+      i = p / nb;
+      j = p - i * nb;
+    }
     T fi[6] = {0, 0, 0, 0, 0, 0}, fj[6] = {0, 0, 0, 0, 0, 0};
-    if (p < npair && (!self || i < j)) {
+    if (p < npair) {
       const int64_t gi = fa + i, gj = fb + j;
       const double d0 = pts[gi] - pts[gj], d1 = pts[N + gi] - pts[N + gj], d2 = pts[2 * N + gi] - pts[2 * N + gj];
       if (!MIXED || d0 * d0 + d1 * d1 + d2 * d2 >= a2x4) {
@@ -830,16 +845,29 @@ __global__ void __launch_bounds__(64, sym_min_waves<T>())
     const int pend = min(p0 + 64, npair);
     // one lane per (target, component); the running sum goes through
     // registers (one LDS read and write per round, not one per term)
-    for (int w = lane; w < na * 6; w += 64) {  // A's target ii: lanes ii*nb .. ii*nb + nb - 1
+    for (int w = lane; w < na * 6; w += 64) {  // A's target ii: one run of consecutive pairs
       const int ii = w / 6, c = w - ii * 6;
-      const int lo = max(ii * nb, p0), hi = min(ii * nb + nb, pend);
+      const int s0 = self ? row0(ii) : ii * nb, len = self ? na - 1 - ii : nb;
+      const int lo = max(s0, p0), hi = min(s0 + len, pend);
       if (lo >= hi) continue;
       T sa = accA[w], ca = cmpA[w];
       for (int r = lo; r < hi; ++r) kadd(sa, ca, vij[(r - p0) * 6 + c]);
       accA[w] = sa;
       cmpA[w] = ca;
     }
-    for (int w = lane; w < nb * 6; w += 64) {  // B's target jj: lanes with p % nb == jj, in order
+    for (int w = lane; self && w < nb * 6; w += 64) {  // B's target jj: pairs (i, jj), i < jj, in order of i
+      const int jj = w / 6, c = w - jj * 6;
+      const int iend = min(rhi, jj - 1);
+      if (rlo > iend) continue;
+      T sb = accB[w], cb = cmpB[w];
+      for (int i = rlo; i <= iend; ++i) {
+        const int r = row0(i) + jj - i - 1;
+        if (r >= p0 && r < pend) kadd(sb, cb, vji[(r - p0) * 6 + c]);
+      }
+      accB[w] = sb;
+      cmpB[w] = cb;
+    }
+    for (int w = lane; !self && w < nb * 6; w += 64) {  // B's target jj: lanes with p % nb == jj, in order
       const int jj = w / 6, c = w - jj * 6;
       const int r0 = p0 + ((jj - p0 % nb) % nb + nb) % nb;
       if (r0 >= pend) continue;
