@@ -756,12 +756,13 @@ __global__ void __launch_bounds__(64, leaf_min_waves<T>())
 // derivative is odd, dG(-x) = -dG(x), so one evaluation per unordered pair of
 // points serves both directions: sigma_i += K(x_i - x_j) q_j and
 // sigma_j += K(x_j - x_i) q_i = -(the contraction of the same dG with q_i).
-// One wave per unordered pair of neighbouring leaves {A, B}: B = A + o with o
-// the neighbour offsets q = 13..26 (q = 13: the leaf with itself, pairs
-// i < j).  Lane = point pair (i in A, j in B); in single precision, pairs
-// closer than 2a are left to k_close_eval.  Each round of 64 pairs is reduced
-// in LDS in a fixed order (a target of A sums its consecutive lanes, a target
-// of B its lanes at stride |B|) into compensated sums, and the block writes one partial
+// One block per unordered pair of neighbouring leaves {A, B}: B = A + o with
+// o the neighbour offsets q = 13..26 (q = 13: the leaf with itself, pairs
+// i < j).  Thread = point pair (i in A, j in B), one wave per block, or four
+// for leaves of more than 64 points in single precision; in single precision,
+// pairs closer than 2a are left to k_close_eval.  Each round of pairs is
+// reduced in LDS in a fixed order (a target of A sums its consecutive pairs,
+// a target of B its pairs in order of i) into compensated sums, and the block writes one partial
 // per (target, neighbour slot): slot q for the targets of A, slot 26 - q (the
 // offset of A seen from B) for those of B.  k_near_sum then adds a target's
 // 27 slots in slot order, so every sum has a fixed order.
@@ -776,15 +777,24 @@ __device__ __forceinline__ void kadd(T& s, T& c, T x) {
 // BIG = false takes the leaf pairs with at most 64 points on each side (LDS
 // for 64 accumulators per side, so LDS does not limit occupancy); BIG = true
 // takes the others, with accumulators for the largest leaf (lmax).
+// Threads of a block: leaf pairs with more than 64 points on a side take
+// rounds of 256 point pairs in single precision (four waves share one set of
+// LDS sums, which would otherwise limit a CU to two waves per SIMD), 64 else.
+template <typename T, bool BIG>
+constexpr int sym_threads() {
+  return BIG && sizeof(T) == 4 ? 256 : 64;
+}
+
 template <typename T>
 constexpr int sym_min_waves() {
   return sizeof(T) == 4 ? 3 : 1;
 }
 
 template <typename T, bool MIXED, bool BIG>
-__global__ void __launch_bounds__(64, sym_min_waves<T>())
+__global__ void __launch_bounds__((sym_threads<T, BIG>()), sym_min_waves<T>())
     k_leaf_sym(const double* pts, int64_t N, const int* first, const int* count, const int* nbr, Med<T> m,
                double a2x4, int lmax, T* part) {
+  constexpr int NT = sym_threads<T, BIG>();  // threads = point pairs per round
   extern __shared__ __align__(16) unsigned char symraw[];
   T* symsh = reinterpret_cast<T*>(symraw);
   const int A = blockIdx.x, q = 13 + blockIdx.y, lane = threadIdx.x;
@@ -798,22 +808,22 @@ __global__ void __launch_bounds__(64, sym_min_waves<T>())
   T* cmpA = accA + lmax * 6;
   T* accB = cmpA + lmax * 6;
   T* cmpB = accB + lmax * 6;
-  T* vij = cmpB + lmax * 6;     // [64][6] contributions to A's targets
-  T* vji = vij + 64 * 6;        // [64][6] contributions to B's targets
-  for (int e = lane; e < lmax * 6; e += 64) accA[e] = cmpA[e] = accB[e] = cmpB[e] = T(0);
+  T* vij = cmpB + lmax * 6;     // [NT][6] contributions to A's targets
+  T* vji = vij + NT * 6;        // [NT][6] contributions to B's targets
+  for (int e = lane; e < lmax * 6; e += NT) accA[e] = cmpA[e] = accB[e] = cmpB[e] = T(0);
   __syncthreads();
   // With the leaf itself only the pairs i < j are enumerated, row by row:
   // row i holds (i, i+1 .. na-1) and starts at pair row0(i).
   const int npair = self ? na * (na - 1) / 2 : na * nb;
   auto row0 = [&](int i) { return i * na - i * (i + 1) / 2; };
   int ic = 0, rlo = 0, rhi = 0;  // this lane's row; rows of the round's first and last pair
-  for (int p0 = 0; p0 < npair; p0 += 64) {
+  for (int p0 = 0; p0 < npair; p0 += NT) {
     const int p = p0 + lane;
     int i, j;
     if (self) {
       while (ic + 1 < na && row0(ic + 1) <= p) ++ic;
       while (rlo + 1 < na && row0(rlo + 1) <= p0) ++rlo;
-      const int plast = min(p0 + 63, npair - 1);
+      const int plast = min(p0 + NT - 1, npair - 1);
       while (rhi + 1 < na && row0(rhi + 1) <= plast) ++rhi;
       i = ic;
       j = i + 1 + (p - row0(i));
@@ -842,10 +852,10 @@ __global__ void __launch_bounds__(64, sym_min_waves<T>())
       vji[lane * 6 + c] = -fj[c];  // dG(x_j - x_i) = -dG(x_i - x_j)
     }
     __syncthreads();
-    const int pend = min(p0 + 64, npair);
+    const int pend = min(p0 + NT, npair);
     // one lane per (target, component); the running sum goes through
     // registers (one LDS read and write per round, not one per term)
-    for (int w = lane; w < na * 6; w += 64) {  // A's target ii: one run of consecutive pairs
+    for (int w = lane; w < na * 6; w += NT) {  // A's target ii: one run of consecutive pairs
       const int ii = w / 6, c = w - ii * 6;
       const int s0 = self ? row0(ii) : ii * nb, len = self ? na - 1 - ii : nb;
       const int lo = max(s0, p0), hi = min(s0 + len, pend);
@@ -855,7 +865,7 @@ __global__ void __launch_bounds__(64, sym_min_waves<T>())
       accA[w] = sa;
       cmpA[w] = ca;
     }
-    for (int w = lane; self && w < nb * 6; w += 64) {  // B's target jj: pairs (i, jj), i < jj, in order of i
+    for (int w = lane; self && w < nb * 6; w += NT) {  // B's target jj: pairs (i, jj), i < jj, in order of i
       const int jj = w / 6, c = w - jj * 6;
       const int iend = min(rhi, jj - 1);
       if (rlo > iend) continue;
@@ -867,7 +877,7 @@ __global__ void __launch_bounds__(64, sym_min_waves<T>())
       accB[w] = sb;
       cmpB[w] = cb;
     }
-    for (int w = lane; !self && w < nb * 6; w += 64) {  // B's target jj: lanes with p % nb == jj, in order
+    for (int w = lane; !self && w < nb * 6; w += NT) {  // B's target jj: lanes with p % nb == jj, in order
       const int jj = w / 6, c = w - jj * 6;
       const int r0 = p0 + ((jj - p0 % nb) % nb + nb) % nb;
       if (r0 >= pend) continue;
@@ -878,7 +888,7 @@ __global__ void __launch_bounds__(64, sym_min_waves<T>())
     }
     __syncthreads();
   }
-  for (int ii = lane; ii < na; ii += 64)
+  for (int ii = lane; ii < na; ii += NT)
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
       double v = (double)accA[ii * 6 + c] - (double)cmpA[ii * 6 + c];
@@ -886,7 +896,7 @@ __global__ void __launch_bounds__(64, sym_min_waves<T>())
       part[((int64_t)(fa + ii) * 27 + q) * 6 + c] = (T)v;
     }
   if (!self)
-    for (int jj = lane; jj < nb; jj += 64)
+    for (int jj = lane; jj < nb; jj += NT)
 #pragma unroll
       for (int c = 0; c < 6; ++c)
         part[((int64_t)(fb + jj) * 27 + (26 - q)) * 6 + c] =
@@ -909,8 +919,8 @@ __global__ void k_near_sum(const T* part, int64_t N, const int* pleaf, const int
   for (int c = 0; c < 6; ++c) sig[i * 6 + c] = tot[c];
 }
 
-template <typename T>
-inline size_t sym_lds(int lmax) { return sizeof(T) * (24 * (size_t)lmax + 2 * 64 * 6); }
+template <typename T, bool BIG>
+inline size_t sym_lds(int lmax) { return sizeof(T) * (24 * (size_t)lmax + 2 * (size_t)sym_threads<T, BIG>() * 6); }
 
 // The near-coincident pairs (closer than 2a) that the single-precision near
 // field skips, in double precision.  The tree holds them per target point, in
@@ -1288,10 +1298,10 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
         STAGE(6, (k_leaf<T, true, true, false><<<(unsigned)LD.n, 64, 0, nst>>>(LEAF_ARGS)));
       else if (t->part) {
         const double a2x4 = 4.0 * m64.a * m64.a;
-        STAGE(6, (k_leaf_sym<T, true, false><<<dim3((unsigned)LD.n, 14), 64, sym_lds<T>(64), nst>>>(
+        STAGE(6, (k_leaf_sym<T, true, false><<<dim3((unsigned)LD.n, 14), sym_threads<T, false>(), sym_lds<T, false>(64), nst>>>(
                      t->pts, N, LD.first, LD.count, t->nbr, m, a2x4, 64, (T*)t->part)));
         if (t->max_leaf_pts > 64)
-          STAGE(6, (k_leaf_sym<T, true, true><<<dim3((unsigned)LD.n, 14), 64, sym_lds<T>(t->max_leaf_pts), nst>>>(
+          STAGE(6, (k_leaf_sym<T, true, true><<<dim3((unsigned)LD.n, 14), sym_threads<T, true>(), sym_lds<T, true>(t->max_leaf_pts), nst>>>(
                        t->pts, N, LD.first, LD.count, t->nbr, m, a2x4, t->max_leaf_pts, (T*)t->part)));
       }
       else
@@ -1311,10 +1321,10 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
       if (pl->iso) {
         STAGE(6, (k_leaf<T, false, true, false><<<(unsigned)LD.n, 64, 0, nst>>>(LEAF_ARGS)));
       } else if (t->part) {
-        STAGE(6, (k_leaf_sym<T, false, false><<<dim3((unsigned)LD.n, 14), 64, sym_lds<T>(64), nst>>>(
+        STAGE(6, (k_leaf_sym<T, false, false><<<dim3((unsigned)LD.n, 14), sym_threads<T, false>(), sym_lds<T, false>(64), nst>>>(
                      t->pts, N, LD.first, LD.count, t->nbr, m, 0.0, 64, (T*)t->part)));
         if (t->max_leaf_pts > 64)
-          STAGE(6, (k_leaf_sym<T, false, true><<<dim3((unsigned)LD.n, 14), 64, sym_lds<T>(t->max_leaf_pts), nst>>>(
+          STAGE(6, (k_leaf_sym<T, false, true><<<dim3((unsigned)LD.n, 14), sym_threads<T, true>(), sym_lds<T, true>(t->max_leaf_pts), nst>>>(
                        t->pts, N, LD.first, LD.count, t->nbr, m, 0.0, t->max_leaf_pts, (T*)t->part)));
         STAGE(6, (k_near_sum<T><<<nblk(N, 256), 256, 0, nst>>>((const T*)t->part, N, t->pleaf, t->nbr, t->sig)));
       } else {
