@@ -1182,7 +1182,7 @@ template <typename T, int P>
 static void tree_pass_p(bool up, unsigned blocks, size_t shm, const int* a, const int* b, const uint32_t* key,
                         const T* in, T* out, const T* S, hipStream_t st) {
   if (up)
-    k_m2m<T, P><<<blocks, 256, shm, st>>>(a, b, key, in, out, S);
+    k_m2m<T, P><<<blocks, 512, shm, st>>>(a, b, key, in, out, S);  // 9 P^2 lines a pass: one round up to P = 7
   else
     k_l2l<T, P><<<blocks, 256, shm, st>>>(a, key, in, out, S);
 }
