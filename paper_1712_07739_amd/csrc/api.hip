@@ -163,7 +163,7 @@ void dfmm_tree_destroy(dfmm_tree* t) {
     hipFree(L.key); hipFree(L.first); hipFree(L.count); hipFree(L.parent); hipFree(L.il_start); hipFree(L.il); hipFree(L.order);
     hipFree(L.ilw); hipFree(L.wbase); hipFree(L.lenq);
   }
-  hipFree(t->cstart); hipFree(t->cpair); hipFree(t->cval); hipFree(t->part); hipFree(t->cuni);
+  hipFree(t->cstart); hipFree(t->cpair); hipFree(t->cval); hipFree(t->part); hipFree(t->cuni); hipFree(t->bigp);
   hipFree(t->pts); hipFree(t->pleaf); hipFree(t->W); hipFree(t->s); hipFree(t->What); hipFree(t->Shat); hipFree(t->sig);
   delete t;
 }

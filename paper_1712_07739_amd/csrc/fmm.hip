@@ -793,11 +793,13 @@ constexpr int sym_min_waves() {
 template <typename T, bool MIXED, bool BIG>
 __global__ void __launch_bounds__((sym_threads<T, BIG>()), sym_min_waves<T>())
     k_leaf_sym(const double* pts, int64_t N, const int* first, const int* count, const int* nbr, Med<T> m,
-               double a2x4, int lmax, T* part) {
+               double a2x4, int lmax, T* part, const int* bigp) {
   constexpr int NT = sym_threads<T, BIG>();  // threads = point pairs per round
   extern __shared__ __align__(16) unsigned char symraw[];
   T* symsh = reinterpret_cast<T*>(symraw);
-  const int A = blockIdx.x, q = 13 + blockIdx.y, lane = threadIdx.x;
+  // small leaves: grid (leaves, 14); large: one block per listed pair
+  const int A = BIG ? bigp[blockIdx.x] / 14 : (int)blockIdx.x;
+  const int q = 13 + (BIG ? bigp[blockIdx.x] % 14 : (int)blockIdx.y), lane = threadIdx.x;
   const int B = nbr[(int64_t)A * 27 + q];
   if (B < 0) return;
   const bool self = q == 13;
@@ -1299,10 +1301,10 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
       else if (t->part) {
         const double a2x4 = 4.0 * m64.a * m64.a;
         STAGE(6, (k_leaf_sym<T, true, false><<<dim3((unsigned)LD.n, 14), sym_threads<T, false>(), sym_lds<T, false>(64), nst>>>(
-                     t->pts, N, LD.first, LD.count, t->nbr, m, a2x4, 64, (T*)t->part)));
-        if (t->max_leaf_pts > 64)
-          STAGE(6, (k_leaf_sym<T, true, true><<<dim3((unsigned)LD.n, 14), sym_threads<T, true>(), sym_lds<T, true>(t->max_leaf_pts), nst>>>(
-                       t->pts, N, LD.first, LD.count, t->nbr, m, a2x4, t->max_leaf_pts, (T*)t->part)));
+                     t->pts, N, LD.first, LD.count, t->nbr, m, a2x4, 64, (T*)t->part, nullptr)));
+        if (t->nbig > 0)
+          STAGE(6, (k_leaf_sym<T, true, true><<<(unsigned)t->nbig, sym_threads<T, true>(), sym_lds<T, true>(t->max_leaf_pts), nst>>>(
+                       t->pts, N, LD.first, LD.count, t->nbr, m, a2x4, t->max_leaf_pts, (T*)t->part, t->bigp)));
       }
       else
         STAGE(6, (k_leaf<T, true, false, false><<<(unsigned)LD.n, 64, 0, nst>>>(LEAF_ARGS)));
@@ -1322,10 +1324,10 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
         STAGE(6, (k_leaf<T, false, true, false><<<(unsigned)LD.n, 64, 0, nst>>>(LEAF_ARGS)));
       } else if (t->part) {
         STAGE(6, (k_leaf_sym<T, false, false><<<dim3((unsigned)LD.n, 14), sym_threads<T, false>(), sym_lds<T, false>(64), nst>>>(
-                     t->pts, N, LD.first, LD.count, t->nbr, m, 0.0, 64, (T*)t->part)));
-        if (t->max_leaf_pts > 64)
-          STAGE(6, (k_leaf_sym<T, false, true><<<dim3((unsigned)LD.n, 14), sym_threads<T, true>(), sym_lds<T, true>(t->max_leaf_pts), nst>>>(
-                       t->pts, N, LD.first, LD.count, t->nbr, m, 0.0, t->max_leaf_pts, (T*)t->part)));
+                     t->pts, N, LD.first, LD.count, t->nbr, m, 0.0, 64, (T*)t->part, nullptr)));
+        if (t->nbig > 0)
+          STAGE(6, (k_leaf_sym<T, false, true><<<(unsigned)t->nbig, sym_threads<T, true>(), sym_lds<T, true>(t->max_leaf_pts), nst>>>(
+                       t->pts, N, LD.first, LD.count, t->nbr, m, 0.0, t->max_leaf_pts, (T*)t->part, t->bigp)));
         STAGE(6, (k_near_sum<T><<<nblk(N, 256), 256, 0, nst>>>((const T*)t->part, N, t->pleaf, t->nbr, t->sig)));
       } else {
         STAGE(6, (k_leaf<T, false, false, false><<<(unsigned)LD.n, 64, 0, nst>>>(LEAF_ARGS)));

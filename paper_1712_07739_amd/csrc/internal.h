@@ -173,6 +173,8 @@ struct dfmm_tree {
   double* sig = nullptr;    // [N][6] stress at sorted points
   void* part = nullptr;     // cubic medium: [N][27][6] near-field partial (float or double) per
                             // neighbour slot (the symmetric near field)
+  int* bigp = nullptr;      // leaf pairs with more than 64 points on a side, A * 14 + (q - 13)
+  int64_t nbig = 0;
   size_t bytes = 0;
   // per-stage timing
   int timing = 0;

@@ -699,7 +699,8 @@ int build_tree_impl(dfmm_plan* pl, const double* seg, int64_t nseg, hipStream_t 
     }
     hipFree(cnt);
   }
-  // near-field pair count (for reporting)
+  // near-field pair count (for reporting), and the large-leaf pairs
+  std::vector<int> hbig;
   {
     std::vector<int> hn(27 * LD.n), hc(LD.n);
     DFMM_D2H(hn.data(), t->nbr, sizeof(int) * hn.size(), st);
@@ -715,6 +716,12 @@ int build_tree_impl(dfmm_plan* pl, const double* seg, int64_t nseg, hipStream_t 
     }
     t->near_pairs = np;
     t->max_leaf_pts = mx;
+    // the symmetric near field's launch for large leaves takes only these pairs
+    for (int64_t a = 0; mx > 64 && a < LD.n; ++a)
+      for (int q = 13; q < 27; ++q) {
+        const int b = hn[27 * a + q];
+        if (b >= 0 && (hc[a] > 64 || hc[b] > 64)) hbig.push_back((int)(a * 14 + (q - 13)));
+      }
   }
   if (!workspaces) {
     DFMM_HIP(hipStreamSynchronize(st));
@@ -740,8 +747,14 @@ int build_tree_impl(dfmm_plan* pl, const double* seg, int64_t nseg, hipStream_t 
   DFMM_HIP(hipMalloc(&t->Shat, bSh));
   DFMM_HIP(hipMalloc(&t->sig, sizeof(double) * 6 * N));
   const size_t part_es = pl->mixed ? sizeof(float) : sizeof(double);
-  if (!pl->iso && t->max_leaf_pts <= (pl->mixed ? kSymMaxLeaf : kSymMaxLeafD))
+  if (!pl->iso && t->max_leaf_pts <= (pl->mixed ? kSymMaxLeaf : kSymMaxLeafD)) {
     DFMM_HIP(hipMalloc(&t->part, part_es * 27 * 6 * N));
+    if (!hbig.empty()) {
+      t->nbig = (int64_t)hbig.size();
+      DFMM_HIP(hipMalloc(&t->bigp, sizeof(int) * hbig.size()));
+      DFMM_HIP(hipMemcpy(t->bigp, hbig.data(), sizeof(int) * hbig.size(), hipMemcpyHostToDevice));
+    }
+  }
   if (pl->mixed) {  // the near-coincident pairs, evaluated in double by every call
     const double sD = pl->prm.box_size / (double)(1 << D);
     const double a2x4 = 4.0 * pl->prm.core_a * pl->prm.core_a;
@@ -799,7 +812,7 @@ int build_tree_impl(dfmm_plan* pl, const double* seg, int64_t nseg, hipStream_t 
   t->bytes = sizeof(double) * 15 * N + sizeof(int) * N + bW + bS + bWh + bSh +
              (sizeof(int2) + 6 * sizeof(double)) * t->nclose + sizeof(int2) * t->nuni +
              (t->cstart ? sizeof(int) * (N + 1) : 0) +
-             (t->part ? part_es * 27 * 6 * N : 0);
+             (t->part ? part_es * 27 * 6 * N : 0) + sizeof(int) * t->nbig;
   DFMM_HIP(hipStreamSynchronize(st));
   return DFMM_OK;
 }
