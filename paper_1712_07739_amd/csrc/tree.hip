@@ -717,7 +717,7 @@ int build_tree_impl(dfmm_plan* pl, const double* seg, int64_t nseg, hipStream_t 
     t->near_pairs = np;
     t->max_leaf_pts = mx;
     // the symmetric near field's launch for large leaves takes only these pairs
-    for (int64_t a = 0; mx > 64 && a < LD.n; ++a)
+    for (int64_t a = 0; !pl->iso && mx > 64 && a < LD.n; ++a)
       for (int q = 13; q < 27; ++q) {
         const int b = hn[27 * a + q];
         if (b >= 0 && (hc[a] > 64 || hc[b] > 64)) hbig.push_back((int)(a * 14 + (q - 13)));
