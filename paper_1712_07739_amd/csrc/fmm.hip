@@ -317,7 +317,7 @@ constexpr size_t lds_fdft_t(int G, size_t es) {
 // contribution -conj(K) w = -conj(K conj(w)) is folded into the same loop
 // with a sign.  Two lanes share a target, each owning three of its six stress
 // rows, and walk the target's interaction list:
-//   Shat[T][f][r] = sum_{(J, o) in I(T)} sum_k Khat_o(f)[r][k] What[f][J][k].
+//   Shat[f][T][r] = sum_{(J, o) in I(T)} sum_k Khat_o(f)[r][k] What[f][J][k].
 // The load of the source's nine values is one of the kernel's limits (with
 // the LDS reads of the spectra and the multiply-adds), so the two lanes of a
 // target split it: lane h loads components 4h..4h+3 and component 8, and the
@@ -454,7 +454,7 @@ k_hadamard(const cplx<float>* What, const cplx<float>* Khat, const int* lenq, co
       asm volatile("" : "+v"(jo));
     }
   }
-  cplx<float>* out = Shat + (t * nf + f) * 6 + 3 * h;
+  cplx<float>* out = Shat + ((int64_t)f * ncell + t) * 6 + 3 * h;
 #pragma unroll
   for (int r = 0; r < 3; ++r) out[r] = cplx<float>{ar[r], ai[r]};
 }
@@ -546,20 +546,12 @@ __global__ void __launch_bounds__(kHad3Threads) k_hadamard3(const cplx<T>* What,
       asm volatile("" : "+v"(jo));
     }
   }
-  cplx<T>* out = Shat + (t * nf + f) * 6 + r0;
+  cplx<T>* out = Shat + ((int64_t)f * ncell + t) * 6 + r0;
   out[0] = cplx<T>{ar0, ai0};
   out[1] = cplx<T>{ar1, ai1};
 }
 
 // ------------------------------------------------------------ inverse DFT
-// One block per cell: Shat[cell][f][6] -> s[cell][6][P^3] (overwrites): the
-// inverse transform of the half spectrum of a real circular convolution, of
-// which only the outputs l < P are needed (the rest is the wrap-around of the
-// embedding).  As in the forward transform, a thread takes one line of a
-// pass in registers and produces all of its P outputs, with the twiddles
-// exp(+2 pi i k / n) in scalar registers.  The first pass reads the spectrum
-// straight from memory, each value once; the last pass uses the Hermitian
-// symmetry of the last axis (f3 = 0 once, f3 > 0 twice, real part).
 // One line of an inverse complex pass, n = 2P - 1 inputs -> the first P
 // outputs, with twiddles c + i sn = exp(+2 pi i k / n).  Inputs f and n - f
 // have conjugate twiddles, so they enter as u = x[f] + x[n - f] (times c) and
@@ -587,6 +579,18 @@ __device__ __forceinline__ void idft_line_pairs(const cplx<T>* x, const T* c, co
   }
 }
 
+// One block per cell: Shat[f][cell][6] -> s[cell][6][P^3] (overwrites): the
+// inverse transform of the half spectrum of a real circular convolution, of
+// which only the outputs l < P are needed (the rest is the wrap-around of the
+// embedding).  As in the forward transform, a thread takes one line of a
+// pass in registers and produces all of its P outputs, with the twiddles
+// exp(+2 pi i k / n) in scalar registers.  The first pass reads the spectrum
+// straight from memory, each value once: a cell's 48-byte row at each
+// frequency, with cells spread over the XCDs in contiguous ranges so that
+// neighbouring cells' rows meet in one L2 (the frequency-major layout makes
+// the Hadamard product's stores land together, which gains more than these
+// reads cost).  The last pass uses the Hermitian symmetry of the last axis
+// (f3 = 0 once, f3 > 0 twice, real part).
 template <typename T, int P>
 __global__ void __launch_bounds__(kDftThreads) k_idft(const cplx<T>* __restrict__ Shat, int64_t ncell,
                                               const T* __restrict__ twg, T* __restrict__ s) {
@@ -600,15 +604,15 @@ __global__ void __launch_bounds__(kDftThreads) k_idft(const cplx<T>* __restrict_
     c[k] = twg[2 * k];
     sn[k] = -twg[2 * k + 1];
   }
-  const int64_t cell = blockIdx.x;
+  const int64_t cell = xcd_block(blockIdx.x, ncell);
   const T scale = T(1) / T(n * n * n);
-  const cplx<T>* src = Shat + cell * nf * 6;
+  const cplx<T>* src = Shat + cell * 6;
   // along the first axis: n -> P
   for (int it = threadIdx.x; it < 6 * n * P; it += blockDim.x) {
     const int g = it % 6, r = it / 6;  // r = f2 P + f3
     cplx<T> x[n];
 #pragma unroll
-    for (int f = 0; f < n; ++f) x[f] = src[(f * n * P + r) * 6 + g];
+    for (int f = 0; f < n; ++f) x[f] = src[(int64_t)(f * n * P + r) * ncell * 6 + g];
     idft_line_pairs<T, P>(x, c, sn, [&](int l, cplx<T> v) { Y1[(g * n * P + r) * P + l] = v; });
   }
   __syncthreads();

@@ -169,7 +169,7 @@ struct dfmm_tree {
   void* W = nullptr;        // [ncell_total][9][p^3]  (float or double)
   void* s = nullptr;        // [ncell_total][6][p^3]
   void* What = nullptr;     // [nf][max level cells][9] complex
-  void* Shat = nullptr;     // [max level cells][nf][6] complex
+  void* Shat = nullptr;     // [nf][max level cells][6] complex
   double* sig = nullptr;    // [N][6] stress at sorted points
   void* part = nullptr;     // cubic medium: [N][27][6] near-field partial (float or double) per
                             // neighbour slot (the symmetric near field)
