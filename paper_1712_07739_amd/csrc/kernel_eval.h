@@ -33,6 +33,32 @@ struct Med {
   const T* cs;      // cos/sin of 2 pi k / (2 nhalf), k < nhalf, interleaved
 };
 
+template <typename T>
+__device__ __forceinline__ T fast_rcp(T x) {
+  return T(1) / x;
+}
+template <>
+__device__ __forceinline__ float fast_rcp<float>(float x) {
+  return __builtin_amdgcn_rcpf(x);  // 1 ulp: ample for the float evaluation
+}
+template <typename T>
+__device__ __forceinline__ T fast_rsqrt(T x) {
+  return T(1) / sqrt(x);
+}
+template <>
+__device__ __forceinline__ float fast_rsqrt<float>(float x) {
+  return __builtin_amdgcn_rsqf(x);  // 1 ulp, as above
+}
+// a / b: exact in double, a times the 1-ulp reciprocal in float
+template <typename T>
+__device__ __forceinline__ T fast_div(T a, T b) {
+  return a / b;
+}
+template <>
+__device__ __forceinline__ float fast_div<float>(float a, float b) {
+  return a * __builtin_amdgcn_rcpf(b);
+}
+
 // D[(v*3+p)*3+q] += scale * d_q G_vp (isotropic, core a).
 template <typename T>
 __device__ __forceinline__ void dg_iso_acc(T x0, T x1, T x2, T mu, T nu, T a, T scale, T* D) {
@@ -40,12 +66,12 @@ __device__ __forceinline__ void dg_iso_acc(T x0, T x1, T x2, T mu, T nu, T a, T 
   T r2 = x0 * x0 + x1 * x1 + x2 * x2;
   T ra2 = r2 + a * a;
   if (ra2 == T(0)) return;
-  T ira = T(1) / sqrt(ra2);
+  T ira = fast_rsqrt(ra2);
   T ira2 = ira * ira;
   T ira3 = ira * ira2;
   T ira5 = ira3 * ira2;
-  T c = scale / (T(8) * T(3.14159265358979323846) * mu);
-  T h = T(1) / (T(2) * (T(1) - nu));
+  T c = fast_div(scale, T(8) * T(3.14159265358979323846) * mu);
+  T h = fast_rcp(T(2) * (T(1) - nu));
   T dl = -(T(2) * ira3 + T(3) * a * a * ira5);  // d_q lap(R_a) = dl * x_q
 #pragma unroll
   for (int v = 0; v < 3; ++v)
@@ -65,22 +91,13 @@ __device__ __forceinline__ void dg_iso_acc(T x0, T x1, T x2, T mu, T nu, T a, T 
       }
 }
 
-template <typename T>
-__device__ __forceinline__ T fast_rcp(T x) {
-  return T(1) / x;
-}
-template <>
-__device__ __forceinline__ float fast_rcp<float>(float x) {
-  return __builtin_amdgcn_rcpf(x);  // 1 ulp: ample for the float evaluation
-}
-
 // D += scale * (singular anisotropic d_q G_vp) by circle quadrature.  Only
 // the (i <= j) half of the symmetric index pair is accumulated.
 template <typename T>
 __device__ __forceinline__ void dg_circle_acc(T x0, T x1, T x2, const Med<T>& m, T scale, T* D) {
   T r2 = x0 * x0 + x1 * x1 + x2 * x2;
   if (r2 == T(0)) return;
-  T ir = T(1) / sqrt(r2);
+  T ir = fast_rsqrt(r2);
   T t[3] = {x0 * ir, x1 * ir, x2 * ir};
   // e1: the axis least aligned with T, made orthogonal to T; e2 = T x e1
   int ax = 0;
@@ -89,7 +106,7 @@ __device__ __forceinline__ void dg_circle_acc(T x0, T x1, T x2, const Med<T>& m,
   if (fabs(t[2]) < am) ax = 2;
   T e1[3] = {-t[ax] * t[0], -t[ax] * t[1], -t[ax] * t[2]};
   e1[ax] += T(1);
-  T n1 = T(1) / sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+  T n1 = fast_rsqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
   e1[0] *= n1; e1[1] *= n1; e1[2] *= n1;
   T e2[3] = {t[1] * e1[2] - t[2] * e1[1], t[2] * e1[0] - t[0] * e1[2], t[0] * e1[1] - t[1] * e1[0]};
   const T cc = m.c12 + m.c44, c44 = m.c44, ch = cc + m.hh;
@@ -145,7 +162,7 @@ __device__ __forceinline__ void dg_circle_acc(T x0, T x1, T x2, const Med<T>& m,
 #pragma unroll
     for (int s = 0; s < 3; ++s) acc[q * 3 + s] = e1[s] * acc_c[q] + e2[s] * acc_s[q] - t[s] * acc_m[q];
   // (2 pi / nphi) * 2 / (8 pi^2 r^2) with nphi = 2 nhalf
-  T f = scale / (T(2) * T(3.14159265358979323846) * T(2 * m.nhalf) * r2);
+  T f = fast_div(scale, T(2) * T(3.14159265358979323846) * T(2 * m.nhalf) * r2);
 #pragma unroll
   for (int q = 0; q < 6; ++q) {
     const int i = PI_[q], j = PJ_[q];
@@ -167,7 +184,7 @@ __device__ __forceinline__ void dg_medium(T x0, T x1, T x2, const Med<T>& m, T* 
   if (!m.iso) {
     T r2 = x0 * x0 + x1 * x1 + x2 * x2;
     if (r2 > T(0)) {
-      T q = r2 / (r2 + m.a * m.a);
+      T q = fast_div(r2, r2 + m.a * m.a);
       damp = q * sqrt(q);
       dg_circle_acc(x0, x1, x2, m, damp, D);
     }
