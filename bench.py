@@ -43,6 +43,16 @@ def hadamard_traffic(order):
     return d["hbm_bytes_per_step"]
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -64,7 +74,8 @@ def main():
                     help="interpolation order p (default: the smallest order meeting the 1e-4 bar, "
                          "7 for cubic1m; its configured p=6 measures 1.15e-4)")
     ap.add_argument("--depth", type=int, default=0, help="override the workload's leaf depth D")
-    ap.add_argument("--err-sample", type=int, default=200, help="segments checked against the GPU FP64 direct sum")
+    ap.add_argument("--err-sample", type=int, default=2000,
+                    help="target segments checked against the GPU FP64 direct sum over all sources")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true",
@@ -216,10 +227,25 @@ def main():
         torch.cuda.synchronize()
         ms64 = 1e3 * (time.perf_counter() - t0) / n64
         f64 = out64.cpu().numpy()[sub]
-        result["fp64_path"] = {"ms_per_step": ms64, "rel_err_vs_fp64_direct":
-                               float(np.linalg.norm(f64 - ref) / np.linalg.norm(ref)),
-                               "mixed_speedup": ms64 / ms_step}
-        log("fp64 FMM path: %.3f ms/step (mixed speedup %.2fx)" % (ms64, ms64 / ms_step))
+        # stage times of the FP64 path (HIP events around every stage)
+        tree64.set_timing(True)
+        for i in range(n64):
+            pk.fmm_forces(plan64, tree64, tseg, tb, out=out64)
+        torch.cuda.synchronize()
+        st64, nc64 = tree64.stage_times()
+        tree64.set_timing(False)
+        had64_ms = st64[3] / nc64
+        ach64 = had_flops / (had64_ms * 1e-3)
+        result["fp64_path"] = {
+            "ms_per_step": ms64, "rel_err_vs_fp64_direct": float(np.linalg.norm(f64 - ref) / np.linalg.norm(ref)),
+            "mixed_speedup": ms64 / ms_step,
+            "stage_ms": {pk.STAGES[i]: st64[i] / nc64 for i in range(pk.N_STAGES)},
+            "roofline": {"kernel": "k_hadamard3 (FP64 M2L in frequency space), all levels of one step",
+                         "bound": "alu", "achieved": ach64 / 1e12, "peak": PEAK_FP64_VALU / 1e12,
+                         "unit": "TFLOP/s", "frac": ach64 / PEAK_FP64_VALU, "traffic": None,
+                         "flop_per_step": had_flops, "ms_per_step": had64_ms}}
+        log("fp64 FMM path: %.3f ms/step (mixed speedup %.2fx); Hadamard %.1f ms = %.1f TFLOP/s"
+            % (ms64, ms64 / ms_step, had64_ms, ach64 / 1e12))
         del tree64, plan64
     if not args.no_cpu_baseline:
         import oracle
@@ -228,13 +254,20 @@ def main():
         k = max(1, args.cpu_sample)
         tgt = synth.segment_subset(ns, k, 77)
         t0 = time.perf_counter()
-        oracle.direct_forces(seg, burg, med, targets=tgt)
+        f_or = oracle.direct_forces(seg, burg, med, targets=tgt)
         cpu_s = time.perf_counter() - t0
+        # the GPU FP64 direct sum that the error sample uses, checked against
+        # the oracle on the same targets in this run
+        f_gd = pk.direct_forces(plan, tseg, tb, targets=torch.tensor(tgt, device=dev), fp32=False).cpu().numpy()
+        e_gd = float(np.linalg.norm(f_gd - f_or) / np.linalg.norm(f_or))
         result["cpu_baseline"] = {
             "value": k / cpu_s, "unit": "segments/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": "%d target segment(s) x all %d source segments (direct FP64 sum, Neumaier), %.1f s"
                       % (k, ns, cpu_s)}
-        log("cpu oracle: %d segment(s) in %.1f s on %d threads" % (k, cpu_s, oracle.num_threads()))
+        result["gpu_direct_vs_oracle_rel_err"] = e_gd
+        log("cpu oracle: %d segment(s) in %.1f s on %d threads (%s); GPU FP64 direct vs oracle %.2e"
+            % (k, cpu_s, oracle.num_threads(), cpu_model(), e_gd))
     print(json.dumps(result), flush=True)
 
 

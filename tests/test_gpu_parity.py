@@ -86,6 +86,13 @@ def test_direct_rejects_bad_targets(env):
     ("iso-p3-D5", ISO, 20, 3, 5),
     ("cubic-p4-D3", CUB, 10, 4, 3),
     ("cubic-p6-D2", CUB, 6, 6, 2),
+    # the order the 1M-segment benchmark runs (p = 7) and the largest order a
+    # plan accepts (p = 8): every order-specialised kernel (DFTs, M2M, L2L,
+    # L2P) at those orders against the oracle's dense M2L
+    ("iso-p7-D3", ISO, 10, 7, 3),
+    ("cubic-p7-D3", CUB, 6, 7, 3),
+    ("iso-p8-D3", ISO, 8, 8, 3),
+    ("cubic-p8-D3", CUB, 5, 8, 3),
 ])
 def test_fmm_fp64_matches_oracle_fmm(env, name, C, nloops, p, D):
     seg, b = synth.make_loops(nloops, 0.01, 0.05, 1 if name == "iso2k" else 17)
