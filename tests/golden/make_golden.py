@@ -16,7 +16,7 @@ sys.path.insert(0, ROOT)
 import oracle  # noqa: E402
 import synth  # noqa: E402
 
-SAMPLES = {"iso200k": 60, "cubic100k": 16, "cubic1m": 6}
+SAMPLES = {"iso200k": 60, "cubic100k": 16, "cubic1m": 64}
 SEED = 424242
 
 
