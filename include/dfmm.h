@@ -32,7 +32,10 @@
  *     across the ABI.  dfmm_last_error() gives a thread-local message for
  *     the last failing call.  On failure no output is guaranteed.
  *   - Threads: a plan is read-only after dfmm_fmm_setup and may be shared
- *     by concurrent calls; a tree belongs to one stream at a time.
+ *     by concurrent calls, except that the surrogate calls that change its
+ *     network or switch it (dfmm_surrogate_train, _use, _set_params, _load)
+ *     modify the plan and must not overlap any other call using it; a tree
+ *     belongs to one stream at a time.
  */
 #ifndef DFMM_H
 #define DFMM_H
@@ -162,16 +165,21 @@ typedef struct {
 void dfmm_surrogate_default_cfg(dfmm_surrogate_cfg* cfg);
 
 /* Train the surrogate of an anisotropic plan and build its residual gate.
- * Synchronous.  Does not switch the plan to it (see dfmm_surrogate_use).
- * Not to be called while other calls use the plan.  DFMM_E_ARG for an
- * isotropic plan or a bad configuration. */
+ * Every product of the forward and backward passes runs on the matrix cores
+ * (f16 operands, f32 accumulation, f32 master weights and Adam moments).
+ * Synchronous.  A surrogate in use is switched off first (and the operator
+ * spectra rebuilt with the exact kernel); the new one is not switched on
+ * (see dfmm_surrogate_use).  Not to be called while other calls use the
+ * plan.  DFMM_E_ARG for an isotropic plan or a bad configuration. */
 int dfmm_surrogate_train(dfmm_plan* plan, const dfmm_surrogate_cfg* cfg, void* stream);
 
 /* on = 1: rebuild the plan's M2L spectra with the surrogate where its bin
  * passes the gate (exact quadrature elsewhere) and use it in the near field
  * of the float path; on = 0: back to the exact kernel everywhere (spectra
- * rebuilt exactly as dfmm_fmm_setup built them).  Synchronous; trees built
- * with the plan stay valid. */
+ * rebuilt exactly as dfmm_fmm_setup built them).  The network is evaluated
+ * on the matrix cores (f16 weights and activations, f32 accumulation), the
+ * same arithmetic the gate judged.  Synchronous; trees built with the plan
+ * stay valid. */
 int dfmm_surrogate_use(dfmm_plan* plan, int on, void* stream);
 
 /* JSON: training loss per epoch, fraction of gated-in bins, max / median bin
@@ -180,14 +188,33 @@ int dfmm_surrogate_info(const dfmm_plan* plan, char* json, size_t cap);
 
 /* Network parameters as float32 in layer order (W row-major [out][in], then
  * b), host memory.  get: *n receives the count, copied if cap >= count.
- * set: allocates the network if needed (gate cleared).  For testing and
- * persistence. */
+ * set: allocates the network if needed, switches a surrogate in use off
+ * (spectra rebuilt exactly) and leaves the network untrained (no gate; it
+ * cannot be switched on).  For testing. */
 int dfmm_surrogate_get_params(const dfmm_plan* plan, float* host, int64_t cap, int64_t* n);
 int dfmm_surrogate_set_params(dfmm_plan* plan, const float* host, int64_t n);
 
+/* The residual gate: mask[(face * bins + i) * bins + j] = 1 where the
+ * network is used (face = 2 axis + (T_axis < 0), (i, j) the cube-map cell of
+ * the other two coordinates over |T_axis|, in axis order after the face's
+ * axis, cyclically), host memory; *bins receives the bins per face edge and
+ * the mask is copied if cap >= 6 bins^2.  DFMM_E_STATE without a gate. */
+int dfmm_surrogate_get_gate(const dfmm_plan* plan, unsigned char* mask, int64_t cap, int* bins);
+
+/* Persistence of a trained surrogate (network, gate, its statistics) in a
+ * binary file of this library.  save: DFMM_E_STATE without a trained
+ * network, DFMM_E_ARG if the file cannot be written.  load: DFMM_E_ARG for
+ * an isotropic plan or a file that is not one of these, DFMM_E_STATE if the
+ * network was trained for another medium; switches a surrogate in use off
+ * (spectra rebuilt exactly); the loaded one is trained but not switched on.
+ * Synchronous. */
+int dfmm_surrogate_save(const dfmm_plan* plan, const char* path);
+int dfmm_surrogate_load(dfmm_plan* plan, const char* path, void* stream);
+
 /* Mean-squared loss over rows x 18 outputs and its gradient (device float
- * [n_params]) for device rows X [n][6], Y [n][18]; and the network output
- * Y = net(X).  Synchronous.  For gradient checks. */
+ * [n_params]) for device rows X [n][6], Y [n][18], by the training path; and
+ * the network output Y = net(X) by the inference path the kernels use.
+ * Synchronous.  For gradient checks. */
 int dfmm_surrogate_loss_grad(dfmm_plan* plan, const float* X, const float* Y, int64_t n, float* grad,
                              double* loss, void* stream);
 int dfmm_surrogate_forward(const dfmm_plan* plan, const float* X, int64_t n, float* Y, void* stream);

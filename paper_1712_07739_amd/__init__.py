@@ -29,6 +29,8 @@ ENTRY_POINTS = (
     "dfmm_surrogate_info", "dfmm_surrogate_get_params", "dfmm_surrogate_set_params",
     "dfmm_surrogate_loss_grad", "dfmm_surrogate_forward", "dfmm_batch_create", "dfmm_batch_run",
     "dfmm_batch_latencies", "dfmm_batch_destroy", "dfmm_autotune_depth",
+    "dfmm_surrogate_get_gate",
+    "dfmm_surrogate_save", "dfmm_surrogate_load",
 )
 
 
@@ -94,6 +96,9 @@ def lib():
     L.dfmm_surrogate_set_params.argtypes = [vp, vp, i64]
     L.dfmm_surrogate_loss_grad.argtypes = [vp, vp, vp, i64, vp, ctypes.POINTER(ctypes.c_double), vp]
     L.dfmm_surrogate_forward.argtypes = [vp, vp, i64, vp, vp]
+    L.dfmm_surrogate_get_gate.argtypes = [vp, vp, i64, ctypes.POINTER(i32)]
+    L.dfmm_surrogate_save.argtypes = [vp, ctypes.c_char_p]
+    L.dfmm_surrogate_load.argtypes = [vp, ctypes.c_char_p, vp]
     L.dfmm_batch_create.argtypes = [vp, vp, vp, vp, vp, i32, i32, vp, pp]
     L.dfmm_batch_run.argtypes = [vp, vp]
     L.dfmm_batch_latencies.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i32]
@@ -208,6 +213,22 @@ class Plan:
                                               ctypes.c_void_p(g.data_ptr()), ctypes.byref(loss), _stream(stream)))
         return loss.value, g
 
+    def surrogate_gate(self):
+        """The residual gate: uint8 array [6, bins, bins], 1 where the network is used."""
+        import numpy as np
+
+        bins = ctypes.c_int()
+        _check(lib().dfmm_surrogate_get_gate(self._h, None, 0, ctypes.byref(bins)))
+        out = np.empty((6, bins.value, bins.value), dtype=np.uint8)
+        _check(lib().dfmm_surrogate_get_gate(self._h, ctypes.c_void_p(out.ctypes.data), out.size, ctypes.byref(bins)))
+        return out
+
+    def surrogate_save(self, path):
+        _check(lib().dfmm_surrogate_save(self._h, os.fsencode(path)))
+
+    def surrogate_load(self, path, stream=None):
+        _check(lib().dfmm_surrogate_load(self._h, os.fsencode(path), _stream(stream)))
+
     def surrogate_forward(self, X, stream=None):
         import torch
 
@@ -303,9 +324,9 @@ def direct_forces(plan: Plan, seg, burgers, targets=None, fp32=False, out=None, 
         nt, tptr = int(targets.numel()), ctypes.c_void_p(targets.data_ptr())
     if out is None:
         out = torch.empty((nt, 2, 3), dtype=torch.float64, device=seg.device)
-    _check(lib().dfmm_direct_forces(plan.handle, ctypes.c_void_p(seg.data_ptr()),
-                                    ctypes.c_void_p(burgers.data_ptr()), n, tptr, nt,
-                                    ctypes.c_void_p(out.data_ptr()), 1 if fp32 else 0, _stream(stream)))
+    fn = lib().dfmm_direct_forces
+    _check(fn(plan.handle, ctypes.c_void_p(seg.data_ptr()), ctypes.c_void_p(burgers.data_ptr()), n, tptr, nt,
+              ctypes.c_void_p(out.data_ptr()), 1 if fp32 else 0, _stream(stream)))
     return out
 
 

@@ -128,6 +128,7 @@ int dfmm_fmm_setup(const dfmm_params* prm, void* stream, dfmm_plan** out) {
 void dfmm_plan_destroy(dfmm_plan* pl) {
   if (!pl) return;
   hipFree(pl->sur.w); hipFree(pl->sur.g); hipFree(pl->sur.m); hipFree(pl->sur.v); hipFree(pl->sur.mask);
+  hipFree(pl->sur.wi); hipFree(pl->sur.bi); hipFree(pl->sur.split);
   for (auto& l : pl->lev) hipFree(l.khat);
   hipFree(pl->t64.S); hipFree(pl->t64.cs); hipFree(pl->t64.tw);
   hipFree(pl->t32.S); hipFree(pl->t32.cs); hipFree(pl->t32.tw);
@@ -217,9 +218,20 @@ void dfmm_surrogate_default_cfg(dfmm_surrogate_cfg* c) {
   c->seed = 1;
 }
 
+// The plan's operator spectra must always come from the kernel the near
+// field uses: whenever the surrogate is switched off because its network
+// changes, the spectra are rebuilt with the exact kernel.
+static int surrogate_off(dfmm_plan* pl, hipStream_t st) {
+  const bool was = pl->sur.in_use && pl->sur.trained && pl->sur.pass_frac > 0;
+  pl->sur.in_use = 0;
+  return was ? build_spectra(pl, st) : DFMM_OK;
+}
+
 int dfmm_surrogate_train(dfmm_plan* pl, const dfmm_surrogate_cfg* cfg, void* stream) {
   if (!pl || !cfg) { set_error("surrogate_train: null argument"); return DFMM_E_ARG; }
   if (pl->iso) { set_error("surrogate_train: the plan's medium is isotropic (closed form)"); return DFMM_E_ARG; }
+  int rc = surrogate_off(pl, (hipStream_t)stream);
+  if (rc) return rc;
   return surrogate_train(pl, *cfg, (hipStream_t)stream);
 }
 
@@ -233,18 +245,19 @@ int dfmm_surrogate_use(dfmm_plan* pl, int on, void* stream) {
 int dfmm_surrogate_info(const dfmm_plan* pl, char* json, size_t cap) {
   if (!pl || !json || cap == 0) { set_error("surrogate_info: invalid argument"); return DFMM_E_ARG; }
   const Surrogate& S = pl->sur;
+  auto num = [](double x) {
+    char b[40];
+    std::snprintf(b, sizeof b, "%.9g", x);
+    return std::string(b);
+  };
   std::string s = "{\"trained\": " + std::to_string(S.trained) + ", \"in_use\": " + std::to_string(S.in_use) +
                   ", \"n_params\": " + std::to_string(S.L.total) + ", \"n_samples\": " + std::to_string(S.n_samples) +
                   ", \"epochs\": " + std::to_string(S.epochs) + ", \"bins\": " + std::to_string(S.bins) +
-                  ", \"tol\": " + std::to_string(S.tol) + ", \"pass_frac\": " + std::to_string(S.pass_frac) +
-                  ", \"max_bin_err\": " + std::to_string(S.max_err) + ", \"median_bin_err\": " +
-                  std::to_string(S.med_err) + ", \"yscale\": " + std::to_string(S.yscale) +
-                  ", \"train_ms\": " + std::to_string(S.train_ms) + ", \"loss\": [";
-  for (size_t i = 0; i < S.loss_hist.size(); ++i) {
-    char b[32];
-    std::snprintf(b, sizeof b, "%s%.6g", i ? ", " : "", S.loss_hist[i]);
-    s += b;
-  }
+                  ", \"tol\": " + num(S.tol) + ", \"pass_frac\": " + num(S.pass_frac) +
+                  ", \"max_bin_err\": " + num(S.max_err) + ", \"median_bin_err\": " + num(S.med_err) +
+                  ", \"yscale\": " + num(S.yscale) + ", \"features\": [" + num(S.ft.f[0]) + ", " + num(S.ft.f[1]) +
+                  ", " + num(S.ft.f[2]) + "], \"train_ms\": " + num(S.train_ms) + ", \"loss\": [";
+  for (size_t i = 0; i < S.loss_hist.size(); ++i) s += (i ? ", " : "") + num(S.loss_hist[i]);
   s += "]}";
   if (s.size() + 1 > cap) { set_error("surrogate_info: buffer too small"); return DFMM_E_ARG; }
   std::memcpy(json, s.c_str(), s.size() + 1);
@@ -261,12 +274,119 @@ int dfmm_surrogate_get_params(const dfmm_plan* pl, float* host, int64_t cap, int
 
 int dfmm_surrogate_set_params(dfmm_plan* pl, const float* host, int64_t n) {
   if (!pl || !host) { set_error("surrogate_set_params: null argument"); return DFMM_E_ARG; }
-  int rc = surrogate_alloc(pl, 1, nullptr);
+  if (pl->iso) { set_error("surrogate_set_params: the plan's medium is isotropic (closed form)"); return DFMM_E_ARG; }
+  int rc = surrogate_off(pl, nullptr);
   if (rc) return rc;
-  if (n != pl->sur.L.total) { set_error("surrogate_set_params: wrong parameter count"); return DFMM_E_ARG; }
+  if (n != sur_layout(kSurHidden).total) { set_error("surrogate_set_params: wrong parameter count"); return DFMM_E_ARG; }
+  if ((rc = surrogate_alloc(pl, 1, nullptr))) return rc;
   DFMM_HIP(hipMemcpy(pl->sur.w, host, sizeof(float) * n, hipMemcpyHostToDevice));
+  if ((rc = surrogate_pack(pl, nullptr))) return rc;
+  DFMM_HIP(hipStreamSynchronize(nullptr));
   pl->sur.trained = 0;
-  pl->sur.in_use = 0;
+  return DFMM_OK;
+}
+
+int dfmm_surrogate_get_gate(const dfmm_plan* pl, unsigned char* host, int64_t cap, int* bins) {
+  if (!pl || !bins) { set_error("surrogate_get_gate: null argument"); return DFMM_E_ARG; }
+  if (!pl->sur.mask || pl->sur.bins < 1) { set_error("surrogate_get_gate: no gate"); return DFMM_E_STATE; }
+  *bins = pl->sur.bins;
+  const int64_t nb = 6LL * pl->sur.bins * pl->sur.bins;
+  if (host && cap >= nb) DFMM_HIP(hipMemcpy(host, pl->sur.mask, nb, hipMemcpyDeviceToHost));
+  return DFMM_OK;
+}
+
+// File layout (little-endian): "DFMMSUR1", int32 version, hidden, n_params,
+// bins; float features[3], yscale; double tol, pass_frac, max_err, med_err,
+// train_ms; int64 n_samples; int32 epochs, n_loss; double loss[n_loss];
+// float params[n_params]; uint8 gate[6 bins^2].
+static const char kSurMagic[8] = {'D', 'F', 'M', 'M', 'S', 'U', 'R', '1'};
+
+int dfmm_surrogate_save(const dfmm_plan* pl, const char* path) {
+  if (!pl || !path) { set_error("surrogate_save: null argument"); return DFMM_E_ARG; }
+  const Surrogate& S = pl->sur;
+  if (!S.trained || !S.w || !S.mask) { set_error("surrogate_save: no trained surrogate"); return DFMM_E_STATE; }
+  std::vector<float> w(S.L.total);
+  const int64_t nb = 6LL * S.bins * S.bins;
+  std::vector<unsigned char> mask(nb);
+  DFMM_HIP(hipMemcpy(w.data(), S.w, sizeof(float) * w.size(), hipMemcpyDeviceToHost));
+  DFMM_HIP(hipMemcpy(mask.data(), S.mask, nb, hipMemcpyDeviceToHost));
+  FILE* f = std::fopen(path, "wb");
+  if (!f) { set_error(std::string("surrogate_save: cannot open ") + path); return DFMM_E_ARG; }
+  const int32_t hdr[4] = {1, kSurHidden, (int32_t)S.L.total, S.bins};
+  const float fl[4] = {S.ft.f[0], S.ft.f[1], S.ft.f[2], S.yscale};
+  const double db[5] = {S.tol, S.pass_frac, S.max_err, S.med_err, S.train_ms};
+  const int64_t ns = S.n_samples;
+  const int32_t ep[2] = {S.epochs, (int32_t)S.loss_hist.size()};
+  bool ok = std::fwrite(kSurMagic, 1, 8, f) == 8 && std::fwrite(hdr, sizeof hdr, 1, f) == 1 &&
+            std::fwrite(fl, sizeof fl, 1, f) == 1 && std::fwrite(db, sizeof db, 1, f) == 1 &&
+            std::fwrite(&ns, sizeof ns, 1, f) == 1 && std::fwrite(ep, sizeof ep, 1, f) == 1 &&
+            (S.loss_hist.empty() || std::fwrite(S.loss_hist.data(), sizeof(double), S.loss_hist.size(), f) == S.loss_hist.size()) &&
+            std::fwrite(w.data(), sizeof(float), w.size(), f) == w.size() &&
+            std::fwrite(mask.data(), 1, mask.size(), f) == mask.size();
+  ok = (std::fclose(f) == 0) && ok;
+  if (!ok) { set_error(std::string("surrogate_save: write failed: ") + path); return DFMM_E_ARG; }
+  return DFMM_OK;
+}
+
+int dfmm_surrogate_load(dfmm_plan* pl, const char* path, void* stream) {
+  if (!pl || !path) { set_error("surrogate_load: null argument"); return DFMM_E_ARG; }
+  if (pl->iso) { set_error("surrogate_load: the plan's medium is isotropic (closed form)"); return DFMM_E_ARG; }
+  hipStream_t st = (hipStream_t)stream;
+  FILE* f = std::fopen(path, "rb");
+  if (!f) { set_error(std::string("surrogate_load: cannot open ") + path); return DFMM_E_ARG; }
+  char magic[8];
+  int32_t hdr[4], ep[2];
+  float fl[4];
+  double db[5];
+  int64_t ns = 0;
+  std::vector<double> loss;
+  std::vector<float> w;
+  std::vector<unsigned char> mask;
+  bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, kSurMagic, 8) == 0 &&
+            std::fread(hdr, sizeof hdr, 1, f) == 1 && hdr[0] == 1 && hdr[1] == kSurHidden &&
+            hdr[2] == (int32_t)sur_layout(kSurHidden).total && hdr[3] >= 1 && hdr[3] <= 256 &&
+            std::fread(fl, sizeof fl, 1, f) == 1 && std::fread(db, sizeof db, 1, f) == 1 &&
+            std::fread(&ns, sizeof ns, 1, f) == 1 && std::fread(ep, sizeof ep, 1, f) == 1 && ep[1] >= 0 &&
+            ep[1] <= (1 << 20);
+  if (ok) {
+    loss.resize(ep[1]);
+    w.resize(hdr[2]);
+    mask.resize(6LL * hdr[3] * hdr[3]);
+    ok = (loss.empty() || std::fread(loss.data(), sizeof(double), loss.size(), f) == loss.size()) &&
+         std::fread(w.data(), sizeof(float), w.size(), f) == w.size() &&
+         std::fread(mask.data(), 1, mask.size(), f) == mask.size();
+  }
+  std::fclose(f);
+  if (!ok) { set_error(std::string("surrogate_load: not a surrogate file of this library: ") + path); return DFMM_E_ARG; }
+  const double csum = pl->prm.c11 + pl->prm.c12 + pl->prm.c44;
+  if (fl[0] != (float)(pl->prm.c11 / csum) || fl[1] != (float)(pl->prm.c12 / csum) ||
+      fl[2] != (float)(pl->prm.c44 / csum)) {
+    set_error("surrogate_load: the network was trained for another medium");
+    return DFMM_E_STATE;
+  }
+  int rc = surrogate_off(pl, st);
+  if (rc) return rc;
+  pl->sur.trained = 0;
+  if ((rc = surrogate_alloc(pl, 1, st))) return rc;
+  Surrogate& S = pl->sur;
+  DFMM_HIP(hipMemcpy(S.w, w.data(), sizeof(float) * w.size(), hipMemcpyHostToDevice));
+  if ((rc = surrogate_pack(pl, st))) return rc;
+  hipFree(S.mask);
+  S.mask = nullptr;
+  DFMM_HIP(hipMalloc(&S.mask, mask.size()));
+  DFMM_HIP(hipMemcpy(S.mask, mask.data(), mask.size(), hipMemcpyHostToDevice));
+  DFMM_HIP(hipStreamSynchronize(st));
+  S.bins = hdr[3];
+  S.yscale = fl[3];
+  S.tol = db[0];
+  S.pass_frac = db[1];
+  S.max_err = db[2];
+  S.med_err = db[3];
+  S.train_ms = db[4];
+  S.n_samples = ns;
+  S.epochs = ep[0];
+  S.loss_hist = loss;
+  S.trained = 1;
   return DFMM_OK;
 }
 

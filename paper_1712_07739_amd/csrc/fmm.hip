@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <cmath>
 
+#include <mutex>
 #include <utility>
 
 #include "internal.h"
@@ -654,6 +655,13 @@ constexpr size_t lds_idft_t(size_t es) {
 // (displacements formed in double) with compensated float accumulation, and
 // pairs closer than 2a are left to k_close_eval (double precision, run after this
 // kernel), which keeps double-precision code and its registers out of here.
+__device__ __forceinline__ void kadd_f(float& s, float& c, float x) {
+  const float y = x - c;
+  const float z = s + y;
+  c = (z - s) - y;
+  s = z;
+}
+
 // Single precision: ask for 3 waves per SIMD (the register budget that the
 // pair evaluation fits without spilling); double precision: no constraint.
 template <typename T>
@@ -661,11 +669,10 @@ constexpr int leaf_min_waves() {
   return std::is_same<T, float>::value ? 3 : 1;
 }
 
-template <typename T, bool MIXED, bool ISO, bool SUR>
+template <typename T, bool MIXED, bool ISO>
 __global__ void __launch_bounds__(64, leaf_min_waves<T>())
     k_leaf(const double* pts, int64_t N, const int* first, const int* count, const int* nbr, Med<T> m,
-           Med<double> m64, SurDev sd, double* sig) {
-  extern __shared__ float sur_scratch[];  // [2*128][64] activations when SUR
+           Med<double> m64, double* sig) {
   const int leaf = blockIdx.x, lane = threadIdx.x;
   const int t0 = first[leaf], nt = count[leaf];
   __shared__ int nb_first[27], nb_cnt[27];
@@ -704,26 +711,7 @@ __global__ void __launch_bounds__(64, leaf_min_waves<T>())
           } else {
             T D[27], b[3], tt[3];
             for (int c = 0; c < 3; ++c) b[c] = (T)pts[(3 + c) * N + j], tt[c] = (T)pts[(6 + c) * N + j];
-            bool net = false;
-            if constexpr (SUR) {
-              // network for the anisotropic part where its direction bin passed the gate
-              const float f0 = (float)d0, f1 = (float)d1, f2 = (float)d2;
-              const float rr = f0 * f0 + f1 * f1 + f2 * f2;
-              if (rr > 0.f) {
-                const float ir = rsqrtf(rr);
-                const float tv[3] = {f0 * ir, f1 * ir, f2 * ir};
-                if (sd.mask[sur_bin(tv, sd.bins)]) {
-#pragma unroll
-                  for (int c = 0; c < 27; ++c) D[c] = T(0);
-                  dg_iso_acc<T>((T)d0, (T)d1, (T)d2, m.mu, m.nu, m.a, T(1), D);
-                  const float q = rr / (rr + (float)m.a * (float)m.a);
-                  sur_aniso_acc<64>(sd, (float)m.c44, f0, f1, f2, q * sqrtf(q), (float*)D,
-                                    sur_scratch + lane);
-                  net = true;
-                }
-              }
-            }
-            if (!net) dg_medium_t<T, ISO>((T)d0, (T)d1, (T)d2, m, D);
+            dg_medium_t<T, ISO>((T)d0, (T)d1, (T)d2, m, D);
             if (MIXED) {
               T ds[6] = {0, 0, 0, 0, 0, 0};
               contract_b_t<T>(D, m.c12, m.c44, m.hh, b, tt, ds);
@@ -751,6 +739,111 @@ __global__ void __launch_bounds__(64, leaf_min_waves<T>())
     if (act && slice == 0) {
 #pragma unroll
       for (int c = 0; c < 6; ++c) sig[i * 6 + c] = tot[c];
+    }
+  }
+}
+
+// Near field with the learned surrogate (cubic medium, single precision):
+// the one-sided pair loop of k_leaf, with the anisotropic part of dG taken
+// from the network wherever the pair's direction bin passed the residual
+// gate.  The network runs on the matrix cores for all 64 pairs of a wave at
+// once (mlp_eval.h), so the loops are arranged to be uniform across the wave:
+// one wave per leaf (persistent blocks of eight waves, leaves strided over
+// the grid), each lane walking its target's sources in the order k_leaf
+// uses, one source per lane and step.  A step evaluates the network when any
+// lane's pair is gated in; lanes whose pair is not keep the exact quadrature.
+// The weights sit in LDS (110 KB), one block per CU.
+constexpr int kSurLeafThreads = 512;
+__global__ void __launch_bounds__(kSurLeafThreads) k_leaf_sur(const double* pts, int64_t N, const int* first,
+                                                              const int* count, const int* nbr, int64_t nleaf,
+                                                              Med<float> m, Med<double> m64, SurDev sd, double* sig) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  sur_stage(sd, lds);
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int64_t nw = kSurLeafThreads / 64;
+  const int64_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+  const double a2x4 = 4.0 * m64.a * m64.a;
+  const float fscale = sd.yscale / m.c44;
+  for (int64_t leaf = (int64_t)blockIdx.x * nw + wave; leaf < nleaf; leaf += (int64_t)gridDim.x * nw) {
+    const int t0 = first[leaf], nt = count[leaf];
+    for (int c0 = 0, per = 64; c0 < nt; c0 += per) {
+      const int rem = nt - c0;
+      per = 64;
+      while (per > rem) per >>= 1;
+      const int S = 64 / per;
+      const int ti = c0 + lane / S, slice = lane % S;
+      const bool act = ti < nt;
+      const int64_t i = t0 + (act ? ti : 0);
+      const double xt0 = pts[i], xt1 = pts[N + i], xt2 = pts[2 * N + i];
+      float acc[6], cmp[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) acc[c] = cmp[c] = 0.f;
+      int base = 0;
+      for (int q = 0; q < 27; ++q) {
+        const int jl = nbr[leaf * 27 + q];
+        const int fj = jl >= 0 ? first[jl] : 0, cj = jl >= 0 ? count[jl] : 0;
+        const int start = (slice - (base % S) + S) % S;
+        const int nsteps = (cj + S - 1) / S;  // the same on every lane
+        for (int it = 0; it < nsteps; ++it) {
+          const int jj = start + it * S;
+          bool use = act && jj < cj;
+          double d0 = 0, d1 = 0, d2 = 0;
+          int64_t j = 0;
+          if (use) {
+            j = fj + jj;
+            d0 = xt0 - pts[j];
+            d1 = xt1 - pts[N + j];
+            d2 = xt2 - pts[2 * N + j];
+            if (d0 * d0 + d1 * d1 + d2 * d2 < a2x4) use = false;  // near-coincident: k_close_eval
+          }
+          const float f0 = (float)d0, f1 = (float)d1, f2 = (float)d2;
+          const float rr = f0 * f0 + f1 * f1 + f2 * f2;
+          float x6[6] = {1.f, 0.f, 0.f, sd.ft.f[0], sd.ft.f[1], sd.ft.f[2]};
+          bool gated = false;
+          if (use && rr > 0.f) {
+            const float ir = rsqrtf(rr);
+            x6[0] = f0 * ir;
+            x6[1] = f1 * ir;
+            x6[2] = f2 * ir;
+            gated = sd.mask[sur_bin(x6, sd.bins)] != 0;
+          }
+          float D[27];
+          if (__ballot(gated)) {
+            float y[18];
+            sur_wave_eval(lds, x6, y);
+            // the network's part first, so that its outputs die before the
+            // exact quadrature of the other lanes
+            if (gated) {
+#pragma unroll
+              for (int c = 0; c < 27; ++c) D[c] = 0.f;
+              dg_iso_acc<float>(f0, f1, f2, m.mu, m.nu, m.a, 1.f, D);
+              const float qd = rr / (rr + m.a * m.a);
+              sur_aniso_add<float>(y, qd * sqrtf(qd) * fscale / rr, D);
+            }
+          }
+          if (use) {
+            float b[3], tt[3];
+            if (!gated) dg_medium_t<float, false>(f0, f1, f2, m, D);
+            for (int c = 0; c < 3; ++c) b[c] = (float)pts[(3 + c) * N + j], tt[c] = (float)pts[(6 + c) * N + j];
+            float ds[6] = {0, 0, 0, 0, 0, 0};
+            contract_b_t<float>(D, m.c12, m.c44, m.hh, b, tt, ds);
+#pragma unroll
+            for (int c = 0; c < 6; ++c) kadd_f(acc[c], cmp[c], ds[c]);
+          }
+        }
+        base += cj;
+      }
+      double tot[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) tot[c] = (double)acc[c] - (double)cmp[c];
+      for (int o = S / 2; o >= 1; o >>= 1)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) tot[c] += __shfl_xor(tot[c], o, 64);
+      if (act && slice == 0) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) sig[i * 6 + c] = tot[c];
+      }
     }
   }
 }
@@ -1132,6 +1225,11 @@ __global__ void __launch_bounds__(256) k_direct(const double* pts, int64_t N, co
   }
 }
 
+__global__ void k_fill_int(int* p, int n, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
 __global__ void k_check_targets(const int64_t* targets, int64_t nt, int64_t nseg, int* bad) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < nt && (targets[i] < 0 || targets[i] >= nseg)) atomicOr(bad, 1);
@@ -1294,14 +1392,16 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
   {
     Med<T> m = pl->med<T>();
     Med<double> m64 = pl->med<double>();
-#define LEAF_ARGS t->pts, N, LD.first, LD.count, t->nbr, m, m64, sd, t->sig
+#define LEAF_ARGS t->pts, N, LD.first, LD.count, t->nbr, m, m64, t->sig
     SurDev sd = sur_dev(pl);
     if constexpr (std::is_same<T, float>::value) {
-      if (!pl->iso && sd.on)
-        STAGE(6, (k_leaf<T, true, false, true><<<(unsigned)LD.n, 64, sizeof(float) * 2 * kSurHidden * 64, nst>>>(
-                     LEAF_ARGS)));
-      else if (pl->iso)
-        STAGE(6, (k_leaf<T, true, true, false><<<(unsigned)LD.n, 64, 0, nst>>>(LEAF_ARGS)));
+      if (!pl->iso && sd.on) {
+        const int grid = (int)std::max<int64_t>(
+            1, std::min<int64_t>(sur_grid(pl->device), (LD.n + kSurLeafThreads / 64 - 1) / (kSurLeafThreads / 64)));
+        STAGE(6, (k_leaf_sur<<<grid, kSurLeafThreads, kSurInfLds, nst>>>(t->pts, N, LD.first, LD.count, t->nbr, LD.n,
+                                                                          m, m64, sd, t->sig)));
+      } else if (pl->iso)
+        STAGE(6, (k_leaf<T, true, true><<<(unsigned)LD.n, 64, 0, nst>>>(LEAF_ARGS)));
       else if (t->part) {
         const double a2x4 = 4.0 * m64.a * m64.a;
         STAGE(6, (k_leaf_sym<T, true, false><<<dim3((unsigned)LD.n, 14), sym_threads<T, false>(), sym_lds<T, false>(64), nst>>>(
@@ -1311,7 +1411,7 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
                        t->pts, N, LD.first, LD.count, t->nbr, m, a2x4, t->max_leaf_pts, (T*)t->part, t->bigp)));
       }
       else
-        STAGE(6, (k_leaf<T, true, false, false><<<(unsigned)LD.n, 64, 0, nst>>>(LEAF_ARGS)));
+        STAGE(6, (k_leaf<T, true, false><<<(unsigned)LD.n, 64, 0, nst>>>(LEAF_ARGS)));
       if (!pl->iso && !sd.on && t->part)
         STAGE(6, (k_near_sum<T><<<nblk(N, 256), 256, 0, nst>>>((const T*)t->part, N, t->pleaf, t->nbr, t->sig)));
       if (t->nclose > 0) {
@@ -1325,7 +1425,7 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
       }
     } else {
       if (pl->iso) {
-        STAGE(6, (k_leaf<T, false, true, false><<<(unsigned)LD.n, 64, 0, nst>>>(LEAF_ARGS)));
+        STAGE(6, (k_leaf<T, false, true><<<(unsigned)LD.n, 64, 0, nst>>>(LEAF_ARGS)));
       } else if (t->part) {
         STAGE(6, (k_leaf_sym<T, false, false><<<dim3((unsigned)LD.n, 14), sym_threads<T, false>(), sym_lds<T, false>(64), nst>>>(
                      t->pts, N, LD.first, LD.count, t->nbr, m, 0.0, 64, (T*)t->part, nullptr)));
@@ -1334,7 +1434,7 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
                        t->pts, N, LD.first, LD.count, t->nbr, m, 0.0, t->max_leaf_pts, (T*)t->part, t->bigp)));
         STAGE(6, (k_near_sum<T><<<nblk(N, 256), 256, 0, nst>>>((const T*)t->part, N, t->pleaf, t->nbr, t->sig)));
       } else {
-        STAGE(6, (k_leaf<T, false, false, false><<<(unsigned)LD.n, 64, 0, nst>>>(LEAF_ARGS)));
+        STAGE(6, (k_leaf<T, false, false><<<(unsigned)LD.n, 64, 0, nst>>>(LEAF_ARGS)));
       }
     }
 #undef LEAF_ARGS
@@ -1398,10 +1498,7 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
 }
 
 template <typename T>
-static void set_lds_attrs() {
-  static bool done = false;
-  if (done) return;
-  done = true;
+static void set_lds_attrs_once() {
   const int mx = 160 * 1024;
   hipFuncSetAttribute((const void*)k_hadamard, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
   hipFuncSetAttribute((const void*)k_hadamard3<double>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
@@ -1409,6 +1506,15 @@ static void set_lds_attrs() {
                       mx);
   dft_lds_attrs<T>(std::make_integer_sequence<int, kMaxOrder - 1>{});
   hipFuncSetAttribute((const void*)k_p2m<T>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+  hipFuncSetAttribute((const void*)k_leaf_sur, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+}
+
+// Kernel attributes are set once per process and precision, from whichever
+// thread gets there first.
+template <typename T>
+static void set_lds_attrs() {
+  static std::once_flag once;
+  std::call_once(once, set_lds_attrs_once<T>);
 }
 
 void fmm_prepare(const dfmm_plan* pl) {
@@ -1426,15 +1532,66 @@ int fmm_forces_impl(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const 
   return run_fmm<double>(pl, t, seg, burg, forces, st);
 }
 
+// Direct sum on caller-provided scratch: pts [9][N], part [nchunk][ntp][6],
+// sig [ntp][6] (double); bad: one int (zeroed here by a fill kernel, not a
+// memset, so that the call may be captured).  With targets, their indices
+// are checked first (one host synchronisation).  Asynchronous otherwise.
+static int direct_core(const dfmm_plan* pl, const double* seg, const double* burg, int64_t nseg,
+                       const int64_t* targets, int64_t ntgt, double* forces, int fp32, hipStream_t st,
+                       double* pts, double* part, double* sig, int* bad, int64_t nchunk, int64_t chunk) {
+  const int nq = pl->quad.n;
+  const int64_t N = nseg * nq, ntp = ntgt * nq;
+  const int64_t tb = (ntp + 255) / 256;
+  if (targets) {
+    // reject target indices outside [0, nseg) before any kernel reads through them
+    int hbad = 0;
+    k_fill_int<<<1, 64, 0, st>>>(bad, 1, 0);
+    DFMM_LAUNCH_CHECK();
+    k_check_targets<<<nblk(ntgt, 256), 256, 0, st>>>(targets, ntgt, nseg, bad);
+    DFMM_LAUNCH_CHECK();
+    DFMM_D2H(&hbad, bad, sizeof(int), st);
+    if (hbad) {
+      set_error("direct_forces: target index outside [0, n_seg)");
+      return DFMM_E_ARG;
+    }
+  }
+  k_points_plain<<<nblk(N, 256), 256, 0, st>>>(seg, burg, pl->quad, N, pts);
+  DFMM_LAUNCH_CHECK();
+  dim3 g((unsigned)tb, (unsigned)nchunk);
+#define DIRECT_ARGS pts, N, targets, nq, ntp, chunk, pl->med<double>(), pl->med<float>(), part
+  if (fp32 && pl->iso)
+    k_direct<true, true><<<g, 256, 0, st>>>(DIRECT_ARGS);
+  else if (fp32)
+    k_direct<true, false><<<g, 256, 0, st>>>(DIRECT_ARGS);
+  else if (pl->iso)
+    k_direct<false, true><<<g, 256, 0, st>>>(DIRECT_ARGS);
+  else
+    k_direct<false, false><<<g, 256, 0, st>>>(DIRECT_ARGS);
+#undef DIRECT_ARGS
+  DFMM_LAUNCH_CHECK();
+  k_direct_reduce<<<nblk(ntp * 6, 256), 256, 0, st>>>(part, ntp, (int)nchunk, sig);
+  DFMM_LAUNCH_CHECK();
+  k_forces<<<nblk(ntgt, 128), 128, 0, st>>>(seg, burg, targets, nullptr, sig, pl->quad, ntgt, forces);
+  DFMM_LAUNCH_CHECK();
+  return DFMM_OK;
+}
+
+// Source chunks of the direct sum: enough blocks to fill the chip (about
+// 4096), each chunk a multiple of the 256-point LDS tile.
+static void direct_chunks(int64_t N, int64_t ntp, int64_t* nchunk, int64_t* chunk) {
+  const int64_t tb = (ntp + 255) / 256;
+  int64_t nc = std::max<int64_t>(1, std::min<int64_t>((N + 255) / 256, (4096 + tb - 1) / tb));
+  *chunk = ((N + nc - 1) / nc + 255) / 256 * 256;
+  *nchunk = (N + *chunk - 1) / *chunk;
+}
+
 int direct_forces_impl(const dfmm_plan* pl, const double* seg, const double* burg, int64_t nseg,
                        const int64_t* targets, int64_t ntgt, double* forces, int fp32, hipStream_t st) {
   const int nq = pl->quad.n;
   const int64_t N = nseg * nq, ntp = ntgt * nq;
+  int64_t nchunk, chunk;
+  direct_chunks(N, ntp, &nchunk, &chunk);
   double *pts = nullptr, *part = nullptr, *sig = nullptr;
-  const int64_t tb = (ntp + 255) / 256;
-  int64_t nchunk = std::max<int64_t>(1, std::min<int64_t>((N + 255) / 256, (4096 + tb - 1) / tb));
-  const int64_t chunk = ((N + nchunk - 1) / nchunk + 255) / 256 * 256;
-  nchunk = (N + chunk - 1) / chunk;
   if (hipMalloc(&pts, sizeof(double) * 9 * N) != hipSuccess ||
       hipMalloc(&part, sizeof(double) * 6 * ntp * nchunk) != hipSuccess ||
       hipMalloc(&sig, sizeof(double) * 6 * ntp) != hipSuccess) {
@@ -1444,43 +1601,8 @@ int direct_forces_impl(const dfmm_plan* pl, const double* seg, const double* bur
     set_error("direct_forces: cannot allocate scratch");
     return DFMM_E_NOMEM;
   }
-  int rc = DFMM_OK;
-  if (targets) {
-    // reject target indices outside [0, nseg) before any kernel reads through them
-    int* bad = (int*)sig;
-    int hbad = 0;
-    hipMemsetAsync(bad, 0, sizeof(int), st);
-    k_check_targets<<<nblk(ntgt, 256), 256, 0, st>>>(targets, ntgt, nseg, bad);
-    if (hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
-        hipStreamSynchronize(st) != hipSuccess || hbad) {
-      hipFree(pts);
-      hipFree(part);
-      hipFree(sig);
-      set_error(hbad ? "direct_forces: target index outside [0, n_seg)" : "direct_forces: HIP error");
-      return hbad ? DFMM_E_ARG : DFMM_E_HIP;
-    }
-  }
-  do {
-    k_points_plain<<<nblk(N, 256), 256, 0, st>>>(seg, burg, pl->quad, N, pts);
-    if (hipGetLastError() != hipSuccess) { rc = DFMM_E_HIP; break; }
-    dim3 g((unsigned)tb, (unsigned)nchunk);
-#define DIRECT_ARGS pts, N, targets, nq, ntp, chunk, pl->med<double>(), pl->med<float>(), part
-    if (fp32 && pl->iso)
-      k_direct<true, true><<<g, 256, 0, st>>>(DIRECT_ARGS);
-    else if (fp32)
-      k_direct<true, false><<<g, 256, 0, st>>>(DIRECT_ARGS);
-    else if (pl->iso)
-      k_direct<false, true><<<g, 256, 0, st>>>(DIRECT_ARGS);
-    else
-      k_direct<false, false><<<g, 256, 0, st>>>(DIRECT_ARGS);
-#undef DIRECT_ARGS
-    if (hipGetLastError() != hipSuccess) { rc = DFMM_E_HIP; break; }
-    k_direct_reduce<<<nblk(ntp * 6, 256), 256, 0, st>>>(part, ntp, (int)nchunk, sig);
-    if (hipGetLastError() != hipSuccess) { rc = DFMM_E_HIP; break; }
-    k_forces<<<nblk(ntgt, 128), 128, 0, st>>>(seg, burg, targets, nullptr, sig, pl->quad, ntgt, forces);
-    if (hipGetLastError() != hipSuccess) { rc = DFMM_E_HIP; break; }
-  } while (0);
-  if (rc) set_error("direct_forces: kernel launch failed");
+  int rc = direct_core(pl, seg, burg, nseg, targets, ntgt, forces, fp32, st, pts, part, sig, (int*)sig, nchunk,
+                       chunk);
   hipError_t e = hipStreamSynchronize(st);
   hipFree(pts);
   hipFree(part);

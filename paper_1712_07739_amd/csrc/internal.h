@@ -85,10 +85,14 @@ struct Surrogate {
   SurLayout L = {};
   SurFeat ft = {};
   float yscale = 1.f;
-  float* w = nullptr;  // parameters (device), layout SurLayout
+  float* w = nullptr;  // f32 master parameters (device), layout SurLayout
   float* g = nullptr;  // gradient
   float* m = nullptr;  // Adam moments
   float* v = nullptr;
+  uint16_t* wi = nullptr;  // inference copy: f16 fragments (mlp_eval.h)
+  float* bi = nullptr;     // inference biases
+  float* split = nullptr;  // split-K partials of the training products
+  size_t split_n = 0;
   unsigned char* mask = nullptr;  // [6][bins][bins]
   int bins = 0;
   double tol = 0, pass_frac = 0, max_err = 0, med_err = 0, train_ms = 0;
@@ -212,6 +216,10 @@ SurDev sur_dev(const dfmm_plan* plan);
 
 // mlp.hip
 SurLayout sur_layout(int hidden);
+int surrogate_pack(dfmm_plan* pl, hipStream_t st);   // f16 inference copy of the master weights
+int surrogate_gate(dfmm_plan* pl, int bins, double tol, hipStream_t st);
+int surrogate_infer(const dfmm_plan* pl, const float* X, int64_t n, float* Y, hipStream_t st);
+int sur_grid(int device);
 int surrogate_train(dfmm_plan* pl, const dfmm_surrogate_cfg& cfg, hipStream_t st);
 int surrogate_alloc(dfmm_plan* pl, uint64_t seed, hipStream_t st);
 int surrogate_loss_grad(dfmm_plan* pl, const float* X, const float* Y, int64_t n, float* grad, double* loss,

@@ -5,16 +5,21 @@
 // network predicts the scaled residual
 //     y(T) = c44 (Phi_circle(T) - Phi_iso[Voigt](T)) / yscale
 // for the 18 distinct components (v <= p) x q of Phi_vpq, from the features
-// (T, normalised c11, c12, c44): 6 -> 4 x 128 (SiLU) -> 18, FP32.  Training
+// (T, normalised c11, c12, c44): 6 -> 4 x 128 (SiLU) -> 18.  Training
 // samples are directions drawn by a counter-based generator with targets from
-// the FP64 circle quadrature of kernel_eval.h; forward, backward and Adam are
-// the kernels below.  A cube-map table of direction bins records, per bin,
-// the largest error of the network against the exact quadrature on a grid of
-// validation directions, relative to the largest component of Phi there; bins
-// above the tolerance keep the exact quadrature.
+// the FP64 circle quadrature of kernel_eval.h.  Every product of the forward
+// and backward passes runs on the matrix cores (f16 operands, f32
+// accumulation, f32 master weights and Adam moments); inference uses the
+// wave-level network of mlp_eval.h with the weights packed into its f16
+// fragment layout after every change.  A cube-map table of direction bins
+// records, per bin, the largest error of the network (as inference computes
+// it) against the exact quadrature on a grid of validation directions,
+// relative to the largest component of Phi there; bins above the tolerance
+// keep the exact quadrature.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <mutex>
 
 #include "internal.h"
 #include "mlp_eval.h"
@@ -87,50 +92,54 @@ __global__ void k_sumsq(const float* Y, int64_t n, double* part) {
   if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
-// C[M x N] (ldc) = op(A) op(B) (+ C if acc), row-major; op(A)[m][k] = TA ? A[k*lda+m] : A[m*lda+k].
-// blockIdx.z selects a K range of length kchunk (split-K); its result goes to
-// C + z * (M * ldc) when split (acc must then be 0).
+// C[M x N] (ldc) = alpha op(A) op(B), row-major, f32 in memory;
+// op(A)[m][k] = TA ? A[k*lda+m] : A[m*lda+k], op(B)[k][n] = TB ? B[n*ldb+k] :
+// B[k*ldb+n].  On the matrix cores: tiles of 64 x 64 per block of four waves
+// (each wave a 32 x 32 quarter, v_mfma_f32_32x32x16_f16), K in chunks of 32
+// staged in LDS as f16, f32 accumulation.  blockIdx.z selects a K range of
+// length kchunk (split-K); its result goes to C + z * (M * ldc).
+constexpr int kGemmKC = 32;
 template <bool TA, bool TB>
 __global__ void __launch_bounds__(256) k_gemm(int M, int N, int K, const float* A, int lda, const float* B, int ldb,
-                                              float* C, int ldc, int acc, int kchunk) {
-  __shared__ float As[16][64 + 1];
-  __shared__ float Bs[16][64 + 1];
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+                                              float* C, int ldc, float alpha, int kchunk) {
+  __shared__ _Float16 As[64][kGemmKC + 8];  // [m][k] (rows padded against bank conflicts)
+  __shared__ _Float16 Bs[64][kGemmKC + 8];  // [n][k]
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int wm = (wv >> 1) * 32, wn = (wv & 1) * 32;
   const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
   const int kb = blockIdx.z * kchunk, ke = min(K, kb + kchunk);
   C += (int64_t)blockIdx.z * M * ldc;
-  float c[4][4] = {};
-  for (int k0 = kb; k0 < ke; k0 += 16) {
-    for (int e = threadIdx.x; e < 16 * 64; e += 256) {
-      int kk = e / 64, mm = e % 64;
-      int gm = m0 + mm, gk = k0 + kk;
-      As[kk][mm] = (gm < M && gk < ke) ? (TA ? A[(int64_t)gk * lda + gm] : A[(int64_t)gm * lda + gk]) : 0.f;
-      int gn = n0 + mm;
-      Bs[kk][mm] = (gn < N && gk < ke) ? (TB ? B[(int64_t)gn * ldb + gk] : B[(int64_t)gk * ldb + gn]) : 0.f;
+  sur_f16v acc = {};
+  for (int k0 = kb; k0 < ke; k0 += kGemmKC) {
+    // reads run along the contiguous index of each operand
+    for (int e = threadIdx.x; e < 64 * kGemmKC; e += 256) {
+      const int i = TA ? e % 64 : e / kGemmKC, k = TA ? e / 64 : e % kGemmKC;
+      const int gm = m0 + i, gk = k0 + k;
+      As[i][k] = (_Float16)((gm < M && gk < ke) ? (TA ? A[(int64_t)gk * lda + gm] : A[(int64_t)gm * lda + gk]) : 0.f);
+    }
+    for (int e = threadIdx.x; e < 64 * kGemmKC; e += 256) {
+      const int j = TB ? e / kGemmKC : e % 64, k = TB ? e % kGemmKC : e / 64;
+      const int gn = n0 + j, gk = k0 + k;
+      Bs[j][k] = (_Float16)((gn < N && gk < ke) ? (TB ? B[(int64_t)gn * ldb + gk] : B[(int64_t)gk * ldb + gn]) : 0.f);
     }
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      float a[4], b[4];
+    for (int kk = 0; kk < kGemmKC; kk += 16) {
+      sur_h8 av, bv;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[kk][ty * 4 + i], b[i] = Bs[kk][tx * 4 + i];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) c[i][j] += a[i] * b[j];
+      for (int e = 0; e < 8; ++e) {
+        av[e] = As[wm + (lane & 31)][kk + 8 * (lane >> 5) + e];
+        bv[e] = Bs[wn + (lane & 31)][kk + 8 * (lane >> 5) + e];
+      }
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, bv, acc, 0, 0, 0);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      int gm = m0 + ty * 4 + i, gn = n0 + tx * 4 + j;
-      if (gm < M && gn < N) {
-        float* p = C + (int64_t)gm * ldc + gn;
-        *p = acc ? *p + c[i][j] : c[i][j];
-      }
-    }
+  for (int r = 0; r < 16; ++r) {
+    const int gm = m0 + wm + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3), gn = n0 + wn + (lane & 31);
+    if (gm < M && gn < N) C[(int64_t)gm * ldc + gn] = alpha * acc[r];
+  }
 }
 
 // Z += b (per column); A = SiLU(Z) when act, else A = Z.
@@ -142,14 +151,16 @@ __global__ void k_bias_act(float* Z, const float* b, int64_t rows, int cols, flo
   A[i] = act ? z / (1.f + expf(-z)) : z;
 }
 
-// dY = 2 (Yp - Y) / (rows*cols); per-block partial sums of the squared error.
-__global__ void k_mse(const float* Yp, const float* Y, int64_t n, float scale, float* dY, double* part) {
+// dY = 2 (Yp - Y) (the 1 / (rows*cols) of the mean is applied to the
+// gradients at the end, so the backward operands stay in f16's normal
+// range); per-block partial sums of the squared error.
+__global__ void k_mse(const float* Yp, const float* Y, int64_t n, float* dY, double* part) {
   __shared__ double sh[256];
   int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   double e = 0.0;
   if (i < n) {
     float d = Yp[i] - Y[i];
-    dY[i] = 2.f * d * scale;
+    dY[i] = 2.f * d;
     e = (double)d * d;
   }
   sh[threadIdx.x] = e;
@@ -169,8 +180,8 @@ __global__ void k_silu_back(const float* dA, const float* Z, int64_t n, float* d
   dZ[i] = dA[i] * s * (1.f + z * (1.f - s));
 }
 
-// db[j] = sum_i dZ[i][j]: one block per column, fixed-order tree reduction
-__global__ void k_colsum(const float* dZ, int rows, int cols, float* db) {
+// db[j] = alpha sum_i dZ[i][j]: one block per column, fixed-order tree reduction
+__global__ void k_colsum(const float* dZ, int rows, int cols, float alpha, float* db) {
   __shared__ float sh[256];
   const int j = blockIdx.x;
   float s = 0.f;
@@ -181,7 +192,7 @@ __global__ void k_colsum(const float* dZ, int rows, int cols, float* db) {
     if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) db[j] = sh[0];
+  if (threadIdx.x == 0) db[j] = alpha * sh[0];
 }
 
 // C[i] = sum over the S split-K partials (fixed order)
@@ -221,10 +232,58 @@ __global__ void k_init_params(float* w, SurLayout L, uint64_t seed) {
   w[i] = (float)((2.0 * u - 1.0) * lim);
 }
 
-// Validation on the cube map: bin b = (face, i, j); nsub x nsub directions per
-// bin; err[b] = max over them of |y_net - y_exact|_inf / |c44 Phi_exact|_inf.
-__global__ void k_gate(const float* w, SurLayout L, SurFeat ft, int bins, int nsub, Med<double> m, float yscale,
-                       float* err) {
+// f32 master parameters -> the f16 fragment layout of the wave-level
+// inference (mlp_eval.h) and its f32 biases.  One thread per f16 value.
+__global__ void k_pack_inference(const float* w, SurLayout L, uint16_t* wi, float* bi) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < kSurInfBias) {
+    const int layer = i < 4 * kSurHidden ? i / kSurHidden : 4, m = i < 4 * kSurHidden ? i % kSurHidden : i - 4 * kSurHidden;
+    bi[i] = m < L.dout[layer] ? w[L.off[layer] + (int64_t)L.dout[layer] * L.din[layer] + m] : 0.f;
+  }
+  if (i >= kSurInfHalves) return;
+  int layer = 4;
+  for (int l = 1; l <= 4; ++l)
+    if (i < sur_frag_base(l)) {
+      layer = l - 1;
+      break;
+    }
+  const int steps = layer == 0 ? 1 : 8;
+  const int local = i - sur_frag_base(layer);
+  const int e = local % 8, lane = (local / 8) % 64, ts = local / kSurFrag;
+  const int t = ts / steps, c = ts % steps, h = lane >> 5;
+  const int m = 32 * t + (lane & 31);
+  const int k = layer == 0 ? 8 * h + e : sur_in_feature(c, h, e);
+  float v = 0.f;
+  if (m < L.dout[layer] && k < L.din[layer]) v = w[L.off[layer] + (int64_t)m * L.din[layer] + k];
+  const _Float16 hv = (_Float16)v;
+  wi[i] = __builtin_bit_cast(uint16_t, hv);
+}
+
+// Network outputs Y[n][18] for rows X[n][6] by the wave-level inference,
+// weights staged in LDS once per block; each wave takes 64 rows at a time.
+__global__ void __launch_bounds__(512) k_sur_infer(SurDev sd, const float* X, int64_t n, float* Y) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  sur_stage(sd, lds);
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int64_t nw = blockDim.x / 64;
+  const int64_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+  for (int64_t base = ((int64_t)blockIdx.x * nw + wave) * 64; base < n; base += (int64_t)gridDim.x * nw * 64) {
+    const int64_t i = base + lane;
+    float x[6] = {1.f, 0.f, 0.f, 0.f, 0.f, 0.f}, y[18];
+    if (i < n)
+#pragma unroll
+      for (int k = 0; k < 6; ++k) x[k] = X[i * 6 + k];
+    sur_wave_eval(lds, x, y);
+    if (i < n)
+#pragma unroll
+      for (int k = 0; k < 18; ++k) Y[i * 18 + k] = y[k];
+  }
+}
+
+// Validation directions of the cube map: bin b = (face, i, j), nsub x nsub
+// directions per bin.  Writes the network's input rows and the exact target.
+__global__ void k_gate_dirs(SurFeat ft, int bins, int nsub, Med<double> m, float* X, double* Yex, double* pmax) {
   int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t nbins = 6LL * bins * bins;
   if (idx >= nbins * nsub * nsub) return;
@@ -241,24 +300,28 @@ __global__ void k_gate(const float* w, SurLayout L, SurFeat ft, int bins, int ns
   T[(ax + 2) % 3] = v;
   double nn = 1.0 / sqrt(T[0] * T[0] + T[1] * T[1] + T[2] * T[2]);
   for (int d = 0; d < 3; ++d) T[d] *= nn;
-  double y[18], pm;
-  exact_residual(T, m, y, &pm);
-  float x[6] = {(float)T[0], (float)T[1], (float)T[2], ft.f[0], ft.f[1], ft.f[2]};
-  float yn[18];
-  float h[2 * kSurHidden];
-  mlp_eval<1>(w, L, x, yn, h);
-  double e = 0.0;
-  for (int c = 0; c < 18; ++c) e = fmax(e, fabs((double)yn[c] * yscale - y[c]));
-  err[idx] = (float)(e / pm);
+  exact_residual(T, m, Yex + idx * 18, pmax + idx);
+  float* x = X + idx * 6;
+  for (int d = 0; d < 3; ++d) x[d] = (float)T[d];
+  x[3] = ft.f[0];
+  x[4] = ft.f[1];
+  x[5] = ft.f[2];
 }
 
-__global__ void k_gate_reduce(const float* err, int64_t nbins, int nsub2, float tol, unsigned char* mask,
-                              float* binerr) {
+// err[b] = max over a bin's directions of |y_net - y_exact|_inf / |c44 Phi|_inf;
+// mask[b] = err[b] <= tol.
+__global__ void k_gate_reduce(const float* Yn, const double* Yex, const double* pmax, float yscale, int64_t nbins,
+                              int nsub2, float tol, unsigned char* mask, float* binerr) {
   int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nbins) return;
-  float e = 0.f;
-  for (int s = 0; s < nsub2; ++s) e = fmaxf(e, err[b * nsub2 + s]);
-  binerr[b] = e;
+  double e = 0.0;
+  for (int s = 0; s < nsub2; ++s) {
+    const int64_t r = b * nsub2 + s;
+    double es = 0.0;
+    for (int c = 0; c < 18; ++c) es = fmax(es, fabs((double)Yn[r * 18 + c] * yscale - Yex[r * 18 + c]));
+    e = fmax(e, es / pmax[r]);
+  }
+  binerr[b] = (float)e;
   mask[b] = e <= tol ? 1 : 0;
 }
 
@@ -276,36 +339,34 @@ SurLayout sur_layout(int hidden) {
   return L;
 }
 
-// Split-K scratch for long reductions (weight gradients over the batch).
-static float* g_split = nullptr;
-static size_t g_split_n = 0;
-
-static int gemm(bool ta, bool tb, int M, int N, int K, const float* A, int lda, const float* B, int ldb, float* C,
-                int ldc, int acc, hipStream_t st) {
-  int S = 1;
+// Split-K scratch of the weight-gradient products (the plan's own buffer).
+static int gemm(Surrogate& S, bool ta, bool tb, int M, int N, int K, const float* A, int lda, const float* B,
+                int ldb, float* C, int ldc, float alpha, hipStream_t st) {
+  int Sp = 1;
   const int tiles = (int)(nb(N, 64) * nb(M, 64));
-  if (!acc && tiles < 64 && K >= 1024) S = std::min(32, K / 256);
-  const int kchunk = ((K + S - 1) / S + 15) / 16 * 16;
-  S = (K + kchunk - 1) / kchunk;
+  if (tiles < 64 && K >= 1024) Sp = std::min(32, K / 256);
+  const int kchunk = ((K + Sp - 1) / Sp + kGemmKC - 1) / kGemmKC * kGemmKC;
+  Sp = (K + kchunk - 1) / kchunk;
   float* out = C;
-  if (S > 1) {
-    size_t need = (size_t)S * M * ldc;
-    if (need > g_split_n) {
-      hipFree(g_split);
-      g_split = nullptr;
-      DFMM_HIP(hipMalloc(&g_split, sizeof(float) * need));
-      g_split_n = need;
+  if (Sp > 1) {
+    size_t need = (size_t)Sp * M * ldc;
+    if (need > S.split_n) {
+      hipFree(S.split);
+      S.split = nullptr;
+      S.split_n = 0;
+      DFMM_HIP(hipMalloc(&S.split, sizeof(float) * need));
+      S.split_n = need;
     }
-    out = g_split;
+    out = S.split;
   }
-  dim3 g(nb(N, 64), nb(M, 64), S);
-  if (!ta && !tb) k_gemm<false, false><<<g, 256, 0, st>>>(M, N, K, A, lda, B, ldb, out, ldc, acc, kchunk);
-  else if (!ta && tb) k_gemm<false, true><<<g, 256, 0, st>>>(M, N, K, A, lda, B, ldb, out, ldc, acc, kchunk);
-  else if (ta && !tb) k_gemm<true, false><<<g, 256, 0, st>>>(M, N, K, A, lda, B, ldb, out, ldc, acc, kchunk);
-  else k_gemm<true, true><<<g, 256, 0, st>>>(M, N, K, A, lda, B, ldb, out, ldc, acc, kchunk);
+  dim3 g(nb(N, 64), nb(M, 64), Sp);
+  if (!ta && !tb) k_gemm<false, false><<<g, 256, 0, st>>>(M, N, K, A, lda, B, ldb, out, ldc, alpha, kchunk);
+  else if (!ta && tb) k_gemm<false, true><<<g, 256, 0, st>>>(M, N, K, A, lda, B, ldb, out, ldc, alpha, kchunk);
+  else if (ta && !tb) k_gemm<true, false><<<g, 256, 0, st>>>(M, N, K, A, lda, B, ldb, out, ldc, alpha, kchunk);
+  else k_gemm<true, true><<<g, 256, 0, st>>>(M, N, K, A, lda, B, ldb, out, ldc, alpha, kchunk);
   DFMM_LAUNCH_CHECK();
-  if (S > 1) {
-    k_sum_parts<<<nb((int64_t)M * ldc, 256), 256, 0, st>>>(g_split, (int64_t)M * ldc, S, C);
+  if (Sp > 1) {
+    k_sum_parts<<<nb((int64_t)M * ldc, 256), 256, 0, st>>>(S.split, (int64_t)M * ldc, Sp, C);
     DFMM_LAUNCH_CHECK();
   }
   return DFMM_OK;
@@ -342,13 +403,14 @@ static void work_free(MlpWork& w) {
   hipFree(w.part);
 }
 
-// Forward of n rows of X (A[0] = X), output in w.A[kSurLayers].
-static int forward(const float* prm, const SurLayout& L, MlpWork& w, const float* X, int n, hipStream_t st) {
+// Training forward of n rows of X (A[0] = X), output in w.A[kSurLayers].
+static int forward(Surrogate& S, const float* prm, MlpWork& w, const float* X, int n, hipStream_t st) {
+  const SurLayout& L = S.L;
   w.A[0] = const_cast<float*>(X);
   for (int l = 0; l < kSurLayers; ++l) {
     const float* W = prm + L.off[l];
     const float* b = W + (int64_t)L.dout[l] * L.din[l];
-    int rc = gemm(false, true, n, L.dout[l], L.din[l], w.A[l], L.din[l], W, L.din[l], w.Z[l], L.dout[l], 0, st);
+    int rc = gemm(S, false, true, n, L.dout[l], L.din[l], w.A[l], L.din[l], W, L.din[l], w.Z[l], L.dout[l], 1.f, st);
     if (rc) return rc;
     k_bias_act<<<nb((int64_t)n * L.dout[l], 256), 256, 0, st>>>(w.Z[l], b, n, L.dout[l], w.A[l + 1],
                                                                  l + 1 < kSurLayers);
@@ -358,27 +420,29 @@ static int forward(const float* prm, const SurLayout& L, MlpWork& w, const float
 }
 
 // Loss (host, mean squared error over rows x 18) and gradient into grad.
-static int loss_grad(const float* prm, float* grad, const SurLayout& L, MlpWork& w, const float* X, const float* Y,
-                     int n, hipStream_t st, double* loss) {
-  int rc = forward(prm, L, w, X, n, st);
+static int loss_grad(Surrogate& S, const float* prm, float* grad, MlpWork& w, const float* X, const float* Y, int n,
+                     hipStream_t st, double* loss) {
+  const SurLayout& L = S.L;
+  int rc = forward(S, prm, w, X, n, st);
   if (rc) return rc;
   const int64_t no = (int64_t)n * 18;
   const unsigned nbk = nb(no, 256);
-  float* dY = w.dZ;  // [n][18]
-  k_mse<<<nbk, 256, 0, st>>>(w.A[kSurLayers], Y, no, 1.f / (float)no, dY, w.part);
+  const float inv = 1.f / (float)no;
+  float* dY = w.dZ;  // [n][18], carries 2 (Yp - Y); the 1/no is applied to the gradients
+  k_mse<<<nbk, 256, 0, st>>>(w.A[kSurLayers], Y, no, dY, w.part);
   DFMM_LAUNCH_CHECK();
   for (int l = kSurLayers - 1; l >= 0; --l) {
     float* gW = grad + L.off[l];
     float* gb = gW + (int64_t)L.dout[l] * L.din[l];
     const float* W = prm + L.off[l];
     // dW = dZ^T A_l ; db = colsum(dZ)
-    if ((rc = gemm(true, false, L.dout[l], L.din[l], n, w.dZ, L.dout[l], w.A[l], L.din[l], gW, L.din[l], 0, st)))
+    if ((rc = gemm(S, true, false, L.dout[l], L.din[l], n, w.dZ, L.dout[l], w.A[l], L.din[l], gW, L.din[l], inv, st)))
       return rc;
-    k_colsum<<<L.dout[l], 256, 0, st>>>(w.dZ, n, L.dout[l], gb);
+    k_colsum<<<L.dout[l], 256, 0, st>>>(w.dZ, n, L.dout[l], inv, gb);
     DFMM_LAUNCH_CHECK();
     if (l > 0) {
       // dA_l = dZ W ; dZ_{l-1} = dA_l * SiLU'(Z_{l-1})
-      if ((rc = gemm(false, false, n, L.din[l], L.dout[l], w.dZ, L.dout[l], W, L.din[l], w.dA, L.din[l], 0, st)))
+      if ((rc = gemm(S, false, false, n, L.din[l], L.dout[l], w.dZ, L.dout[l], W, L.din[l], w.dA, L.din[l], 1.f, st)))
         return rc;
       k_silu_back<<<nb((int64_t)n * L.din[l], 256), 256, 0, st>>>(w.dA, w.Z[l - 1], (int64_t)n * L.din[l], w.dZ);
       DFMM_LAUNCH_CHECK();
@@ -391,6 +455,39 @@ static int loss_grad(const float* prm, float* grad, const SurLayout& L, MlpWork&
     for (double x : h) s += x;
     *loss = s / (double)no;
   }
+  return DFMM_OK;
+}
+
+// The inference copy of the current master weights.
+int surrogate_pack(dfmm_plan* pl, hipStream_t st) {
+  Surrogate& S = pl->sur;
+  if (!S.wi) {
+    DFMM_HIP(hipMalloc(&S.wi, sizeof(uint16_t) * kSurInfHalves));
+    DFMM_HIP(hipMalloc(&S.bi, sizeof(float) * kSurInfBias));
+  }
+  k_pack_inference<<<nb(kSurInfHalves, 256), 256, 0, st>>>(S.w, S.L, S.wi, S.bi);
+  DFMM_LAUNCH_CHECK();
+  return DFMM_OK;
+}
+
+// Blocks of the persistent inference kernels: one per CU (the weights take
+// 110 KB of its LDS).
+int sur_grid(int device) {
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || ncu <= 0) ncu = 256;
+  return ncu;
+}
+
+int surrogate_infer(const dfmm_plan* pl, const float* X, int64_t n, float* Y, hipStream_t st) {
+  static std::once_flag once;
+  std::call_once(once, [] {
+    hipFuncSetAttribute((const void*)k_sur_infer, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSurInfLds);
+  });
+  SurDev sd = sur_dev(pl);
+  const int64_t waves = (n + 63) / 64;
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(sur_grid(pl->device), (waves + 7) / 8));
+  k_sur_infer<<<grid, 512, kSurInfLds, st>>>(sd, X, n, Y);
+  DFMM_LAUNCH_CHECK();
   return DFMM_OK;
 }
 
@@ -412,7 +509,66 @@ int surrogate_alloc(dfmm_plan* pl, uint64_t seed, hipStream_t st) {
   DFMM_LAUNCH_CHECK();
   DFMM_HIP(hipMemsetAsync(S.m, 0, sizeof(float) * P, st));
   DFMM_HIP(hipMemsetAsync(S.v, 0, sizeof(float) * P, st));
+  int rc = surrogate_pack(pl, st);
+  if (rc) return rc;
   DFMM_HIP(hipStreamSynchronize(st));
+  return DFMM_OK;
+}
+
+// Residual gate of the current weights: bins of bins x bins per cube face,
+// nsub x nsub validation directions per bin.
+int surrogate_gate(dfmm_plan* pl, int bins, double tol, hipStream_t st) {
+  Surrogate& S = pl->sur;
+  const int64_t nbins = 6LL * bins * bins;
+  const int nsub = 3;
+  const int64_t nd = nbins * nsub * nsub;
+  float *X = nullptr, *Yn = nullptr, *binerr = nullptr;
+  double *Yex = nullptr, *pmax = nullptr;
+  int rc = DFMM_OK;
+  if (hipMalloc(&X, sizeof(float) * 6 * nd) != hipSuccess || hipMalloc(&Yn, sizeof(float) * 18 * nd) != hipSuccess ||
+      hipMalloc(&Yex, sizeof(double) * 18 * nd) != hipSuccess || hipMalloc(&pmax, sizeof(double) * nd) != hipSuccess ||
+      hipMalloc(&binerr, sizeof(float) * nbins) != hipSuccess) {
+    set_error("surrogate: cannot allocate the gate's scratch");
+    rc = DFMM_E_NOMEM;
+  }
+  if (rc == DFMM_OK) {
+    hipFree(S.mask);
+    S.mask = nullptr;
+    if (hipMalloc(&S.mask, nbins) != hipSuccess) {
+      set_error("surrogate: cannot allocate the gate");
+      rc = DFMM_E_NOMEM;
+    }
+  }
+  std::vector<float> hb(nbins);
+  if (rc == DFMM_OK) {
+    S.bins = bins;
+    S.tol = tol;
+    k_gate_dirs<<<nb(nd, 64), 64, 0, st>>>(S.ft, bins, nsub, pl->med<double>(), X, Yex, pmax);
+    rc = hipGetLastError() == hipSuccess ? DFMM_OK : DFMM_E_HIP;
+    if (rc == DFMM_OK) rc = surrogate_infer(pl, X, nd, Yn, st);
+    if (rc == DFMM_OK) {
+      k_gate_reduce<<<nb(nbins, 256), 256, 0, st>>>(Yn, Yex, pmax, S.yscale, nbins, nsub * nsub, (float)tol, S.mask,
+                                                    binerr);
+      rc = hipGetLastError() == hipSuccess ? DFMM_OK : DFMM_E_HIP;
+    }
+    if (rc == DFMM_OK && (hipMemcpyAsync(hb.data(), binerr, sizeof(float) * nbins, hipMemcpyDeviceToHost, st) != hipSuccess ||
+                          hipStreamSynchronize(st) != hipSuccess))
+      rc = DFMM_E_HIP;
+    if (rc == DFMM_E_HIP) set_error("surrogate: gate kernels failed");
+  }
+  hipFree(X);
+  hipFree(Yn);
+  hipFree(Yex);
+  hipFree(pmax);
+  hipFree(binerr);
+  if (rc) return rc;
+  int64_t pass = 0;
+  for (float e : hb) pass += e <= tol;
+  std::vector<float> sorted(hb);
+  std::sort(sorted.begin(), sorted.end());
+  S.pass_frac = (double)pass / nbins;
+  S.max_err = sorted.back();
+  S.med_err = sorted[nbins / 2];
   return DFMM_OK;
 }
 
@@ -467,7 +623,7 @@ int surrogate_train(dfmm_plan* pl, const dfmm_surrogate_cfg& cfg, hipStream_t st
       int64_t row = ((k + (int64_t)ep * 7919) % steps_per_epoch) * cfg.batch;
       bool want = (k == steps_per_epoch - 1);
       double l = 0;
-      rc = loss_grad(S.w, S.g, S.L, w, X + row * 6, Y + row * 18, cfg.batch, st, want ? &l : nullptr);
+      rc = loss_grad(S, S.w, S.g, w, X + row * 6, Y + row * 18, cfg.batch, st, want ? &l : nullptr);
       if (rc) break;
       double frac = (double)step / (double)std::max<int64_t>(1, total - 1);
       float lr = (float)(cfg.lr * (0.01 + 0.99 * 0.5 * (1.0 + std::cos(M_PI * frac))));
@@ -482,31 +638,8 @@ int surrogate_train(dfmm_plan* pl, const dfmm_surrogate_cfg& cfg, hipStream_t st
   hipFree(X);
   hipFree(Y);
   if (rc) return rc;
-  // residual gate on the cube map
-  S.bins = cfg.bins;
-  S.tol = cfg.tol;
-  const int64_t nbins = 6LL * cfg.bins * cfg.bins;
-  const int nsub = 3;
-  float *err = nullptr, *binerr = nullptr;
-  DFMM_HIP(hipMalloc(&err, sizeof(float) * nbins * nsub * nsub));
-  DFMM_HIP(hipMalloc(&binerr, sizeof(float) * nbins));
-  hipFree(S.mask);
-  DFMM_HIP(hipMalloc(&S.mask, nbins));
-  k_gate<<<nb(nbins * nsub * nsub, 64), 64, 0, st>>>(S.w, S.L, S.ft, cfg.bins, nsub, m, S.yscale, err);
-  DFMM_LAUNCH_CHECK();
-  k_gate_reduce<<<nb(nbins, 256), 256, 0, st>>>(err, nbins, nsub * nsub, (float)cfg.tol, S.mask, binerr);
-  DFMM_LAUNCH_CHECK();
-  std::vector<float> hb(nbins);
-  DFMM_D2H(hb.data(), binerr, sizeof(float) * nbins, st);
-  hipFree(err);
-  hipFree(binerr);
-  int64_t pass = 0;
-  for (float e : hb) pass += e <= cfg.tol;
-  std::vector<float> sorted(hb);
-  std::sort(sorted.begin(), sorted.end());
-  S.pass_frac = (double)pass / nbins;
-  S.max_err = sorted.back();
-  S.med_err = sorted[nbins / 2];
+  if ((rc = surrogate_pack(pl, st))) return rc;
+  if ((rc = surrogate_gate(pl, cfg.bins, cfg.tol, st))) return rc;
   S.n_samples = n;
   S.epochs = cfg.epochs;
   S.trained = 1;
@@ -515,30 +648,24 @@ int surrogate_train(dfmm_plan* pl, const dfmm_surrogate_cfg& cfg, hipStream_t st
 }
 
 // Test hooks: loss and gradient of the current weights on rows (X, Y) given
-// on the device, and network outputs for rows X.
+// on the device (the training path), and the network outputs for rows X
+// (the inference path the kernels use).
 int surrogate_loss_grad(dfmm_plan* pl, const float* X, const float* Y, int64_t n, float* grad, double* loss,
                         hipStream_t st) {
   Surrogate& S = pl->sur;
   MlpWork w;
   int rc = work_alloc(w, S.L, (int)n);
-  if (rc == DFMM_OK) rc = loss_grad(S.w, grad, S.L, w, X, Y, (int)n, st, loss);
+  if (rc == DFMM_OK) rc = loss_grad(S, S.w, grad, w, X, Y, (int)n, st, loss);
   hipStreamSynchronize(st);
   work_free(w);
   return rc;
 }
 
 int surrogate_forward(const dfmm_plan* pl, const float* X, int64_t n, float* Yout, hipStream_t st) {
-  const Surrogate& S = pl->sur;
-  MlpWork w;
-  int rc = work_alloc(w, S.L, (int)n);
-  if (rc == DFMM_OK) rc = forward(S.w, S.L, w, X, (int)n, st);
-  if (rc == DFMM_OK)
-    rc = hipMemcpyAsync(Yout, w.A[kSurLayers], sizeof(float) * 18 * n, hipMemcpyDeviceToDevice, st) == hipSuccess
-             ? DFMM_OK
-             : DFMM_E_HIP;
-  hipStreamSynchronize(st);
-  work_free(w);
-  return rc;
+  int rc = surrogate_infer(pl, X, n, Yout, st);
+  if (rc) return rc;
+  DFMM_HIP(hipStreamSynchronize(st));
+  return DFMM_OK;
 }
 
 }  // namespace dfmm
