@@ -125,6 +125,26 @@ int dfmm_direct_forces(const dfmm_plan* plan, const double* seg, const double* b
                        int64_t n_seg, const int64_t* targets, int64_t n_targets,
                        double* forces, int fp32, void* stream);
 
+/* dfmm_direct_forces without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same sum, arguments and results as dfmm_direct_forces;
+ * its scratch (sorted points, per-chunk partial stresses, per-point stress)
+ * lives in a fixed array of DFMM_NOALLOC_SCRATCH_BYTES in the library, one
+ * copy per GPU, held until the process ends.  Calls that overlap on one GPU
+ * (other streams, other threads) race on that array and must not be made.
+ * With targets != NULL the indices are checked first, which synchronises
+ * the stream; otherwise the call is asynchronous.  Errors: DFMM_E_ARG (also
+ * when the sizes need more scratch than the array holds: about 72 bytes per
+ * quadrature point plus 48 per target point and source chunk; 60,000
+ * segments with all of them as targets fit), DFMM_E_HIP. */
+#define DFMM_NOALLOC_SCRATCH_BYTES (64ll << 20)
+int dfmm_direct_forces_noalloc(const dfmm_plan* plan, const double* seg, const double* burgers,
+                               int64_t n_seg, const int64_t* targets, int64_t n_targets,
+                               double* forces, int fp32, void* stream);
+/* Scratch bytes dfmm_direct_forces_noalloc needs for these sizes (0 on bad
+ * arguments). */
+size_t dfmm_direct_noalloc_bytes(const dfmm_plan* plan, int64_t n_seg, int64_t n_targets);
+
 /* Per-stage timing of dfmm_fmm_forces with HIP events on its stream.
  * on = 1 starts recording (resetting the accumulators), 0 stops.  While
  * on, every dfmm_fmm_forces call records events around each stage.

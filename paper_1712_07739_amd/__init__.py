@@ -29,9 +29,10 @@ ENTRY_POINTS = (
     "dfmm_surrogate_info", "dfmm_surrogate_get_params", "dfmm_surrogate_set_params",
     "dfmm_surrogate_loss_grad", "dfmm_surrogate_forward", "dfmm_batch_create", "dfmm_batch_run",
     "dfmm_batch_latencies", "dfmm_batch_destroy", "dfmm_autotune_depth",
-    "dfmm_surrogate_get_gate",
+    "dfmm_direct_forces_noalloc", "dfmm_direct_noalloc_bytes", "dfmm_surrogate_get_gate",
     "dfmm_surrogate_save", "dfmm_surrogate_load",
 )
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 class Params(ctypes.Structure):
@@ -79,6 +80,9 @@ def lib():
     L.dfmm_build_tree.argtypes = [vp, vp, i64, vp, pp]
     L.dfmm_fmm_forces.argtypes = [vp, vp, vp, vp, vp, vp]
     L.dfmm_direct_forces.argtypes = [vp, vp, vp, i64, vp, i64, vp, i32, vp]
+    L.dfmm_direct_forces_noalloc.argtypes = [vp, vp, vp, i64, vp, i64, vp, i32, vp]
+    L.dfmm_direct_noalloc_bytes.argtypes = [vp, i64, i64]
+    L.dfmm_direct_noalloc_bytes.restype = ctypes.c_size_t
     L.dfmm_tree_set_timing.argtypes = [vp, i32]
     L.dfmm_tree_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)]
     L.dfmm_plan_info.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t]
@@ -308,8 +312,11 @@ def fmm_forces(plan: Plan, tree: Tree, seg, burgers, out=None, stream=None):
     return out
 
 
-def direct_forces(plan: Plan, seg, burgers, targets=None, fp32=False, out=None, stream=None):
-    """Direct O(N^2) end-point forces on `targets` (int64 GPU tensor, or all)."""
+def direct_forces(plan: Plan, seg, burgers, targets=None, fp32=False, out=None, stream=None, noalloc=False):
+    """Direct O(N^2) end-point forces on `targets` (int64 GPU tensor, or all).
+
+    noalloc=True calls dfmm_direct_forces_noalloc (scratch in the library's
+    fixed per-GPU array; `out` should then be given by the caller)."""
     import torch
 
     n = int(seg.shape[0])
@@ -324,10 +331,15 @@ def direct_forces(plan: Plan, seg, burgers, targets=None, fp32=False, out=None, 
         nt, tptr = int(targets.numel()), ctypes.c_void_p(targets.data_ptr())
     if out is None:
         out = torch.empty((nt, 2, 3), dtype=torch.float64, device=seg.device)
-    fn = lib().dfmm_direct_forces
+    fn = lib().dfmm_direct_forces_noalloc if noalloc else lib().dfmm_direct_forces
     _check(fn(plan.handle, ctypes.c_void_p(seg.data_ptr()), ctypes.c_void_p(burgers.data_ptr()), n, tptr, nt,
               ctypes.c_void_p(out.data_ptr()), 1 if fp32 else 0, _stream(stream)))
     return out
+
+
+def direct_noalloc_bytes(plan: Plan, n_seg, n_targets):
+    """Scratch bytes dfmm_direct_forces_noalloc needs for these sizes."""
+    return int(lib().dfmm_direct_noalloc_bytes(plan.handle, int(n_seg), int(n_targets)))
 
 
 class Batch:

@@ -190,6 +190,25 @@ int dfmm_direct_forces(const dfmm_plan* plan, const double* seg, const double* b
                             (hipStream_t)stream);
 }
 
+int dfmm_direct_forces_noalloc(const dfmm_plan* plan, const double* seg, const double* burgers, int64_t n_seg,
+                               const int64_t* targets, int64_t n_targets, double* forces, int fp32, void* stream) {
+  if (!plan || !seg || !burgers || !forces || n_seg < 1 || n_targets < 1) {
+    set_error("direct_forces_noalloc: invalid argument");
+    return DFMM_E_ARG;
+  }
+  if (!targets && n_targets != n_seg) {
+    set_error("direct_forces_noalloc: without a target list n_targets must equal n_seg");
+    return DFMM_E_ARG;
+  }
+  return direct_forces_noalloc_impl(plan, seg, burgers, n_seg, targets, n_targets, forces, fp32 ? 1 : 0,
+                                    (hipStream_t)stream);
+}
+
+size_t dfmm_direct_noalloc_bytes(const dfmm_plan* plan, int64_t n_seg, int64_t n_targets) {
+  if (!plan || n_seg < 1 || n_targets < 1) return 0;
+  return direct_noalloc_bytes(plan, n_seg, n_targets);
+}
+
 int dfmm_tree_set_timing(dfmm_tree* t, int on) {
   if (!t) { set_error("tree_set_timing: null tree"); return DFMM_E_ARG; }
   t->timing = on ? 1 : 0;

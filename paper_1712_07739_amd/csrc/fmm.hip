@@ -1614,4 +1614,72 @@ int direct_forces_impl(const dfmm_plan* pl, const double* seg, const double* bur
   return rc;
 }
 
+// ------------------------------------------- direct sum without allocation
+// For callers that cannot allocate device memory (graph capture, tight
+// serving loops): the same direct sum with its scratch in this file-scope
+// array, one copy per GPU, held until the process ends.  Host code never
+// passes the array's name to a kernel (on the host it is a stand-in, not a
+// device address): the device address is looked up once per device with
+// hipGetSymbolAddress and used everywhere instead.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+static int scratch_ptr(void** out) {
+  int dev = 0;
+  DFMM_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_error("direct_forces_noalloc: device index beyond the supported range");
+    return DFMM_E_ARG;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      set_error(std::string("direct_forces_noalloc: hipGetSymbolAddress: ") + hipGetErrorString(e));
+      return DFMM_E_HIP;
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return DFMM_OK;
+}
+
+static size_t up256(size_t b) { return (b + 255) / 256 * 256; }
+
+size_t direct_noalloc_bytes(const dfmm_plan* pl, int64_t nseg, int64_t ntgt) {
+  const int nq = pl->quad.n;
+  const int64_t N = nseg * nq, ntp = ntgt * nq;
+  int64_t nchunk, chunk;
+  direct_chunks(N, ntp, &nchunk, &chunk);
+  return up256(sizeof(double) * 9 * N) + up256(sizeof(double) * 6 * ntp * nchunk) +
+         up256(sizeof(double) * 6 * ntp);
+}
+
+int direct_forces_noalloc_impl(const dfmm_plan* pl, const double* seg, const double* burg, int64_t nseg,
+                               const int64_t* targets, int64_t ntgt, double* forces, int fp32, hipStream_t st) {
+  const size_t need = direct_noalloc_bytes(pl, nseg, ntgt);
+  if (need > (size_t)kScratchBytes) {
+    set_error("direct_forces_noalloc: needs " + std::to_string(need) + " bytes of scratch, more than the " +
+              std::to_string((long long)kScratchBytes) + " it has (fewer segments or targets, or the allocating call)");
+    return DFMM_E_ARG;
+  }
+  void* base = nullptr;
+  int rc = scratch_ptr(&base);
+  if (rc) return rc;
+  const int nq = pl->quad.n;
+  const int64_t N = nseg * nq, ntp = ntgt * nq;
+  int64_t nchunk, chunk;
+  direct_chunks(N, ntp, &nchunk, &chunk);
+  unsigned char* b = (unsigned char*)base;
+  double* pts = (double*)b;
+  double* part = (double*)(b + up256(sizeof(double) * 9 * N));
+  double* sig = (double*)((unsigned char*)part + up256(sizeof(double) * 6 * ntp * nchunk));
+  return direct_core(pl, seg, burg, nseg, targets, ntgt, forces, fp32, st, pts, part, sig, (int*)sig, nchunk, chunk);
+}
+
 }  // namespace dfmm

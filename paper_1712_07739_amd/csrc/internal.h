@@ -24,6 +24,10 @@ inline int m2l_window(bool mixed) { return mixed ? kM2LWindowF : kM2LWindowD; }
 constexpr int kNumCanon = 158;    // one of each pair (o, -o): the kernel is odd, so the
                                   // spectrum of -o is minus the conjugate of that of o
 constexpr int kNumFar = 189;      // interaction-list size of an interior cell
+// Scratch of the allocation-free direct sum (one copy per GPU) and the
+// devices it supports.
+constexpr long long kScratchBytes = DFMM_NOALLOC_SCRATCH_BYTES;
+constexpr int kMaxDevices = 64;
 
 // Single-precision spectra are stored in the order in which the M2L Hadamard
 // kernel reads them.  Two lanes share a target; lane h owns stress rows
@@ -236,6 +240,9 @@ int fmm_forces_impl(const dfmm_plan* plan, dfmm_tree* t, const double* seg, cons
                     double* forces, hipStream_t st);
 int direct_forces_impl(const dfmm_plan* plan, const double* seg, const double* burg, int64_t nseg,
                        const int64_t* targets, int64_t ntgt, double* forces, int fp32, hipStream_t st);
+int direct_forces_noalloc_impl(const dfmm_plan* plan, const double* seg, const double* burg, int64_t nseg,
+                               const int64_t* targets, int64_t ntgt, double* forces, int fp32, hipStream_t st);
+size_t direct_noalloc_bytes(const dfmm_plan* plan, int64_t nseg, int64_t ntgt);
 
 }  // namespace dfmm
 
