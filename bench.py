@@ -74,6 +74,8 @@ def main():
                     help="interpolation order p (default: the smallest order meeting the 1e-4 bar, "
                          "7 for cubic1m; its configured p=6 measures 1.15e-4)")
     ap.add_argument("--depth", type=int, default=0, help="override the workload's leaf depth D")
+    ap.add_argument("--m2l-mode", default="sym", choices=["fft", "sym"],
+                    help="M2L operator store: 158 offset spectra (fft) or 16 symmetry classes (sym)")
     ap.add_argument("--err-sample", type=int, default=2000,
                     help="target segments checked against the GPU FP64 direct sum over all sources")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -123,7 +125,8 @@ def main():
 
     def make_plan(precision):
         p = pk.make_params(prm["order"], prm["depth"], prm["c11"], prm["c12"], prm["c44"], prm["core_a"],
-                           prm["box_lo"], prm["box_size"], precision=precision)
+                           prm["box_lo"], prm["box_size"], precision=precision,
+                           m2l_mode=pk.DFMM_M2L_FFT_SYM if args.m2l_mode == "sym" else pk.DFMM_M2L_FFT)
         return pk.Plan(p)
 
     t0 = time.perf_counter()
@@ -203,14 +206,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n_seg": ns, "order": prm["order"], "depth": prm["depth"],
                    "C": [prm["c11"], prm["c12"], prm["c44"]], "core_a": prm["core_a"],
-                   "precision": args.precision, "configured_order": configured_order},
+                   "precision": args.precision, "configured_order": configured_order, "m2l_mode": args.m2l_mode},
         "rel_err_vs_fp64_direct": err, "err_sample_segments": int(len(sub)),
         "stage_ms": {pk.STAGES[i]: stage_ms[i] / ncalls for i in range(pk.N_STAGES)},
         "stage_ms_note": "separate pass with HIP events around each stage, stages one by one (in the timed "
                          "region the near field runs on a second stream beside the far field)",
         "setup_s": setup_s, "build_tree_s": tree_s,
-        "plan": {k: info[k] for k in ("n_freq", "n_circle", "n_circle_float", "float_rule_err", "spectra_bytes")
-                 if k in info},
+        "plan": {k: info[k] for k in ("n_freq", "n_circle", "n_circle_float", "float_rule_err", "spectra_bytes",
+                                      "stored_offsets", "generator_fp64_bytes_per_level",
+                                      "mem_unif_fp64_bytes_per_level") if k in info},
         "surrogate": sur, "m2l_pairs": tinfo["m2l_pairs"],
         "near_pairs": tinfo["near_pairs"], "roofline": roof,
     }

@@ -58,6 +58,20 @@ typedef enum {
 } dfmm_status;
 
 enum { DFMM_FP64 = 0, DFMM_MIXED = 1 };
+/* M2L operator store (Eq. mem_unif and the symmetry reduction of Sec. 6):
+ * DFMM_M2L_FFT keeps the spectra of the 158 canonical offsets (one of each
+ * pair o, -o of the 316; the kernel is odd); DFMM_M2L_FFT_SYM keeps only the
+ * 16 offsets that represent the classes of the 316 under the 48 reflections
+ * and axis permutations of the cube (which leave a cubic or isotropic medium
+ * unchanged) and expands them in the M2L product: about a tenth of the
+ * memory and a quarter of the precompute's kernel evaluations. */
+enum { DFMM_M2L_FFT = 0, DFMM_M2L_FFT_SYM = 1 };
+/* Anisotropic kernel: DFMM_KERNEL_EXACT is the unit-circle quadrature;
+ * DFMM_KERNEL_SURROGATE trains the library's network at setup (default
+ * configuration, dfmm_surrogate_default_cfg) and uses it wherever its
+ * residual gate passes, the exact quadrature elsewhere (see the surrogate
+ * calls below).  Ignored for isotropic media (closed form). */
+enum { DFMM_KERNEL_EXACT = 0, DFMM_KERNEL_SURROGATE = 1 };
 
 typedef struct dfmm_plan dfmm_plan; /* medium, order, depth, M2L spectra        */
 typedef struct dfmm_tree dfmm_tree; /* sorted points, cells, lists, workspaces   */
@@ -81,16 +95,21 @@ typedef struct {
                          DFMM_MIXED: P2M..L2P and the near field in float with
                          float accumulation, near pairs closer than 2a in
                          double, far + near combined and forces in double     */
+  int m2l_mode;       /* DFMM_M2L_FFT or DFMM_M2L_FFT_SYM (operator store)       */
+  int aniso_kernel;   /* DFMM_KERNEL_EXACT or DFMM_KERNEL_SURROGATE              */
 } dfmm_params;
 
 /* Fill *p with defaults: order 5, depth 4, isotropic mu = 1, nu = 0.3,
- * a = 1e-3, root cube [-0.05, 1.05]^3, n_quad 3, n_circle 64, FP64. */
+ * a = 1e-3, root cube [-0.05, 1.05]^3, n_quad 3, n_circle 64, FP64,
+ * DFMM_M2L_FFT, DFMM_KERNEL_EXACT. */
 void dfmm_default_params(dfmm_params* p);
 
 /* Precompute a plan (Sec. 4.1, Eq. m2l and Theorem 1): for every level 2..D
- * the kernel on the lattice of node offsets, the 316 block-Toeplitz
- * generators and their DFTs.  The operators depend only on the kernel, not on
- * the segments, and are reused by every tree and every call.  Synchronous.
+ * the kernel on the lattice of node offsets, the block-Toeplitz generators
+ * of the stored offsets (158, or 16 with DFMM_M2L_FFT_SYM) and their DFTs;
+ * with DFMM_KERNEL_SURROGATE (cubic media) the network is trained first.
+ * The operators depend only on the kernel, not on the segments, and are
+ * reused by every tree and every call.  Synchronous.
  * Errors: DFMM_E_ARG for out-of-range parameters or a stiffness that is not
  * positive definite; DFMM_E_NOMEM; DFMM_E_HIP. */
 int dfmm_fmm_setup(const dfmm_params* prm, void* stream, dfmm_plan** out);

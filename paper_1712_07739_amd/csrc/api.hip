@@ -1,4 +1,5 @@
 // C ABI of libdfmm: argument checking, object lifetime, error reporting.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -52,6 +53,8 @@ void dfmm_default_params(dfmm_params* p) {
   p->n_quad = 3;
   p->n_circle = 64;
   p->precision = DFMM_FP64;
+  p->m2l_mode = DFMM_M2L_FFT;
+  p->aniso_kernel = DFMM_KERNEL_EXACT;
 }
 
 const char* dfmm_status_string(int s) {
@@ -95,6 +98,14 @@ int dfmm_fmm_setup(const dfmm_params* prm, void* stream, dfmm_plan** out) {
     set_error("fmm_setup: precision must be DFMM_FP64 or DFMM_MIXED");
     return DFMM_E_ARG;
   }
+  if (q.m2l_mode != DFMM_M2L_FFT && q.m2l_mode != DFMM_M2L_FFT_SYM) {
+    set_error("fmm_setup: m2l_mode must be DFMM_M2L_FFT or DFMM_M2L_FFT_SYM");
+    return DFMM_E_ARG;
+  }
+  if (q.aniso_kernel != DFMM_KERNEL_EXACT && q.aniso_kernel != DFMM_KERNEL_SURROGATE) {
+    set_error("fmm_setup: aniso_kernel must be DFMM_KERNEL_EXACT or DFMM_KERNEL_SURROGATE");
+    return DFMM_E_ARG;
+  }
   auto t0 = std::chrono::steady_clock::now();
   dfmm_plan* pl = new dfmm_plan();
   pl->prm = q;
@@ -103,6 +114,7 @@ int dfmm_fmm_setup(const dfmm_params* prm, void* stream, dfmm_plan** out) {
   pl->nf = pl->n * pl->n * q.order;
   pl->D = q.depth;
   pl->mixed = q.precision == DFMM_MIXED;
+  pl->sym = q.m2l_mode == DFMM_M2L_FFT_SYM;
   pl->iso = std::fabs(2.0 * q.c44 - (q.c11 - q.c12)) <= 1e-12 * std::fabs(q.c44);
   if (pl->iso) {
     pl->mu = q.c44;
@@ -116,6 +128,15 @@ int dfmm_fmm_setup(const dfmm_params* prm, void* stream, dfmm_plan** out) {
   gauss_legendre(q.n_quad, pl->quad.u, pl->quad.w);
   hipGetDevice(&pl->device);
   int rc = setup_tables(pl, (hipStream_t)stream);
+  if (rc == DFMM_OK && q.aniso_kernel == DFMM_KERNEL_SURROGATE && !pl->iso) {
+    dfmm_surrogate_cfg cfg;
+    dfmm_surrogate_default_cfg(&cfg);
+    rc = surrogate_train(pl, cfg, (hipStream_t)stream);
+    if (rc == DFMM_OK) {
+      pl->sur.in_use = 1;
+      rc = build_spectra(pl, (hipStream_t)stream);
+    }
+  }
   if (rc) {
     dfmm_plan_destroy(pl);
     return rc;
@@ -132,7 +153,7 @@ void dfmm_plan_destroy(dfmm_plan* pl) {
   for (auto& l : pl->lev) hipFree(l.khat);
   hipFree(pl->t64.S); hipFree(pl->t64.cs); hipFree(pl->t64.tw);
   hipFree(pl->t32.S); hipFree(pl->t32.cs); hipFree(pl->t32.tw);
-  hipFree(pl->oid343); hipFree(pl->off158);
+  hipFree(pl->oid343); hipFree(pl->off158); hipFree(pl->cls16); hipFree(pl->symtab);
   delete pl;
 }
 
@@ -166,6 +187,7 @@ void dfmm_tree_destroy(dfmm_tree* t) {
   }
   hipFree(t->cstart); hipFree(t->cpair); hipFree(t->cval); hipFree(t->part); hipFree(t->cuni); hipFree(t->bigp);
   hipFree(t->pts); hipFree(t->pleaf); hipFree(t->W); hipFree(t->s); hipFree(t->What); hipFree(t->Shat); hipFree(t->sig);
+  hipFree(t->kexp);
   delete t;
 }
 
@@ -430,10 +452,12 @@ int dfmm_plan_info(const dfmm_plan* pl, char* json, size_t cap) {
       json, cap,
       "{\"order\": %d, \"depth\": %d, \"n_fft\": %d, \"n_freq\": %d, \"isotropic\": %d, \"mixed\": %d, "
       "\"mu\": %.17g, \"nu\": %.17g, \"mem_unif_fp64_bytes_per_level\": %.0f, "
+      "\"m2l_mode\": %d, \"stored_offsets\": %d, \"generator_fp64_bytes_per_level\": %zu, "
       "\"spectra_bytes\": %zu, \"levels_stored\": %d, \"setup_ms\": %.3f, \"n_quad\": %d, \"n_circle\": %d, "
-      "\"n_circle_float\": %d, \"float_rule_err\": %.3g}",
-      p, pl->D, pl->n, pl->nf, pl->iso, pl->mixed, pl->mu, pl->nu, mem_unif, pl->khat_bytes, pl->D - 1,
-      pl->setup_ms, pl->quad.n, pl->prm.n_circle, 2 * pl->nhalf32, pl->float_rule_err);
+      "\"n_circle_float\": %d, \"float_rule_err\": %.3g, \"surrogate_in_use\": %d}",
+      p, pl->D, pl->n, pl->nf, pl->iso, pl->mixed, pl->mu, pl->nu, mem_unif, pl->sym,
+      pl->sym ? kNumSymClass : kNumCanon, pl->gen_bytes / (size_t)std::max(1, pl->D - 1), pl->khat_bytes, pl->D - 1,
+      pl->setup_ms, pl->quad.n, pl->prm.n_circle, 2 * pl->nhalf32, pl->float_rule_err, sur_dev(pl).on);
   if (w < 0 || (size_t)w >= cap) { set_error("plan_info: buffer too small"); return DFMM_E_ARG; }
   return DFMM_OK;
 }

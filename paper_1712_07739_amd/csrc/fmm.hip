@@ -331,6 +331,50 @@ constexpr size_t lds_fdft_t(int G, size_t es) {
 // neighbouring windows share sources in that XCD's L2.
 // The spectra take 73.3 KB of LDS per block, so two blocks (384 targets,
 // twelve waves each) share a CU: six waves per SIMD.
+// Symmetry-reduced store: one level's spectra of the 158 canonical offsets,
+// expanded from the 16 class spectra Kc [nf][16][54] into the layout the
+// Hadamard kernels read (float: slot order, kKOffsetF per offset; double:
+// row-major 6 x 9), in a workspace of the tree, before the level's product.
+// With o = R o_c,
+//   Khat_o(f)[a b w r] = det(R) s_a s_b s_w s_r Khat_{o_c}(R^T f)[pi(a) pi(b) pi(w) pi(r)],
+// where (R^T f)_{pi(i)} = s_i f_i (mod n) and the half spectrum supplies g
+// with g_3 >= p as the conjugate of -g.  One thread per (f, id, source
+// entry), so a wave's loads run along the class spectrum's rows.
+__device__ __constant__ const int kVoigtA[6] = {0, 1, 2, 1, 0, 0};
+__device__ __constant__ const int kVoigtB[6] = {0, 1, 2, 2, 2, 1};
+__device__ __constant__ const int kVoigtOf[9] = {0, 5, 4, 5, 1, 3, 4, 3, 2};
+template <typename T>
+__global__ void k_sym_expand(const cplx<T>* __restrict__ Kc, const SymEntry* __restrict__ symtab, int nf, int n,
+                             int p, cplx<T>* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)nf * kNumCanon * 54) return;
+  const int f = (int)(e / (kNumCanon * 54));
+  const int rem = (int)(e - (int64_t)f * kNumCanon * 54), id = rem / 54, src = rem - 54 * id;
+  const int fv[3] = {f / (n * p), (f / p) % n, f % p};
+  const SymEntry se = symtab[id];
+  int g[3], pinv[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const int t = se.sg[i] * fv[i];
+    g[se.pi[i]] = t < 0 ? t + n : t;
+    pinv[se.pi[i]] = i;
+  }
+  const bool cj = g[2] >= p;
+  if (cj)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) g[i] = g[i] == 0 ? 0 : n - g[i];
+  const int abs_ = src / 9, wrs = src - 9 * abs_;
+  const int a = pinv[kVoigtA[abs_]], b = pinv[kVoigtB[abs_]], w = pinv[wrs / 3], r = pinv[wrs % 3];
+  const int sgn = se.det * se.sg[a] * se.sg[b] * se.sg[w] * se.sg[r];
+  const cplx<T> x = Kc[((int64_t)((g[0] * n + g[1]) * p + g[2]) * kNumSymClass + se.cls) * 54 + src];
+  const cplx<T> v{sgn > 0 ? x.re : -x.re, (sgn > 0) != cj ? x.im : -x.im};
+  const int ab = kVoigtOf[3 * a + b], wr = w * 3 + r;
+  if (sizeof(T) == 4)
+    out[((int64_t)f * kNumCanon + id) * kKOffsetF + (ab / 3) * kKHalfF + (ab % 3) * 9 + had_slot_of(ab / 3, wr)] = v;
+  else
+    out[((int64_t)f * kNumCanon + id) * 54 + ab * 9 + wr] = v;
+}
+
 constexpr int kHadThreads = 2 * kM2LWindowF;
 static_assert(kM2LWindowF % kWaveTargets == 0 && 2 * kWaveTargets == 64,
               "a wave holds kWaveTargets targets, two lanes each");
@@ -1462,13 +1506,20 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
     const int nwin = (int)((Lv.n + wsz - 1) / wsz);
     const int remap = nwin >= 16;
     dim3 g(remap ? 8 * ((nwin + 7) / 8) : nwin, nf);
+    // symmetry-reduced store: this level's 158 offset spectra, expanded into
+    // the tree's workspace
+    const cplx<T>* kh = (const cplx<T>*)pl->lev[l].khat;
+    if (pl->sym) {
+      STAGE(3, (k_sym_expand<T><<<nblk((int64_t)nf * kNumCanon * 54, 256), 256, 0, st>>>(kh, pl->symtab, nf, n, p,
+                                                                                        (cplx<T>*)t->kexp)));
+      kh = (const cplx<T>*)t->kexp;
+    }
     if constexpr (std::is_same<T, float>::value)
       STAGE(3, (k_hadamard<<<g, kHadThreads, sizeof(cplx<float>) * kNumCanon * kKOffsetF, st>>>(
-                   What, (const cplx<float>*)pl->lev[l].khat, Lv.lenq, Lv.wbase, Lv.ilw, Lv.order, Lv.n, nf, nwin,
-                   remap, Shat)));
+                   What, kh, Lv.lenq, Lv.wbase, Lv.ilw, Lv.order, Lv.n, nf, nwin, remap, Shat)));
     else
       STAGE(3, (k_hadamard3<T><<<g, kHad3Threads, sizeof(cplx<T>) * kNumCanon * kKStride3, st>>>(
-                   What, (const cplx<T>*)pl->lev[l].khat, Lv.il_start, Lv.il, Lv.order, Lv.n, nf, nwin, remap, Shat)));
+                   What, kh, Lv.il_start, Lv.il, Lv.order, Lv.n, nf, nwin, remap, Shat)));
     STAGE(4, dft<T>(p, false, (unsigned)Lv.n, Shat, Lv.n, tb.tw, s + Lv.off * 6 * p3, st));
   }
   {
@@ -1493,7 +1544,6 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
     DFMM_HIP(hipEventRecord(t->done, st));
     t->done_set = true;
   }
-  (void)n;
   return tm.finish();
 }
 

@@ -106,9 +106,27 @@ struct Surrogate {
 };
 
 struct LevelTables {
-  void* khat = nullptr;  // DFT of the circulant embedding of each canonical offset's
-                         // generator: double [nf][158][54] complex (row-major 6 x 9);
-                         // float [nf][158][kKOffsetF] complex in slot order
+  void* khat = nullptr;  // DFT of the circulant embedding of each stored offset's
+                         // generator.  DFMM_M2L_FFT: the 158 canonical offsets,
+                         // double [nf][158][54] complex (row-major 6 x 9), float
+                         // [nf][158][kKOffsetF] complex in slot order.
+                         // DFMM_M2L_FFT_SYM: the 16 symmetry classes, [nf][16][54]
+                         // complex (row-major 6 x 9) in the plan's precision.
+};
+
+// Symmetry reduction of the M2L operators: the 316 offsets fall into 16
+// classes under the 48 signed permutations R of the axes (the cube's
+// symmetry group, which maps a cubic or isotropic medium onto itself).  The
+// kernel obeys K(R x) = det(R) rho(R) K(x) with rho(R) acting on each of its
+// four indices, so the spectrum of offset R o_c is
+//   Khat_{R o_c}(f)[a b w r] = det(R) s_a s_b s_w s_r Khat_{o_c}(R^T f)[pi(a) pi(b) pi(w) pi(r)]
+// with R_ij = s_i [j == pi(i)].  Per canonical id: class, pi, s and det(R).
+constexpr int kNumSymClass = 16;
+struct SymEntry {
+  int cls;
+  int pi[3];
+  int sg[3];
+  int det;
 };
 
 }  // namespace dfmm
@@ -126,6 +144,10 @@ struct dfmm_plan {
   dfmm::Tables<float> t32;
   int* oid343 = nullptr;   // device [343]: offset (o+3) lex index -> 2*canonical id + mirrored, or -1
   int* off158 = nullptr;   // device [158][3]: canonical id -> offset
+  int sym = 0;             // operator store: 0 = 158 offset spectra, 1 = 16 class spectra
+  int* cls16 = nullptr;    // device [16][3]: class representatives (|o| sorted, descending)
+  dfmm::SymEntry* symtab = nullptr;  // device [158]: class and R of each canonical id
+  size_t gen_bytes = 0;    // kernel values behind the stored spectra (real generators, FP64)
   std::vector<dfmm::LevelTables> lev;  // index = level (0..D); used for 2..D
   double setup_ms = 0;
   size_t khat_bytes = 0;
@@ -179,6 +201,8 @@ struct dfmm_tree {
   void* What = nullptr;     // [nf][max level cells][9] complex
   void* Shat = nullptr;     // [nf][max level cells][6] complex
   double* sig = nullptr;    // [N][6] stress at sorted points
+  void* kexp = nullptr;     // symmetry-reduced plans: one level's 158 offset spectra, expanded
+                            // from the 16 classes before that level's Hadamard product
   void* part = nullptr;     // cubic medium: [N][27][6] near-field partial (float or double) per
                             // neighbour slot (the symmetric near field)
   int* bigp = nullptr;      // leaf pairs with more than 64 points on a side, A * 14 + (q - 13)

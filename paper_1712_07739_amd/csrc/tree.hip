@@ -746,6 +746,11 @@ int build_tree_impl(dfmm_plan* pl, const double* seg, int64_t nseg, hipStream_t 
   DFMM_HIP(hipMalloc(&t->What, bWh));
   DFMM_HIP(hipMalloc(&t->Shat, bSh));
   DFMM_HIP(hipMalloc(&t->sig, sizeof(double) * 6 * N));
+  size_t bKx = 0;
+  if (pl->sym) {  // one level of expanded offset spectra (the plan keeps the 16 classes)
+    bKx = (size_t)pl->nf * kNumCanon * (pl->mixed ? kKOffsetF : 54) * 2 * es;
+    DFMM_HIP(hipMalloc(&t->kexp, bKx));
+  }
   const size_t part_es = pl->mixed ? sizeof(float) : sizeof(double);
   if (!pl->iso && t->max_leaf_pts <= (pl->mixed ? kSymMaxLeaf : kSymMaxLeafD)) {
     DFMM_HIP(hipMalloc(&t->part, part_es * 27 * 6 * N));
@@ -812,7 +817,7 @@ int build_tree_impl(dfmm_plan* pl, const double* seg, int64_t nseg, hipStream_t 
   t->bytes = sizeof(double) * 15 * N + sizeof(int) * N + bW + bS + bWh + bSh +
              (sizeof(int2) + 6 * sizeof(double)) * t->nclose + sizeof(int2) * t->nuni +
              (t->cstart ? sizeof(int) * (N + 1) : 0) +
-             (t->part ? part_es * 27 * 6 * N : 0) + sizeof(int) * t->nbig;
+             (t->part ? part_es * 27 * 6 * N : 0) + sizeof(int) * t->nbig + bKx;
   DFMM_HIP(hipStreamSynchronize(st));
   return DFMM_OK;
 }

@@ -294,3 +294,99 @@ def test_full_size_fmm_vs_oracle_samples(env, name, precision):
     err_p = oracle.rel_err(f[tgt], ref)
     print("%s p=%d precision=%d: rel err = %.3e" % (name, prm["order"], precision, err_p))
     assert err < err_p <= 3e-4
+
+
+# ----------------------------------------- symmetry-reduced operator store
+@pytest.mark.parametrize("name,C,nloops,p,D", [
+    ("iso-p4-D3", ISO, 20, 4, 3),
+    ("cubic-p5-D3", CUB, 10, 5, 3),
+    ("cubic-p7-D3", CUB, 6, 7, 3),
+    ("iso-p3-D5", ISO, 20, 3, 5),
+])
+def test_symmetry_reduced_operators_match_oracle_fmm(env, name, C, nloops, p, D):
+    """DFMM_M2L_FFT_SYM stores the spectra of the 16 class representatives
+    only and expands them in the Hadamard product (class, signed permutation
+    and det of each offset); the result is the same approximation as the
+    158-offset store and the oracle's dense M2L."""
+    torch, pk, dev = env
+    seg, b = synth.make_loops(nloops, 0.01, 0.05, 17)
+    ref_fmm = oracle.fmm_forces(seg, b, oracle.medium(*C, 1e-3), p, D, BOX_LO, BOX)
+    ts, tb = torch.tensor(seg, device=dev), torch.tensor(b, device=dev)
+    out = {}
+    for mode in (0, 1):
+        for prec in (0, 1):
+            prm = pk.make_params(p, D, *C, 1e-3, BOX_LO, BOX, precision=prec, m2l_mode=mode)
+            plan = pk.Plan(prm)
+            tree = pk.Tree(plan, ts)
+            out[mode, prec] = pk.fmm_forces(plan, tree, ts, tb).cpu().numpy()
+            info = plan.info()
+            assert info["m2l_mode"] == mode and info["stored_offsets"] == (16 if mode else 158)
+    assert oracle.rel_err(out[1, 0], ref_fmm) <= 1e-10, name
+    assert oracle.rel_err(out[1, 1], ref_fmm) <= 2e-5, name
+    # the same operators up to rounding: FP64 stores agree far below the bar
+    assert oracle.rel_err(out[1, 0], out[0, 0]) <= 1e-13, name
+    assert oracle.rel_err(out[1, 1], out[0, 1]) <= 2e-6, name
+
+
+def test_operator_memory_against_the_paper(env):
+    """Eq. mem_unif at p = 7 (the paper prints about 300 MB per level) and the
+    16-operator store's reduction by 316/16 (about 20x, Sec. 6), from the
+    plan's own accounting of the FP64 generators behind its spectra."""
+    torch, pk, dev = env
+    pn = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_numbers.json")))
+    D = 3
+    infos = {}
+    for mode in (0, 1):
+        plan = pk.Plan(pk.make_params(7, D, *CUB, 1e-3, BOX_LO, BOX, precision=0, m2l_mode=mode))
+        infos[mode] = plan.info()
+    mem = infos[0]["mem_unif_fp64_bytes_per_level"] / 1e6
+    assert abs(mem - pn["mem_unif_p7_MB"]["value"]) <= pn["mem_unif_p7_MB"]["rel_tol"] * pn["mem_unif_p7_MB"]["value"]
+    # the plan keeps one of each pair (o, -o): half of the 316 generators
+    assert infos[0]["generator_fp64_bytes_per_level"] * 2 == infos[0]["mem_unif_fp64_bytes_per_level"]
+    assert infos[1]["stored_offsets"] == pn["m2l_operators_with_symmetry"]["value"]
+    factor = infos[0]["mem_unif_fp64_bytes_per_level"] / infos[1]["generator_fp64_bytes_per_level"]
+    f = pn["symmetry_memory_factor"]
+    assert abs(factor - f["value"]) <= f["rel_tol"] * f["value"], factor
+    # the spectra actually held (half spectrum, complex): 158 -> 16 offsets
+    assert infos[0]["spectra_bytes"] * 16 == infos[1]["spectra_bytes"] * 158
+    print("operator memory per level at p=7: Eq. mem_unif %.1f MB, 16-class generators %.1f MB (x%.2f); "
+          "spectra held %.1f MB -> %.1f MB for %d levels"
+          % (mem, infos[1]["generator_fp64_bytes_per_level"] / 1e6, factor, infos[0]["spectra_bytes"] / 1e6,
+             infos[1]["spectra_bytes"] / 1e6, D - 1))
+
+
+def test_dense_tree_lists_have_the_paper_counts(env):
+    """All 8^l cells occupied (a point in every leaf): every cell's
+    interaction list is counted by brute force in the test, and interior
+    cells have the paper's 189 far cells and 27 neighbours (App. B)."""
+    torch, pk, dev = env
+    pn = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_numbers.json")))
+    D = 4
+    n = 2 ** D
+    h = BOX / n
+    c = (np.arange(n) + 0.5) * h + BOX_LO[0]
+    P = np.stack(np.meshgrid(c, c, c, indexing="ij"), -1).reshape(-1, 3)
+    seg = np.stack([P - 0.1 * h, P + 0.1 * h], axis=1)  # 3 points per leaf
+    prm = pk.make_params(3, D, *ISO, 1e-3, BOX_LO, BOX)
+    plan = pk.Plan(prm)
+    tree = pk.Tree(plan, torch.tensor(seg, device=dev))
+    info = tree.info()
+    for lv in info["levels"]:
+        l = lv["level"]
+        m = 2 ** l
+        idx = np.arange(m)
+        # per axis, the number of cells j with |i - j| >= 2 and |i/2 - j/2| <= 1
+        cnt = np.array([[1 if abs(i - j) >= 2 and abs(i // 2 - j // 2) <= 1 else 0 for j in idx] for i in idx])
+        near = np.array([[1 if abs(i - j) <= 1 else 0 for j in idx] for i in idx])
+        cand = np.array([[1 if abs(i // 2 - j // 2) <= 1 else 0 for j in idx] for i in idx])
+        # far = (parent neighbours' children) minus (own neighbours), in 3D
+        c1, nr = cand.sum(1), near.sum(1)
+        far = (np.einsum("i,j,k->ijk", c1, c1, c1) - np.einsum("i,j,k->ijk", nr, nr, nr))
+        assert lv["cells"] == m ** 3
+        assert lv["m2l_pairs"] == int(far.sum()), l
+        if m >= 8:  # interior cells
+            assert far[3, 3, 3] == pn["far_cells"]["value"]
+            assert nr[3] ** 3 == pn["near_cells"]["value"]
+    assert info["near_pairs"] == sum(
+        int(np.prod([min(i + 1, n - 1) - max(i - 1, 0) + 1 for i in cc])) * 3 * 3
+        for cc in np.ndindex(n, n, n))
