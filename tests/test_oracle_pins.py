@@ -297,3 +297,41 @@ def test_scaling_rotation_linearity():
     fc = oracle.direct_forces(seg, b, cub, targets=tgt)
     fcr = oracle.direct_forces(seg @ Rx.T, b @ Rx.T, cub, targets=tgt)
     assert np.allclose(fcr, fc @ Rx.T, rtol=1e-9, atol=1e-11 * np.abs(fc).max())
+
+
+# ------------------------------------------- cube symmetry of the kernel
+@pytest.mark.parametrize("C,a", [((1.0, 0.6, 0.5), 1e-3), (ISO, 0.0), (ISO, 2e-2)])
+def test_kernel_transforms_under_the_cube_group(C, a):
+    """The reading behind the symmetry-reduced M2L store (Sec. 6): for every
+    signed permutation R of the axes (48 elements, which leave a cubic or
+    isotropic stiffness unchanged), K(R x) = det(R) R.R.R.R K(x) on the
+    kernel's four indices (the det from the Levi-Civita symbol in Eq.
+    kernel).  Checked on the oracle's kernel at random points, and shown to
+    fail without the det for the improper elements."""
+    import itertools
+
+    VA, VB = (0, 1, 2, 1, 0, 0), (0, 1, 2, 2, 2, 1)
+
+    def full(K6):
+        F = np.zeros((3, 3, 3, 3))
+        for ab in range(6):
+            F[VA[ab], VB[ab]] = K6[ab]
+            F[VB[ab], VA[ab]] = K6[ab]
+        return F
+
+    med = oracle.medium(*C, a)
+    rng = np.random.default_rng(8)
+    for x in rng.normal(size=(3, 3)) * 0.05:
+        K = full(oracle.kernel_batch(x[None], med)[0].reshape(6, 3, 3))
+        scale = np.abs(K).max()
+        for perm in itertools.permutations(range(3)):
+            for sg in itertools.product((1, -1), repeat=3):
+                R = np.zeros((3, 3))
+                for i in range(3):
+                    R[i, perm[i]] = sg[i]
+                d = round(np.linalg.det(R))
+                KR = full(oracle.kernel_batch((R @ x)[None], med)[0].reshape(6, 3, 3))
+                T = np.einsum("ai,bj,wk,rl,ijkl->abwr", R, R, R, R, K)
+                assert np.abs(KR - d * T).max() <= 1e-12 * scale
+                if d < 0:
+                    assert np.abs(KR - T).max() > 1e-3 * scale
