@@ -25,18 +25,20 @@ PEAK_HBM = 8.0e12
 # Smallest interpolation order whose force error on the workload is <= 1e-4
 # (measured: cubic1m p=6 1.15e-4, p=7 3.0e-5 against the FP64 direct sum).
 BAR_ORDER = {"cubic1m": 7, "iso200k": 6, "cubic100k": 6}
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_hadamard_cubic1m_p7_traffic.json")
+def traffic_file(kernel):
+    return os.path.join(ROOT, "profiles", "%s_cubic1m_p7_traffic.json" % kernel)
 
 
-def hadamard_traffic(order):
-    """HBM bytes per step of the k_hadamard launches, from the committed
-    rocprofv3 FETCH_SIZE/WRITE_SIZE summary, if it was taken on the current
-    kernel source and the same order; else None."""
+def hadamard_traffic(order, kernel="k_hadamard", workload="cubic1m"):
+    """HBM bytes per step of the Hadamard kernel's launches, from the
+    committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary, if it was taken on the
+    current kernel source, the same workload and the same order; else None."""
     import hashlib
 
-    if not os.path.exists(TRAFFIC_FILE):
+    path = traffic_file(kernel)
+    if workload != "cubic1m" or not os.path.exists(path):
         return None
-    d = json.load(open(TRAFFIC_FILE))
+    d = json.load(open(path))
     src = open(os.path.join(ROOT, "paper_1712_07739_amd", "csrc", "fmm.hip"), "rb").read()
     if d.get("fmm_hip_sha256") != hashlib.sha256(src).hexdigest() or d.get("order") != order:
         return None
@@ -69,7 +71,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="cubic1m")
-    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--precision", default="mixed16", choices=["mixed", "mixed16", "fp64"],
+                    help="mixed: f32 evaluation; mixed16: f32 with f16 operands in the M2L product; fp64")
     ap.add_argument("--order", type=int, default=0,
                     help="interpolation order p (default: the smallest order meeting the 1e-4 bar, "
                          "7 for cubic1m; its configured p=6 measures 1.15e-4)")
@@ -121,7 +124,7 @@ def main():
         prm["depth"] = args.depth
     ns = seg.shape[0]
     log("workload %s: %d segments" % (args.workload, ns))
-    prec = pk.DFMM_MIXED if args.precision == "mixed" else pk.DFMM_FP64
+    prec = {"mixed": pk.DFMM_MIXED, "mixed16": pk.DFMM_MIXED_F16, "fp64": pk.DFMM_FP64}[args.precision]
 
     def make_plan(precision):
         p = pk.make_params(prm["order"], prm["depth"], prm["c11"], prm["c12"], prm["c44"], prm["core_a"],
@@ -137,7 +140,7 @@ def main():
     log("setup %.2f s %s" % (setup_s, info))
     sur = None
     cubic = abs(2 * prm["c44"] - (prm["c11"] - prm["c12"])) > 1e-12
-    if cubic and prec == pk.DFMM_MIXED and not args.no_surrogate:
+    if cubic and prec != pk.DFMM_FP64 and not args.no_surrogate:
         # the learned surrogate of the anisotropic kernel: 2M samples, residual gate 1e-5,
         # the exact quadrature wherever a direction bin fails the gate
         t0 = time.perf_counter()
@@ -195,14 +198,18 @@ def main():
     had_flops = hadamard_flops(tinfo, nf)
     had_ms = stage_ms[3] / ncalls
     achieved = had_flops / (had_ms * 1e-3)
-    peak = PEAK_FP32_VALU if prec == pk.DFMM_MIXED else PEAK_FP64_VALU
-    roof = {"kernel": "k_hadamard (M2L in frequency space), all levels of one step", "bound": "alu",
+    peak = PEAK_FP32_VALU if prec != pk.DFMM_FP64 else PEAK_FP64_VALU
+    kname = "k_hadamard16 (M2L in frequency space, f16 operands)" if prec == pk.DFMM_MIXED_F16 else \
+        "k_hadamard (M2L in frequency space)"
+    roof = {"kernel": kname + ", all levels of one step", "bound": "alu",
             "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak,
-            "traffic": hadamard_traffic(prm["order"]), "flop_per_step": had_flops, "ms_per_step": had_ms}
+            "traffic": hadamard_traffic(prm["order"], "k_hadamard16" if prec == pk.DFMM_MIXED_F16 else "k_hadamard",
+                                        args.workload),
+            "flop_per_step": had_flops, "ms_per_step": had_ms}
     result = {
         "metric": METRIC, "value": ns / (ms_step * 1e-3), "unit": "segments/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32" if prec == pk.DFMM_MIXED else "f64",
+        "scaling": "weak", "vs_baseline": None, "dtype": {pk.DFMM_MIXED: "f32", pk.DFMM_MIXED_F16: "f16/f32", pk.DFMM_FP64: "f64"}[prec],
         "data": "synthetic",
         "config": {"workload": args.workload, "n_seg": ns, "order": prm["order"], "depth": prm["depth"],
                    "C": [prm["c11"], prm["c12"], prm["c44"]], "core_a": prm["core_a"],
@@ -219,38 +226,44 @@ def main():
         "near_pairs": tinfo["near_pairs"], "roofline": roof,
     }
     del tree
-    if not args.no_fp64_compare and prec == pk.DFMM_MIXED:
-        plan64 = make_plan(pk.DFMM_FP64)
-        tree64 = pk.Tree(plan64, tseg)
-        out64 = pk.fmm_forces(plan64, tree64, tseg, tb)
+    def other_path(precision, kernel, peak):
+        """Time and error of the same workload in another precision (same
+        tree shape, its own plan): K calls as issued, then K with stage events."""
+        plan2 = make_plan(precision)
+        tree2 = pk.Tree(plan2, tseg)
+        out2 = pk.fmm_forces(plan2, tree2, tseg, tb)
         torch.cuda.synchronize()
+        n2 = max(1, min(args.steps, 3))
         t0 = time.perf_counter()
-        n64 = max(1, min(args.steps, 2))
-        for i in range(n64):
-            pk.fmm_forces(plan64, tree64, tseg, tb, out=out64)
+        for i in range(n2):
+            pk.fmm_forces(plan2, tree2, tseg, tb, out=out2)
         torch.cuda.synchronize()
-        ms64 = 1e3 * (time.perf_counter() - t0) / n64
-        f64 = out64.cpu().numpy()[sub]
-        # stage times of the FP64 path (HIP events around every stage)
-        tree64.set_timing(True)
-        for i in range(n64):
-            pk.fmm_forces(plan64, tree64, tseg, tb, out=out64)
+        ms2 = 1e3 * (time.perf_counter() - t0) / n2
+        f2 = out2.cpu().numpy()[sub]
+        tree2.set_timing(True)
+        for i in range(n2):
+            pk.fmm_forces(plan2, tree2, tseg, tb, out=out2)
         torch.cuda.synchronize()
-        st64, nc64 = tree64.stage_times()
-        tree64.set_timing(False)
-        had64_ms = st64[3] / nc64
-        ach64 = had_flops / (had64_ms * 1e-3)
-        result["fp64_path"] = {
-            "ms_per_step": ms64, "rel_err_vs_fp64_direct": float(np.linalg.norm(f64 - ref) / np.linalg.norm(ref)),
-            "mixed_speedup": ms64 / ms_step,
-            "stage_ms": {pk.STAGES[i]: st64[i] / nc64 for i in range(pk.N_STAGES)},
-            "roofline": {"kernel": "k_hadamard3 (FP64 M2L in frequency space), all levels of one step",
-                         "bound": "alu", "achieved": ach64 / 1e12, "peak": PEAK_FP64_VALU / 1e12,
-                         "unit": "TFLOP/s", "frac": ach64 / PEAK_FP64_VALU, "traffic": None,
-                         "flop_per_step": had_flops, "ms_per_step": had64_ms}}
-        log("fp64 FMM path: %.3f ms/step (mixed speedup %.2fx); Hadamard %.1f ms = %.1f TFLOP/s"
-            % (ms64, ms64 / ms_step, had64_ms, ach64 / 1e12))
-        del tree64, plan64
+        st2, nc2 = tree2.stage_times()
+        tree2.set_timing(False)
+        had2_ms = st2[3] / nc2
+        ach2 = had_flops / (had2_ms * 1e-3)
+        res = {
+            "ms_per_step": ms2, "rel_err_vs_fp64_direct": float(np.linalg.norm(f2 - ref) / np.linalg.norm(ref)),
+            "speedup_of_headline": ms2 / ms_step,
+            "stage_ms": {pk.STAGES[i]: st2[i] / nc2 for i in range(pk.N_STAGES)},
+            "roofline": {"kernel": kernel + ", all levels of one step", "bound": "alu", "achieved": ach2 / 1e12,
+                         "peak": peak / 1e12, "unit": "TFLOP/s", "frac": ach2 / peak, "traffic": None,
+                         "flop_per_step": had_flops, "ms_per_step": had2_ms}}
+        log("%s path: %.3f ms/step (headline speedup %.2fx), error %.3e; Hadamard %.1f ms = %.1f TFLOP/s"
+            % (kernel, ms2, ms2 / ms_step, res["rel_err_vs_fp64_direct"], had2_ms, ach2 / 1e12))
+        del tree2, plan2
+        return res
+
+    if not args.no_fp64_compare and prec != pk.DFMM_FP64:
+        if prec == pk.DFMM_MIXED_F16:
+            result["mixed_f32_path"] = other_path(pk.DFMM_MIXED, "k_hadamard (f32 operands)", PEAK_FP32_VALU)
+        result["fp64_path"] = other_path(pk.DFMM_FP64, "k_hadamard3 (FP64 M2L in frequency space)", PEAK_FP64_VALU)
     if not args.no_cpu_baseline:
         import oracle
 

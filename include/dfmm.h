@@ -57,7 +57,11 @@ typedef enum {
   DFMM_E_STATE = -6       /* objects that do not belong together (plan/tree)     */
 } dfmm_status;
 
-enum { DFMM_FP64 = 0, DFMM_MIXED = 1 };
+/* Arithmetic of the evaluation (the operators are always precomputed in
+ * double precision).  DFMM_MIXED_F16 is DFMM_MIXED with the M2L Hadamard
+ * product taking f16 operands (operator spectra and source spectra, each
+ * level scaled into f16's range) with f32 accumulation. */
+enum { DFMM_FP64 = 0, DFMM_MIXED = 1, DFMM_MIXED_F16 = 2 };
 /* M2L operator store (Eq. mem_unif and the symmetry reduction of Sec. 6):
  * DFMM_M2L_FFT keeps the spectra of the 158 canonical offsets (one of each
  * pair o, -o of the 316; the kernel is odd); DFMM_M2L_FFT_SYM keeps only the
@@ -94,7 +98,9 @@ typedef struct {
   int precision;      /* DFMM_FP64: all arithmetic in double.
                          DFMM_MIXED: P2M..L2P and the near field in float with
                          float accumulation, near pairs closer than 2a in
-                         double, far + near combined and forces in double     */
+                         double, far + near combined and forces in double.
+                         DFMM_MIXED_F16: as DFMM_MIXED, the M2L product on
+                         f16 operands with f32 accumulation                   */
   int m2l_mode;       /* DFMM_M2L_FFT or DFMM_M2L_FFT_SYM (operator store)       */
   int aniso_kernel;   /* DFMM_KERNEL_EXACT or DFMM_KERNEL_SURROGATE              */
 } dfmm_params;

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libdfmm.so")
 
 DFMM_FP64 = 0
 DFMM_MIXED = 1
+DFMM_MIXED_F16 = 2
 DFMM_M2L_FFT = 0
 DFMM_M2L_FFT_SYM = 1
 DFMM_KERNEL_EXACT = 0

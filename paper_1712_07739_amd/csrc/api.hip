@@ -94,8 +94,8 @@ int dfmm_fmm_setup(const dfmm_params* prm, void* stream, dfmm_plan** out) {
     set_error("fmm_setup: stiffness is not positive definite");
     return DFMM_E_ARG;
   }
-  if (q.precision != DFMM_FP64 && q.precision != DFMM_MIXED) {
-    set_error("fmm_setup: precision must be DFMM_FP64 or DFMM_MIXED");
+  if (q.precision != DFMM_FP64 && q.precision != DFMM_MIXED && q.precision != DFMM_MIXED_F16) {
+    set_error("fmm_setup: precision must be DFMM_FP64, DFMM_MIXED or DFMM_MIXED_F16");
     return DFMM_E_ARG;
   }
   if (q.m2l_mode != DFMM_M2L_FFT && q.m2l_mode != DFMM_M2L_FFT_SYM) {
@@ -113,7 +113,8 @@ int dfmm_fmm_setup(const dfmm_params* prm, void* stream, dfmm_plan** out) {
   pl->n = 2 * q.order - 1;
   pl->nf = pl->n * pl->n * q.order;
   pl->D = q.depth;
-  pl->mixed = q.precision == DFMM_MIXED;
+  pl->mixed = q.precision != DFMM_FP64;
+  pl->h16 = q.precision == DFMM_MIXED_F16;
   pl->sym = q.m2l_mode == DFMM_M2L_FFT_SYM;
   pl->iso = std::fabs(2.0 * q.c44 - (q.c11 - q.c12)) <= 1e-12 * std::fabs(q.c44);
   if (pl->iso) {
@@ -187,7 +188,7 @@ void dfmm_tree_destroy(dfmm_tree* t) {
   }
   hipFree(t->cstart); hipFree(t->cpair); hipFree(t->cval); hipFree(t->part); hipFree(t->cuni); hipFree(t->bigp);
   hipFree(t->pts); hipFree(t->pleaf); hipFree(t->W); hipFree(t->s); hipFree(t->What); hipFree(t->Shat); hipFree(t->sig);
-  hipFree(t->kexp);
+  hipFree(t->kexp); hipFree(t->wmax);
   delete t;
 }
 

@@ -204,6 +204,46 @@ __device__ __forceinline__ int64_t xcd_block(int64_t L, int64_t n) {
   return x * q + (x < r ? x : r) + k;
 }
 
+// ------------------------------------------------- f16 scale of a level
+// DFMM_MIXED_F16: the source spectra of a level are stored as f16 scaled by
+// a power of two s_W, from the level's largest multipole weight m:
+// |What| <= p^3 m (the forward DFT has unit-modulus twiddles), so s_W puts
+// p^3 m in [2^13, 2^14), clear of f16's overflow; f16's relative precision
+// does not depend on the scale.
+__device__ __forceinline__ float h16_wscale(const unsigned* wmax, int p3) {
+  const float m = __uint_as_float(*wmax) * (float)p3;
+  if (!(m > 0.f) || !(m < 3.0e38f)) return 1.f;
+  int e;
+  frexpf(m, &e);
+  return ldexpf(1.f, 14 - e);
+}
+
+// Largest |x| over the n floats of one level's weights into *out (float
+// bits; non-negative floats order as unsigned integers): one atomic per block.
+__global__ void __launch_bounds__(256) k_wmax(const float* x, int64_t n, unsigned* out) {
+  __shared__ float sh[256];
+  float m = 0.f;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    m = fmaxf(m, fabsf(x[i]));
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] = fmaxf(sh[threadIdx.x], sh[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicMax(out, __float_as_uint(sh[0]));
+}
+
+__global__ void k_fill_uint(unsigned* p, int n, unsigned v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__device__ __forceinline__ uint32_t pack_h2(float re, float im) {
+  const _Float16 a = (_Float16)re, b = (_Float16)im;
+  return (uint32_t)__builtin_bit_cast(uint16_t, a) | ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
+}
+
 // ------------------------------------------------------------ forward DFT
 constexpr int kDftThreads = 512;  // threads per block of the DFT kernels
 // One block per cell of a level: W[cell][9][P^3] (real, zero-padded to n^3,
@@ -250,9 +290,10 @@ __device__ __forceinline__ void dft_line_pairs(const cplx<T>* x, const T* c, con
   }
 }
 
-template <typename T, int P>
+template <typename T, int P, bool H16>
 __global__ void __launch_bounds__(kDftThreads) k_fdft(const T* __restrict__ W, int64_t ncell, int G,
-                                              const T* __restrict__ twg, cplx<T>* __restrict__ What) {
+                                              const T* __restrict__ twg, cplx<T>* __restrict__ What,
+                                              const unsigned* __restrict__ wmax) {
   constexpr int n = 2 * P - 1, p3 = P * P * P;
   extern __shared__ __align__(16) unsigned char shraw[];
   cplx<T>* X1 = (cplx<T>*)shraw;  // [G][P][P][P]  (g, m1, m2, f3)
@@ -299,8 +340,16 @@ __global__ void __launch_bounds__(kDftThreads) k_fdft(const T* __restrict__ W, i
       cplx<T> x[P];
 #pragma unroll
       for (int m = 0; m < P; ++m) x[m] = X2[(g * P + m) * n * P + r];
-      dft_line_pairs<T, P>(x, c, s,
-                           [&](int f, cplx<T> v) { What[((int64_t)(f * n * P + r) * ncell + cell) * 9 + c0 + g] = v; });
+      if constexpr (H16) {
+        const float sw = h16_wscale(wmax, p3);
+        uint32_t* W16 = reinterpret_cast<uint32_t*>(What);
+        dft_line_pairs<T, P>(x, c, s, [&](int f, cplx<T> v) {
+          W16[((int64_t)(f * n * P + r) * ncell + cell) * 9 + c0 + g] = pack_h2((float)v.re * sw, (float)v.im * sw);
+        });
+      } else {
+        dft_line_pairs<T, P>(x, c, s,
+                             [&](int f, cplx<T> v) { What[((int64_t)(f * n * P + r) * ncell + cell) * 9 + c0 + g] = v; });
+      }
     }
     __syncthreads();
   }
@@ -343,9 +392,9 @@ constexpr size_t lds_fdft_t(int G, size_t es) {
 __device__ __constant__ const int kVoigtA[6] = {0, 1, 2, 1, 0, 0};
 __device__ __constant__ const int kVoigtB[6] = {0, 1, 2, 2, 2, 1};
 __device__ __constant__ const int kVoigtOf[9] = {0, 5, 4, 5, 1, 3, 4, 3, 2};
-template <typename T>
+template <typename T, bool H16>
 __global__ void k_sym_expand(const cplx<T>* __restrict__ Kc, const SymEntry* __restrict__ symtab, int nf, int n,
-                             int p, cplx<T>* __restrict__ out) {
+                             int p, float scale, cplx<T>* __restrict__ out) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (int64_t)nf * kNumCanon * 54) return;
   const int f = (int)(e / (kNumCanon * 54));
@@ -369,7 +418,10 @@ __global__ void k_sym_expand(const cplx<T>* __restrict__ Kc, const SymEntry* __r
   const cplx<T> x = Kc[((int64_t)((g[0] * n + g[1]) * p + g[2]) * kNumSymClass + se.cls) * 54 + src];
   const cplx<T> v{sgn > 0 ? x.re : -x.re, (sgn > 0) != cj ? x.im : -x.im};
   const int ab = kVoigtOf[3 * a + b], wr = w * 3 + r;
-  if (sizeof(T) == 4)
+  if (H16)
+    reinterpret_cast<uint32_t*>(out)[((int64_t)f * kNumCanon + id) * kKOffsetH + (ab / 3) * kKHalfH + (ab % 3) * 9 +
+                                     had_slot_of(ab / 3, wr)] = pack_h2((float)v.re * scale, (float)v.im * scale);
+  else if (sizeof(T) == 4)
     out[((int64_t)f * kNumCanon + id) * kKOffsetF + (ab / 3) * kKHalfF + (ab % 3) * 9 + had_slot_of(ab / 3, wr)] = v;
   else
     out[((int64_t)f * kNumCanon + id) * 54 + ab * 9 + wr] = v;
@@ -493,6 +545,113 @@ k_hadamard(const cplx<float>* What, const cplx<float>* Khat, const int* lenq, co
     for (int e = 0; e < len; ++e, eb += kStep) {
       const uint32_t jn = entry(eb + kStep);
       cplx<float> v[5];
+      load_src(jo, v);
+      pair(jo, v);
+      jo = jn;
+      asm volatile("" : "+v"(jo));
+    }
+  }
+  cplx<float>* out = Shat + ((int64_t)f * ncell + t) * 6 + 3 * h;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) out[r] = cplx<float>{ar[r], ai[r]};
+}
+
+// The Hadamard product on f16 operands (DFMM_MIXED_F16): the same blocks,
+// lanes, list walk and slot order as k_hadamard, with every complex value a
+// pair of f16 (real in the low half) and the products done by
+// v_dot2_f32_f16, two multiply-adds with f32 accumulation per instruction.
+// With w = (wr, wi) and K = (kr, ki),
+//   K w:          re = (kr, ki).(wr, -wi),  im = (kr, ki).(wi, wr)
+//   -conj(K) w:   re = (kr, ki).(-wr, -wi), im = (kr, ki).(-wi, wr)
+// (the mirrored offset, as in k_hadamard), so each source value is prepared
+// once per pair with a sign mask and a half swap, and the dot products
+// accumulate straight into the target's sums.  The spectra take half the LDS
+// (37.9 KB per frequency) and the source rows half the memory (36 bytes).
+// Both carry power-of-two scales that the inverse DFT removes.
+typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+__global__ void __launch_bounds__(kHadThreads) __attribute__((amdgpu_waves_per_eu(6, 6)))
+k_hadamard16(const uint32_t* What, const uint32_t* Khat, const int* lenq, const int* wbase, const uint32_t* ilw,
+             const uint32_t* order, int64_t ncell, int nf, int nwin, int remap, cplx<float>* Shat) {
+  extern __shared__ __align__(16) unsigned char shraw[];
+  uint4* Ks4 = (uint4*)shraw;  // [158][15] 16-byte units
+  int win, f;
+  if (remap) {
+    const int64_t L = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+    const int wx = (nwin + 7) / 8;
+    const int xcd = (int)(L % 8);
+    const int64_t k = L / 8;
+    f = (int)(k / wx);
+    win = xcd * wx + (int)(k % wx);
+    if (win >= nwin || f >= nf) return;
+  } else {
+    win = blockIdx.x;
+    f = blockIdx.y;
+  }
+  const uint4* kf = reinterpret_cast<const uint4*>(Khat + (int64_t)f * kNumCanon * kKOffsetH);
+  for (int e = threadIdx.x; e < kNumCanon * kKOffsetH / 4; e += blockDim.x) Ks4[e] = kf[e];
+  __syncthreads();
+  const int64_t tt = (int64_t)win * kM2LWindowF + threadIdx.x / 2;
+  if (tt >= ncell) return;  // both lanes of a target leave together
+  const int h = threadIdx.x & 1;
+  const int64_t t = order[tt];
+  const int len = lenq[tt];
+  float ar[3] = {0.f, 0.f, 0.f}, ai[3] = {0.f, 0.f, 0.f};
+  const char* wfb = reinterpret_cast<const char*>(What + (int64_t)f * ncell * 9);
+  const char* ilb = reinterpret_cast<const char*>(ilw);
+  constexpr uint32_t kStep = kWaveTargets * sizeof(uint32_t);
+  const char* kb = reinterpret_cast<const char*>(shraw) + h * (kKHalfH * 4);
+  const uint32_t hoff = 16u * (uint32_t)h;
+  auto entry = [&](uint32_t eb) { return *reinterpret_cast<const uint32_t*>(ilb + eb); };
+  typedef unsigned u4a4 __attribute__((ext_vector_type(4), aligned(4)));
+  auto load_src = [&](uint32_t j, uint32_t* v) {
+    const uint32_t o = (j & 0x7FFFFFu) * 36u;
+    const u4a4 x = *reinterpret_cast<const u4a4*>(wfb + (o + hoff));
+    v[0] = x.x;
+    v[1] = x.y;
+    v[2] = x.z;
+    v[3] = x.w;
+    v[4] = *reinterpret_cast<const uint32_t*>(wfb + o + 32);
+  };
+  auto pair = [&](uint32_t j, const uint32_t* v) {
+    const bool mir = (j >> 31) != 0;
+    const uint32_t mu = mir ? 0x80008000u : 0x80000000u, mv = mir ? 0x00008000u : 0u;
+    uint32_t w[9];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) w[k] = v[k];
+    // the partner lane's four components (quad permutation 1, 0, 3, 2)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) w[5 + k] = (uint32_t)__builtin_amdgcn_mov_dpp((int)v[k], 0xB1, 0xF, 0xF, false);
+    half2v u[9], q[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      u[k] = __builtin_bit_cast(half2v, w[k] ^ mu);
+      q[k] = __builtin_bit_cast(half2v, __builtin_amdgcn_alignbit(w[k], w[k], 16) ^ mv);
+    }
+    const uint4* K4 = reinterpret_cast<const uint4*>(kb + ((j >> 23) & 0xFFu) * (uint32_t)(kKOffsetH * 4));
+    uint32_t kk[28];
+#pragma unroll
+    for (int i = 0; i < 7; ++i) {
+      const uint4 x = K4[i];
+      kk[4 * i] = x.x;
+      kk[4 * i + 1] = x.y;
+      kk[4 * i + 2] = x.z;
+      kk[4 * i + 3] = x.w;
+    }
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        const half2v kv = __builtin_bit_cast(half2v, kk[9 * r + k]);
+        ar[r] = __builtin_amdgcn_fdot2(kv, u[k], ar[r], false);
+        ai[r] = __builtin_amdgcn_fdot2(kv, q[k], ai[r], false);
+      }
+  };
+  if (len > 0) {
+    uint32_t eb = kStep * (uint32_t)wbase[tt / kWaveTargets] + sizeof(uint32_t) * (uint32_t)(tt % kWaveTargets);
+    uint32_t jo = entry(eb);
+    for (int e = 0; e < len; ++e, eb += kStep) {
+      const uint32_t jn = entry(eb + kStep);
+      uint32_t v[5];
       load_src(jo, v);
       pair(jo, v);
       jo = jn;
@@ -638,7 +797,8 @@ __device__ __forceinline__ void idft_line_pairs(const cplx<T>* x, const T* c, co
 // (f3 = 0 once, f3 > 0 twice, real part).
 template <typename T, int P>
 __global__ void __launch_bounds__(kDftThreads) k_idft(const cplx<T>* __restrict__ Shat, int64_t ncell,
-                                              const T* __restrict__ twg, T* __restrict__ s) {
+                                              const T* __restrict__ twg, T* __restrict__ s,
+                                              const unsigned* __restrict__ wmax, float kscale) {
   constexpr int n = 2 * P - 1, p3 = P * P * P, nf = n * n * P;
   extern __shared__ __align__(16) unsigned char shraw[];
   cplx<T>* Y1 = (cplx<T>*)shraw;     // [6][n(f2)][P(f3)][P(l1)]
@@ -650,7 +810,8 @@ __global__ void __launch_bounds__(kDftThreads) k_idft(const cplx<T>* __restrict_
     sn[k] = -twg[2 * k + 1];
   }
   const int64_t cell = xcd_block(blockIdx.x, ncell);
-  const T scale = T(1) / T(n * n * n);
+  // the f16 product's spectra carry the operator and source scales
+  const T scale = wmax ? T(1) / (T(n * n * n) * (T)kscale * (T)h16_wscale(wmax, p3)) : T(1) / T(n * n * n);
   const cplx<T>* src = Shat + cell * 6;
   // along the first axis: n -> P
   for (int it = threadIdx.x; it < 6 * n * P; it += blockDim.x) {
@@ -1299,27 +1460,34 @@ static int dft_groups(bool fwd) {
   return 1;
 }
 
+// wmax: non-null for DFMM_MIXED_F16 (f16 source spectra, scaled; the inverse
+// transform removes the operator scale kscale and the source scale).
 template <typename T, int P>
 static void dft_launch(bool fwd, unsigned blocks, const void* in, int64_t ncell, const T* tw, void* out,
-                       hipStream_t st) {
+                       const unsigned* wmax, float kscale, hipStream_t st) {
   const int G = dft_groups<T, P>(fwd);
-  if (fwd)
-    k_fdft<T, P><<<blocks, kDftThreads, lds_fdft_t<P>(G, sizeof(T)), st>>>((const T*)in, ncell, G, tw, (cplx<T>*)out);
+  if (fwd && wmax)
+    k_fdft<T, P, true><<<blocks, kDftThreads, lds_fdft_t<P>(G, sizeof(T)), st>>>((const T*)in, ncell, G, tw,
+                                                                               (cplx<T>*)out, wmax);
+  else if (fwd)
+    k_fdft<T, P, false><<<blocks, kDftThreads, lds_fdft_t<P>(G, sizeof(T)), st>>>((const T*)in, ncell, G, tw,
+                                                                                (cplx<T>*)out, nullptr);
   else
-    k_idft<T, P><<<blocks, kDftThreads, lds_idft_t<P>(sizeof(T)), st>>>((const cplx<T>*)in, ncell, tw, (T*)out);
+    k_idft<T, P><<<blocks, kDftThreads, lds_idft_t<P>(sizeof(T)), st>>>((const cplx<T>*)in, ncell, tw, (T*)out,
+                                                                         wmax, kscale);
 }
 
 template <typename T>
 static void dft(int p, bool fwd, unsigned blocks, const void* in, int64_t ncell, const T* tw, void* out,
-                hipStream_t st) {
+                const unsigned* wmax, float kscale, hipStream_t st) {
   switch (p) {
-    case 2: dft_launch<T, 2>(fwd, blocks, in, ncell, tw, out, st); break;
-    case 3: dft_launch<T, 3>(fwd, blocks, in, ncell, tw, out, st); break;
-    case 4: dft_launch<T, 4>(fwd, blocks, in, ncell, tw, out, st); break;
-    case 5: dft_launch<T, 5>(fwd, blocks, in, ncell, tw, out, st); break;
-    case 6: dft_launch<T, 6>(fwd, blocks, in, ncell, tw, out, st); break;
-    case 7: dft_launch<T, 7>(fwd, blocks, in, ncell, tw, out, st); break;
-    default: dft_launch<T, 8>(fwd, blocks, in, ncell, tw, out, st); break;
+    case 2: dft_launch<T, 2>(fwd, blocks, in, ncell, tw, out, wmax, kscale, st); break;
+    case 3: dft_launch<T, 3>(fwd, blocks, in, ncell, tw, out, wmax, kscale, st); break;
+    case 4: dft_launch<T, 4>(fwd, blocks, in, ncell, tw, out, wmax, kscale, st); break;
+    case 5: dft_launch<T, 5>(fwd, blocks, in, ncell, tw, out, wmax, kscale, st); break;
+    case 6: dft_launch<T, 6>(fwd, blocks, in, ncell, tw, out, wmax, kscale, st); break;
+    case 7: dft_launch<T, 7>(fwd, blocks, in, ncell, tw, out, wmax, kscale, st); break;
+    default: dft_launch<T, 8>(fwd, blocks, in, ncell, tw, out, wmax, kscale, st); break;
   }
 }
 
@@ -1352,7 +1520,8 @@ static void tree_pass(int p, bool up, unsigned blocks, size_t shm, const int* a,
 template <typename T, int... Ps>
 static void dft_lds_attrs(std::integer_sequence<int, Ps...>) {
   const int mx = 160 * 1024;
-  ((void)hipFuncSetAttribute((const void*)k_fdft<T, Ps + 2>, hipFuncAttributeMaxDynamicSharedMemorySize, mx), ...);
+  ((void)hipFuncSetAttribute((const void*)k_fdft<T, Ps + 2, false>, hipFuncAttributeMaxDynamicSharedMemorySize, mx), ...);
+  ((void)hipFuncSetAttribute((const void*)k_fdft<T, Ps + 2, true>, hipFuncAttributeMaxDynamicSharedMemorySize, mx), ...);
   ((void)hipFuncSetAttribute((const void*)k_idft<T, Ps + 2>, hipFuncAttributeMaxDynamicSharedMemorySize, mx), ...);
   ((void)hipFuncSetAttribute((const void*)k_m2m<T, Ps + 2>, hipFuncAttributeMaxDynamicSharedMemorySize, mx), ...);
   ((void)hipFuncSetAttribute((const void*)k_l2l<T, Ps + 2>, hipFuncAttributeMaxDynamicSharedMemorySize, mx), ...);
@@ -1498,10 +1667,23 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
                                W + Lp.off * 9 * p3, tb.S, st));
     }
   }
+  // DFMM_MIXED_F16: each level's largest weight, for the f16 scale of its spectra
+  const bool h16 = std::is_same<T, float>::value && pl->h16;
+  if (h16) {
+    STAGE(2, (k_fill_uint<<<1, 64, 0, st>>>(t->wmax, D + 1, 0u)));
+    for (int l = 2; l <= D; ++l) {
+      const auto& Lv = t->lv[l];
+      const int64_t nw = Lv.n * 9 * p3;
+      if (nw > 0)
+        STAGE(2, (k_wmax<<<(unsigned)std::min<int64_t>(2048, (nw + 255) / 256), 256, 0, st>>>(
+                     (const float*)(W + Lv.off * 9 * p3), nw, t->wmax + l)));
+    }
+  }
   for (int l = 2; l <= D; ++l) {
     const auto& Lv = t->lv[l];
     if (Lv.n == 0) continue;
-    STAGE(2, dft<T>(p, true, (unsigned)Lv.n, W + Lv.off * 9 * p3, Lv.n, tb.tw, What, st));
+    const unsigned* wm = h16 ? t->wmax + l : nullptr;
+    STAGE(2, dft<T>(p, true, (unsigned)Lv.n, W + Lv.off * 9 * p3, Lv.n, tb.tw, What, wm, 1.f, st));
     const int wsz = m2l_window(pl->mixed);
     const int nwin = (int)((Lv.n + wsz - 1) / wsz);
     const int remap = nwin >= 16;
@@ -1509,18 +1691,27 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
     // symmetry-reduced store: this level's 158 offset spectra, expanded into
     // the tree's workspace
     const cplx<T>* kh = (const cplx<T>*)pl->lev[l].khat;
+    const float ksc = pl->lev[l].kscale;
     if (pl->sym) {
-      STAGE(3, (k_sym_expand<T><<<nblk((int64_t)nf * kNumCanon * 54, 256), 256, 0, st>>>(kh, pl->symtab, nf, n, p,
-                                                                                        (cplx<T>*)t->kexp)));
+      if (h16)
+        STAGE(3, (k_sym_expand<T, true><<<nblk((int64_t)nf * kNumCanon * 54, 256), 256, 0, st>>>(
+                     kh, pl->symtab, nf, n, p, ksc, (cplx<T>*)t->kexp)));
+      else
+        STAGE(3, (k_sym_expand<T, false><<<nblk((int64_t)nf * kNumCanon * 54, 256), 256, 0, st>>>(
+                     kh, pl->symtab, nf, n, p, 1.f, (cplx<T>*)t->kexp)));
       kh = (const cplx<T>*)t->kexp;
     }
-    if constexpr (std::is_same<T, float>::value)
+    if (h16)
+      STAGE(3, (k_hadamard16<<<g, kHadThreads, sizeof(uint32_t) * kNumCanon * kKOffsetH, st>>>(
+                   (const uint32_t*)What, (const uint32_t*)kh, Lv.lenq, Lv.wbase, Lv.ilw, Lv.order, Lv.n, nf, nwin,
+                   remap, (cplx<float>*)Shat)));
+    else if constexpr (std::is_same<T, float>::value)
       STAGE(3, (k_hadamard<<<g, kHadThreads, sizeof(cplx<float>) * kNumCanon * kKOffsetF, st>>>(
                    What, kh, Lv.lenq, Lv.wbase, Lv.ilw, Lv.order, Lv.n, nf, nwin, remap, Shat)));
     else
       STAGE(3, (k_hadamard3<T><<<g, kHad3Threads, sizeof(cplx<T>) * kNumCanon * kKStride3, st>>>(
                    What, kh, Lv.il_start, Lv.il, Lv.order, Lv.n, nf, nwin, remap, Shat)));
-    STAGE(4, dft<T>(p, false, (unsigned)Lv.n, Shat, Lv.n, tb.tw, s + Lv.off * 6 * p3, st));
+    STAGE(4, dft<T>(p, false, (unsigned)Lv.n, Shat, Lv.n, tb.tw, s + Lv.off * 6 * p3, wm, ksc, st));
   }
   {
     size_t shm = es * 12 * p3;
@@ -1551,6 +1742,7 @@ template <typename T>
 static void set_lds_attrs_once() {
   const int mx = 160 * 1024;
   hipFuncSetAttribute((const void*)k_hadamard, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+  hipFuncSetAttribute((const void*)k_hadamard16, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
   hipFuncSetAttribute((const void*)k_hadamard3<double>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
   hipFuncSetAttribute((const void*)k_leaf_sym<T, sizeof(T) == 4, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                       mx);

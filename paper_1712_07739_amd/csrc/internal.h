@@ -41,6 +41,11 @@ constexpr int kMaxDevices = 64;
 // banks (an even one leaves half of them idle and doubles up the rest).
 constexpr int kKHalfF = 28;
 constexpr int kKOffsetF = 2 * kKHalfF + 2;
+// The f16 Hadamard product keeps the same slot order with one 32-bit word
+// (f16 real, f16 imaginary) per complex value: per offset two halves of 28
+// words and 4 pad words, 15 16-byte units (odd, for the same reason).
+constexpr int kKHalfH = 28;
+constexpr int kKOffsetH = 2 * kKHalfH + 4;
 __host__ __device__ constexpr int had_slot_of(int h, int k) {
   return k == 8 ? 4 : ((k >> 2) == h ? k - 4 * h : 5 + k - 4 * (1 - h));
 }
@@ -106,10 +111,12 @@ struct Surrogate {
 };
 
 struct LevelTables {
+  float kscale = 1.f;    // DFMM_MIXED_F16: power of two the f16 operator spectra are scaled by
   void* khat = nullptr;  // DFT of the circulant embedding of each stored offset's
                          // generator.  DFMM_M2L_FFT: the 158 canonical offsets,
                          // double [nf][158][54] complex (row-major 6 x 9), float
-                         // [nf][158][kKOffsetF] complex in slot order.
+                         // [nf][158][kKOffsetF] complex in slot order (DFMM_MIXED_F16:
+                         // [nf][158][kKOffsetH] f16 pairs, scaled by kscale).
                          // DFMM_M2L_FFT_SYM: the 16 symmetry classes, [nf][16][54]
                          // complex (row-major 6 x 9) in the plan's precision.
 };
@@ -145,6 +152,7 @@ struct dfmm_plan {
   int* oid343 = nullptr;   // device [343]: offset (o+3) lex index -> 2*canonical id + mirrored, or -1
   int* off158 = nullptr;   // device [158][3]: canonical id -> offset
   int sym = 0;             // operator store: 0 = 158 offset spectra, 1 = 16 class spectra
+  int h16 = 0;             // DFMM_MIXED_F16: f16 operands in the M2L product
   int* cls16 = nullptr;    // device [16][3]: class representatives (|o| sorted, descending)
   dfmm::SymEntry* symtab = nullptr;  // device [158]: class and R of each canonical id
   size_t gen_bytes = 0;    // kernel values behind the stored spectra (real generators, FP64)
@@ -201,6 +209,7 @@ struct dfmm_tree {
   void* What = nullptr;     // [nf][max level cells][9] complex
   void* Shat = nullptr;     // [nf][max level cells][6] complex
   double* sig = nullptr;    // [N][6] stress at sorted points
+  unsigned* wmax = nullptr; // DFMM_MIXED_F16: per level, the largest |W| (float bits), for the f16 scale
   void* kexp = nullptr;     // symmetry-reduced plans: one level's 158 offset spectra, expanded
                             // from the 16 classes before that level's Hadamard product
   void* part = nullptr;     // cubic medium: [N][27][6] near-field partial (float or double) per

@@ -402,6 +402,7 @@ __global__ void k_il_wave(const uint32_t* order, const int* il_start, const int2
 // offset first, then the earliest such entry, else the earliest entry).  This
 // only permutes each target's list: 228 -> 208.6 ms of M2L on 1M segments,
 // for about 6 ms of tree build.  One wave per group of 8 targets.
+template <int kUnits, int kHalf>
 __global__ void k_il_bank(const int* lenq, const int* wbase, int64_t n, int64_t ngroups, uint32_t* ilw) {
   __shared__ uint32_t ent[8][kNumFar + 1];
   __shared__ int used[16];
@@ -409,7 +410,6 @@ __global__ void k_il_bank(const int* lenq, const int* wbase, int64_t n, int64_t 
   if (G >= ngroups) return;
   static_assert(kWaveTargets % 8 == 0, "groups of 8 targets per wave");
   constexpr int kGroups = kWaveTargets / 8;
-  constexpr int kUnits = kKOffsetF / 2, kHalf = kKHalfF / 2;  // 16-byte units per offset, lane 1's start
   const int64_t w = G / kGroups;
   const int p = (int)(G % kGroups), lane = threadIdx.x;
   const int64_t base = (int64_t)kWaveTargets * wbase[w];
@@ -690,7 +690,11 @@ int build_tree_impl(dfmm_plan* pl, const double* seg, int64_t nseg, hipStream_t 
       DFMM_LAUNCH_CHECK();
       {
         const int64_t ng = nw * (kWaveTargets / 8);
-        k_il_bank<<<(unsigned)ng, 64, 0, st>>>(L.lenq, L.wbase, L.n, ng, L.ilw);
+        // 16-byte units per offset and lane 1's start, in the layout of the spectra in LDS
+        if (pl->h16)
+          k_il_bank<kKOffsetH / 4, kKHalfH / 4><<<(unsigned)ng, 64, 0, st>>>(L.lenq, L.wbase, L.n, ng, L.ilw);
+        else
+          k_il_bank<kKOffsetF / 2, kKHalfF / 2><<<(unsigned)ng, 64, 0, st>>>(L.lenq, L.wbase, L.n, ng, L.ilw);
         DFMM_LAUNCH_CHECK();
       }
       DFMM_HIP(hipStreamSynchronize(st));
@@ -748,9 +752,11 @@ int build_tree_impl(dfmm_plan* pl, const double* seg, int64_t nseg, hipStream_t 
   DFMM_HIP(hipMalloc(&t->sig, sizeof(double) * 6 * N));
   size_t bKx = 0;
   if (pl->sym) {  // one level of expanded offset spectra (the plan keeps the 16 classes)
-    bKx = (size_t)pl->nf * kNumCanon * (pl->mixed ? kKOffsetF : 54) * 2 * es;
+    bKx = pl->h16 ? (size_t)pl->nf * kNumCanon * kKOffsetH * sizeof(uint32_t)
+                  : (size_t)pl->nf * kNumCanon * (pl->mixed ? kKOffsetF : 54) * 2 * es;
     DFMM_HIP(hipMalloc(&t->kexp, bKx));
   }
+  if (pl->h16) DFMM_HIP(hipMalloc(&t->wmax, sizeof(unsigned) * (D + 1)));
   const size_t part_es = pl->mixed ? sizeof(float) : sizeof(double);
   if (!pl->iso && t->max_leaf_pts <= (pl->mixed ? kSymMaxLeaf : kSymMaxLeafD)) {
     DFMM_HIP(hipMalloc(&t->part, part_es * 27 * 6 * N));

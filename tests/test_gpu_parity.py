@@ -390,3 +390,54 @@ def test_dense_tree_lists_have_the_paper_counts(env):
     assert info["near_pairs"] == sum(
         int(np.prod([min(i + 1, n - 1) - max(i - 1, 0) + 1 for i in cc])) * 3 * 3
         for cc in np.ndindex(n, n, n))
+
+
+# ------------------------------------------------- f16 operands in the M2L
+F16_U = 2.0 ** -11  # unit roundoff of IEEE half precision
+
+
+@pytest.mark.parametrize("name,C,nloops,p,D,mode", [
+    ("iso-p4-D3", ISO, 50, 4, 3, 0),
+    ("cubic-p5-D3", CUB, 10, 5, 3, 1),
+    ("cubic-p7-D3", CUB, 6, 7, 3, 1),
+    ("iso-p6-D4", ISO, 30, 6, 4, 0),
+])
+def test_fmm_f16_m2l_matches_oracle_fmm(env, name, C, nloops, p, D, mode):
+    """DFMM_MIXED_F16: the Hadamard product takes f16 operator and source
+    spectra (f32 accumulation).  Each f16 operand carries a relative
+    rounding error of at most 2^-11, so every product term at most 2^-10:
+    the far field is off by at most about 2^-10 of itself, and the forces by
+    that times the far field's share, which the oracle's FMM reports.  The
+    bar adds that to the f32 path's 2e-5."""
+    torch, pk, dev = env
+    seg, b = synth.make_loops(nloops, 0.01, 0.05, 1 if name == "iso-p4-D3" else 17)
+    med = oracle.medium(*C, 1e-3)
+    ref, ref_far, _ = oracle.fmm_forces(seg, b, med, p, D, BOX_LO, BOX, return_parts=True)
+    share = float(np.linalg.norm(ref_far) / np.linalg.norm(ref))
+    ts, tb = torch.tensor(seg, device=dev), torch.tensor(b, device=dev)
+    prm = pk.make_params(p, D, *C, 1e-3, BOX_LO, BOX, precision=2, m2l_mode=mode)
+    plan = pk.Plan(prm)
+    tree = pk.Tree(plan, ts)
+    f16 = pk.fmm_forces(plan, tree, ts, tb).cpu().numpy()
+    err = oracle.rel_err(f16, ref)
+    bar = 2e-5 + 2 * F16_U * share
+    print("%s: f16 M2L vs oracle FMM %.2e (far-field share %.3f, bar %.2e)" % (name, err, share, bar))
+    assert err <= bar, name
+    # repeated calls are bit-identical (the scales are recomputed each call)
+    assert np.array_equal(f16, pk.fmm_forces(plan, tree, ts, tb).cpu().numpy())
+
+
+def test_full_size_f16_m2l_vs_oracle_samples(env):
+    """The 1M-segment cubic workload with f16 operands in the M2L at p = 7:
+    the force error against the oracle's direct sum on the 64 golden
+    segments stays within the 1e-4 bar."""
+    torch, pk, dev = env
+    g = _golden("cubic1m")
+    seg, b, prm = synth.make_workload("cubic1m")
+    C = (prm["c11"], prm["c12"], prm["c44"])
+    tgt = np.asarray(g["targets"])
+    ref = np.asarray(g["forces"])
+    f, plan, tree = run_fmm(env, seg, b, C, 7, prm["depth"], precision=2)
+    err = oracle.rel_err(f[tgt], ref)
+    print("cubic1m p=7 f16 M2L: rel err vs oracle on %d segments = %.3e" % (len(tgt), err))
+    assert err <= 1e-4
