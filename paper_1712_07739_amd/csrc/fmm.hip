@@ -418,10 +418,14 @@ __global__ void k_sym_expand(const cplx<T>* __restrict__ Kc, const SymEntry* __r
   const cplx<T> x = Kc[((int64_t)((g[0] * n + g[1]) * p + g[2]) * kNumSymClass + se.cls) * 54 + src];
   const cplx<T> v{sgn > 0 ? x.re : -x.re, (sgn > 0) != cj ? x.im : -x.im};
   const int ab = kVoigtOf[3 * a + b], wr = w * 3 + r;
-  if (H16)
-    reinterpret_cast<uint32_t*>(out)[((int64_t)f * kNumCanon + id) * kKOffsetH + (ab / 3) * kKHalfH + (ab % 3) * 9 +
-                                     had_slot_of(ab / 3, wr)] = pack_h2((float)v.re * scale, (float)v.im * scale);
-  else if (sizeof(T) == 4)
+  if (H16) {
+    // all 316 offsets: slot 2 id holds o, slot 2 id + 1 holds -o (-conj)
+    uint32_t* o32 = reinterpret_cast<uint32_t*>(out);
+    const int64_t e0 = ((int64_t)f * kNumOffsets + 2 * id) * kKOffsetH + (ab / 3) * kKHalfH + (ab % 3) * 9 +
+                       had_slot_of(ab / 3, wr);
+    o32[e0] = pack_h2((float)v.re * scale, (float)v.im * scale);
+    o32[e0 + kKOffsetH] = pack_h2(-(float)v.re * scale, (float)v.im * scale);
+  } else if (sizeof(T) == 4)
     out[((int64_t)f * kNumCanon + id) * kKOffsetF + (ab / 3) * kKHalfF + (ab % 3) * 9 + had_slot_of(ab / 3, wr)] = v;
   else
     out[((int64_t)f * kNumCanon + id) * 54 + ab * 9 + wr] = v;
@@ -559,21 +563,21 @@ k_hadamard(const cplx<float>* What, const cplx<float>* Khat, const int* lenq, co
 // The Hadamard product on f16 operands (DFMM_MIXED_F16): the same blocks,
 // lanes, list walk and slot order as k_hadamard, with every complex value a
 // pair of f16 (real in the low half) and the products done by
-// v_dot2_f32_f16, two multiply-adds with f32 accumulation per instruction.
-// With w = (wr, wi) and K = (kr, ki),
-//   K w:          re = (kr, ki).(wr, -wi),  im = (kr, ki).(wi, wr)
-//   -conj(K) w:   re = (kr, ki).(-wr, -wi), im = (kr, ki).(-wi, wr)
-// (the mirrored offset, as in k_hadamard), so each source value is prepared
-// once per pair with a sign mask and a half swap, and the dot products
-// accumulate straight into the target's sums.  The spectra take half the LDS
-// (37.9 KB per frequency) and the source rows half the memory (36 bytes).
-// Both carry power-of-two scales that the inverse DFT removes.
+// v_dot2_f32_f16, two multiply-adds with f32 accumulation per instruction:
+//   K w:  re = (kr, ki).(wr, -wi),  im = (kr, ki).(wi, wr),
+// each source value prepared once per pair (a sign flip and a half swap).
+// LDS holds the spectra of all 316 offsets (the mirrored offset -o as -conj
+// of o), so there is no per-pair mirror handling; a list entry's bits 23..31
+// are the offset's slot 2 id + mirror.  The spectra take 74 KB of LDS per
+// frequency (two blocks per CU, as for the f32 product) and a source row 36
+// bytes.  Operator and source spectra carry power-of-two scales that the
+// inverse DFT removes.
 typedef _Float16 half2v __attribute__((ext_vector_type(2)));
 __global__ void __launch_bounds__(kHadThreads) __attribute__((amdgpu_waves_per_eu(6, 6)))
 k_hadamard16(const uint32_t* What, const uint32_t* Khat, const int* lenq, const int* wbase, const uint32_t* ilw,
              const uint32_t* order, int64_t ncell, int nf, int nwin, int remap, cplx<float>* Shat) {
   extern __shared__ __align__(16) unsigned char shraw[];
-  uint4* Ks4 = (uint4*)shraw;  // [158][15] 16-byte units
+  uint4* Ks4 = (uint4*)shraw;  // [316][15] 16-byte units
   int win, f;
   if (remap) {
     const int64_t L = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
@@ -587,8 +591,8 @@ k_hadamard16(const uint32_t* What, const uint32_t* Khat, const int* lenq, const 
     win = blockIdx.x;
     f = blockIdx.y;
   }
-  const uint4* kf = reinterpret_cast<const uint4*>(Khat + (int64_t)f * kNumCanon * kKOffsetH);
-  for (int e = threadIdx.x; e < kNumCanon * kKOffsetH / 4; e += blockDim.x) Ks4[e] = kf[e];
+  const uint4* kf = reinterpret_cast<const uint4*>(Khat + (int64_t)f * kNumOffsets * kKOffsetH);
+  for (int e = threadIdx.x; e < kNumOffsets * kKOffsetH / 4; e += blockDim.x) Ks4[e] = kf[e];
   __syncthreads();
   const int64_t tt = (int64_t)win * kM2LWindowF + threadIdx.x / 2;
   if (tt >= ncell) return;  // both lanes of a target leave together
@@ -603,6 +607,7 @@ k_hadamard16(const uint32_t* What, const uint32_t* Khat, const int* lenq, const 
   const uint32_t hoff = 16u * (uint32_t)h;
   auto entry = [&](uint32_t eb) { return *reinterpret_cast<const uint32_t*>(ilb + eb); };
   typedef unsigned u4a4 __attribute__((ext_vector_type(4), aligned(4)));
+  // lane h: components 4h..4h+3 and 8 of the 36-byte source row
   auto load_src = [&](uint32_t j, uint32_t* v) {
     const uint32_t o = (j & 0x7FFFFFu) * 36u;
     const u4a4 x = *reinterpret_cast<const u4a4*>(wfb + (o + hoff));
@@ -613,21 +618,13 @@ k_hadamard16(const uint32_t* What, const uint32_t* Khat, const int* lenq, const 
     v[4] = *reinterpret_cast<const uint32_t*>(wfb + o + 32);
   };
   auto pair = [&](uint32_t j, const uint32_t* v) {
-    const bool mir = (j >> 31) != 0;
-    const uint32_t mu = mir ? 0x80008000u : 0x80000000u, mv = mir ? 0x00008000u : 0u;
     uint32_t w[9];
 #pragma unroll
     for (int k = 0; k < 5; ++k) w[k] = v[k];
     // the partner lane's four components (quad permutation 1, 0, 3, 2)
 #pragma unroll
     for (int k = 0; k < 4; ++k) w[5 + k] = (uint32_t)__builtin_amdgcn_mov_dpp((int)v[k], 0xB1, 0xF, 0xF, false);
-    half2v u[9], q[9];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      u[k] = __builtin_bit_cast(half2v, w[k] ^ mu);
-      q[k] = __builtin_bit_cast(half2v, __builtin_amdgcn_alignbit(w[k], w[k], 16) ^ mv);
-    }
-    const uint4* K4 = reinterpret_cast<const uint4*>(kb + ((j >> 23) & 0xFFu) * (uint32_t)(kKOffsetH * 4));
+    const uint4* K4 = reinterpret_cast<const uint4*>(kb + (j >> 23) * (uint32_t)(kKOffsetH * 4));
     uint32_t kk[28];
 #pragma unroll
     for (int i = 0; i < 7; ++i) {
@@ -638,13 +635,16 @@ k_hadamard16(const uint32_t* What, const uint32_t* Khat, const int* lenq, const 
       kk[4 * i + 3] = x.w;
     }
 #pragma unroll
-    for (int r = 0; r < 3; ++r)
+    for (int k = 0; k < 9; ++k) {
+      const half2v u = __builtin_bit_cast(half2v, w[k] ^ 0x80000000u);                   // (wr, -wi)
+      const half2v q = __builtin_bit_cast(half2v, __builtin_amdgcn_alignbit(w[k], w[k], 16));  // (wi, wr)
 #pragma unroll
-      for (int k = 0; k < 9; ++k) {
+      for (int r = 0; r < 3; ++r) {
         const half2v kv = __builtin_bit_cast(half2v, kk[9 * r + k]);
-        ar[r] = __builtin_amdgcn_fdot2(kv, u[k], ar[r], false);
-        ai[r] = __builtin_amdgcn_fdot2(kv, q[k], ai[r], false);
+        ar[r] = __builtin_amdgcn_fdot2(kv, u, ar[r], false);
+        ai[r] = __builtin_amdgcn_fdot2(kv, q, ai[r], false);
       }
+    }
   };
   if (len > 0) {
     uint32_t eb = kStep * (uint32_t)wbase[tt / kWaveTargets] + sizeof(uint32_t) * (uint32_t)(tt % kWaveTargets);
@@ -1702,7 +1702,7 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
       kh = (const cplx<T>*)t->kexp;
     }
     if (h16)
-      STAGE(3, (k_hadamard16<<<g, kHadThreads, sizeof(uint32_t) * kNumCanon * kKOffsetH, st>>>(
+      STAGE(3, (k_hadamard16<<<g, kHadThreads, sizeof(uint32_t) * kNumOffsets * kKOffsetH, st>>>(
                    (const uint32_t*)What, (const uint32_t*)kh, Lv.lenq, Lv.wbase, Lv.ilw, Lv.order, Lv.n, nf, nwin,
                    remap, (cplx<float>*)Shat)));
     else if constexpr (std::is_same<T, float>::value)

@@ -376,7 +376,9 @@ __global__ void k_wave_len(const uint32_t* order, const int* il_start, int n, in
 
 // Copy each target's list into its wave's block, step-major, one 32-bit word
 // per entry: source cell in bits 0..22, canonical offset in bits 23..30,
-// mirror flag in bit 31.
+// mirror flag in bit 31 (CODE9, the f16 product: offset code 2 id + mirror
+// in bits 23..31, its slot among the 316 offsets' spectra).
+template <bool CODE9>
 __global__ void k_il_wave(const uint32_t* order, const int* il_start, const int2* il, const int* wbase, int n,
                           uint32_t* ilw) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
@@ -386,7 +388,8 @@ __global__ void k_il_wave(const uint32_t* order, const int* il_start, const int2
   uint32_t* dst = ilw + (int64_t)kWaveTargets * wbase[q / kWaveTargets] + q % kWaveTargets;
   for (int i = 0; i < len; ++i) {
     const int2 v = il[b + i];
-    dst[(int64_t)kWaveTargets * i] = (uint32_t)v.x | ((uint32_t)(v.y >> 1) << 23) | ((uint32_t)(v.y & 1) << 31);
+    dst[(int64_t)kWaveTargets * i] = CODE9 ? (uint32_t)v.x | ((uint32_t)v.y << 23)
+                                           : (uint32_t)v.x | ((uint32_t)(v.y >> 1) << 23) | ((uint32_t)(v.y & 1) << 31);
   }
 }
 
@@ -402,7 +405,7 @@ __global__ void k_il_wave(const uint32_t* order, const int* il_start, const int2
 // offset first, then the earliest such entry, else the earliest entry).  This
 // only permutes each target's list: 228 -> 208.6 ms of M2L on 1M segments,
 // for about 6 ms of tree build.  One wave per group of 8 targets.
-template <int kUnits, int kHalf>
+template <int kUnits, int kHalf, bool CODE9>
 __global__ void k_il_bank(const int* lenq, const int* wbase, int64_t n, int64_t ngroups, uint32_t* ilw) {
   __shared__ uint32_t ent[8][kNumFar + 1];
   __shared__ int used[16];
@@ -429,7 +432,7 @@ __global__ void k_il_bank(const int* lenq, const int* wbase, int64_t n, int64_t 
       if (s >= len[j]) continue;
       int best = -1;  // key: priority * 256 + (255 - offset from s)
       for (int c = s + lane; c < len[j]; c += 64) {
-        const int code = (int)((ent[j][c] >> 23) & 0xFFu);
+        const int code = (int)((ent[j][c] >> 23) & (CODE9 ? 0x1FFu : 0xFFu));
         const int g0 = (kUnits * code) & 15, g1 = (g0 + kHalf) & 15;
         const int u0 = used[g0], u1 = used[g1];
         int pr = 0;
@@ -443,7 +446,7 @@ __global__ void k_il_bank(const int* lenq, const int* wbase, int64_t n, int64_t 
         const uint32_t e = ent[j][pick];
         ent[j][pick] = ent[j][s];
         ent[j][s] = e;
-        const int code = (int)((e >> 23) & 0xFFu);
+        const int code = (int)((e >> 23) & (CODE9 ? 0x1FFu : 0xFFu));
         const int g0 = (kUnits * code) & 15;
         used[g0] = code;
         used[(g0 + kHalf) & 15] = code;
@@ -686,15 +689,19 @@ int build_tree_impl(dfmm_plan* pl, const double* seg, int64_t nseg, hipStream_t 
       }
       DFMM_HIP(hipMalloc(&L.ilw, sizeof(uint32_t) * kWaveTargets * std::max<int64_t>(steps, 1)));
       DFMM_HIP(hipMemsetAsync(L.ilw, 0, sizeof(uint32_t) * kWaveTargets * std::max<int64_t>(steps, 1), st));
-      k_il_wave<<<nb(L.n, 128), 128, 0, st>>>(L.order, L.il_start, L.il, L.wbase, (int)L.n, L.ilw);
+      if (pl->h16)
+        k_il_wave<true><<<nb(L.n, 128), 128, 0, st>>>(L.order, L.il_start, L.il, L.wbase, (int)L.n, L.ilw);
+      else
+        k_il_wave<false><<<nb(L.n, 128), 128, 0, st>>>(L.order, L.il_start, L.il, L.wbase, (int)L.n, L.ilw);
       DFMM_LAUNCH_CHECK();
       {
         const int64_t ng = nw * (kWaveTargets / 8);
         // 16-byte units per offset and lane 1's start, in the layout of the spectra in LDS
         if (pl->h16)
-          k_il_bank<kKOffsetH / 4, kKHalfH / 4><<<(unsigned)ng, 64, 0, st>>>(L.lenq, L.wbase, L.n, ng, L.ilw);
+          k_il_bank<kKOffsetH / 4, kKHalfH / 4, true><<<(unsigned)ng, 64, 0, st>>>(L.lenq, L.wbase, L.n, ng, L.ilw);
         else
-          k_il_bank<kKOffsetF / 2, kKHalfF / 2><<<(unsigned)ng, 64, 0, st>>>(L.lenq, L.wbase, L.n, ng, L.ilw);
+          k_il_bank<kKOffsetF / 2, kKHalfF / 2, false><<<(unsigned)ng, 64, 0, st>>>(L.lenq, L.wbase, L.n, ng,
+                                                                                   L.ilw);
         DFMM_LAUNCH_CHECK();
       }
       DFMM_HIP(hipStreamSynchronize(st));
@@ -752,7 +759,7 @@ int build_tree_impl(dfmm_plan* pl, const double* seg, int64_t nseg, hipStream_t 
   DFMM_HIP(hipMalloc(&t->sig, sizeof(double) * 6 * N));
   size_t bKx = 0;
   if (pl->sym) {  // one level of expanded offset spectra (the plan keeps the 16 classes)
-    bKx = pl->h16 ? (size_t)pl->nf * kNumCanon * kKOffsetH * sizeof(uint32_t)
+    bKx = pl->h16 ? (size_t)pl->nf * kNumOffsets * kKOffsetH * sizeof(uint32_t)
                   : (size_t)pl->nf * kNumCanon * (pl->mixed ? kKOffsetF : 54) * 2 * es;
     DFMM_HIP(hipMalloc(&t->kexp, bKx));
   }
