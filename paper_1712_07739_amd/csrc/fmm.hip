@@ -565,7 +565,8 @@ k_hadamard(const cplx<float>* What, const cplx<float>* Khat, const int* lenq, co
 // pair of f16 (real in the low half) and the products done by
 // v_dot2_f32_f16, two multiply-adds with f32 accumulation per instruction:
 //   K w:  re = (kr, ki).(wr, -wi),  im = (kr, ki).(wi, wr),
-// each source value prepared once per pair (a sign flip and a half swap).
+// the sign of the real part's product taken by the instruction's neg_hi
+// modifier and the imaginary part's operand half-swapped once per pair.
 // LDS holds the spectra of all 316 offsets (the mirrored offset -o as -conj
 // of o), so there is no per-pair mirror handling; a list entry's bits 23..31
 // are the offset's slot 2 id + mirror.  The spectra take 74 KB of LDS per
@@ -636,13 +637,13 @@ k_hadamard16(const uint32_t* What, const uint32_t* Khat, const int* lenq, const 
     }
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-      const half2v u = __builtin_bit_cast(half2v, w[k] ^ 0x80000000u);                   // (wr, -wi)
       const half2v q = __builtin_bit_cast(half2v, __builtin_amdgcn_alignbit(w[k], w[k], 16));  // (wi, wr)
 #pragma unroll
       for (int r = 0; r < 3; ++r) {
-        const half2v kv = __builtin_bit_cast(half2v, kk[9 * r + k]);
-        ar[r] = __builtin_amdgcn_fdot2(kv, u, ar[r], false);
-        ai[r] = __builtin_amdgcn_fdot2(kv, q, ai[r], false);
+        // re: (kr, ki).(wr, -wi), the sign taken by the instruction's neg_hi
+        // modifier on the source operand
+        asm("v_dot2_f32_f16 %0, %1, %2, %0 neg_hi:[0,1,0]" : "+v"(ar[r]) : "v"(kk[9 * r + k]), "v"(w[k]));
+        ai[r] = __builtin_amdgcn_fdot2(__builtin_bit_cast(half2v, kk[9 * r + k]), q, ai[r], false);
       }
     }
   };
