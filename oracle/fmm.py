@@ -39,6 +39,26 @@ def lagrange_basis(p: int, t: np.ndarray) -> np.ndarray:
     return out
 
 
+def lsq_projector(p, d):
+    """Stabilised interpolation on the p equispaced nodes (Sec. 4.3, the
+    remark after Alg. fast_sum): the least-squares polynomial of degree d
+    fitted to the node values.  Its values at the nodes are P f with
+    P = V (V^T V)^{-1} V^T, V[m, k] = phi_k(x_m) for a basis phi_0..phi_d of
+    the polynomials of degree <= d (Legendre on [-1, 1] here; P does not
+    depend on the basis).  As the fit has degree <= p-1 it is reproduced by
+    the Lagrange interpolant through the nodes, so the fitted function is
+    sum_m ell_m(x) (P f)_m: the least-squares basis is the Lagrange basis
+    times P.  d = p - 1 gives P = I."""
+    x = np.linspace(-1.0, 1.0, p)
+    V = np.polynomial.legendre.legvander(x, d)  # [p, d+1]
+    return V @ np.linalg.solve(V.T @ V, V.T)
+
+
+def _project(P, a):
+    """Apply P to each of the three node axes of a[..., p, p, p]."""
+    return np.einsum("ai,bj,ck,...ijk->...abc", P, P, P, a)
+
+
 def _kern(kernel, x):
     """Kernel values [n, 6, 9] at displacements x[n, 3]."""
     if callable(kernel):
@@ -54,11 +74,18 @@ def _direct(kernel, xt, ys, q):
     return stress(xt, ys, q, kernel)
 
 
-def fmm_stress(y, q, kernel, p, D, box_lo, box_size, return_parts=False):
+def fmm_stress(y, q, kernel, p, D, box_lo, box_size, return_parts=False, lsq_degree=None):
     """Stress at every point y[N,3] from all points (y, q[N,9]) by Alg. lagrange.
 
     kernel is a packed medium (numpy array, see ``oracle.medium``) or a
-    callable x[n,3] -> K[n,6,9].  Returns sigma[N,6] (Voigt order)."""
+    callable x[n,3] -> K[n,6,9].  Returns sigma[N,6] (Voigt order).
+
+    lsq_degree = d switches the interpolant to the least-squares polynomial
+    of degree d on the same nodes (``lsq_projector``): the multipole weights
+    enter the M2L as P W (P on every axis), and the local values of every
+    cell are replaced by P s before they are passed to the children (L2L)
+    or to the points (L2P).  The upward pass keeps the Lagrange weights,
+    whose parent transfer is exact (M2M)."""
     y = np.asarray(y, dtype=np.float64).reshape(-1, 3)
     q = np.asarray(q, dtype=np.float64).reshape(-1, 9)
     N = y.shape[0]
@@ -103,6 +130,8 @@ def fmm_stress(y, q, kernel, p, D, box_lo, box_size, return_parts=False):
             ip = index[lvl][tuple(cc // 2)]
             b = cc % 2
             W[lvl][ip] += np.einsum("im,jn,ko,wmno->wijk", S[b[0]], S[b[1]], S[b[2]], W[lvl + 1][ic])
+    Pm = None if lsq_degree is None else lsq_projector(p, lsq_degree)
+    Win = W if Pm is None else {lvl: _project(Pm, W[lvl]) for lvl in W}
     # -- M2L (step 2), dense sum over nodes (Eq. m2l)
     s = {lvl: np.zeros((len(cells[lvl]), 6, p, p, p)) for lvl in cells}
     g = np.arange(p)
@@ -134,14 +163,18 @@ def fmm_stress(y, q, kernel, p, D, box_lo, box_size, return_parts=False):
                           dd[2][None, None, :, None, None, :]]  # [l1,l2,l3,m1,m2,m3,6,9]
                 ops[o] = op
             pl = np.asarray(pl)
-            contrib = np.einsum("abcdefxw,nwdef->nxabc", ops[o], W[lvl][pl[:, 1]])
+            contrib = np.einsum("abcdefxw,nwdef->nxabc", ops[o], Win[lvl][pl[:, 1]])
             np.add.at(s[lvl], pl[:, 0], contrib)
     # -- L2L (step 3.a)
+    if Pm is not None:
+        s[2] = _project(Pm, s[2])
     for lvl in range(3, D + 1):
         for ic, cc in enumerate(cells[lvl]):
             ip = index[lvl - 1][tuple(cc // 2)]
             b = cc % 2
             s[lvl][ic] += np.einsum("im,jn,ko,xijk->xmno", S[b[0]], S[b[1]], S[b[2]], s[lvl - 1][ip])
+        if Pm is not None:
+            s[lvl] = _project(Pm, s[lvl])
     # -- L2P (step 3.b, far part) and the near field over N(I)
     sig_far = np.zeros((N, 6))
     sig_near = np.zeros((N, 6))
@@ -162,11 +195,11 @@ def fmm_stress(y, q, kernel, p, D, box_lo, box_size, return_parts=False):
     return sig_far + sig_near
 
 
-def fmm_forces(seg, burg, kernel, p, D, box_lo, box_size, nq=3, return_parts=False):
+def fmm_forces(seg, burg, kernel, p, D, box_lo, box_size, nq=3, return_parts=False, lsq_degree=None):
     """End-point forces f[N_s, 2, 3] with the stress from ``fmm_stress``."""
     seg = np.asarray(seg, dtype=np.float64).reshape(-1, 2, 3)
     y, q = points(seg, burg, nq)
-    out = fmm_stress(y, q, kernel, p, D, box_lo, box_size, return_parts=return_parts)
+    out = fmm_stress(y, q, kernel, p, D, box_lo, box_size, return_parts=return_parts, lsq_degree=lsq_degree)
     tgt = np.arange(seg.shape[0])
     if return_parts:
         sig, sf, sn = out

@@ -47,6 +47,38 @@ def test_fmm_exact_for_polynomial_kernels(p, D):
     assert np.abs(s2 - ref2).max() > 1e-6 * np.abs(ref2).max()
 
 
+@pytest.mark.parametrize("p,d,D", [(4, 2, 3), (4, 1, 3), (3, 1, 4)])
+def test_lsq_fmm_exact_for_polynomial_kernels_of_its_degree(p, d, D):
+    """The least-squares interpolant of degree d (the stabilised scheme of
+    Sec. 4.3) reproduces polynomials of degree <= d from their node values,
+    so with such a kernel every transfer is exact and the FMM equals the
+    direct sum; a kernel of degree d + 1 is not reproduced (while the plain
+    Lagrange FMM with the same p, of degree p - 1 > d, still reproduces it)."""
+    seg, b = synth.make_loops(4, 0.05, 0.15, 21)
+    y, q = oracle.points(seg, b)
+    K = poly_kernel(d + 1, 7)  # degree d in each coordinate
+    ref = direct_numpy(K, y, q)
+    s = oracle.fmm_stress(y, q, K, p, D, BOX_LO, BOX, lsq_degree=d)
+    assert np.abs(s - ref).max() <= 1e-10 * np.abs(ref).max()
+    K2 = poly_kernel(d + 2, 8)  # degree d + 1
+    ref2 = direct_numpy(K2, y, q)
+    s2 = oracle.fmm_stress(y, q, K2, p, D, BOX_LO, BOX, lsq_degree=d)
+    assert np.abs(s2 - ref2).max() > 1e-6 * np.abs(ref2).max()
+    s3 = oracle.fmm_stress(y, q, K2, p, D, BOX_LO, BOX)
+    assert np.abs(s3 - ref2).max() <= 1e-10 * np.abs(ref2).max()
+
+
+def test_lsq_of_full_degree_is_the_lagrange_fmm():
+    """d = p - 1: the least-squares fit through p nodes is the interpolant."""
+    seg, b = synth.make_loops(8, 0.01, 0.05, 4)
+    med = oracle.medium(*synth.loops.ISO, 1e-3)
+    f_lag = oracle.fmm_forces(seg, b, med, 4, 3, BOX_LO, BOX)
+    f_lsq = oracle.fmm_forces(seg, b, med, 4, 3, BOX_LO, BOX, lsq_degree=3)
+    assert oracle.rel_err(f_lsq, f_lag) <= 1e-13
+    P = oracle.fmm.lsq_projector(6, 3)
+    assert np.allclose(P @ P, P, atol=1e-13) and np.allclose(P, P.T, atol=1e-14)
+
+
 def test_fmm_all_near_equals_direct():
     # every point within the 2x2x2 centre leaves at depth 2: no M2L pair exists
     seg, b = synth.make_loops(5, 0.02, 0.05, 3)
