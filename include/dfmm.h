@@ -103,11 +103,21 @@ typedef struct {
                          f16 operands with f32 accumulation                   */
   int m2l_mode;       /* DFMM_M2L_FFT or DFMM_M2L_FFT_SYM (operator store)       */
   int aniso_kernel;   /* DFMM_KERNEL_EXACT or DFMM_KERNEL_SURROGATE              */
+  int lsq_degree;     /* 0: Lagrange interpolation on the p equispaced nodes
+                         (degree p-1).  d in 1..p-1: the stabilised scheme of
+                         Sec. 4.3, the least-squares polynomial of degree d
+                         fitted to the node values (the M2L takes the fit's
+                         node values of each W, and L2L/L2P those of each
+                         local expansion; M2M and P2M stay Lagrange);
+                         DFMM_LSQ_AUTO: the largest d < 2 sqrt(p), which is
+                         p-1 (plain interpolation) for p < 6.  Degree p-1 is
+                         run as 0.                                             */
 } dfmm_params;
+#define DFMM_LSQ_AUTO (-1)
 
 /* Fill *p with defaults: order 5, depth 4, isotropic mu = 1, nu = 0.3,
  * a = 1e-3, root cube [-0.05, 1.05]^3, n_quad 3, n_circle 64, FP64,
- * DFMM_M2L_FFT, DFMM_KERNEL_EXACT. */
+ * DFMM_M2L_FFT, DFMM_KERNEL_EXACT, Lagrange interpolation (lsq_degree 0). */
 void dfmm_default_params(dfmm_params* p);
 
 /* Precompute a plan (Sec. 4.1, Eq. m2l and Theorem 1): for every level 2..D

@@ -55,6 +55,7 @@ void dfmm_default_params(dfmm_params* p) {
   p->precision = DFMM_FP64;
   p->m2l_mode = DFMM_M2L_FFT;
   p->aniso_kernel = DFMM_KERNEL_EXACT;
+  p->lsq_degree = 0;
 }
 
 const char* dfmm_status_string(int s) {
@@ -102,6 +103,10 @@ int dfmm_fmm_setup(const dfmm_params* prm, void* stream, dfmm_plan** out) {
     set_error("fmm_setup: m2l_mode must be DFMM_M2L_FFT or DFMM_M2L_FFT_SYM");
     return DFMM_E_ARG;
   }
+  if (q.lsq_degree < DFMM_LSQ_AUTO || q.lsq_degree > q.order - 1) {
+    set_error("fmm_setup: lsq_degree must be DFMM_LSQ_AUTO, 0 (Lagrange) or in [1, order - 1]");
+    return DFMM_E_ARG;
+  }
   if (q.aniso_kernel != DFMM_KERNEL_EXACT && q.aniso_kernel != DFMM_KERNEL_SURROGATE) {
     set_error("fmm_setup: aniso_kernel must be DFMM_KERNEL_EXACT or DFMM_KERNEL_SURROGATE");
     return DFMM_E_ARG;
@@ -115,6 +120,14 @@ int dfmm_fmm_setup(const dfmm_params* prm, void* stream, dfmm_plan** out) {
   pl->D = q.depth;
   pl->mixed = q.precision != DFMM_FP64;
   pl->h16 = q.precision == DFMM_MIXED_F16;
+  if (q.lsq_degree == DFMM_LSQ_AUTO) {  // largest d < 2 sqrt(p)
+    int d = 0;
+    while ((d + 1) * (d + 1) < 4 * q.order) ++d;
+    pl->lsq = std::min(d, q.order - 1);
+  } else {
+    pl->lsq = q.lsq_degree;
+  }
+  if (pl->lsq == q.order - 1) pl->lsq = 0;  // the fit through all p nodes is the interpolant
   pl->sym = q.m2l_mode == DFMM_M2L_FFT_SYM;
   pl->iso = std::fabs(2.0 * q.c44 - (q.c11 - q.c12)) <= 1e-12 * std::fabs(q.c44);
   if (pl->iso) {
@@ -152,7 +165,7 @@ void dfmm_plan_destroy(dfmm_plan* pl) {
   hipFree(pl->sur.w); hipFree(pl->sur.g); hipFree(pl->sur.m); hipFree(pl->sur.v); hipFree(pl->sur.mask);
   hipFree(pl->sur.wi); hipFree(pl->sur.bi); hipFree(pl->sur.split);
   for (auto& l : pl->lev) hipFree(l.khat);
-  hipFree(pl->t64.S); hipFree(pl->t64.cs); hipFree(pl->t64.tw);
+  hipFree(pl->t64.S); hipFree(pl->t64.cs); hipFree(pl->t64.tw); hipFree(pl->t64.Pm); hipFree(pl->t32.Pm);
   hipFree(pl->t32.S); hipFree(pl->t32.cs); hipFree(pl->t32.tw);
   hipFree(pl->oid343); hipFree(pl->off158); hipFree(pl->cls16); hipFree(pl->symtab);
   delete pl;
@@ -455,10 +468,10 @@ int dfmm_plan_info(const dfmm_plan* pl, char* json, size_t cap) {
       "\"mu\": %.17g, \"nu\": %.17g, \"mem_unif_fp64_bytes_per_level\": %.0f, "
       "\"m2l_mode\": %d, \"stored_offsets\": %d, \"generator_fp64_bytes_per_level\": %zu, "
       "\"spectra_bytes\": %zu, \"levels_stored\": %d, \"setup_ms\": %.3f, \"n_quad\": %d, \"n_circle\": %d, "
-      "\"n_circle_float\": %d, \"float_rule_err\": %.3g, \"surrogate_in_use\": %d}",
+      "\"n_circle_float\": %d, \"float_rule_err\": %.3g, \"surrogate_in_use\": %d, \"lsq_degree\": %d}",
       p, pl->D, pl->n, pl->nf, pl->iso, pl->mixed, pl->mu, pl->nu, mem_unif, pl->sym,
       pl->sym ? kNumSymClass : kNumCanon, pl->gen_bytes / (size_t)std::max(1, pl->D - 1), pl->khat_bytes, pl->D - 1,
-      pl->setup_ms, pl->quad.n, pl->prm.n_circle, 2 * pl->nhalf32, pl->float_rule_err, sur_dev(pl).on);
+      pl->setup_ms, pl->quad.n, pl->prm.n_circle, 2 * pl->nhalf32, pl->float_rule_err, sur_dev(pl).on, pl->lsq);
   if (w < 0 || (size_t)w >= cap) { set_error("plan_info: buffer too small"); return DFMM_E_ARG; }
   return DFMM_OK;
 }

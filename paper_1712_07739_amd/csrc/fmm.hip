@@ -31,12 +31,18 @@ static inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / 
 
 template <typename T>
 __device__ __forceinline__ T lagr(int p, int i, T t) {
-  // ell_i(t) for nodes k/(p-1), k = 0..p-1
+  // ell_i(t) for nodes k/(p-1), k = 0..p-1: the numerator's product, then
+  // one division by the integer product of (i - k) (exact in int, at most
+  // 7! in magnitude), not one division per factor
   T v = T(1);
+  int den = 1;
   T tp = t * T(p - 1);
   for (int k = 0; k < p; ++k)
-    if (k != i) v *= (tp - T(k)) / T(i - k);
-  return v;
+    if (k != i) {
+      v *= tp - T(k);
+      den *= i - k;
+    }
+  return v / T(den);
 }
 
 // ---------------------------------------------------------------- points
@@ -194,6 +200,27 @@ __global__ void k_l2l(const int* parent, const uint32_t* key, const T* sp, T* sc
   __syncthreads();
   T* dst = sc + (int64_t)c * 6 * p3;
   pass_axis<T, true, true, P, 0>(A, dst, Sg, (bits >> 2) & 1, 6);
+}
+
+// Stabilised interpolation (Sec. 4.3): the least-squares projector Pm of the
+// node values (symmetric, p x p) along the three axes of every cell of a
+// level, in place, ncomp components per cell.  Applied to the multipole
+// weights that enter the M2L and to the local values before they go to the
+// children or the points.  One block per cell.
+template <typename T, int P>
+__global__ void k_project(T* data, int ncomp, const T* __restrict__ Pm) {
+  extern __shared__ unsigned char shraw[];
+  constexpr int p3 = P * P * P;
+  T* A = (T*)shraw;
+  T* B = A + ncomp * p3;
+  T* src = data + (int64_t)blockIdx.x * ncomp * p3;
+  for (int e = threadIdx.x; e < ncomp * p3; e += blockDim.x) A[e] = src[e];
+  __syncthreads();
+  pass_axis<T, false, false, P, 2>(A, B, Pm, 0, ncomp);
+  __syncthreads();
+  pass_axis<T, false, false, P, 1>(B, A, Pm, 0, ncomp);
+  __syncthreads();
+  pass_axis<T, false, false, P, 0>(A, src, Pm, 0, ncomp);
 }
 
 // Blocks are dispatched round-robin over the 8 XCDs; this bijection of
@@ -1518,6 +1545,22 @@ static void tree_pass(int p, bool up, unsigned blocks, size_t shm, const int* a,
   }
 }
 
+template <typename T>
+static void project(int p, unsigned blocks, T* data, int ncomp, const T* Pm, hipStream_t st) {
+  const size_t shm = sizeof(T) * 2 * ncomp * (size_t)p * p * p;
+#define PROJ(P_) k_project<T, P_><<<blocks, 256, shm, st>>>(data, ncomp, Pm)
+  switch (p) {
+    case 2: PROJ(2); break;
+    case 3: PROJ(3); break;
+    case 4: PROJ(4); break;
+    case 5: PROJ(5); break;
+    case 6: PROJ(6); break;
+    case 7: PROJ(7); break;
+    default: PROJ(8); break;
+  }
+#undef PROJ
+}
+
 template <typename T, int... Ps>
 static void dft_lds_attrs(std::integer_sequence<int, Ps...>) {
   const int mx = 160 * 1024;
@@ -1526,6 +1569,7 @@ static void dft_lds_attrs(std::integer_sequence<int, Ps...>) {
   ((void)hipFuncSetAttribute((const void*)k_idft<T, Ps + 2>, hipFuncAttributeMaxDynamicSharedMemorySize, mx), ...);
   ((void)hipFuncSetAttribute((const void*)k_m2m<T, Ps + 2>, hipFuncAttributeMaxDynamicSharedMemorySize, mx), ...);
   ((void)hipFuncSetAttribute((const void*)k_l2l<T, Ps + 2>, hipFuncAttributeMaxDynamicSharedMemorySize, mx), ...);
+  ((void)hipFuncSetAttribute((const void*)k_project<T, Ps + 2>, hipFuncAttributeMaxDynamicSharedMemorySize, mx), ...);
 }
 
 struct StageTimer {
@@ -1668,6 +1712,11 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
                                W + Lp.off * 9 * p3, tb.S, st));
     }
   }
+  // stabilised interpolation: the M2L takes the projected weights (the
+  // upward pass above used the Lagrange ones, whose parent transfer is exact)
+  if (pl->lsq > 0)
+    for (int l = 2; l <= D; ++l)
+      if (t->lv[l].n > 0) STAGE(1, project<T>(p, (unsigned)t->lv[l].n, W + t->lv[l].off * 9 * p3, 9, tb.Pm, st));
   // DFMM_MIXED_F16: each level's largest weight, for the f16 scale of its spectra
   const bool h16 = std::is_same<T, float>::value && pl->h16;
   if (h16) {
@@ -1715,12 +1764,17 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
     STAGE(4, dft<T>(p, false, (unsigned)Lv.n, Shat, Lv.n, tb.tw, s + Lv.off * 6 * p3, wm, ksc, st));
   }
   {
+    // stabilised interpolation: each level's local values are projected
+    // before they go to the children (L2L) or the points (L2P)
+    if (pl->lsq > 0 && t->lv[2].n > 0)
+      STAGE(5, project<T>(p, (unsigned)t->lv[2].n, s + t->lv[2].off * 6 * p3, 6, tb.Pm, st));
     size_t shm = es * 12 * p3;
     for (int l = 3; l <= D; ++l) {
       const auto& Lv = t->lv[l];
       const auto& Lp = t->lv[l - 1];
       STAGE(5, tree_pass<T>(p, false, (unsigned)Lv.n, shm, Lv.parent, nullptr, Lv.key, s + Lp.off * 6 * p3,
                                s + Lv.off * 6 * p3, tb.S, st));
+      if (pl->lsq > 0 && Lv.n > 0) STAGE(5, project<T>(p, (unsigned)Lv.n, s + Lv.off * 6 * p3, 6, tb.Pm, st));
     }
   }
   if (nst != st) {

@@ -86,6 +86,7 @@ struct Tables {
   T* S = nullptr;   // [2][p][p]: S[b][i][m] = parent basis i at child node m of octant bit b
   T* cs = nullptr;  // circle cos/sin [nhalf][2]
   T* tw = nullptr;  // DFT twiddles [n][2]: exp(-2 pi i k / n)
+  T* Pm = nullptr;  // [p][p] least-squares projector of the node values (stabilised interpolation)
 };
 
 // Trained network of the anisotropic-kernel surrogate and its residual gate.
@@ -153,6 +154,7 @@ struct dfmm_plan {
   int* off158 = nullptr;   // device [158][3]: canonical id -> offset
   int sym = 0;             // operator store: 0 = 158 offset spectra, 1 = 16 class spectra
   int h16 = 0;             // DFMM_MIXED_F16: f16 operands in the M2L product
+  int lsq = 0;             // least-squares degree of the stabilised interpolation (0: Lagrange)
   int* cls16 = nullptr;    // device [16][3]: class representatives (|o| sorted, descending)
   dfmm::SymEntry* symtab = nullptr;  // device [158]: class and R of each canonical id
   size_t gen_bytes = 0;    // kernel values behind the stored spectra (real generators, FP64)

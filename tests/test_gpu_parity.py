@@ -441,3 +441,81 @@ def test_full_size_f16_m2l_vs_oracle_samples(env):
     err = oracle.rel_err(f[tgt], ref)
     print("cubic1m p=7 f16 M2L: rel err vs oracle on %d segments = %.3e" % (len(tgt), err))
     assert err <= 1e-4
+
+
+# ------------------------------------------- stabilised interpolation (LS)
+def lsq_auto(p):
+    """The degree DFMM_LSQ_AUTO picks: the largest d < 2 sqrt(p), the bound
+    Sec. 4.3 gives for a stable least-squares fit on p equispaced nodes, at
+    most p - 1 (which is the interpolant itself: the plan reports 0)."""
+    d = 0
+    while (d + 1) ** 2 < 4 * p:
+        d += 1
+    d = min(d, p - 1)
+    return 0 if d == p - 1 else d
+
+
+@pytest.mark.parametrize("name,C,nloops,p,D,d,mode", [
+    ("iso-p4-D3-d2", ISO, 40, 4, 3, 2, 0),
+    ("cubic-p6-D3-auto", CUB, 10, 6, 3, -1, 1),
+    ("iso-p7-D3-d4", ISO, 6, 7, 3, 4, 1),
+    ("cubic-p6-D4-d3", CUB, 8, 6, 4, 3, 0),
+])
+def test_lsq_fmm_matches_oracle_lsq_fmm(env, name, C, nloops, p, D, d, mode):
+    """Least-squares interpolation of degree d on the p equispaced nodes
+    (Sec. 4.3): the GPU FMM against the oracle's FMM with the same
+    projector, in FP64 (<= 1e-10), single precision (<= 2e-5) and with f16
+    M2L operands (the f16 bar of the Lagrange path)."""
+    torch, pk, dev = env
+    seg, b = synth.make_loops(nloops, 0.01, 0.05, 23)
+    med = oracle.medium(*C, 1e-3)
+    deg = lsq_auto(p) if d < 0 else d
+    assert deg > 0
+    ref, ref_far, _ = oracle.fmm_forces(seg, b, med, p, D, BOX_LO, BOX, return_parts=True, lsq_degree=deg)
+    share = float(np.linalg.norm(ref_far) / np.linalg.norm(ref))
+    ts, tb = torch.tensor(seg, device=dev), torch.tensor(b, device=dev)
+    bars = {0: 1e-10, 1: 2e-5, 2: 2e-5 + 2 * F16_U * share}
+    for prec, bar in bars.items():
+        plan = pk.Plan(pk.make_params(p, D, *C, 1e-3, BOX_LO, BOX, precision=prec, m2l_mode=mode, lsq_degree=d))
+        assert plan.info()["lsq_degree"] == deg
+        tree = pk.Tree(plan, ts)
+        f = pk.fmm_forces(plan, tree, ts, tb).cpu().numpy()
+        err = oracle.rel_err(f, ref)
+        print("%s precision %d: LS FMM vs oracle LS FMM %.2e (bar %.2e)" % (name, prec, err, bar))
+        assert err <= bar, (name, prec)
+
+
+def test_lsq_of_full_degree_is_the_lagrange_path(env):
+    """d = p - 1 is interpolation: the plan runs the Lagrange path and the
+    forces are bit-identical to it."""
+    torch, pk, dev = env
+    seg, b = synth.make_loops(20, 0.01, 0.05, 5)
+    ts, tb = torch.tensor(seg, device=dev), torch.tensor(b, device=dev)
+    out = []
+    for d in (0, 4):
+        plan = pk.Plan(pk.make_params(5, 3, *CUB, 1e-3, BOX_LO, BOX, precision=1, lsq_degree=d))
+        assert plan.info()["lsq_degree"] == 0
+        tree = pk.Tree(plan, ts)
+        out.append(pk.fmm_forces(plan, tree, ts, tb).cpu().numpy())
+    assert np.array_equal(out[0], out[1])
+
+
+def test_lsq_error_vs_direct(env):
+    """Accuracy of the stabilised FMM against the FP64 direct sum, next to
+    the Lagrange FMM of the same order: printed for each order, and the
+    least-squares error still falls with the order (orders below 6 have
+    no degree d < 2 sqrt(p) under p - 1 and run the Lagrange path)."""
+    seg, b = synth.make_loops(50, 0.01, 0.05, 1)
+    ref = oracle.direct_forces(seg, b, oracle.medium(*ISO, 1e-3))
+    torch, pk, dev = env
+    ts, tb = torch.tensor(seg, device=dev), torch.tensor(b, device=dev)
+    errs = []
+    for p in (4, 5, 6, 7, 8):
+        row = []
+        for d in (0, -1):
+            plan = pk.Plan(pk.make_params(p, 3, *ISO, 1e-3, BOX_LO, BOX, precision=0, lsq_degree=d))
+            tree = pk.Tree(plan, ts)
+            row.append(oracle.rel_err(pk.fmm_forces(plan, tree, ts, tb).cpu().numpy(), ref))
+        print("p=%d: Lagrange %.3e, least squares (d=%d) %.3e" % (p, row[0], lsq_auto(p), row[1]))
+        errs.append(row[1])
+    assert errs[-1] < errs[0] / 4
