@@ -11,25 +11,44 @@ namespace dfmm {
 static thread_local std::string g_err;
 void set_error(const std::string& msg) { g_err = msg; }
 
-// Gauss-Legendre nodes/weights on [-1, 1]: eigenvalue-free Newton iteration
-// on P_n (three-term recurrence).
+// Gauss-Legendre nodes and weights on [-1, 1] from the Jacobi matrix of the
+// Legendre polynomials (zero diagonal, off-diagonal b_k = k / sqrt(4k^2 - 1)):
+// the nodes are its eigenvalues, found one by one by bisection on the Sturm
+// count of the LDL^T pivots of J - x I; the weight of a node x is the
+// Christoffel number 1 / sum_k phi_k(x)^2 over the orthonormal polynomials
+// phi_0 .. phi_{n-1}, which the same b_k generate.
 static void gauss_legendre(int n, double* u, double* w) {
-  for (int i = 0; i < n; ++i) {
-    double x = std::cos(M_PI * (i + 0.75) / (n + 0.5)), d = 1.0;
-    for (int it = 0; it < 100; ++it) {
-      double a = 1.0, b = x;
-      for (int k = 2; k <= n; ++k) {
-        double c = ((2.0 * k - 1.0) * x * b - (k - 1.0) * a) / k;
-        a = b;
-        b = c;
-      }
-      d = n * (x * b - a) / (x * x - 1.0);
-      double dx = b / d;
-      x -= dx;
-      if (std::fabs(dx) < 1e-16) break;
+  auto beta = [](int k) { return k / std::sqrt(4.0 * k * k - 1.0); };
+  auto below = [&](double x) {  // eigenvalues of J smaller than x
+    int c = 0;
+    double d = -x;
+    for (int k = 0; k < n; ++k) {
+      if (k > 0) d = -x - beta(k) * beta(k) / d;
+      if (d == 0.0) d = -1e-300;
+      if (d < 0.0) ++c;
     }
-    u[n - 1 - i] = x;
-    w[n - 1 - i] = 2.0 / ((1.0 - x * x) * d * d);
+    return c;
+  };
+  for (int i = 0; i < n; ++i) {
+    double lo = -1.0, hi = 1.0;  // the i-th smallest eigenvalue lies in [lo, hi)
+    while (hi - lo > 0.0) {
+      const double mid = 0.5 * (lo + hi);
+      if (mid <= lo || mid >= hi) break;
+      if (below(mid) > i)
+        hi = mid;
+      else
+        lo = mid;
+    }
+    const double x = 0.5 * (lo + hi);
+    double prev = 0.0, cur = 1.0 / std::sqrt(2.0), sum = cur * cur;
+    for (int k = 0; k + 1 < n; ++k) {
+      const double next = (x * cur - (k > 0 ? beta(k) * prev : 0.0)) / beta(k + 1);
+      prev = cur;
+      cur = next;
+      sum += cur * cur;
+    }
+    u[i] = x;
+    w[i] = 1.0 / sum;
   }
 }
 }  // namespace dfmm
