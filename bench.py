@@ -263,7 +263,7 @@ def main():
     if not args.no_fp64_compare and prec != pk.DFMM_FP64:
         if prec == pk.DFMM_MIXED_F16:
             result["mixed_f32_path"] = other_path(pk.DFMM_MIXED, "k_hadamard (f32 operands)", PEAK_FP32_VALU)
-        result["fp64_path"] = other_path(pk.DFMM_FP64, "k_hadamard3 (FP64 M2L in frequency space)", PEAK_FP64_VALU)
+        result["fp64_path"] = other_path(pk.DFMM_FP64, "k_hadamard64 (FP64 M2L in frequency space)", PEAK_FP64_VALU)
     if not args.no_cpu_baseline:
         import oracle
 

@@ -691,26 +691,20 @@ k_hadamard16(const uint32_t* What, const uint32_t* Khat, const int* lenq, const 
   for (int r = 0; r < 3; ++r) out[r] = cplx<float>{ar[r], ai[r]};
 }
 
-// Per offset 55 complex in LDS (54 used): an odd number of 16-byte units, so
-// that the lanes' reads of unrelated offsets spread over the LDS banks.
-constexpr int kKStride3 = 55;
-// Double precision keeps three lanes per target (two rows each): with twice
-// the bytes per value its LDS and register budget favour the shorter rows.
-// Each lane loads the source's whole row.  The next list entry is loaded one
-// step ahead (carried through an empty asm statement, which keeps the
-// compiler from turning it back into a load at the top of the loop), so a
-// step's source loads do not wait on its index; the index past the end of
-// the list is clamped to its last entry.  (Prefetching the source values as
-// well, with two buffers, needs 168 registers and spills.)
-constexpr int kHad3Threads = 3 * kM2LWindowD;
-template <typename T>
-__global__ void __launch_bounds__(kHad3Threads) k_hadamard3(const cplx<T>* What, const cplx<T>* Khat,
-                                                          const int* il_start, const int2* il,
-                                                          const uint32_t* order, int64_t ncell, int nf, int nwin,
-                                                          int remap, cplx<T>* Shat) {
-  static_assert(sizeof(T) == 8, "the three-lane kernel is the double-precision one");
+// The double-precision Hadamard product: the blocks, lanes, list walk and
+// source split of k_hadamard, with one 16-byte complex per LDS unit.  The
+// spectra of a frequency arrive row-major (6 x 9 per canonical offset) and
+// are put into the lanes' slot order while they are copied into LDS: half h
+// (stress rows 3h..3h+2) of offset c starts at unit 55 c + 27 h.  They take
+// 139 KB, so one block of 1024 threads (four waves per SIMD) runs per CU.
+// Per step a lane reads 27 complex spectrum values (432 B of LDS) for 108
+// double multiply-adds: LDS reads are this kernel's limit.
+constexpr int kHadThreadsD = 2 * kM2LWindowD;
+__global__ void __launch_bounds__(kHadThreadsD)
+k_hadamard64(const cplx<double>* What, const cplx<double>* Khat, const int* lenq, const int* wbase, const uint32_t* ilw,
+             const uint32_t* order, int64_t ncell, int nf, int nwin, int remap, cplx<double>* Shat) {
   extern __shared__ __align__(16) unsigned char shraw[];
-  cplx<T>* Ks = (cplx<T>*)shraw;  // [158][kKStride3]
+  cplx<double>* Ks = (cplx<double>*)shraw;  // [158][kKOffsetD]
   int win, f;
   if (remap) {
     const int64_t L = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
@@ -724,63 +718,89 @@ __global__ void __launch_bounds__(kHad3Threads) k_hadamard3(const cplx<T>* What,
     win = blockIdx.x;
     f = blockIdx.y;
   }
-  const cplx<T>* kf = Khat + (int64_t)f * kNumCanon * 54;
-  for (int e = threadIdx.x; e < kNumCanon * 54; e += blockDim.x) Ks[(e / 54) * kKStride3 + e % 54] = kf[e];
+  const cplx<double>* kf = Khat + (int64_t)f * kNumCanon * 54;
+  for (int e = threadIdx.x; e < kNumCanon * 54; e += blockDim.x) {
+    const int id = e / 54, src = e - 54 * id;
+    const int row = src / 9, k = src - 9 * row, hh = row / 3;
+    Ks[id * kKOffsetD + hh * kKHalfD + (row - 3 * hh) * 9 + had_slot_of(hh, k)] = kf[e];
+  }
   __syncthreads();
-  const int64_t tt = (int64_t)win * kM2LWindowD + threadIdx.x / 3;
-  if (tt >= ncell) return;
-  const int r0 = 2 * (threadIdx.x % 3);
+  const int64_t tt = (int64_t)win * kM2LWindowD + threadIdx.x / 2;
+  if (tt >= ncell) return;  // both lanes of a target leave together
+  const int h = threadIdx.x & 1;
   const int64_t t = order[tt];
-  T ar0 = 0, ai0 = 0, ar1 = 0, ai1 = 0;
-  const int e0 = il_start[t], e1 = il_start[t + 1];
-  const cplx<T>* wf = What + (int64_t)f * ncell * 9;
-  auto load_src = [&](int2 j, cplx<T>* v) {
-    const cplx<T>* w = wf + (int64_t)j.x * 9;
+  const int len = lenq[tt];
+  double ar[3] = {0.0, 0.0, 0.0}, ai[3] = {0.0, 0.0, 0.0};
+  // list entries as in k_hadamard: source cell in bits 0..22, canonical
+  // offset in bits 23..30, mirror flag in bit 31
+  const char* wfb = reinterpret_cast<const char*>(What + (int64_t)f * ncell * 9);
+  const char* ilb = reinterpret_cast<const char*>(ilw);
+  constexpr uint32_t kStep = kWaveTargets * sizeof(uint32_t);
+  const cplx<double>* kb = Ks + h * kKHalfD;
+  const uint32_t hoff = 64u * (uint32_t)h;
+  auto entry = [&](uint32_t eb) { return *reinterpret_cast<const uint32_t*>(ilb + eb); };
+  auto load_src = [&](uint32_t j, double2* v) {
+    // components 4h..4h+3 and 8 of the source row (144 bytes)
+    const uint32_t o = (j & 0x7FFFFFu) * 144u;
 #pragma unroll
-    for (int k = 0; k < 9; ++k) v[k] = w[k];
+    for (int k = 0; k < 4; ++k) v[k] = *reinterpret_cast<const double2*>(wfb + (o + hoff) + 16 * k);
+    v[4] = *reinterpret_cast<const double2*>(wfb + o + 128);
   };
-  auto pair = [&](int2 j, const cplx<T>* v, T use) {
-    const T sg = ((j.y & 1) ? T(-1) : T(1)) * use;
-    // rows r0 and r0+1 of the offset's 6x9 block: 18 consecutive complex values
-    const cplx<T>* K = Ks + (j.y >> 1) * kKStride3 + r0 * 9;
-    cplx<T> kk[18];
+  auto pair = [&](uint32_t j, const double2* v) {
+    // mirrored offset: conjugate the source values and negate the real part
+    // of the result
+    const uint32_t sgb = j & 0x80000000u;
+    const double sg = __hiloint2double((int)(0x3ff00000u | sgb), 0);
+    double wr[9], wi[9];
 #pragma unroll
-    for (int i = 0; i < 18; ++i) kk[i] = K[i];
-    // complex multiply-accumulate as four fused multiply-adds each
-    T cr0 = 0, ci0 = 0, cr1 = 0, ci1 = 0;
-    const T sw = (j.y & 1) ? T(-1) : T(1);
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      const T wr = v[k].re, wi = sw * v[k].im;
-      const cplx<T> k0 = kk[k], k1 = kk[9 + k];
-      cr0 = fma(k0.re, wr, cr0);
-      cr0 = fma(-k0.im, wi, cr0);
-      ci0 = fma(k0.re, wi, ci0);
-      ci0 = fma(k0.im, wr, ci0);
-      cr1 = fma(k1.re, wr, cr1);
-      cr1 = fma(-k1.im, wi, cr1);
-      ci1 = fma(k1.re, wi, ci1);
-      ci1 = fma(k1.im, wr, ci1);
+    for (int k = 0; k < 5; ++k) {
+      wr[k] = v[k].x;
+      wi[k] = __hiloint2double(__double2hiint(v[k].y) ^ (int)sgb, __double2loint(v[k].y));
     }
-    ar0 = fma(sg, cr0, ar0);
-    ai0 = fma(use, ci0, ai0);
-    ar1 = fma(sg, cr1, ar1);
-    ai1 = fma(use, ci1, ai1);
+    // swap halves with the neighbouring lane (quad permutation 1, 0, 3, 2)
+    auto swap = [](double x) {
+      const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), 0xB1, 0xF, 0xF, false);
+      const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), 0xB1, 0xF, 0xF, false);
+      return __hiloint2double(hi, lo);
+    };
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      wr[5 + k] = swap(wr[k]);
+      wi[5 + k] = swap(wi[k]);
+    }
+    const cplx<double>* K = kb + ((j >> 23) & 0xFFu) * (uint32_t)kKOffsetD;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      double cr = 0.0, ci = 0.0;
+#pragma unroll
+      for (int s = 0; s < 9; ++s) {
+        const double2 q = *reinterpret_cast<const double2*>(K + 9 * r + s);
+        cr = fma(q.x, wr[s], cr);
+        cr = fma(-q.y, wi[s], cr);
+        ci = fma(q.x, wi[s], ci);
+        ci = fma(q.y, wr[s], ci);
+      }
+      ar[r] = fma(sg, cr, ar[r]);
+      ai[r] += ci;
+    }
   };
-  if (e0 < e1) {  // the three lanes of a target run the same iterations
-    int2 jo = il[e0];
-    for (int e = e0; e < e1; ++e) {
-      const int2 jn = il[min(e + 1, e1 - 1)];
-      cplx<T> v[9];
+  // next entry one step ahead, as in k_hadamard; the two lanes of a target
+  // run the same iterations
+  if (len > 0) {
+    uint32_t eb = kStep * (uint32_t)wbase[tt / kWaveTargets] + sizeof(uint32_t) * (uint32_t)(tt % kWaveTargets);
+    uint32_t jo = entry(eb);
+    for (int e = 0; e < len; ++e, eb += kStep) {
+      const uint32_t jn = entry(eb + kStep);
+      double2 v[5];
       load_src(jo, v);
-      pair(jo, v, T(1));
+      pair(jo, v);
       jo = jn;
       asm volatile("" : "+v"(jo));
     }
   }
-  cplx<T>* out = Shat + ((int64_t)f * ncell + t) * 6 + r0;
-  out[0] = cplx<T>{ar0, ai0};
-  out[1] = cplx<T>{ar1, ai1};
+  cplx<double>* out = Shat + ((int64_t)f * ncell + t) * 6 + 3 * h;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) out[r] = cplx<double>{ar[r], ai[r]};
 }
 
 // ------------------------------------------------------------ inverse DFT
@@ -1759,8 +1779,8 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
       STAGE(3, (k_hadamard<<<g, kHadThreads, sizeof(cplx<float>) * kNumCanon * kKOffsetF, st>>>(
                    What, kh, Lv.lenq, Lv.wbase, Lv.ilw, Lv.order, Lv.n, nf, nwin, remap, Shat)));
     else
-      STAGE(3, (k_hadamard3<T><<<g, kHad3Threads, sizeof(cplx<T>) * kNumCanon * kKStride3, st>>>(
-                   What, kh, Lv.il_start, Lv.il, Lv.order, Lv.n, nf, nwin, remap, Shat)));
+      STAGE(3, (k_hadamard64<<<g, kHadThreadsD, sizeof(cplx<double>) * kNumCanon * kKOffsetD, st>>>(
+                   What, kh, Lv.lenq, Lv.wbase, Lv.ilw, Lv.order, Lv.n, nf, nwin, remap, Shat)));
     STAGE(4, dft<T>(p, false, (unsigned)Lv.n, Shat, Lv.n, tb.tw, s + Lv.off * 6 * p3, wm, ksc, st));
   }
   {
@@ -1798,7 +1818,7 @@ static void set_lds_attrs_once() {
   const int mx = 160 * 1024;
   hipFuncSetAttribute((const void*)k_hadamard, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
   hipFuncSetAttribute((const void*)k_hadamard16, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-  hipFuncSetAttribute((const void*)k_hadamard3<double>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+  hipFuncSetAttribute((const void*)k_hadamard64, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
   hipFuncSetAttribute((const void*)k_leaf_sym<T, sizeof(T) == 4, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                       mx);
   dft_lds_attrs<T>(std::make_integer_sequence<int, kMaxOrder - 1>{});

@@ -15,11 +15,12 @@ namespace dfmm {
 constexpr int kMaxOrder = 8;
 constexpr int kMaxQuad = 8;
 constexpr int kNumOffsets = 316;  // M2L offsets in [-3,3]^3 outside [-1,1]^3
-// Targets per M2L block (one window of Morton-consecutive targets): two lanes
-// per target in single precision, three in double, 768 threads either way (a
-// whole multiple of four waves, so a CU's four SIMDs get equal shares).
+// Targets per M2L block (one window of Morton-consecutive targets), two lanes
+// per target: 768 threads in single precision (two blocks per CU), 1024 in
+// double, whose spectra (139 KB) leave room for one block per CU.  Both are
+// whole multiples of four waves, so a CU's four SIMDs get equal shares.
 constexpr int kM2LWindowF = 384;
-constexpr int kM2LWindowD = 256;
+constexpr int kM2LWindowD = 512;
 inline int m2l_window(bool mixed) { return mixed ? kM2LWindowF : kM2LWindowD; }
 constexpr int kNumCanon = 158;    // one of each pair (o, -o): the kernel is odd, so the
                                   // spectrum of -o is minus the conjugate of that of o
@@ -46,6 +47,10 @@ constexpr int kKOffsetF = 2 * kKHalfF + 2;
 // words and 4 pad words, 15 16-byte units (odd, for the same reason).
 constexpr int kKHalfH = 28;
 constexpr int kKOffsetH = 2 * kKHalfH + 4;
+// Double precision: one complex value per 16-byte LDS unit, the two halves of
+// 27 values back to back and one pad unit, 55 units per offset (odd).
+constexpr int kKHalfD = 27;
+constexpr int kKOffsetD = 2 * kKHalfD + 1;
 __host__ __device__ constexpr int had_slot_of(int h, int k) {
   return k == 8 ? 4 : ((k >> 2) == h ? k - 4 * h : 5 + k - 4 * (1 - h));
 }

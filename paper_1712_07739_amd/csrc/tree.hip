@@ -362,7 +362,7 @@ __global__ void k_len_keys(const int* il_start, const int* parent, const int* pm
   val[i] = (uint32_t)i;
 }
 
-// Single-precision plans: per wave of kWaveTargets consecutive targets of the
+// Per wave of kWaveTargets consecutive targets of the
 // processing order, the longest list (+ the prefetch pad), and each target's
 // list length by processing position.
 __global__ void k_wave_len(const uint32_t* order, const int* il_start, int n, int* lenq, int* wlen) {
@@ -670,7 +670,7 @@ int build_tree_impl(dfmm_plan* pl, const double* seg, int64_t nseg, hipStream_t 
     rc = radix_sort(okey, L.order, L.n, 8 + wbits, st);
     hipFree(pmax);
     if (rc) return rc;
-    if (pl->mixed) {  // the wave-blocked lists of the single-precision M2L kernel
+    {  // the wave-blocked lists of the M2L kernels
       const int64_t nw = (L.n + kWaveTargets - 1) / kWaveTargets;
       int* wlen = nullptr;
       DFMM_HIP(hipMalloc(&wlen, sizeof(int) * (nw + 1)));
@@ -699,9 +699,11 @@ int build_tree_impl(dfmm_plan* pl, const double* seg, int64_t nseg, hipStream_t 
         // 16-byte units per offset and lane 1's start, in the layout of the spectra in LDS
         if (pl->h16)
           k_il_bank<kKOffsetH / 4, kKHalfH / 4, true><<<(unsigned)ng, 64, 0, st>>>(L.lenq, L.wbase, L.n, ng, L.ilw);
-        else
+        else if (pl->mixed)
           k_il_bank<kKOffsetF / 2, kKHalfF / 2, false><<<(unsigned)ng, 64, 0, st>>>(L.lenq, L.wbase, L.n, ng,
                                                                                    L.ilw);
+        else
+          k_il_bank<kKOffsetD, kKHalfD, false><<<(unsigned)ng, 64, 0, st>>>(L.lenq, L.wbase, L.n, ng, L.ilw);
         DFMM_LAUNCH_CHECK();
       }
       DFMM_HIP(hipStreamSynchronize(st));
