@@ -29,18 +29,36 @@ def traffic_file(kernel):
     return os.path.join(ROOT, "profiles", "%s_cubic1m_p7_traffic.json" % kernel)
 
 
+def kernel_source_sha(kernel):
+    """SHA-256 of a kernel's definition in fmm.hip (from its __global__
+    line to the brace that closes its body), so that a traffic figure goes
+    stale exactly when that kernel's code changes."""
+    import hashlib
+    import re
+
+    src = open(os.path.join(ROOT, "paper_1712_07739_amd", "csrc", "fmm.hip")).read()
+    m = re.search(r"__global__[^;{]*?\b%s\s*\(" % re.escape(kernel), src)
+    if m is None:
+        return None
+    i = src.index("{", m.end())
+    depth = 0
+    for j in range(i, len(src)):
+        depth += {"{": 1, "}": -1}.get(src[j], 0)
+        if depth == 0:
+            return hashlib.sha256(src[m.start():j + 1].encode()).hexdigest()
+    return None
+
+
 def hadamard_traffic(order, kernel="k_hadamard", workload="cubic1m"):
     """HBM bytes per step of the Hadamard kernel's launches, from the
     committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary, if it was taken on the
-    current kernel source, the same workload and the same order; else None."""
-    import hashlib
-
+    current source of that kernel, the same workload and the same order;
+    else None."""
     path = traffic_file(kernel)
     if workload != "cubic1m" or not os.path.exists(path):
         return None
     d = json.load(open(path))
-    src = open(os.path.join(ROOT, "paper_1712_07739_amd", "csrc", "fmm.hip"), "rb").read()
-    if d.get("fmm_hip_sha256") != hashlib.sha256(src).hexdigest() or d.get("order") != order:
+    if d.get("kernel_sha256") is None or d.get("kernel_sha256") != kernel_source_sha(kernel) or d.get("order") != order:
         return None
     return d["hbm_bytes_per_step"]
 
@@ -199,12 +217,13 @@ def main():
     had_ms = stage_ms[3] / ncalls
     achieved = had_flops / (had_ms * 1e-3)
     peak = PEAK_FP32_VALU if prec != pk.DFMM_FP64 else PEAK_FP64_VALU
-    kname = "k_hadamard16 (M2L in frequency space, f16 operands)" if prec == pk.DFMM_MIXED_F16 else \
-        "k_hadamard (M2L in frequency space)"
+    kname = {pk.DFMM_MIXED_F16: "k_hadamard16 (M2L in frequency space, f16 operands)",
+             pk.DFMM_MIXED: "k_hadamard (M2L in frequency space, f32 operands)",
+             pk.DFMM_FP64: "k_hadamard64 (FP64 M2L in frequency space)"}[prec]
     roof = {"kernel": kname + ", all levels of one step", "bound": "alu",
             "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak,
-            "traffic": hadamard_traffic(prm["order"], "k_hadamard16" if prec == pk.DFMM_MIXED_F16 else "k_hadamard",
-                                        args.workload),
+            "traffic": hadamard_traffic(prm["order"], {pk.DFMM_MIXED_F16: "k_hadamard16", pk.DFMM_MIXED: "k_hadamard",
+                                                       pk.DFMM_FP64: "k_hadamard64"}[prec], args.workload),
             "flop_per_step": had_flops, "ms_per_step": had_ms}
     result = {
         "metric": METRIC, "value": ns / (ms_step * 1e-3), "unit": "segments/s", "n_gpus": 1,
@@ -226,7 +245,7 @@ def main():
         "near_pairs": tinfo["near_pairs"], "roofline": roof,
     }
     del tree
-    def other_path(precision, kernel, peak):
+    def other_path(precision, kernel, peak, kshort):
         """Time and error of the same workload in another precision (same
         tree shape, its own plan): K calls as issued, then K with stage events."""
         plan2 = make_plan(precision)
@@ -253,7 +272,8 @@ def main():
             "speedup_of_headline": ms2 / ms_step,
             "stage_ms": {pk.STAGES[i]: st2[i] / nc2 for i in range(pk.N_STAGES)},
             "roofline": {"kernel": kernel + ", all levels of one step", "bound": "alu", "achieved": ach2 / 1e12,
-                         "peak": peak / 1e12, "unit": "TFLOP/s", "frac": ach2 / peak, "traffic": None,
+                         "peak": peak / 1e12, "unit": "TFLOP/s", "frac": ach2 / peak,
+                         "traffic": hadamard_traffic(prm["order"], kshort, args.workload),
                          "flop_per_step": had_flops, "ms_per_step": had2_ms}}
         log("%s path: %.3f ms/step (headline speedup %.2fx), error %.3e; Hadamard %.1f ms = %.1f TFLOP/s"
             % (kernel, ms2, ms2 / ms_step, res["rel_err_vs_fp64_direct"], had2_ms, ach2 / 1e12))
@@ -262,8 +282,10 @@ def main():
 
     if not args.no_fp64_compare and prec != pk.DFMM_FP64:
         if prec == pk.DFMM_MIXED_F16:
-            result["mixed_f32_path"] = other_path(pk.DFMM_MIXED, "k_hadamard (f32 operands)", PEAK_FP32_VALU)
-        result["fp64_path"] = other_path(pk.DFMM_FP64, "k_hadamard64 (FP64 M2L in frequency space)", PEAK_FP64_VALU)
+            result["mixed_f32_path"] = other_path(pk.DFMM_MIXED, "k_hadamard (f32 operands)", PEAK_FP32_VALU,
+                                                  "k_hadamard")
+        result["fp64_path"] = other_path(pk.DFMM_FP64, "k_hadamard64 (FP64 M2L in frequency space)", PEAK_FP64_VALU,
+                                         "k_hadamard64")
     if not args.no_cpu_baseline:
         import oracle
 
