@@ -112,12 +112,23 @@ typedef struct {
                          DFMM_LSQ_AUTO: the largest d < 2 sqrt(p), which is
                          p-1 (plain interpolation) for p < 6.  Degree p-1 is
                          run as 0.                                             */
+  int leaf_max;       /* 0: uniform tree, every leaf on level `depth`.  n > 0:
+                         adaptive tree (Sec. 3: the region is partitioned until
+                         every leaf holds few segments): a cell above level
+                         `depth` holding more than n quadrature points is
+                         split, so leaves lie on several levels; the FMM then
+                         adds the lists that join leaves of different levels
+                         (direct sums with adjacent leaves of any level,
+                         multipole weights of finer cells acting on a leaf's
+                         points, points of coarser leaves acting on a cell's
+                         nodes).  Requires lsq_degree 0 and the exact kernel. */
 } dfmm_params;
 #define DFMM_LSQ_AUTO (-1)
 
 /* Fill *p with defaults: order 5, depth 4, isotropic mu = 1, nu = 0.3,
  * a = 1e-3, root cube [-0.05, 1.05]^3, n_quad 3, n_circle 64, FP64,
- * DFMM_M2L_FFT, DFMM_KERNEL_EXACT, Lagrange interpolation (lsq_degree 0). */
+ * DFMM_M2L_FFT, DFMM_KERNEL_EXACT, Lagrange interpolation (lsq_degree 0),
+ * uniform tree (leaf_max 0). */
 void dfmm_default_params(dfmm_params* p);
 
 /* Precompute a plan (Sec. 4.1, Eq. m2l and Theorem 1): for every level 2..D

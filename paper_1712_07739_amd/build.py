@@ -7,7 +7,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdfmm.so")
-SOURCES = ["api.hip", "setup.hip", "tree.hip", "fmm.hip", "mlp.hip", "batch.hip"]
+SOURCES = ["api.hip", "setup.hip", "tree.hip", "adaptive.hip", "fmm.hip", "mlp.hip", "batch.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -75,6 +75,7 @@ void dfmm_default_params(dfmm_params* p) {
   p->m2l_mode = DFMM_M2L_FFT;
   p->aniso_kernel = DFMM_KERNEL_EXACT;
   p->lsq_degree = 0;
+  p->leaf_max = 0;
 }
 
 const char* dfmm_status_string(int s) {
@@ -120,6 +121,11 @@ int dfmm_fmm_setup(const dfmm_params* prm, void* stream, dfmm_plan** out) {
   }
   if (q.m2l_mode != DFMM_M2L_FFT && q.m2l_mode != DFMM_M2L_FFT_SYM) {
     set_error("fmm_setup: m2l_mode must be DFMM_M2L_FFT or DFMM_M2L_FFT_SYM");
+    return DFMM_E_ARG;
+  }
+  if (q.leaf_max < 0) { set_error("fmm_setup: leaf_max must be >= 0"); return DFMM_E_ARG; }
+  if (q.leaf_max > 0 && (q.lsq_degree != 0 || q.aniso_kernel != DFMM_KERNEL_EXACT)) {
+    set_error("fmm_setup: the adaptive tree (leaf_max > 0) takes Lagrange interpolation and the exact kernel");
     return DFMM_E_ARG;
   }
   if (q.lsq_degree < DFMM_LSQ_AUTO || q.lsq_degree > q.order - 1) {
@@ -221,6 +227,9 @@ void dfmm_tree_destroy(dfmm_tree* t) {
   hipFree(t->cstart); hipFree(t->cpair); hipFree(t->cval); hipFree(t->part); hipFree(t->cuni); hipFree(t->bigp);
   hipFree(t->pts); hipFree(t->pleaf); hipFree(t->W); hipFree(t->s); hipFree(t->What); hipFree(t->Shat); hipFree(t->sig);
   hipFree(t->kexp); hipFree(t->wmax);
+  hipFree(t->gl_cell); hipFree(t->gl_pf); hipFree(t->gl_pc); hipFree(t->gkey); hipFree(t->glev); hipFree(t->gord);
+  hipFree(t->ustart); hipFree(t->usrc); hipFree(t->wstart); hipFree(t->wsrc); hipFree(t->xstart); hipFree(t->xsrc);
+  hipFree(t->xcells); hipFree(t->wleaves);
   delete t;
 }
 
@@ -501,10 +510,15 @@ int dfmm_tree_info(const dfmm_tree* t, char* json, size_t cap) {
                   ", \"depth\": " + std::to_string(t->D) + ", \"m2l_pairs\": " + std::to_string(t->npairs) +
                   ", \"near_pairs\": " + std::to_string(t->near_pairs) +
                   ", \"max_leaf_points\": " + std::to_string(t->max_leaf_pts) +
-                  ", \"workspace_bytes\": " + std::to_string(t->bytes) + ", \"levels\": [";
+                  ", \"workspace_bytes\": " + std::to_string(t->bytes) + ", \"adaptive\": " +
+                  std::to_string(t->adaptive) + ", \"leaves\": " +
+                  std::to_string(t->adaptive ? t->nleaf : (t->D >= 2 ? t->lv[t->D].n : 0)) +
+                  ", \"u_pairs\": " + std::to_string(t->nu) + ", \"w_pairs\": " + std::to_string(t->nw) +
+                  ", \"x_pairs\": " + std::to_string(t->nx) + ", \"levels\": [";
   for (int l = 2; l <= t->D; ++l) {
     if (l > 2) s += ", ";
     s += "{\"level\": " + std::to_string(l) + ", \"cells\": " + std::to_string(t->lv[l].n) +
+         ", \"leaves\": " + std::to_string(t->adaptive ? t->leaf_n[l] : (l == t->D ? t->lv[l].n : 0)) +
          ", \"m2l_pairs\": " + std::to_string(t->lv[l].npairs) + "}";
   }
   s += "]}";

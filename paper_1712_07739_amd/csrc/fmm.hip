@@ -80,12 +80,14 @@ __device__ __forceinline__ void cell_lo(uint32_t key, double lo0, double lo1, do
 // 64 with their 1D basis values and 9-component strengths b (x) t.
 template <typename T>
 __global__ void k_p2m(const double* pts, int64_t N, const int* first, const int* count, const uint32_t* key,
-                      double lo0, double lo1, double lo2, double sD, int p, T* W) {
+                      double lo0, double lo1, double lo2, double sD, int p, T* W, const int* cell) {
   extern __shared__ unsigned char shraw[];
   T* Lb = (T*)shraw;          // [64][3][p]
   T* qs = Lb + 64 * 3 * p;    // [64][9]
-  const int leaf = blockIdx.x, p3 = p * p * p;
-  const int f0 = first[leaf], cnt = count[leaf];
+  // leaf blockIdx.x of the launch; its cell (the row of key and W) is the
+  // same index, or cell[blockIdx.x] (the leaves of one level of an adaptive tree)
+  const int li = blockIdx.x, leaf = cell ? cell[li] : li, p3 = p * p * p;
+  const int f0 = first[li], cnt = count[li];
   double lo[3];
   cell_lo(key[leaf], lo0, lo1, lo2, sD, lo);
   const int tid = threadIdx.x;
@@ -1638,7 +1640,7 @@ struct StageTimer {
 template <typename T>
 static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const double* burg, double* forces,
                    hipStream_t st) {
-  const int p = pl->p, p3 = p * p * p, n = pl->n, nf = pl->nf, D = pl->D;
+  const int p = pl->p, p3 = p * p * p, n = pl->n, nf = pl->nf, D = t->D;  // the tree's deepest level
   const int64_t N = t->N;
   const size_t es = sizeof(T);
   const Tables<T>& tb = *(const Tables<T>*)(std::is_same<T, double>::value ? (const void*)&pl->t64
@@ -1667,13 +1669,20 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
     DFMM_HIP(hipStreamWaitEvent(t->side, t->fork, 0));
     nst = t->side;
   }
+#define ACALL(call)     \
+  do {                  \
+    int r_ = (call);    \
+    if (r_) return r_;  \
+  } while (0)
   {
     Med<T> m = pl->med<T>();
     Med<double> m64 = pl->med<double>();
 #define LEAF_ARGS t->pts, N, LD.first, LD.count, t->nbr, m, m64, t->sig
     SurDev sd = sur_dev(pl);
     if constexpr (std::is_same<T, float>::value) {
-      if (!pl->iso && sd.on) {
+      if (t->adaptive) {
+        STAGE(6, ACALL(adapt_near<T>(pl, t, nst)));
+      } else if (!pl->iso && sd.on) {
         const int grid = (int)std::max<int64_t>(
             1, std::min<int64_t>(sur_grid(pl->device), (LD.n + kSurLeafThreads / 64 - 1) / (kSurLeafThreads / 64)));
         STAGE(6, (k_leaf_sur<<<grid, kSurLeafThreads, kSurInfLds, nst>>>(t->pts, N, LD.first, LD.count, t->nbr, LD.n,
@@ -1690,7 +1699,7 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
       }
       else
         STAGE(6, (k_leaf<T, true, false><<<(unsigned)LD.n, 64, 0, nst>>>(LEAF_ARGS)));
-      if (!pl->iso && !sd.on && t->part)
+      if (!t->adaptive && !pl->iso && !sd.on && t->part)
         STAGE(6, (k_near_sum<T><<<nblk(N, 256), 256, 0, nst>>>((const T*)t->part, N, t->pleaf, t->nbr, t->sig)));
       if (t->nclose > 0) {
         if (pl->iso)
@@ -1702,7 +1711,9 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
         STAGE(6, (k_close_sum<<<nblk(N, 256), 256, 0, nst>>>(t->cstart, N, t->cval, t->sig)));
       }
     } else {
-      if (pl->iso) {
+      if (t->adaptive) {
+        STAGE(6, ACALL(adapt_near<T>(pl, t, nst)));
+      } else if (pl->iso) {
         STAGE(6, (k_leaf<T, false, true><<<(unsigned)LD.n, 64, 0, nst>>>(LEAF_ARGS)));
       } else if (t->part) {
         STAGE(6, (k_leaf_sym<T, false, false><<<dim3((unsigned)LD.n, 14), sym_threads<T, false>(), sym_lds<T, false>(64), nst>>>(
@@ -1717,12 +1728,22 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
     }
 #undef LEAF_ARGS
   }
-  {
-    int bs = std::max(64, ((p3 + 63) / 64) * 64);
-    size_t shm = es * (64 * 3 * p + 64 * 9);
-    STAGE(0, (k_p2m<T><<<(unsigned)LD.n, bs, shm, st>>>(t->pts, N, LD.first, LD.count, LD.key, lo[0], lo[1],
-                                                           lo[2], sD, p, W + LD.off * 9 * p3)));
-  }
+  const int p2m_bs = std::max(64, ((p3 + 63) / 64) * 64);
+  const size_t p2m_shm = es * (64 * 3 * p + 64 * 9);
+  // P2M of the leaves of level l of an adaptive tree (after that level's M2M,
+  // which leaves zeros in its leaves)
+  auto p2m_level = [&](int l) {
+    if (t->leaf_n[l] > 0)
+      k_p2m<T><<<(unsigned)t->leaf_n[l], p2m_bs, p2m_shm, st>>>(
+          t->pts, N, t->gl_pf + t->leaf_off[l], t->gl_pc + t->leaf_off[l], t->gkey, lo[0], lo[1], lo[2],
+          L / std::ldexp(1.0, l), p, W, t->gl_cell + t->leaf_off[l]);
+  };
+  if (t->adaptive)
+    STAGE(0, p2m_level(D));
+  else
+    STAGE(0, (k_p2m<T><<<(unsigned)LD.n, p2m_bs, p2m_shm, st>>>(t->pts, N, LD.first, LD.count, LD.key, lo[0],
+                                                                  lo[1], lo[2], sD, p, W + LD.off * 9 * p3,
+                                                                  nullptr)));
   {
     size_t shm = es * 27 * p3;
     for (int l = D - 1; l >= 2; --l) {
@@ -1730,6 +1751,7 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
       const auto& Lp = t->lv[l];
       STAGE(1, tree_pass<T>(p, true, (unsigned)Lp.n, shm, Lp.first, Lp.count, Lc.key, W + Lc.off * 9 * p3,
                                W + Lp.off * 9 * p3, tb.S, st));
+      if (t->adaptive) STAGE(1, p2m_level(l));
     }
   }
   // stabilised interpolation: the M2L takes the projected weights (the
@@ -1783,6 +1805,9 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
                    What, kh, Lv.lenq, Lv.wbase, Lv.ilw, Lv.order, Lv.n, nf, nwin, remap, Shat)));
     STAGE(4, dft<T>(p, false, (unsigned)Lv.n, Shat, Lv.n, tb.tw, s + Lv.off * 6 * p3, wm, ksc, st));
   }
+  // adaptive tree: the points of each X leaf onto the nodes of the cells
+  // that list it, before the local values go down the tree
+  if (t->adaptive) STAGE(4, ACALL(adapt_p2l<T>(pl, t, s, st)));
   {
     // stabilised interpolation: each level's local values are projected
     // before they go to the children (L2L) or the points (L2P)
@@ -1801,7 +1826,12 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
     DFMM_HIP(hipEventRecord(t->join, nst));
     DFMM_HIP(hipStreamWaitEvent(st, t->join, 0));
   }
-  {
+  if (t->adaptive) {
+    // W lists (multipole weights at the nodes of finer cells onto a leaf's
+    // points), then L2P from each point's leaf, whatever its level
+    STAGE(6, ACALL(adapt_m2p<T>(pl, t, W, st)));
+    STAGE(6, ACALL(adapt_l2p<T>(pl, t, s, st)));
+  } else {
     STAGE(6, l2p_launch<T>(p, N, t->pts, t->pleaf, LD.key, s + LD.off * 6 * p3, lo, sD, t->sig, st));
   }
   STAGE(7, (k_forces<<<nblk(t->nseg, 128), 128, 0, st>>>(seg, burg, nullptr, t->inv, t->sig, pl->quad,

@@ -13,6 +13,7 @@
 namespace dfmm {
 
 constexpr int kMaxOrder = 8;
+constexpr int kMaxLevels = 10;  // deepest leaf level (30-bit Morton keys)
 constexpr int kMaxQuad = 8;
 constexpr int kNumOffsets = 316;  // M2L offsets in [-3,3]^3 outside [-1,1]^3
 // Targets per M2L block (one window of Morton-consecutive targets), two lanes
@@ -238,6 +239,31 @@ struct dfmm_tree {
   double* cval = nullptr;  // [nclose][6] per-pair stress, written by every call
   int64_t nuni = 0;
   int2* cuni = nullptr;     // [nuni] unordered pairs: (entry (i, j) with i < j, entry (j, i))
+  // Adaptive tree (plan leaf_max > 0): cells below a leaf are pruned and the
+  // levels' arrays hold the cells that remain (first/count: children, zero for
+  // a leaf).  Leaves of all levels are numbered level by level ("ordinals").
+  int adaptive = 0;
+  int64_t nleaf = 0;
+  int64_t leaf_off[dfmm::kMaxLevels + 1] = {}, leaf_n[dfmm::kMaxLevels + 1] = {};  // ordinals of each level's leaves
+  int* gl_cell = nullptr;        // [nleaf] global cell index (over levels 2..D)
+  int* gl_pf = nullptr;          // [nleaf] first sorted point
+  int* gl_pc = nullptr;          // [nleaf] points
+  uint32_t* gkey = nullptr;      // [ncell_total] Morton key at the cell's level
+  unsigned char* glev = nullptr; // [ncell_total] level
+  int* gord = nullptr;           // [ncell_total] leaf ordinal, or -1
+  int* ustart = nullptr;         // [nleaf + 1] U lists: adjacent leaves (ordinals), any level
+  int* usrc = nullptr;
+  int64_t nu = 0;
+  int* wstart = nullptr;         // [nleaf + 1] W lists: source cells (global) acting on a leaf's points
+  int* wsrc = nullptr;
+  int64_t nw = 0;
+  int* xstart = nullptr;         // [ncell_total + 1] X lists: source leaves acting on a cell's nodes
+  int* xsrc = nullptr;
+  int64_t nx = 0;
+  int* xcells = nullptr;         // cells with a non-empty X list
+  int64_t nxcell = 0;
+  int* wleaves = nullptr;        // leaves with a non-empty W list
+  int64_t nwleaf = 0;
   // recorded at the end of every call that is not being captured into a
   // graph: destroy and the query calls wait on it (an event the tree owns,
   // valid whatever becomes of the caller's streams)
@@ -271,8 +297,27 @@ int surrogate_loss_grad(dfmm_plan* pl, const float* X, const float* Y, int64_t n
 int surrogate_forward(const dfmm_plan* pl, const float* X, int64_t n, float* Yout, hipStream_t st);
 
 // tree.hip
+// Exclusive scan of in[0..n) (n >= 1) into out, the total in *total (host).
+int scan_excl(const int* in, int* out, int64_t n, hipStream_t st, int64_t* total);
+// Stable LSD radix sort of (keys, vals) (n >= 1) by the low `bits` bits of keys.
+int radix_sort(uint32_t* keys, uint32_t* vals, int64_t n, int bits, hipStream_t st);
 int build_tree_impl(dfmm_plan* plan, const double* seg, int64_t nseg, hipStream_t st, dfmm_tree* t,
                     bool workspaces = true);
+
+// adaptive.hip
+int adapt_prune(const dfmm_plan* plan, dfmm_tree* t, hipStream_t st);  // levels -> adaptive levels, leaves
+int adapt_lists(const dfmm_plan* plan, dfmm_tree* t, hipStream_t st);  // U, W, X lists, point leaves
+// near-coincident pairs over the U lists: counts (fill = false) or the pairs
+int adapt_close_find(const dfmm_plan* plan, dfmm_tree* t, bool fill, int* cnt, const int* cstart, int2* cpair,
+                     hipStream_t st);
+template <typename T>
+int adapt_near(const dfmm_plan* plan, dfmm_tree* t, hipStream_t st);    // U lists (writes sig)
+template <typename T>
+int adapt_m2p(const dfmm_plan* plan, dfmm_tree* t, const T* W, hipStream_t st);  // W lists (adds to sig)
+template <typename T>
+int adapt_p2l(const dfmm_plan* plan, dfmm_tree* t, T* s, hipStream_t st);        // X lists (adds to s)
+template <typename T>
+int adapt_l2p(const dfmm_plan* plan, dfmm_tree* t, const T* s, hipStream_t st);  // adds to sig
 
 // fmm.hip
 void fmm_prepare(const dfmm_plan* plan);  // one-time kernel attributes (outside graph capture)

@@ -12,46 +12,9 @@
 #include <cmath>
 
 #include "internal.h"
+#include "morton.h"
 
 namespace dfmm {
-
-// ------------------------------------------------------------------ utils
-__device__ __forceinline__ uint32_t spread3(uint32_t v) {
-  v &= 0x3ff;
-  v = (v | (v << 16)) & 0x030000FF;
-  v = (v | (v << 8)) & 0x0300F00F;
-  v = (v | (v << 4)) & 0x030C30C3;
-  v = (v | (v << 2)) & 0x09249249;
-  return v;
-}
-__device__ __forceinline__ uint32_t compact3(uint32_t v) {
-  v &= 0x09249249;
-  v = (v | (v >> 2)) & 0x030C30C3;
-  v = (v | (v >> 4)) & 0x0300F00F;
-  v = (v | (v >> 8)) & 0x030000FF;
-  v = (v | (v >> 16)) & 0x3ff;
-  return v;
-}
-// key bit 3b+2 = x_b, 3b+1 = y_b, 3b = z_b
-__device__ __forceinline__ uint32_t morton(int x, int y, int z) {
-  return (spread3(x) << 2) | (spread3(y) << 1) | spread3(z);
-}
-__device__ __forceinline__ void demorton(uint32_t k, int& x, int& y, int& z) {
-  x = compact3(k >> 2);
-  y = compact3(k >> 1);
-  z = compact3(k);
-}
-__device__ __forceinline__ int bsearch_key(const uint32_t* keys, int n, uint32_t k) {
-  int lo = 0, hi = n - 1;
-  while (lo <= hi) {
-    int mid = (lo + hi) >> 1;
-    uint32_t v = keys[mid];
-    if (v == k) return mid;
-    if (v < k) lo = mid + 1;
-    else hi = mid - 1;
-  }
-  return -1;
-}
 
 // --------------------------------------------------------------- points
 __global__ void k_make_keys(const double* seg, int64_t nseg, Quad qd, double lo0, double lo1, double lo2,
@@ -131,7 +94,7 @@ __global__ void k_add_tile_offsets(int* out, int64_t n, const int* offs) {
 }
 
 // Exclusive scan of in[0..n) into out; returns the total in *total (host).
-static int scan_excl(const int* in, int* out, int64_t n, hipStream_t st, int64_t* total) {
+int scan_excl(const int* in, int* out, int64_t n, hipStream_t st, int64_t* total) {
   int64_t nt = (n + SC_TILE - 1) / SC_TILE;
   int* sums = nullptr;
   int* sums_ex = nullptr;
@@ -219,7 +182,7 @@ __global__ void k_rs_scatter(const uint32_t* kin, const uint32_t* vin, uint32_t*
 }
 
 // Sort (keys, vals) by the low `bits` bits of keys; result in keys/vals.
-static int radix_sort(uint32_t* keys, uint32_t* vals, int64_t n, int bits, hipStream_t st) {
+int radix_sort(uint32_t* keys, uint32_t* vals, int64_t n, int bits, hipStream_t st) {
   int nblk = (int)((n + RS_TILE - 1) / RS_TILE);
   uint32_t *k2 = nullptr, *v2 = nullptr;
   int *hist = nullptr, *offs = nullptr;
@@ -540,7 +503,8 @@ __global__ void k_close_uni(const int2* cpair, const int* cstart, int64_t nclose
 static inline unsigned nb(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 int build_tree_impl(dfmm_plan* pl, const double* seg, int64_t nseg, hipStream_t st, dfmm_tree* t, bool workspaces) {
-  const int D = pl->D, nq = pl->quad.n;
+  int D = pl->D;
+  const int nq = pl->quad.n;
   const int64_t N = nseg * nq;
   if (N >= (int64_t)1 << 31) {
     set_error("build_tree: too many quadrature points (limit 2^31)");
@@ -612,6 +576,13 @@ int build_tree_impl(dfmm_plan* pl, const double* seg, int64_t nseg, hipStream_t 
   hipFree(flags);
   hipFree(idx);
   hipFree(keys);
+  // adaptive tree: cells below a leaf pruned, leaves on several levels; the
+  // tree's depth becomes its deepest level
+  if (pl->prm.leaf_max > 0) {
+    rc = adapt_prune(pl, t, st);
+    if (rc) return rc;
+    D = t->D;
+  }
   // global cell numbering over levels 2..D
   t->ncell_total = 0;
   t->max_level_cells = 0;
@@ -620,11 +591,13 @@ int build_tree_impl(dfmm_plan* pl, const double* seg, int64_t nseg, hipStream_t 
     t->ncell_total += t->lv[l].n;
     t->max_level_cells = std::max<int64_t>(t->max_level_cells, t->lv[l].n);
   }
-  // neighbours of the leaves
+  // neighbours of the leaves (uniform tree)
   auto& LD = t->lv[D];
-  DFMM_HIP(hipMalloc(&t->nbr, sizeof(int) * 27 * LD.n));
-  k_leaf_nbrs<<<nb(LD.n, 128), 128, 0, st>>>(LD.key, (int)LD.n, D, t->nbr);
-  DFMM_LAUNCH_CHECK();
+  if (!t->adaptive) {
+    DFMM_HIP(hipMalloc(&t->nbr, sizeof(int) * 27 * LD.n));
+    k_leaf_nbrs<<<nb(LD.n, 128), 128, 0, st>>>(LD.key, (int)LD.n, D, t->nbr);
+    DFMM_LAUNCH_CHECK();
+  }
   // interaction lists
   t->npairs = 0;
   for (int l = 2; l <= D; ++l) {
@@ -714,7 +687,10 @@ int build_tree_impl(dfmm_plan* pl, const double* seg, int64_t nseg, hipStream_t 
   }
   // near-field pair count (for reporting), and the large-leaf pairs
   std::vector<int> hbig;
-  {
+  if (t->adaptive) {  // U, W, X lists, the leaf of every point, near pairs
+    rc = adapt_lists(pl, t, st);
+    if (rc) return rc;
+  } else {
     std::vector<int> hn(27 * LD.n), hc(LD.n);
     DFMM_D2H(hn.data(), t->nbr, sizeof(int) * hn.size(), st);
     DFMM_D2H(hc.data(), LD.count, sizeof(int) * hc.size(), st);
@@ -751,9 +727,11 @@ int build_tree_impl(dfmm_plan* pl, const double* seg, int64_t nseg, hipStream_t 
   DFMM_HIP(hipEventCreateWithFlags(&t->join, hipEventDisableTiming));
   DFMM_HIP(hipEventCreateWithFlags(&t->done, hipEventDisableTiming));
   DFMM_HIP(hipMalloc(&t->pts, sizeof(double) * 9 * N));
-  DFMM_HIP(hipMalloc(&t->pleaf, sizeof(int) * N));
-  k_point_leaf<<<(unsigned)LD.n, 64, 0, st>>>(LD.first, LD.count, (int)LD.n, t->pleaf);
-  DFMM_LAUNCH_CHECK();
+  if (!t->adaptive) {
+    DFMM_HIP(hipMalloc(&t->pleaf, sizeof(int) * N));
+    k_point_leaf<<<(unsigned)LD.n, 64, 0, st>>>(LD.first, LD.count, (int)LD.n, t->pleaf);
+    DFMM_LAUNCH_CHECK();
+  }
   DFMM_HIP(hipMalloc(&t->W, bW));
   DFMM_HIP(hipMalloc(&t->s, bS));
   DFMM_HIP(hipMalloc(&t->What, bWh));
@@ -767,7 +745,7 @@ int build_tree_impl(dfmm_plan* pl, const double* seg, int64_t nseg, hipStream_t 
   }
   if (pl->h16) DFMM_HIP(hipMalloc(&t->wmax, sizeof(unsigned) * (D + 1)));
   const size_t part_es = pl->mixed ? sizeof(float) : sizeof(double);
-  if (!pl->iso && t->max_leaf_pts <= (pl->mixed ? kSymMaxLeaf : kSymMaxLeafD)) {
+  if (!t->adaptive && !pl->iso && t->max_leaf_pts <= (pl->mixed ? kSymMaxLeaf : kSymMaxLeafD)) {
     DFMM_HIP(hipMalloc(&t->part, part_es * 27 * 6 * N));
     if (!hbig.empty()) {
       t->nbig = (int64_t)hbig.size();
@@ -783,10 +761,15 @@ int build_tree_impl(dfmm_plan* pl, const double* seg, int64_t nseg, hipStream_t 
     int* cnt = nullptr;
     DFMM_HIP(hipMalloc(&cnt, sizeof(int) * (N + 1)));
     DFMM_HIP(hipMemsetAsync(cnt + N, 0, sizeof(int), st));
-    k_close_find<false><<<nb(N, 128), 128, 0, st>>>(t->pts, N, t->pleaf, LD.first, LD.count, LD.key, t->nbr,
-                                                   pl->prm.box_lo[0], pl->prm.box_lo[1], pl->prm.box_lo[2], sD,
-                                                   a2x4, cnt, nullptr, nullptr);
-    DFMM_LAUNCH_CHECK();
+    if (t->adaptive) {
+      rc = adapt_close_find(pl, t, false, cnt, nullptr, nullptr, st);
+      if (rc) return rc;
+    } else {
+      k_close_find<false><<<nb(N, 128), 128, 0, st>>>(t->pts, N, t->pleaf, LD.first, LD.count, LD.key, t->nbr,
+                                                     pl->prm.box_lo[0], pl->prm.box_lo[1], pl->prm.box_lo[2], sD,
+                                                     a2x4, cnt, nullptr, nullptr);
+      DFMM_LAUNCH_CHECK();
+    }
     DFMM_HIP(hipMalloc(&t->cstart, sizeof(int) * (N + 1)));
     rc = scan_excl(cnt, t->cstart, N + 1, st, &t->nclose);
     hipFree(cnt);
@@ -797,10 +780,15 @@ int build_tree_impl(dfmm_plan* pl, const double* seg, int64_t nseg, hipStream_t 
     }
     DFMM_HIP(hipMalloc(&t->cpair, sizeof(int2) * std::max<int64_t>(t->nclose, 1)));
     DFMM_HIP(hipMalloc(&t->cval, sizeof(double) * 6 * std::max<int64_t>(t->nclose, 1)));
-    k_close_find<true><<<nb(N, 128), 128, 0, st>>>(t->pts, N, t->pleaf, LD.first, LD.count, LD.key, t->nbr,
-                                                  pl->prm.box_lo[0], pl->prm.box_lo[1], pl->prm.box_lo[2], sD,
-                                                  a2x4, nullptr, t->cstart, t->cpair);
-    DFMM_LAUNCH_CHECK();
+    if (t->adaptive) {
+      rc = adapt_close_find(pl, t, true, nullptr, t->cstart, t->cpair, st);
+      if (rc) return rc;
+    } else {
+      k_close_find<true><<<nb(N, 128), 128, 0, st>>>(t->pts, N, t->pleaf, LD.first, LD.count, LD.key, t->nbr,
+                                                    pl->prm.box_lo[0], pl->prm.box_lo[1], pl->prm.box_lo[2], sD,
+                                                    a2x4, nullptr, t->cstart, t->cpair);
+      DFMM_LAUNCH_CHECK();
+    }
     if (t->nclose > 0) {  // the unordered pairs with their two list entries
       int *flag = nullptr, *upos = nullptr;
       DFMM_HIP(hipMalloc(&flag, sizeof(int) * (t->nclose + 1)));
@@ -832,7 +820,11 @@ int build_tree_impl(dfmm_plan* pl, const double* seg, int64_t nseg, hipStream_t 
   t->bytes = sizeof(double) * 15 * N + sizeof(int) * N + bW + bS + bWh + bSh +
              (sizeof(int2) + 6 * sizeof(double)) * t->nclose + sizeof(int2) * t->nuni +
              (t->cstart ? sizeof(int) * (N + 1) : 0) +
-             (t->part ? part_es * 27 * 6 * N : 0) + sizeof(int) * t->nbig + bKx;
+             (t->part ? part_es * 27 * 6 * N : 0) + sizeof(int) * t->nbig + bKx +
+             (t->adaptive ? sizeof(int) * (3 * t->nleaf + 2 * (t->nleaf + 1) + t->nu + 2 * t->nw + t->nwleaf +
+                                           t->nxcell + 2 * t->ncell_total + 1) +
+                                5 * t->ncell_total
+                          : 0);
   DFMM_HIP(hipStreamSynchronize(st));
   return DFMM_OK;
 }

@@ -11,12 +11,16 @@ from test_oracle_fmm import direct_numpy, poly_kernel
 BOX_LO, BOX = synth.loops.BOX_LO, synth.loops.BOX_SIZE
 
 
-def clustered(n_big=4, n_small=3, seed_small=5):
-    """A few large loops and a tight cluster of small ones: leaves of the
-    adaptive tree then sit on three levels, and W/X lists are not empty."""
-    seg1, b1 = synth.make_loops(n_big, 0.05, 0.15, 21)
-    seg2, b2 = synth.make_loops(n_small, 0.01, 0.03, seed_small)
-    seg2 = seg2 - seg2.mean(axis=(0, 1)) + 0.3
+def clustered(n_big=4, n_small=3, seed=26):
+    """A few loops spread over the cube and a tight cluster of small ones
+    (each moved next to one centre): leaves of the adaptive tree then sit on
+    three or more levels, and the W/X lists are not empty."""
+    seg1, b1 = synth.make_loops(n_big, 0.04, 0.1, seed)
+    seg2, b2 = synth.make_loops(n_small, 0.01, 0.03, seed + 100)
+    rng = np.random.default_rng(seed + 200)
+    for k in range(n_small):
+        s = seg2[40 * k:40 * k + 40]
+        seg2[40 * k:40 * k + 40] = s - s.reshape(-1, 3).mean(axis=0) + 0.3 + rng.uniform(-0.03, 0.03, size=3)
     return np.concatenate([seg1, seg2]), np.concatenate([b1, b2])
 
 
@@ -89,7 +93,7 @@ def test_full_split_is_the_uniform_fmm():
 
 
 def test_adaptive_forces_converge_to_direct():
-    seg, b = clustered(3, 2, 7)
+    seg, b = clustered(3, 2, 23)
     med = oracle.medium(*synth.loops.CUBIC_A25, 1e-3)
     ref = oracle.direct_forces(seg, b, med)
     errs = [oracle.rel_err(fmm_forces_adaptive(seg, b, med, p, 4, BOX_LO, BOX, 40), ref) for p in (3, 4, 5)]
