@@ -95,6 +95,9 @@ def main():
                     help="interpolation order p (default: the smallest order meeting the 1e-4 bar, "
                          "7 for cubic1m; its configured p=6 measures 1.15e-4)")
     ap.add_argument("--depth", type=int, default=0, help="override the workload's leaf depth D")
+    ap.add_argument("--leaf-max", type=int, default=0,
+                    help="adaptive tree: split cells holding more than this many quadrature points, down to "
+                         "the depth (0: uniform tree)")
     ap.add_argument("--m2l-mode", default="sym", choices=["fft", "sym"],
                     help="M2L operator store: 158 offset spectra (fft) or 16 symmetry classes (sym)")
     ap.add_argument("--err-sample", type=int, default=2000,
@@ -147,7 +150,8 @@ def main():
     def make_plan(precision):
         p = pk.make_params(prm["order"], prm["depth"], prm["c11"], prm["c12"], prm["c44"], prm["core_a"],
                            prm["box_lo"], prm["box_size"], precision=precision,
-                           m2l_mode=pk.DFMM_M2L_FFT_SYM if args.m2l_mode == "sym" else pk.DFMM_M2L_FFT)
+                           m2l_mode=pk.DFMM_M2L_FFT_SYM if args.m2l_mode == "sym" else pk.DFMM_M2L_FFT,
+                           leaf_max=args.leaf_max)
         return pk.Plan(p)
 
     t0 = time.perf_counter()
@@ -158,7 +162,7 @@ def main():
     log("setup %.2f s %s" % (setup_s, info))
     sur = None
     cubic = abs(2 * prm["c44"] - (prm["c11"] - prm["c12"])) > 1e-12
-    if cubic and prec != pk.DFMM_FP64 and not args.no_surrogate:
+    if cubic and prec != pk.DFMM_FP64 and not args.no_surrogate and not args.leaf_max:
         # the learned surrogate of the anisotropic kernel: 2M samples, residual gate 1e-5,
         # the exact quadrature wherever a direction bin fails the gate
         t0 = time.perf_counter()
@@ -178,7 +182,8 @@ def main():
     torch.cuda.synchronize()
     tree_s = time.perf_counter() - t0
     tinfo = tree.info()
-    log("tree %.3f s: m2l pairs %d, near pairs %d" % (tree_s, tinfo["m2l_pairs"], tinfo["near_pairs"]))
+    log("tree %.3f s: m2l pairs %d, near pairs %d, leaves %d, w/x pairs %d" % (
+        tree_s, tinfo["m2l_pairs"], tinfo["near_pairs"], tinfo["leaves"], tinfo["w_pairs"]))
     out = torch.empty((ns, 2, 3), dtype=torch.float64, device=dev)
     for i in range(args.warmup):
         pk.fmm_forces(plan, tree, tseg, tb, out=out)
@@ -232,7 +237,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n_seg": ns, "order": prm["order"], "depth": prm["depth"],
                    "C": [prm["c11"], prm["c12"], prm["c44"]], "core_a": prm["core_a"],
-                   "precision": args.precision, "configured_order": configured_order, "m2l_mode": args.m2l_mode},
+                   "precision": args.precision, "configured_order": configured_order, "m2l_mode": args.m2l_mode,
+                   "tree": "adaptive, leaves of at most %d points" % args.leaf_max if args.leaf_max else "uniform"},
         "rel_err_vs_fp64_direct": err, "err_sample_segments": int(len(sub)),
         "stage_ms": {pk.STAGES[i]: stage_ms[i] / ncalls for i in range(pk.N_STAGES)},
         "stage_ms_note": "separate pass with HIP events around each stage, stages one by one (in the timed "

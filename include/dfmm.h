@@ -303,6 +303,13 @@ int dfmm_batch_create(const dfmm_plan* const* plans, dfmm_tree* const* trees, co
                       const double* const* burgers, double* const* forces, int n_cfg, int n_lanes,
                       void* stream, dfmm_batch** out);
 int dfmm_batch_run(dfmm_batch* batch, void* stream);
+/* One-shot form: the n_cfg force evaluations in one graph launch over
+ * min(4, n_cfg) branches (dfmm_batch_create, run, destroy), for callers that
+ * evaluate a set of configurations once.  Same arguments and errors as
+ * dfmm_batch_create; synchronous (returns when every forces[i] is written);
+ * allocates the graph and its streams for the duration of the call. */
+int dfmm_forces_batched(const dfmm_plan* const* plans, dfmm_tree* const* trees, const double* const* seg,
+                        const double* const* burgers, double* const* forces, int n_cfg, void* stream);
 int dfmm_batch_latencies(dfmm_batch* batch, double* ms, int n_cfg);
 void dfmm_batch_destroy(dfmm_batch* batch);
 

@@ -36,7 +36,7 @@ ENTRY_POINTS = (
     "dfmm_surrogate_loss_grad", "dfmm_surrogate_forward", "dfmm_batch_create", "dfmm_batch_run",
     "dfmm_batch_latencies", "dfmm_batch_destroy", "dfmm_autotune_depth",
     "dfmm_direct_forces_noalloc", "dfmm_direct_noalloc_bytes", "dfmm_surrogate_get_gate",
-    "dfmm_surrogate_save", "dfmm_surrogate_load",
+    "dfmm_surrogate_save", "dfmm_surrogate_load", "dfmm_forces_batched",
 )
 NOALLOC_SCRATCH_BYTES = 64 << 20
 
@@ -115,6 +115,7 @@ def lib():
     L.dfmm_batch_run.argtypes = [vp, vp]
     L.dfmm_batch_latencies.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i32]
     L.dfmm_batch_destroy.argtypes = [vp]
+    L.dfmm_forces_batched.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int, vp]
     L.dfmm_autotune_depth.argtypes = [ctypes.POINTER(Params), vp, vp, i64, i32, i32, vp, ctypes.POINTER(i32),
                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     for name in ENTRY_POINTS:
@@ -387,6 +388,18 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def forces_batched(plans, trees, segs, burgers, forces, stream=None):
+    """dfmm_forces_batched: the force evaluations of many configurations in
+    one graph launch, returned when all are written (forces: caller tensors)."""
+    n = len(plans)
+    assert len(trees) == len(segs) == len(burgers) == len(forces) == n
+    P = ctypes.c_void_p * n
+    args = (P(*[p.handle for p in plans]), P(*[t.handle for t in trees]), P(*[x.data_ptr() for x in segs]),
+            P(*[x.data_ptr() for x in burgers]), P(*[x.data_ptr() for x in forces]))
+    _check(lib().dfmm_forces_batched(*[ctypes.cast(a, ctypes.c_void_p) for a in args], n, _stream(stream)))
+    return forces
 
 
 def autotune_depth(params: Params, seg, burgers, d_min=3, d_max=7, stream=None):

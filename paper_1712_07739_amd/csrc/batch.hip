@@ -202,6 +202,20 @@ void dfmm_batch_destroy(dfmm_batch* b) {
   batch_free(b);
 }
 
+int dfmm_forces_batched(const dfmm_plan* const* plans, dfmm_tree* const* trees, const double* const* seg,
+                        const double* const* burgers, double* const* forces, int n_cfg, void* stream) {
+  dfmm_batch* b = nullptr;
+  int rc = dfmm_batch_create(plans, trees, seg, burgers, forces, n_cfg, std::min(4, std::max(1, n_cfg)), stream, &b);
+  if (rc) return rc;
+  rc = dfmm_batch_run(b, stream);
+  if (rc == DFMM_OK && hipStreamSynchronize((hipStream_t)stream) != hipSuccess) {
+    set_error("forces_batched: stream synchronisation failed");
+    rc = DFMM_E_HIP;
+  }
+  dfmm_batch_destroy(b);
+  return rc;
+}
+
 int dfmm_autotune_depth(const dfmm_params* prm, const double* seg, const double* burgers, int64_t n_seg, int d_min,
                         int d_max, void* stream, int* best, double* pred_ms, double* meas_ms) {
   if (!prm || !seg || !burgers || !best || n_seg < 1 || d_min < 2 || d_max > 10 || d_min > d_max ||

@@ -93,3 +93,21 @@ def test_depth_autotuner(env):
         truth = {k: _measured_ms(pk, torch, (5, *ISO, 1e-3, BOX_LO, BOX), k, ts, tb) for k in range(2, 7)}
         print("  independent timing:", {k: round(v, 3) for k, v in truth.items()})
         assert truth[d] <= 1.25 * min(truth.values()) + 0.05
+
+
+def test_forces_batched_one_shot_equals_individual_calls(env):
+    """dfmm_forces_batched (create, run, destroy in one call) writes the same
+    forces as individual dfmm_fmm_forces calls."""
+    torch, pk, dev = env
+    plan = pk.Plan(pk.make_params(4, 3, *ISO, 1e-3, BOX_LO, BOX, precision=1))
+    cfg = []
+    for i, nl in enumerate([4, 9, 2]):
+        seg, b = synth.make_loops(nl, 0.01, 0.05, 950 + i)
+        ts, tb = torch.tensor(seg, device=dev), torch.tensor(b, device=dev)
+        tree = pk.Tree(plan, ts)
+        ref = pk.fmm_forces(plan, tree, ts, tb).cpu().numpy()
+        cfg.append((tree, ts, tb, torch.zeros((len(seg), 2, 3), dtype=torch.float64, device=dev), ref))
+    pk.forces_batched([plan] * 3, [c[0] for c in cfg], [c[1] for c in cfg], [c[2] for c in cfg],
+                      [c[3] for c in cfg])
+    for c in cfg:
+        assert np.array_equal(c[3].cpu().numpy(), c[4])
