@@ -457,7 +457,7 @@ __global__ void k_sym_expand(const cplx<T>* __restrict__ Kc, const SymEntry* __r
   } else if (sizeof(T) == 4)
     out[((int64_t)f * kNumCanon + id) * kKOffsetF + (ab / 3) * kKHalfF + (ab % 3) * 9 + had_slot_of(ab / 3, wr)] = v;
   else
-    out[((int64_t)f * kNumCanon + id) * 54 + ab * 9 + wr] = v;
+    out[((int64_t)f * kNumCanon + id) * kKOffsetD + (ab / 3) * kKHalfD + (ab % 3) * 9 + had_slot_of(ab / 3, wr)] = v;
 }
 
 constexpr int kHadThreads = 2 * kM2LWindowF;
@@ -695,12 +695,14 @@ k_hadamard16(const uint32_t* What, const uint32_t* Khat, const int* lenq, const 
 
 // The double-precision Hadamard product: the blocks, lanes, list walk and
 // source split of k_hadamard, with one 16-byte complex per LDS unit.  The
-// spectra of a frequency arrive row-major (6 x 9 per canonical offset) and
-// are put into the lanes' slot order while they are copied into LDS: half h
-// (stress rows 3h..3h+2) of offset c starts at unit 55 c + 27 h.  They take
-// 139 KB, so one block of 1024 threads (four waves per SIMD) runs per CU.
-// Per step a lane reads 27 complex spectrum values (432 B of LDS) for 108
-// double multiply-adds: LDS reads are this kernel's limit.
+// spectra of a frequency are stored in the lanes' slot order (half h = stress
+// rows 3h..3h+2 of offset c at unit 55 c + 27 h), and a block copies them into
+// LDS as they are: 139 KB, so one block of 1024 threads (four waves per SIMD)
+// runs per CU.  Per step a lane reads 27 complex spectrum values (432 B of
+// LDS) for 108 double multiply-adds: LDS reads are this kernel's limit.
+// (Reading one of the three rows from memory instead, to share the load
+// between LDS and L2, made the kernel 2.5 times slower: the rows are 144-byte
+// reads at random offsets.)
 constexpr int kHadThreadsD = 2 * kM2LWindowD;
 __global__ void __launch_bounds__(kHadThreadsD)
 k_hadamard64(const cplx<double>* What, const cplx<double>* Khat, const int* lenq, const int* wbase, const uint32_t* ilw,
@@ -720,12 +722,9 @@ k_hadamard64(const cplx<double>* What, const cplx<double>* Khat, const int* lenq
     win = blockIdx.x;
     f = blockIdx.y;
   }
-  const cplx<double>* kf = Khat + (int64_t)f * kNumCanon * 54;
-  for (int e = threadIdx.x; e < kNumCanon * 54; e += blockDim.x) {
-    const int id = e / 54, src = e - 54 * id;
-    const int row = src / 9, k = src - 9 * row, hh = row / 3;
-    Ks[id * kKOffsetD + hh * kKHalfD + (row - 3 * hh) * 9 + had_slot_of(hh, k)] = kf[e];
-  }
+  const double2* kf = reinterpret_cast<const double2*>(Khat + (int64_t)f * kNumCanon * kKOffsetD);
+  double2* Ks2 = reinterpret_cast<double2*>(Ks);
+  for (int e = threadIdx.x; e < kNumCanon * kKOffsetD; e += blockDim.x) Ks2[e] = kf[e];
   __syncthreads();
   const int64_t tt = (int64_t)win * kM2LWindowD + threadIdx.x / 2;
   if (tt >= ncell) return;  // both lanes of a target leave together

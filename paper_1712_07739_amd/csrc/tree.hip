@@ -740,7 +740,7 @@ int build_tree_impl(dfmm_plan* pl, const double* seg, int64_t nseg, hipStream_t 
   size_t bKx = 0;
   if (pl->sym) {  // one level of expanded offset spectra (the plan keeps the 16 classes)
     bKx = pl->h16 ? (size_t)pl->nf * kNumOffsets * kKOffsetH * sizeof(uint32_t)
-                  : (size_t)pl->nf * kNumCanon * (pl->mixed ? kKOffsetF : 54) * 2 * es;
+                  : (size_t)pl->nf * kNumCanon * (pl->mixed ? kKOffsetF : kKOffsetD) * 2 * es;
     DFMM_HIP(hipMalloc(&t->kexp, bKx));
   }
   if (pl->h16) DFMM_HIP(hipMalloc(&t->wmax, sizeof(unsigned) * (D + 1)));

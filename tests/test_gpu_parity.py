@@ -347,8 +347,10 @@ def test_operator_memory_against_the_paper(env):
     factor = infos[0]["mem_unif_fp64_bytes_per_level"] / infos[1]["generator_fp64_bytes_per_level"]
     f = pn["symmetry_memory_factor"]
     assert abs(factor - f["value"]) <= f["rel_tol"] * f["value"], factor
-    # the spectra actually held (half spectrum, complex): 158 -> 16 offsets
-    assert infos[0]["spectra_bytes"] * 16 == infos[1]["spectra_bytes"] * 158
+    # the spectra actually held (half spectrum, complex): 158 -> 16 offsets (the
+    # 158-offset FP64 store keeps each offset in the product's slot order, 55
+    # entries with one pad; the class store 54)
+    assert infos[0]["spectra_bytes"] * 16 * 54 == infos[1]["spectra_bytes"] * 158 * 55
     print("operator memory per level at p=7: Eq. mem_unif %.1f MB, 16-class generators %.1f MB (x%.2f); "
           "spectra held %.1f MB -> %.1f MB for %d levels"
           % (mem, infos[1]["generator_fp64_bytes_per_level"] / 1e6, factor, infos[0]["spectra_bytes"] / 1e6,
