@@ -346,10 +346,13 @@ def bench_batch(args):
         % (sizes[med], d_med, {k: round(v, 2) for k, v in pred.items()}, {k: round(v, 2) for k, v in meas.items()},
            {d: depths.count(d) for d in sorted(set(depths))}))
     plans = {d: pk.Plan(pk.make_params(order, d, *C, synth.loops.CORE_A, synth.loops.BOX_LO,
-                                       synth.loops.BOX_SIZE, precision=pk.DFMM_MIXED)) for d in set(depths)}
+                                       synth.loops.BOX_SIZE, precision=pk.DFMM_MIXED_F16,
+                                       m2l_mode=pk.DFMM_M2L_FFT_SYM)) for d in set(depths)}
     trees = [pk.Tree(plans[d], s) for d, s in zip(depths, segs)]
     outs = [torch.empty((n, 2, 3), dtype=torch.float64, device=dev) for n in sizes]
-    batch = pk.Batch([plans[d] for d in depths], trees, segs, burgs, outs, lanes=4)
+    lanes, lane_ms = pk.autotune_batch_lanes([plans[d] for d in depths], trees, segs, burgs, outs, reps=2)
+    log("batch branches -> ms per replay %s: %d branches" % ({k: round(v, 2) for k, v in lane_ms.items()}, lanes))
+    batch = pk.Batch([plans[d] for d in depths], trees, segs, burgs, outs, lanes=lanes)
     for _ in range(args.warmup):
         batch.run()
     torch.cuda.synchronize()
@@ -370,10 +373,10 @@ def bench_batch(args):
         "metric": "batched FMM force evaluation throughput, 64 ensembles of 5k-150k segments",
         "value": sum(sizes) / (ms_step * 1e-3), "unit": "segments/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "vs_baseline": None, "dtype": "f16/f32", "data": "synthetic",
         "config": {"workload": "batch64", "n_ensembles": 64, "n_seg_total": int(sum(sizes)), "order": order,
                    "medium": "isotropic", "depths": {str(d): depths.count(d) for d in sorted(set(depths))},
-                   "graph_lanes": 4},
+                   "graph_lanes": lanes, "graph_lanes_ms": {str(k): v for k, v in lane_ms.items()}},
         "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99)),
         "latency_ms_max": float(lat.max()), "rel_err_vs_fp64_direct_max": max(errs),
     }

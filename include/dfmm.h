@@ -310,6 +310,17 @@ int dfmm_batch_run(dfmm_batch* batch, void* stream);
  * allocates the graph and its streams for the duration of the call. */
 int dfmm_forces_batched(const dfmm_plan* const* plans, dfmm_tree* const* trees, const double* const* seg,
                         const double* const* burgers, double* const* forces, int n_cfg, void* stream);
+/* Launch-shape autotuner of the batch graph: the same n_cfg evaluations
+ * captured with 1, 2, 4 and 8 parallel branches (counts above n_cfg are
+ * skipped, 1 always tried), each graph replayed `reps` times after one
+ * warm-up; *best = the branch count with the smallest mean time per replay
+ * (ms[0..3], if non-NULL: that mean for 1, 2, 4, 8 branches, 0 where not
+ * tried).  The forces are written by every replay.  Synchronous; allocates
+ * (one graph at a time).  Errors: as dfmm_batch_create, DFMM_E_ARG for
+ * reps < 1. */
+int dfmm_autotune_batch_lanes(const dfmm_plan* const* plans, dfmm_tree* const* trees, const double* const* seg,
+                              const double* const* burgers, double* const* forces, int n_cfg, int reps, void* stream,
+                              int* best, double* ms);
 int dfmm_batch_latencies(dfmm_batch* batch, double* ms, int n_cfg);
 void dfmm_batch_destroy(dfmm_batch* batch);
 

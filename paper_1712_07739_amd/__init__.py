@@ -36,7 +36,7 @@ ENTRY_POINTS = (
     "dfmm_surrogate_loss_grad", "dfmm_surrogate_forward", "dfmm_batch_create", "dfmm_batch_run",
     "dfmm_batch_latencies", "dfmm_batch_destroy", "dfmm_autotune_depth",
     "dfmm_direct_forces_noalloc", "dfmm_direct_noalloc_bytes", "dfmm_surrogate_get_gate",
-    "dfmm_surrogate_save", "dfmm_surrogate_load", "dfmm_forces_batched",
+    "dfmm_surrogate_save", "dfmm_surrogate_load", "dfmm_forces_batched", "dfmm_autotune_batch_lanes",
 )
 NOALLOC_SCRATCH_BYTES = 64 << 20
 
@@ -116,6 +116,8 @@ def lib():
     L.dfmm_batch_latencies.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i32]
     L.dfmm_batch_destroy.argtypes = [vp]
     L.dfmm_forces_batched.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int, vp]
+    L.dfmm_autotune_batch_lanes.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int, ctypes.c_int, vp,
+                                            ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
     L.dfmm_autotune_depth.argtypes = [ctypes.POINTER(Params), vp, vp, i64, i32, i32, vp, ctypes.POINTER(i32),
                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     for name in ENTRY_POINTS:
@@ -400,6 +402,20 @@ def forces_batched(plans, trees, segs, burgers, forces, stream=None):
             P(*[x.data_ptr() for x in burgers]), P(*[x.data_ptr() for x in forces]))
     _check(lib().dfmm_forces_batched(*[ctypes.cast(a, ctypes.c_void_p) for a in args], n, _stream(stream)))
     return forces
+
+
+def autotune_batch_lanes(plans, trees, segs, burgers, forces, reps=3, stream=None):
+    """dfmm_autotune_batch_lanes: the batch graph's branch count with the
+    smallest mean replay time; returns (best, {branches: ms})."""
+    n = len(plans)
+    P = ctypes.c_void_p * n
+    args = (P(*[p.handle for p in plans]), P(*[t.handle for t in trees]), P(*[x.data_ptr() for x in segs]),
+            P(*[x.data_ptr() for x in burgers]), P(*[x.data_ptr() for x in forces]))
+    best = ctypes.c_int()
+    ms = (ctypes.c_double * 4)()
+    _check(lib().dfmm_autotune_batch_lanes(*[ctypes.cast(a, ctypes.c_void_p) for a in args], n, reps,
+                                           _stream(stream), ctypes.byref(best), ms))
+    return best.value, {b: ms[k] for k, b in enumerate((1, 2, 4, 8)) if ms[k] > 0}
 
 
 def autotune_depth(params: Params, seg, burgers, d_min=3, d_max=7, stream=None):

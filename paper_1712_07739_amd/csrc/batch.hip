@@ -202,6 +202,52 @@ void dfmm_batch_destroy(dfmm_batch* b) {
   batch_free(b);
 }
 
+int dfmm_autotune_batch_lanes(const dfmm_plan* const* plans, dfmm_tree* const* trees, const double* const* seg,
+                              const double* const* burgers, double* const* forces, int n_cfg, int reps, void* stream,
+                              int* best, double* ms) {
+  if (!best || reps < 1 || n_cfg < 1) {
+    set_error("autotune_batch_lanes: invalid argument");
+    return DFMM_E_ARG;
+  }
+  const hipStream_t st = (hipStream_t)stream;
+  const int cand[4] = {1, 2, 4, 8};
+  double best_ms = 0;
+  *best = 0;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) hipEventDestroy(e0);
+    set_error("autotune_batch_lanes: cannot create events");
+    return DFMM_E_HIP;
+  }
+  int rc = DFMM_OK;
+  for (int k = 0; k < 4 && rc == DFMM_OK; ++k) {
+    if (ms) ms[k] = 0;
+    if (cand[k] > n_cfg && k > 0) continue;
+    dfmm_batch* b = nullptr;
+    rc = dfmm_batch_create(plans, trees, seg, burgers, forces, n_cfg, cand[k], stream, &b);
+    if (rc) break;
+    rc = dfmm_batch_run(b, stream);  // warm-up
+    if (rc == DFMM_OK && hipEventRecord(e0, st) != hipSuccess) rc = DFMM_E_HIP;
+    for (int r = 0; r < reps && rc == DFMM_OK; ++r) rc = dfmm_batch_run(b, stream);
+    if (rc == DFMM_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+      rc = DFMM_E_HIP;
+    float t = 0.f;
+    if (rc == DFMM_OK && hipEventElapsedTime(&t, e0, e1) != hipSuccess) rc = DFMM_E_HIP;
+    dfmm_batch_destroy(b);
+    if (rc) break;
+    const double per = t / reps;
+    if (ms) ms[k] = per;
+    if (*best == 0 || per < best_ms) {
+      best_ms = per;
+      *best = cand[k];
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc == DFMM_E_HIP) set_error("autotune_batch_lanes: a HIP call failed");
+  return rc;
+}
+
 int dfmm_forces_batched(const dfmm_plan* const* plans, dfmm_tree* const* trees, const double* const* seg,
                         const double* const* burgers, double* const* forces, int n_cfg, void* stream) {
   dfmm_batch* b = nullptr;

@@ -111,3 +111,24 @@ def test_forces_batched_one_shot_equals_individual_calls(env):
                       [c[3] for c in cfg])
     for c in cfg:
         assert np.array_equal(c[3].cpu().numpy(), c[4])
+
+
+def test_batch_branch_autotuner(env):
+    """The launch-shape autotuner times the batch graph at 1, 2, 4 and 8
+    branches, returns the fastest measured count, and every replay writes the
+    individual calls' forces."""
+    torch, pk, dev = env
+    plan = pk.Plan(pk.make_params(4, 3, *ISO, 1e-3, BOX_LO, BOX, precision=1))
+    cfg = []
+    for i, nl in enumerate([6, 2, 11, 4, 8]):
+        seg, b = synth.make_loops(nl, 0.01, 0.05, 970 + i)
+        ts, tb = torch.tensor(seg, device=dev), torch.tensor(b, device=dev)
+        tree = pk.Tree(plan, ts)
+        ref = pk.fmm_forces(plan, tree, ts, tb).cpu().numpy()
+        cfg.append((tree, ts, tb, torch.zeros((len(seg), 2, 3), dtype=torch.float64, device=dev), ref))
+    best, ms = pk.autotune_batch_lanes([plan] * 5, [c[0] for c in cfg], [c[1] for c in cfg], [c[2] for c in cfg],
+                                       [c[3] for c in cfg], reps=2)
+    print("batch branches -> ms per replay:", ms, "best", best)
+    assert sorted(ms) == [1, 2, 4] and best in ms and ms[best] == min(ms.values())
+    for c in cfg:
+        assert np.array_equal(c[3].cpu().numpy(), c[4])
