@@ -122,13 +122,20 @@ typedef struct {
                          multipole weights of finer cells acting on a leaf's
                          points, points of coarser leaves acting on a cell's
                          nodes).  Requires lsq_degree 0 and the exact kernel. */
+  int freq_chunks;    /* M2L spectra in chunks along the first frequency
+                         axis (1..2p-1): a tree holds the source and target
+                         spectra of one chunk of one level at a time, the
+                         forward transform is repeated per chunk and the
+                         inverse transforms are summed.  0: as few chunks as
+                         keep them within half of the device memory free at
+                         tree build.                                          */
 } dfmm_params;
 #define DFMM_LSQ_AUTO (-1)
 
 /* Fill *p with defaults: order 5, depth 4, isotropic mu = 1, nu = 0.3,
  * a = 1e-3, root cube [-0.05, 1.05]^3, n_quad 3, n_circle 64, FP64,
  * DFMM_M2L_FFT, DFMM_KERNEL_EXACT, Lagrange interpolation (lsq_degree 0),
- * uniform tree (leaf_max 0). */
+ * uniform tree (leaf_max 0), spectrum chunks chosen at tree build (freq_chunks 0). */
 void dfmm_default_params(dfmm_params* p);
 
 /* Precompute a plan (Sec. 4.1, Eq. m2l and Theorem 1): for every level 2..D

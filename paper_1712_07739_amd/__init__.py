@@ -50,7 +50,7 @@ class Params(ctypes.Structure):
         ("core_a", ctypes.c_double), ("box_lo", ctypes.c_double * 3), ("box_size", ctypes.c_double),
         ("n_quad", ctypes.c_int), ("n_circle", ctypes.c_int), ("precision", ctypes.c_int),
         ("m2l_mode", ctypes.c_int), ("aniso_kernel", ctypes.c_int), ("lsq_degree", ctypes.c_int),
-        ("leaf_max", ctypes.c_int),
+        ("leaf_max", ctypes.c_int), ("freq_chunks", ctypes.c_int),
     ]
 
 
@@ -156,10 +156,10 @@ def default_params():
 
 
 def make_params(order, depth, c11, c12, c44, core_a, box_lo, box_size, n_quad=3, n_circle=64,
-                precision=DFMM_FP64, m2l_mode=DFMM_M2L_FFT, aniso_kernel=DFMM_KERNEL_EXACT, lsq_degree=0, leaf_max=0):
+                precision=DFMM_FP64, m2l_mode=DFMM_M2L_FFT, aniso_kernel=DFMM_KERNEL_EXACT, lsq_degree=0, leaf_max=0, freq_chunks=0):
     p = default_params()
     p.m2l_mode, p.aniso_kernel, p.lsq_degree = int(m2l_mode), int(aniso_kernel), int(lsq_degree)
-    p.leaf_max = int(leaf_max)
+    p.leaf_max, p.freq_chunks = int(leaf_max), int(freq_chunks)
     p.order, p.depth = int(order), int(depth)
     p.c11, p.c12, p.c44, p.core_a = float(c11), float(c12), float(c44), float(core_a)
     for i in range(3):

@@ -76,6 +76,7 @@ void dfmm_default_params(dfmm_params* p) {
   p->aniso_kernel = DFMM_KERNEL_EXACT;
   p->lsq_degree = 0;
   p->leaf_max = 0;
+  p->freq_chunks = 0;
 }
 
 const char* dfmm_status_string(int s) {
@@ -124,6 +125,7 @@ int dfmm_fmm_setup(const dfmm_params* prm, void* stream, dfmm_plan** out) {
     return DFMM_E_ARG;
   }
   if (q.leaf_max < 0) { set_error("fmm_setup: leaf_max must be >= 0"); return DFMM_E_ARG; }
+  if (q.freq_chunks < 0) { set_error("fmm_setup: freq_chunks must be >= 0"); return DFMM_E_ARG; }
   if (q.leaf_max > 0 && (q.lsq_degree != 0 || q.aniso_kernel != DFMM_KERNEL_EXACT)) {
     set_error("fmm_setup: the adaptive tree (leaf_max > 0) takes Lagrange interpolation and the exact kernel");
     return DFMM_E_ARG;
@@ -514,7 +516,8 @@ int dfmm_tree_info(const dfmm_tree* t, char* json, size_t cap) {
                   std::to_string(t->adaptive) + ", \"leaves\": " +
                   std::to_string(t->adaptive ? t->nleaf : (t->D >= 2 ? t->lv[t->D].n : 0)) +
                   ", \"u_pairs\": " + std::to_string(t->nu) + ", \"w_pairs\": " + std::to_string(t->nw) +
-                  ", \"x_pairs\": " + std::to_string(t->nx) + ", \"levels\": [";
+                  ", \"x_pairs\": " + std::to_string(t->nx) + ", \"freq_chunks\": " + std::to_string(t->fchunks) +
+                  ", \"levels\": [";
   for (int l = 2; l <= t->D; ++l) {
     if (l > 2) s += ", ";
     s += "{\"level\": " + std::to_string(l) + ", \"cells\": " + std::to_string(t->lv[l].n) +

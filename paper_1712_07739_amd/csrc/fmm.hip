@@ -319,10 +319,12 @@ __device__ __forceinline__ void dft_line_pairs(const cplx<T>* x, const T* c, con
   }
 }
 
+// Only the frequencies with first index f1 in [fa, fb) are stored, at f - fa n P
+// (the spectrum in chunks along the first axis, for large trees).
 template <typename T, int P, bool H16>
 __global__ void __launch_bounds__(kDftThreads) k_fdft(const T* __restrict__ W, int64_t ncell, int G,
                                               const T* __restrict__ twg, cplx<T>* __restrict__ What,
-                                              const unsigned* __restrict__ wmax) {
+                                              const unsigned* __restrict__ wmax, int fa, int fb) {
   constexpr int n = 2 * P - 1, p3 = P * P * P;
   extern __shared__ __align__(16) unsigned char shraw[];
   cplx<T>* X1 = (cplx<T>*)shraw;  // [G][P][P][P]  (g, m1, m2, f3)
@@ -373,11 +375,14 @@ __global__ void __launch_bounds__(kDftThreads) k_fdft(const T* __restrict__ W, i
         const float sw = h16_wscale(wmax, p3);
         uint32_t* W16 = reinterpret_cast<uint32_t*>(What);
         dft_line_pairs<T, P>(x, c, s, [&](int f, cplx<T> v) {
-          W16[((int64_t)(f * n * P + r) * ncell + cell) * 9 + c0 + g] = pack_h2((float)v.re * sw, (float)v.im * sw);
+          if (f >= fa && f < fb)
+            W16[((int64_t)((f - fa) * n * P + r) * ncell + cell) * 9 + c0 + g] =
+                pack_h2((float)v.re * sw, (float)v.im * sw);
         });
       } else {
-        dft_line_pairs<T, P>(x, c, s,
-                             [&](int f, cplx<T> v) { What[((int64_t)(f * n * P + r) * ncell + cell) * 9 + c0 + g] = v; });
+        dft_line_pairs<T, P>(x, c, s, [&](int f, cplx<T> v) {
+          if (f >= fa && f < fb) What[((int64_t)((f - fa) * n * P + r) * ncell + cell) * 9 + c0 + g] = v;
+        });
       }
     }
     __syncthreads();
@@ -845,9 +850,13 @@ __device__ __forceinline__ void idft_line_pairs(const cplx<T>* x, const T* c, co
 // reads cost).  The last pass uses the Hermitian symmetry of the last axis
 // (f3 = 0 once, f3 > 0 twice, real part).
 template <typename T, int P>
+// With the spectrum in chunks: Shat holds the frequencies with first index
+// f1 in [fa, fb) (the others count as zero, the transform being linear), and
+// acc adds the result to s instead of writing it.
 __global__ void __launch_bounds__(kDftThreads) k_idft(const cplx<T>* __restrict__ Shat, int64_t ncell,
                                               const T* __restrict__ twg, T* __restrict__ s,
-                                              const unsigned* __restrict__ wmax, float kscale) {
+                                              const unsigned* __restrict__ wmax, float kscale, int fa, int fb,
+                                              int acc_out) {
   constexpr int n = 2 * P - 1, p3 = P * P * P, nf = n * n * P;
   extern __shared__ __align__(16) unsigned char shraw[];
   cplx<T>* Y1 = (cplx<T>*)shraw;     // [6][n(f2)][P(f3)][P(l1)]
@@ -867,7 +876,8 @@ __global__ void __launch_bounds__(kDftThreads) k_idft(const cplx<T>* __restrict_
     const int g = it % 6, r = it / 6;  // r = f2 P + f3
     cplx<T> x[n];
 #pragma unroll
-    for (int f = 0; f < n; ++f) x[f] = src[(int64_t)(f * n * P + r) * ncell * 6 + g];
+    for (int f = 0; f < n; ++f)
+      x[f] = (f >= fa && f < fb) ? src[(int64_t)((f - fa) * n * P + r) * ncell * 6 + g] : cplx<T>{T(0), T(0)};
     idft_line_pairs<T, P>(x, c, sn, [&](int l, cplx<T> v) { Y1[(g * n * P + r) * P + l] = v; });
   }
   __syncthreads();
@@ -892,7 +902,8 @@ __global__ void __launch_bounds__(kDftThreads) k_idft(const cplx<T>* __restrict_
       T acc = 0;
 #pragma unroll
       for (int f = 1; f < P; ++f) acc = fma(x[f].re, c[(f * l) % n], fma(-x[f].im, sn[(f * l) % n], acc));
-      out[l] = (x[0].re + T(2) * acc) * scale;
+      const T v = (x[0].re + T(2) * acc) * scale;
+      out[l] = acc_out ? out[l] + v : v;
     }
   }
 }
@@ -1513,30 +1524,32 @@ static int dft_groups(bool fwd) {
 // transform removes the operator scale kscale and the source scale).
 template <typename T, int P>
 static void dft_launch(bool fwd, unsigned blocks, const void* in, int64_t ncell, const T* tw, void* out,
-                       const unsigned* wmax, float kscale, hipStream_t st) {
+                       const unsigned* wmax, float kscale, int fa, int fb, int acc, hipStream_t st) {
   const int G = dft_groups<T, P>(fwd);
   if (fwd && wmax)
     k_fdft<T, P, true><<<blocks, kDftThreads, lds_fdft_t<P>(G, sizeof(T)), st>>>((const T*)in, ncell, G, tw,
-                                                                               (cplx<T>*)out, wmax);
+                                                                               (cplx<T>*)out, wmax, fa, fb);
   else if (fwd)
     k_fdft<T, P, false><<<blocks, kDftThreads, lds_fdft_t<P>(G, sizeof(T)), st>>>((const T*)in, ncell, G, tw,
-                                                                                (cplx<T>*)out, nullptr);
+                                                                                (cplx<T>*)out, nullptr, fa, fb);
   else
     k_idft<T, P><<<blocks, kDftThreads, lds_idft_t<P>(sizeof(T)), st>>>((const cplx<T>*)in, ncell, tw, (T*)out,
-                                                                         wmax, kscale);
+                                                                         wmax, kscale, fa, fb, acc);
 }
 
+// fa, fb: the chunk of first frequency indices (0, n for the whole
+// spectrum); acc: the inverse transform adds to its output.
 template <typename T>
 static void dft(int p, bool fwd, unsigned blocks, const void* in, int64_t ncell, const T* tw, void* out,
-                const unsigned* wmax, float kscale, hipStream_t st) {
+                const unsigned* wmax, float kscale, int fa, int fb, int acc, hipStream_t st) {
   switch (p) {
-    case 2: dft_launch<T, 2>(fwd, blocks, in, ncell, tw, out, wmax, kscale, st); break;
-    case 3: dft_launch<T, 3>(fwd, blocks, in, ncell, tw, out, wmax, kscale, st); break;
-    case 4: dft_launch<T, 4>(fwd, blocks, in, ncell, tw, out, wmax, kscale, st); break;
-    case 5: dft_launch<T, 5>(fwd, blocks, in, ncell, tw, out, wmax, kscale, st); break;
-    case 6: dft_launch<T, 6>(fwd, blocks, in, ncell, tw, out, wmax, kscale, st); break;
-    case 7: dft_launch<T, 7>(fwd, blocks, in, ncell, tw, out, wmax, kscale, st); break;
-    default: dft_launch<T, 8>(fwd, blocks, in, ncell, tw, out, wmax, kscale, st); break;
+    case 2: dft_launch<T, 2>(fwd, blocks, in, ncell, tw, out, wmax, kscale, fa, fb, acc, st); break;
+    case 3: dft_launch<T, 3>(fwd, blocks, in, ncell, tw, out, wmax, kscale, fa, fb, acc, st); break;
+    case 4: dft_launch<T, 4>(fwd, blocks, in, ncell, tw, out, wmax, kscale, fa, fb, acc, st); break;
+    case 5: dft_launch<T, 5>(fwd, blocks, in, ncell, tw, out, wmax, kscale, fa, fb, acc, st); break;
+    case 6: dft_launch<T, 6>(fwd, blocks, in, ncell, tw, out, wmax, kscale, fa, fb, acc, st); break;
+    case 7: dft_launch<T, 7>(fwd, blocks, in, ncell, tw, out, wmax, kscale, fa, fb, acc, st); break;
+    default: dft_launch<T, 8>(fwd, blocks, in, ncell, tw, out, wmax, kscale, fa, fb, acc, st); break;
   }
 }
 
@@ -1774,11 +1787,9 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
     const auto& Lv = t->lv[l];
     if (Lv.n == 0) continue;
     const unsigned* wm = h16 ? t->wmax + l : nullptr;
-    STAGE(2, dft<T>(p, true, (unsigned)Lv.n, W + Lv.off * 9 * p3, Lv.n, tb.tw, What, wm, 1.f, st));
     const int wsz = m2l_window(pl->mixed);
     const int nwin = (int)((Lv.n + wsz - 1) / wsz);
     const int remap = nwin >= 16;
-    dim3 g(remap ? 8 * ((nwin + 7) / 8) : nwin, nf);
     // symmetry-reduced store: this level's 158 offset spectra, expanded into
     // the tree's workspace
     const cplx<T>* kh = (const cplx<T>*)pl->lev[l].khat;
@@ -1792,17 +1803,28 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
                      kh, pl->symtab, nf, n, p, 1.f, (cplx<T>*)t->kexp)));
       kh = (const cplx<T>*)t->kexp;
     }
-    if (h16)
-      STAGE(3, (k_hadamard16<<<g, kHadThreads, sizeof(uint32_t) * kNumOffsets * kKOffsetH, st>>>(
-                   (const uint32_t*)What, (const uint32_t*)kh, Lv.lenq, Lv.wbase, Lv.ilw, Lv.order, Lv.n, nf, nwin,
-                   remap, (cplx<float>*)Shat)));
-    else if constexpr (std::is_same<T, float>::value)
-      STAGE(3, (k_hadamard<<<g, kHadThreads, sizeof(cplx<float>) * kNumCanon * kKOffsetF, st>>>(
-                   What, kh, Lv.lenq, Lv.wbase, Lv.ilw, Lv.order, Lv.n, nf, nwin, remap, Shat)));
-    else
-      STAGE(3, (k_hadamard64<<<g, kHadThreadsD, sizeof(cplx<double>) * kNumCanon * kKOffsetD, st>>>(
-                   What, kh, Lv.lenq, Lv.wbase, Lv.ilw, Lv.order, Lv.n, nf, nwin, remap, Shat)));
-    STAGE(4, dft<T>(p, false, (unsigned)Lv.n, Shat, Lv.n, tb.tw, s + Lv.off * 6 * p3, wm, ksc, st));
+    // the spectrum in chunks of first frequency indices [fa, fb): forward
+    // DFT of the chunk, its Hadamard product, inverse DFT added to s
+    for (int fa = 0; fa < n; fa += t->fchunk) {
+      const int fb = std::min(n, fa + t->fchunk);
+      const int nfc = (fb - fa) * n * p;     // frequencies of the chunk
+      const int64_t fbase = (int64_t)fa * n * p;
+      dim3 g(remap ? 8 * ((nwin + 7) / 8) : nwin, nfc);
+      STAGE(2, dft<T>(p, true, (unsigned)Lv.n, W + Lv.off * 9 * p3, Lv.n, tb.tw, What, wm, 1.f, fa, fb, 0, st));
+      if (h16)
+        STAGE(3, (k_hadamard16<<<g, kHadThreads, sizeof(uint32_t) * kNumOffsets * kKOffsetH, st>>>(
+                     (const uint32_t*)What, (const uint32_t*)kh + fbase * kNumOffsets * kKOffsetH, Lv.lenq,
+                     Lv.wbase, Lv.ilw, Lv.order, Lv.n, nfc, nwin, remap, (cplx<float>*)Shat)));
+      else if constexpr (std::is_same<T, float>::value)
+        STAGE(3, (k_hadamard<<<g, kHadThreads, sizeof(cplx<float>) * kNumCanon * kKOffsetF, st>>>(
+                     What, kh + fbase * kNumCanon * kKOffsetF, Lv.lenq, Lv.wbase, Lv.ilw, Lv.order, Lv.n, nfc,
+                     nwin, remap, Shat)));
+      else
+        STAGE(3, (k_hadamard64<<<g, kHadThreadsD, sizeof(cplx<double>) * kNumCanon * kKOffsetD, st>>>(
+                     What, kh + fbase * kNumCanon * kKOffsetD, Lv.lenq, Lv.wbase, Lv.ilw, Lv.order, Lv.n, nfc, nwin,
+                     remap, Shat)));
+      STAGE(4, dft<T>(p, false, (unsigned)Lv.n, Shat, Lv.n, tb.tw, s + Lv.off * 6 * p3, wm, ksc, fa, fb, fa > 0, st));
+    }
   }
   // adaptive tree: the points of each X leaf onto the nodes of the cells
   // that list it, before the local values go down the tree

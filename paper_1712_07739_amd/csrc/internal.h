@@ -214,8 +214,10 @@ struct dfmm_tree {
   double* pts = nullptr;    // sorted point data [9][N]: x, y, z, bx, by, bz, tx, ty, tz
   void* W = nullptr;        // [ncell_total][9][p^3]  (float or double)
   void* s = nullptr;        // [ncell_total][6][p^3]
-  void* What = nullptr;     // [nf][max level cells][9] complex
-  void* Shat = nullptr;     // [nf][max level cells][6] complex
+  int fchunk = 0;           // first frequency indices per chunk of the spectra (n: whole)
+  int fchunks = 1;          // chunks per level
+  void* What = nullptr;     // [chunk frequencies][max level cells][9] complex (f16 pairs or T)
+  void* Shat = nullptr;     // [chunk frequencies][max level cells][6] complex
   double* sig = nullptr;    // [N][6] stress at sorted points
   unsigned* wmax = nullptr; // DFMM_MIXED_F16: per level, the largest |W| (float bits), for the f16 scale
   void* kexp = nullptr;     // symmetry-reduced plans: one level's 158 offset spectra, expanded

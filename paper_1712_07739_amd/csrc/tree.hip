@@ -720,8 +720,29 @@ int build_tree_impl(dfmm_plan* pl, const double* seg, int64_t nseg, hipStream_t 
   const int p3 = pl->p * pl->p * pl->p;
   const size_t es = pl->mixed ? sizeof(float) : sizeof(double);
   size_t bW = es * 9 * p3 * t->ncell_total, bS = es * 6 * p3 * t->ncell_total;
-  size_t bWh = es * 2 * 9 * (size_t)pl->nf * t->max_level_cells;
-  size_t bSh = es * 2 * 6 * (size_t)pl->nf * t->max_level_cells;
+  // Source and target spectra of one level, whole or in chunks of first
+  // frequency indices: the plan's freq_chunks, or (0) as few chunks as keep
+  // them within half of the device memory free once the rest is allocated.
+  const size_t per_f = ((pl->h16 ? sizeof(uint32_t) : es * 2) * 9 + es * 2 * 6) * (size_t)t->max_level_cells;
+  {
+    const int n = pl->n;
+    int chunks = pl->prm.freq_chunks;
+    if (chunks <= 0) {
+      size_t fr = 0, total = 0;
+      DFMM_HIP(hipMemGetInfo(&fr, &total));
+      const size_t rest = es * 15 * p3 * t->ncell_total + sizeof(double) * 15 * N;
+      const size_t budget = fr > rest ? (fr - rest) / 2 : 0;
+      const size_t whole = per_f * (size_t)pl->nf;
+      chunks = 1;
+      while (chunks < n && whole / chunks > budget) ++chunks;
+    }
+    chunks = std::min(chunks, n);
+    t->fchunk = (n + chunks - 1) / chunks;
+    t->fchunks = (n + t->fchunk - 1) / t->fchunk;
+  }
+  const size_t nfc = (size_t)t->fchunk * pl->n * pl->p;
+  size_t bWh = (pl->h16 ? sizeof(uint32_t) : es * 2) * 9 * nfc * t->max_level_cells;
+  size_t bSh = es * 2 * 6 * nfc * t->max_level_cells;
   DFMM_HIP(hipStreamCreateWithFlags(&t->side, hipStreamNonBlocking));
   DFMM_HIP(hipEventCreateWithFlags(&t->fork, hipEventDisableTiming));
   DFMM_HIP(hipEventCreateWithFlags(&t->join, hipEventDisableTiming));

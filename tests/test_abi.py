@@ -42,15 +42,15 @@ def test_params_struct_matches_header_defaults(L):
     assert (p.order, p.depth, p.n_quad, p.n_circle, p.precision) == (5, 4, 3, 64, 0)
     assert abs(p.c11 - 3.5) < 1e-15 and abs(p.c12 - 1.5) < 1e-15 and p.c44 == 1.0
     assert p.box_size == 1.1 and list(p.box_lo) == [-0.05] * 3
-    assert (p.m2l_mode, p.aniso_kernel, p.lsq_degree, p.leaf_max) == (0, 0, 0, 0)
-    # layout: 2 ints, 4 doubles, 3 doubles, 1 double, 7 ints (+ padding)
+    assert (p.m2l_mode, p.aniso_kernel, p.lsq_degree, p.leaf_max, p.freq_chunks) == (0, 0, 0, 0, 0)
+    # layout: 2 ints, 4 doubles, 3 doubles, 1 double, 8 ints
     assert ctypes.sizeof(pk.Params) == 8 + 8 * 8 + 32
 
 
 @pytest.mark.parametrize("field,value", [
     ("order", 1), ("order", 9), ("depth", 1), ("depth", 11), ("n_quad", 0), ("n_circle", 7),
     ("c44", -1.0), ("core_a", -1e-3), ("box_size", 0.0), ("precision", 3), ("m2l_mode", 2),
-    ("aniso_kernel", 5), ("lsq_degree", 5), ("lsq_degree", -2), ("leaf_max", -1),
+    ("aniso_kernel", 5), ("lsq_degree", 5), ("lsq_degree", -2), ("leaf_max", -1), ("freq_chunks", -1),
 ])
 def test_setup_rejects_bad_parameters_before_touching_the_gpu(L, field, value):
     import paper_1712_07739_amd as pk

@@ -521,3 +521,27 @@ def test_lsq_error_vs_direct(env):
         print("p=%d: Lagrange %.3e, least squares (d=%d) %.3e" % (p, row[0], lsq_auto(p), row[1]))
         errs.append(row[1])
     assert errs[-1] < errs[0] / 4
+
+
+# ------------------------------------------------ spectra in frequency chunks
+@pytest.mark.parametrize("chunks,expect", [(2, 2), (3, 3), (4, 3), (9, 9)])
+def test_frequency_chunks_match_the_whole_spectrum(env, chunks, expect):
+    """The M2L spectra taken in chunks of first frequency indices (the
+    forward transform per chunk, the inverse transforms summed) give the
+    whole-spectrum result: FP64 to 1e-13 and against the oracle's FMM to
+    1e-10, single precision and f16 operands to 1e-6 (only the summation
+    order of the inverse transform changes)."""
+    torch, pk, dev = env
+    seg, b = synth.make_loops(25, 0.01, 0.05, 31)
+    ts, tb = torch.tensor(seg, device=dev), torch.tensor(b, device=dev)
+    ref_o = oracle.fmm_forces(seg, b, oracle.medium(*CUB, 1e-3), 5, 4, BOX_LO, BOX)
+    for prec, bar in ((0, 1e-13), (1, 1e-6), (2, 1e-6)):
+        out = {}
+        for c in (1, chunks):
+            plan = pk.Plan(pk.make_params(5, 4, *CUB, 1e-3, BOX_LO, BOX, precision=prec, m2l_mode=1, freq_chunks=c))
+            tree = pk.Tree(plan, ts)
+            assert tree.info()["freq_chunks"] == (1 if c == 1 else expect)
+            out[c] = pk.fmm_forces(plan, tree, ts, tb).cpu().numpy()
+        assert oracle.rel_err(out[chunks], out[1]) <= bar, prec
+        if prec == 0:
+            assert oracle.rel_err(out[chunks], ref_o) <= 1e-10
