@@ -24,7 +24,7 @@ PEAK_FP64_VALU = 78.6e12
 PEAK_HBM = 8.0e12
 # Smallest interpolation order whose force error on the workload is <= 1e-4
 # (measured: cubic1m p=6 1.15e-4, p=7 3.0e-5 against the FP64 direct sum).
-BAR_ORDER = {"cubic1m": 7, "iso200k": 6, "cubic100k": 6}
+BAR_ORDER = {"cubic1m": 7, "cubic10m": 7, "iso200k": 6, "cubic100k": 6}
 def traffic_file(kernel):
     return os.path.join(ROOT, "profiles", "%s_cubic1m_p7_traffic.json" % kernel)
 
@@ -182,8 +182,9 @@ def main():
     torch.cuda.synchronize()
     tree_s = time.perf_counter() - t0
     tinfo = tree.info()
-    log("tree %.3f s: m2l pairs %d, near pairs %d, leaves %d, w/x pairs %d" % (
-        tree_s, tinfo["m2l_pairs"], tinfo["near_pairs"], tinfo["leaves"], tinfo["w_pairs"]))
+    log("tree %.3f s: m2l pairs %d, near pairs %d, leaves %d, w/x pairs %d, spectrum chunks %d, workspace %.1f GB" % (
+        tree_s, tinfo["m2l_pairs"], tinfo["near_pairs"], tinfo["leaves"], tinfo["w_pairs"], tinfo["freq_chunks"],
+        tinfo["workspace_bytes"] / 1e9))
     out = torch.empty((ns, 2, 3), dtype=torch.float64, device=dev)
     for i in range(args.warmup):
         pk.fmm_forces(plan, tree, tseg, tb, out=out)
@@ -238,7 +239,8 @@ def main():
         "config": {"workload": args.workload, "n_seg": ns, "order": prm["order"], "depth": prm["depth"],
                    "C": [prm["c11"], prm["c12"], prm["c44"]], "core_a": prm["core_a"],
                    "precision": args.precision, "configured_order": configured_order, "m2l_mode": args.m2l_mode,
-                   "tree": "adaptive, leaves of at most %d points" % args.leaf_max if args.leaf_max else "uniform"},
+                   "tree": "adaptive, leaves of at most %d points" % args.leaf_max if args.leaf_max else "uniform",
+                   "freq_chunks": tinfo["freq_chunks"]},
         "rel_err_vs_fp64_direct": err, "err_sample_segments": int(len(sub)),
         "stage_ms": {pk.STAGES[i]: stage_ms[i] / ncalls for i in range(pk.N_STAGES)},
         "stage_ms_note": "separate pass with HIP events around each stage, stages one by one (in the timed "

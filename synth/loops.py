@@ -81,12 +81,14 @@ CUBIC_A25 = (1.0, 0.6, 0.5)
 # and leaf depth D.  Sizes follow the configurations the method is exercised
 # on: a small isotropic case the oracle finishes in seconds, a 200k-segment
 # isotropic case, a 100k-segment cubic case (Zener ratio 2.5) and a
-# 1M-segment cubic case.
+# 1M-segment cubic case, and a 10M-segment cubic case for one GPU's capacity.
 WORKLOADS = {
     "iso2k": dict(n_loops=50, r=(0.01, 0.05), seed=1, C=ISO, order=4, depth=3),
     "iso200k": dict(n_loops=5000, r=(0.002, 0.02), seed=2, C=ISO, order=5, depth=6),
     "cubic100k": dict(n_loops=2500, r=(0.002, 0.02), seed=3, C=CUBIC_A25, order=5, depth=5),
     "cubic1m": dict(n_loops=25000, r=(0.002, 0.02), seed=5, C=CUBIC_A25, order=6, depth=7),
+    # ten times the 1M case at the same loop density per leaf (one level deeper)
+    "cubic10m": dict(n_loops=250000, r=(0.002, 0.02), seed=6, C=CUBIC_A25, order=6, depth=8),
 }
 CORE_A = 1e-3
 
