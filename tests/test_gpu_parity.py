@@ -238,6 +238,20 @@ def test_errors_for_bad_coordinates(env):
     with pytest.raises(pk.DfmmError) as e:
         pk.fmm_forces(plan2, tree, ts, torch.zeros((2, 3), dtype=torch.float64, device=dev))
     assert e.value.status == -6
+    # no segments at all: rejected before any work
+    with pytest.raises(pk.DfmmError) as e:
+        pk.Tree(plan, torch.zeros((0, 2, 3), dtype=torch.float64, device=dev))
+    assert e.value.status == -1
+
+
+def test_maximum_depth(env):
+    """Depth 10, the deepest the 30-bit Morton keys allow (2^30 leaves in
+    the key space), on a small input: against the oracle's FMM."""
+    seg, b = synth.make_loops(4, 0.01, 0.03, 41)
+    ref = oracle.fmm_forces(seg, b, oracle.medium(*ISO, 1e-3), 3, 10, BOX_LO, BOX)
+    f, plan, tree = run_fmm(env, seg, b, ISO, 3, 10)
+    assert tree.info()["depth"] == 10
+    assert oracle.rel_err(f, ref) <= 1e-10
 
 
 def test_determinism_and_stage_timing(env):
