@@ -70,6 +70,26 @@ def make_loops(n_loops: int, r_min: float, r_max: float, seed: int):
     return segs, burg
 
 
+def make_clustered(n_clusters: int, per_cluster: int, cluster_r: float, r_small: tuple, n_spread: int,
+                   r_spread: tuple, seed: int):
+    """Loops of very uneven density: n_clusters tight clusters, each of
+    per_cluster small loops (radii r_small) whose centres are moved to
+    uniform points of a ball of radius cluster_r around the cluster centre
+    (cluster centres uniform in [0.1, 0.9]^3), plus n_spread loops spread over
+    the unit cube (radii r_spread).  Drawn from make_loops' streams (seed, and
+    seed + 1 for the spread loops) and default_rng(seed + 2) for the moves."""
+    segs, burg = make_loops(n_clusters * per_cluster, r_small[0], r_small[1], seed)
+    rng = np.random.default_rng(seed + 2)
+    centres = rng.uniform(0.1, 0.9, size=(n_clusters, 3))
+    for il in range(n_clusters * per_cluster):
+        s = segs[il * SEGS_PER_LOOP:(il + 1) * SEGS_PER_LOOP]
+        d = rng.normal(size=3)
+        d *= cluster_r * rng.uniform() ** (1.0 / 3.0) / np.linalg.norm(d)
+        s += centres[il // per_cluster] + d - s.reshape(-1, 3).mean(axis=0)
+    seg2, b2 = make_loops(n_spread, r_spread[0], r_spread[1], seed + 1)
+    return np.concatenate([segs, seg2]), np.concatenate([burg, b2])
+
+
 # Isotropic medium: shear modulus 1, Poisson ratio 0.3 -> cubic constants
 # C11 = lambda + 2 mu, C12 = lambda, C44 = mu.
 _MU, _NU = 1.0, 0.3
@@ -87,8 +107,12 @@ WORKLOADS = {
     "iso200k": dict(n_loops=5000, r=(0.002, 0.02), seed=2, C=ISO, order=5, depth=6),
     "cubic100k": dict(n_loops=2500, r=(0.002, 0.02), seed=3, C=CUBIC_A25, order=5, depth=5),
     "cubic1m": dict(n_loops=25000, r=(0.002, 0.02), seed=5, C=CUBIC_A25, order=6, depth=7),
-    # ten times the 1M case at the same loop density per leaf (one level deeper)
+    # ten times the 1M case in the same cube
     "cubic10m": dict(n_loops=250000, r=(0.002, 0.02), seed=6, C=CUBIC_A25, order=6, depth=8),
+    # 1M segments of very uneven density: 40 clusters of 500 small loops in
+    # balls of radius 0.01, and 5,000 loops spread over the cube
+    "cluster1m": dict(clusters=(40, 500, 0.01, (0.001, 0.003)), n_loops=5000, r=(0.002, 0.02), seed=7,
+                      C=CUBIC_A25, order=6, depth=7),
 }
 CORE_A = 1e-3
 
@@ -96,7 +120,11 @@ CORE_A = 1e-3
 def make_workload(name: str):
     """Return (seg, burgers, params dict) for a named workload."""
     w = WORKLOADS[name]
-    seg, b = make_loops(w["n_loops"], w["r"][0], w["r"][1], w["seed"])
+    if "clusters" in w:
+        nc, per, cr, rs = w["clusters"]
+        seg, b = make_clustered(nc, per, cr, rs, w["n_loops"], w["r"], w["seed"])
+    else:
+        seg, b = make_loops(w["n_loops"], w["r"][0], w["r"][1], w["seed"])
     prm = dict(
         c11=w["C"][0], c12=w["C"][1], c44=w["C"][2], core_a=CORE_A,
         order=w["order"], depth=w["depth"], box_lo=BOX_LO, box_size=BOX_SIZE,
