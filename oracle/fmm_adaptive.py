@@ -27,7 +27,9 @@ definitions (brute force over all cells), and the transfers of Alg. lagrange
 Every pair of points is then counted exactly once (``coverage`` checks it
 combinatorially), and with a kernel that is a polynomial of degree p-1 in
 each coordinate every far transfer is exact, so the FMM equals the direct
-sum: the pins of this module.
+sum: the pins of this module.  Optionally (``direct_max``) a W or X pair
+whose finer cell holds few points is summed directly instead, which keeps
+both properties.
 """
 from __future__ import annotations
 
@@ -136,12 +138,24 @@ class AdaptiveTree:
                 "w_pairs": sum(len(v) for v in self.W.values()), "x_pairs": sum(len(v) for v in self.X.values())}
 
 
-def fmm_stress_adaptive(y, q, kernel, p, Dmax, box_lo, box_size, leaf_max, return_parts=False, tree=None):
+def _subtree_points(T, c):
+    """Indices of the points below cell c (its leaves' points)."""
+    if T.leaf[c]:
+        return T.pts[c]
+    return np.concatenate([_subtree_points(T, ch) for ch in T.children[c]])
+
+
+def fmm_stress_adaptive(y, q, kernel, p, Dmax, box_lo, box_size, leaf_max, return_parts=False, tree=None,
+                        direct_max=None):
     """Stress at every point y[N,3] from all points (y, q[N,9]) by the
     adaptive Lagrange FMM on the tree that ``leaf_max`` and ``Dmax`` define.
     kernel: packed medium or callable x[n,3] -> K[n,6,9].  Returns
-    sigma[N,6]; with return_parts also the far part (L2P and M2P) and the
-    near part (U lists)."""
+    sigma[N,6]; with return_parts also the far part (L2P and W lists) and
+    the near part (U lists, and the W/X pairs evaluated directly).
+
+    direct_max = m: a W or X pair whose finer cell A holds at most m points
+    is summed directly between the points of A and of the leaf (exact; a
+    pair through A's nodes costs p^3 evaluations per point of the leaf)."""
     y = np.asarray(y, dtype=np.float64).reshape(-1, 3)
     q = np.asarray(q, dtype=np.float64).reshape(-1, 9)
     N = y.shape[0]
@@ -191,11 +205,20 @@ def fmm_stress_adaptive(y, q, kernel, p, Dmax, box_lo, box_size, leaf_max, retur
                                   dd[1][None, :, None, None, :, None],
                                   dd[2][None, None, :, None, None, :]]  # [l1,l2,l3,m1,m2,m3,6,9]
                 s[b] += np.einsum("abcdefxw,wdef->xabc", ops[o], W[a])
+    def direct_pair(a):
+        return direct_max is not None and len(_subtree_points(T, a)) <= direct_max
+
     # -- X lists: the source leaf's points straight onto the target's nodes
+    # (or, for a small target cell, onto the points below it)
+    sig_x = np.zeros((N, 6))
     for b in range(T.n):
         if T.level[b] >= 2 and T.X[b]:
             src = np.sort(np.concatenate([T.pts[a] for a in T.X[b]]))
-            s[b] += _direct(kernel, T.nodes(b, p), y[src], q[src]).T.reshape(6, p, p, p)
+            if direct_pair(b):
+                tgt = np.sort(_subtree_points(T, b))
+                sig_x[tgt] += _direct(kernel, y[tgt], y[src], q[src])
+            else:
+                s[b] += _direct(kernel, T.nodes(b, p), y[src], q[src]).T.reshape(6, p, p, p)
     # -- downward pass: L2L into every cell of level >= 3
     for l in range(3, Dmax + 1):
         for c in T.by_level[l]:
@@ -211,19 +234,26 @@ def fmm_stress_adaptive(y, q, kernel, p, Dmax, box_lo, box_size, leaf_max, retur
         L1, L2, L3 = bases(c, idx)
         sig_far[idx] = np.einsum("xabc,na,nb,nc->nx", s[c], L1, L2, L3)
         for a in T.W[c]:
-            sig_far[idx] += _direct(kernel, y[idx], T.nodes(a, p), W[a].reshape(9, -1).T)
+            if direct_pair(a):
+                sa = np.sort(_subtree_points(T, a))
+                sig_near[idx] += _direct(kernel, y[idx], y[sa], q[sa])
+            else:
+                sig_far[idx] += _direct(kernel, y[idx], T.nodes(a, p), W[a].reshape(9, -1).T)
         src = np.sort(np.concatenate([T.pts[a] for a in T.U[c]]))
-        sig_near[idx] = _direct(kernel, y[idx], y[src], q[src])
+        sig_near[idx] += _direct(kernel, y[idx], y[src], q[src])
+    sig_near += sig_x
     if return_parts:
         return sig_far + sig_near, sig_far, sig_near
     return sig_far + sig_near
 
 
-def fmm_forces_adaptive(seg, burg, kernel, p, Dmax, box_lo, box_size, leaf_max, nq=3, return_parts=False):
+def fmm_forces_adaptive(seg, burg, kernel, p, Dmax, box_lo, box_size, leaf_max, nq=3, return_parts=False,
+                        direct_max=None):
     """End-point forces f[N_s, 2, 3] with the stress from ``fmm_stress_adaptive``."""
     seg = np.asarray(seg, dtype=np.float64).reshape(-1, 2, 3)
     y, q = points(seg, burg, nq)
-    out = fmm_stress_adaptive(y, q, kernel, p, Dmax, box_lo, box_size, leaf_max, return_parts=return_parts)
+    out = fmm_stress_adaptive(y, q, kernel, p, Dmax, box_lo, box_size, leaf_max, return_parts=return_parts,
+                              direct_max=direct_max)
     tgt = np.arange(seg.shape[0])
     if return_parts:
         return tuple(assemble_forces(seg, burg, tgt, o, nq) for o in out)

@@ -65,6 +65,22 @@ def test_exact_for_polynomial_kernels(case):
     assert np.abs(s - ref).max() <= 1e-10 * np.abs(ref).max()
 
 
+def test_direct_small_pairs_keep_exactness(case):
+    """W/X pairs whose finer cell holds at most p^3 points summed directly:
+    still exact for polynomial kernels, and with direct_max 0 the plain
+    adaptive FMM."""
+    _, _, y, q, T = case
+    p = 3
+    K = poly_kernel(p, 5)
+    ref = direct_numpy(K, y, q)
+    s_d = fmm_stress_adaptive(y, q, K, p, 4, BOX_LO, BOX, 40, tree=T, direct_max=p ** 3)
+    assert np.abs(s_d - ref).max() <= 1e-10 * np.abs(ref).max()
+    med = oracle.medium(*synth.loops.ISO, 1e-3)
+    s0 = fmm_stress_adaptive(y, q, med, p, 4, BOX_LO, BOX, 40, tree=T)
+    s00 = fmm_stress_adaptive(y, q, med, p, 4, BOX_LO, BOX, 40, tree=T, direct_max=0)
+    assert np.array_equal(s0, s00)
+
+
 @pytest.mark.parametrize("drop", ["W", "X"])
 def test_a_dropped_list_breaks_exactness(case, drop):
     """The exactness pin has teeth: without the W (or X) interactions the
