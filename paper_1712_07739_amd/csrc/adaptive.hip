@@ -92,12 +92,15 @@ __global__ void k_compact(int n, const int* keep, const int* leaf, const int* ni
 // lord + their rank among the level's leaves).
 __global__ void k_leaf_emit(int n, const int* keep, const int* leaf, const int* nidx, const int* lidx, const int* np,
                             const int* pf, const uint32_t* key, int level, int goff, int lord, int* gl_cell,
-                            int* gl_pf, int* gl_pc, uint32_t* gkey, unsigned char* glev, int* gord) {
+                            int* gl_pf, int* gl_pc, uint32_t* gkey, unsigned char* glev, int* gord, int* gsf,
+                            int* gsn) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n || !keep[c]) return;
   const int g = goff + nidx[c];
   gkey[g] = key[c];
   glev[g] = (unsigned char)level;
+  gsf[g] = pf[c];
+  gsn[g] = np[c];
   if (leaf[c]) {
     const int o = lord + lidx[c];
     gl_cell[o] = g;
@@ -176,6 +179,8 @@ int adapt_prune(const dfmm_plan* pl, dfmm_tree* t, hipStream_t st) {
   ACHK(hipMalloc(&t->gkey, sizeof(uint32_t) * ncell));
   ACHK(hipMalloc(&t->glev, ncell));
   ACHK(hipMalloc(&t->gord, sizeof(int) * ncell));
+  ACHK(hipMalloc(&t->gsf, sizeof(int) * ncell));
+  ACHK(hipMalloc(&t->gsn, sizeof(int) * ncell));
   std::vector<dfmm_tree::Level> nl(D + 1);
   for (int l = 2; l <= De; ++l) {
     const int64_t n = t->lv[l].n, m = nkeep[l];
@@ -191,7 +196,7 @@ int adapt_prune(const dfmm_plan* pl, dfmm_tree* t, hipStream_t st) {
     ACHK(hipGetLastError());
     k_leaf_emit<<<nbk(n, 256), 256, 0, st>>>((int)n, keep[l], leaf[l], nidx[l], lidx[l], np[l], pf[l],
                                             t->lv[l].key, l, (int)goff[l], (int)lord[l], t->gl_cell, t->gl_pf,
-                                            t->gl_pc, t->gkey, t->glev, t->gord);
+                                            t->gl_pc, t->gkey, t->glev, t->gord, t->gsf, t->gsn);
     ACHK(hipGetLastError());
   }
   ACHK(hipStreamSynchronize(st));
@@ -310,9 +315,47 @@ __global__ void k_count_tgt(const uint32_t* tgt, int64_t n, int* cnt) {
   if (k < n) atomicAdd(&cnt[tgt[k]], 1);
 }
 
-__global__ void k_nonempty(const int* start, int n, int* flag) {
+// Cells with an X list through their nodes (more than pmax points below),
+// or (gsn == nullptr) entries with a non-empty list.
+__global__ void k_nonempty(const int* start, int n, const int* gsn, int pmax, int* flag) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) flag[i] = start[i + 1] > start[i] ? 1 : 0;
+  if (i < n) flag[i] = (start[i + 1] > start[i] && (!gsn || gsn[i] > pmax)) ? 1 : 0;
+}
+
+// Direct source ranges of each leaf (FILL = false counts): its U leaves, the
+// cells of its W list with at most pmax points below, and, for each of its
+// cells from its own up to level 3 with at most pmax points below, the
+// leaves of that cell's X list (whose points then act on all points below
+// the cell).
+template <bool FILL>
+__global__ void k_direct_lists(int nleaf, const int* gl_cell, const int* gl_pf, const int* gl_pc,
+                               const uint32_t* gkey, const unsigned char* glev, LevelTab lt, const int* ustart,
+                               const int* usrc, const int* wstart, const int* wsrc, const int* xstart,
+                               const int* xsrc, const int* gsf, const int* gsn, int pmax, int* cnt,
+                               const int* start, int2* out) {
+  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= nleaf) return;
+  int k = 0;
+  int64_t w = FILL ? start[o] : 0;
+  auto emit = [&](int f, int n) {
+    if (FILL) out[w++] = make_int2(f, n);
+    ++k;
+  };
+  for (int q = ustart[o]; q < ustart[o + 1]; ++q) emit(gl_pf[usrc[q]], gl_pc[usrc[q]]);
+  for (int q = wstart[o]; q < wstart[o + 1]; ++q) {
+    const int a = wsrc[q];
+    if (gsn[a] <= pmax) emit(gsf[a], gsn[a]);
+  }
+  const int c = gl_cell[o], l = glev[c];
+  const uint32_t key = gkey[c];
+  for (int la = l; la >= 3; --la) {
+    const int r = bsearch_key(lt.key[la], lt.n[la], key >> (3 * (l - la)));
+    if (r < 0) continue;  // cannot happen: the ancestors of a kept cell are kept
+    const int g = lt.off[la] + r;
+    if (gsn[g] > pmax) continue;
+    for (int q = xstart[g]; q < xstart[g + 1]; ++q) emit(gl_pf[xsrc[q]], gl_pc[xsrc[q]]);
+  }
+  if (!FILL) cnt[o] = k;
 }
 
 __global__ void k_compact_idx(const int* flag, const int* pos, int n, int* out) {
@@ -327,12 +370,12 @@ __global__ void k_point_leaf_ad(const int* pf, const int* pc, int nleaf, int* pl
 }
 
 // near-field point pairs of the U lists, summed (for reporting)
-__global__ void k_u_pairs_sum(const int* ustart, const int* usrc, const int* pc, int nleaf,
+__global__ void k_u_pairs_sum(const int* dstart, const int2* drange, const int* pc, int nleaf,
                               unsigned long long* total) {
   const int o = blockIdx.x * blockDim.x + threadIdx.x;
   if (o >= nleaf) return;
   unsigned long long s = 0;
-  for (int q = ustart[o]; q < ustart[o + 1]; ++q) s += (unsigned long long)pc[usrc[q]];
+  for (int q = dstart[o]; q < dstart[o + 1]; ++q) s += (unsigned long long)drange[q].y;
   atomicAdd(total, s * (unsigned long long)pc[o]);
 }
 
@@ -375,7 +418,6 @@ static int pairs_to_csr(uint32_t*& tgt, uint32_t*& src, int64_t np, int64_t nt, 
 }
 
 int adapt_lists(const dfmm_plan* pl, dfmm_tree* t, hipStream_t st) {
-  (void)pl;
   const int64_t nleaf = t->nleaf, ncell = t->ncell_total;
   const LevelTab lt = level_tab(t);
   int rc = DFMM_OK;
@@ -444,7 +486,11 @@ int adapt_lists(const dfmm_plan* pl, dfmm_tree* t, hipStream_t st) {
     }
     t->wsrc = (int*)sr;
   }
-  // the cells with an X list and the leaves with a W list
+  // A W or X pair whose finer cell holds at most p^3 points is summed
+  // directly (p^3 evaluations per point through the nodes would cost more):
+  // the cells whose X list goes through their nodes, the leaves with a W
+  // list, and the direct source ranges of every leaf
+  const int pmax = pl->p * pl->p * pl->p;
   {
     const int64_t nmax = std::max(ncell, nleaf);
     int *flag = nullptr, *pos = nullptr;
@@ -453,7 +499,7 @@ int adapt_lists(const dfmm_plan* pl, dfmm_tree* t, hipStream_t st) {
     for (int which = 0; which < 2 && rc == DFMM_OK; ++which) {
       const int64_t n = which ? nleaf : ncell;
       const int* start = which ? t->wstart : t->xstart;
-      k_nonempty<<<nbk(n, 256), 256, 0, st>>>(start, (int)n, flag);
+      k_nonempty<<<nbk(n, 256), 256, 0, st>>>(start, (int)n, which ? nullptr : t->gsn, pmax, flag);
       DFMM_LAUNCH_CHECK();
       int64_t m = 0;
       rc = scan_excl(flag, pos, n, st, &m);
@@ -468,6 +514,24 @@ int adapt_lists(const dfmm_plan* pl, dfmm_tree* t, hipStream_t st) {
     hipFree(pos);
     if (rc) return rc;
   }
+  {
+    int* cnt = nullptr;
+    DFMM_HIP(hipMalloc(&cnt, sizeof(int) * (nleaf + 1)));
+    DFMM_HIP(hipMalloc(&t->dstart, sizeof(int) * (nleaf + 1)));
+    DFMM_HIP(hipMemsetAsync(cnt + nleaf, 0, sizeof(int), st));
+    k_direct_lists<false><<<nbk(nleaf, 128), 128, 0, st>>>(
+        (int)nleaf, t->gl_cell, t->gl_pf, t->gl_pc, t->gkey, t->glev, lt, t->ustart, t->usrc, t->wstart, t->wsrc,
+        t->xstart, t->xsrc, t->gsf, t->gsn, pmax, cnt, nullptr, nullptr);
+    DFMM_LAUNCH_CHECK();
+    rc = scan_excl(cnt, t->dstart, nleaf + 1, st, &t->nd);
+    hipFree(cnt);
+    if (rc) return rc;
+    DFMM_HIP(hipMalloc(&t->drange, sizeof(int2) * std::max<int64_t>(t->nd, 1)));
+    k_direct_lists<true><<<nbk(nleaf, 128), 128, 0, st>>>(
+        (int)nleaf, t->gl_cell, t->gl_pf, t->gl_pc, t->gkey, t->glev, lt, t->ustart, t->usrc, t->wstart, t->wsrc,
+        t->xstart, t->xsrc, t->gsf, t->gsn, pmax, nullptr, t->dstart, t->drange);
+    DFMM_LAUNCH_CHECK();
+  }
   // leaf of every sorted point, and the near-field pair count
   DFMM_HIP(hipMalloc(&t->pleaf, sizeof(int) * t->N));
   k_point_leaf_ad<<<(unsigned)nleaf, 64, 0, st>>>(t->gl_pf, t->gl_pc, (int)nleaf, t->pleaf);
@@ -475,7 +539,7 @@ int adapt_lists(const dfmm_plan* pl, dfmm_tree* t, hipStream_t st) {
   unsigned long long* tot = nullptr;
   DFMM_HIP(hipMalloc(&tot, sizeof(unsigned long long)));
   DFMM_HIP(hipMemsetAsync(tot, 0, sizeof(unsigned long long), st));
-  k_u_pairs_sum<<<nbk(nleaf, 256), 256, 0, st>>>(t->ustart, t->usrc, t->gl_pc, (int)nleaf, tot);
+  k_u_pairs_sum<<<nbk(nleaf, 256), 256, 0, st>>>(t->dstart, t->drange, t->gl_pc, (int)nleaf, tot);
   DFMM_LAUNCH_CHECK();
   unsigned long long h = 0;
   DFMM_HIP(hipMemcpyAsync(&h, tot, sizeof(h), hipMemcpyDeviceToHost, st));
@@ -485,40 +549,26 @@ int adapt_lists(const dfmm_plan* pl, dfmm_tree* t, hipStream_t st) {
   return DFMM_OK;
 }
 
-// Near-coincident pairs over the U lists (single precision): per sorted
-// target point, the sources closer than 2a in its leaf's U leaves, in the
-// order of the U list and then of the points; a U leaf whose box lies at
-// least 2a from the target (relative margin 1e-9) is skipped.
+// Near-coincident pairs of the direct sums (single precision): per sorted
+// target point, the sources closer than 2a in its leaf's direct source
+// ranges (the U leaves and the W/X pairs summed directly: cells finer than
+// 2a can be closer than 2a without touching), in the order of the ranges
+// and then of the points.  The relation is symmetric, as the close-pair pass
+// needs: j lies in a direct range of i's leaf iff i lies in one of j's.
 template <bool FILL>
-__global__ void k_close_find_u(const double* pts, int64_t N, const int* pleaf, const int* gl_cell, const int* gl_pf,
-                               const int* gl_pc, const uint32_t* gkey, const unsigned char* glev, const int* ustart,
-                               const int* usrc, double lo0, double lo1, double lo2, double L, double a2x4, int* cnt,
-                               const int* cstart, int2* cpair) {
+__global__ void k_close_find_u(const double* pts, int64_t N, const int* pleaf, const int* dstart,
+                               const int2* drange, double a2x4, int* cnt, const int* cstart, int2* cpair) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
   const int g = pleaf[i];
-  const double x[3] = {pts[i], pts[N + i], pts[2 * N + i]};
-  const double lo[3] = {lo0, lo1, lo2};
-  const double lim = a2x4 * (1.0 + 1e-9);
+  const double x0 = pts[i], x1 = pts[N + i], x2 = pts[2 * N + i];
   int c = 0;
   int64_t w = FILL ? cstart[i] : 0;
-  for (int q = ustart[g]; q < ustart[g + 1]; ++q) {
-    const int a = usrc[q];
-    const int ca = gl_cell[a];
-    const double s = ldexp(L, -(int)glev[ca]);
-    int cs[3];
-    demorton(gkey[ca], cs[0], cs[1], cs[2]);
-    double gap = 0.0;
-    for (int d = 0; d < 3; ++d) {
-      const double b0 = lo[d] + cs[d] * s, b1 = b0 + s;
-      const double e = x[d] < b0 ? b0 - x[d] : (x[d] > b1 ? x[d] - b1 : 0.0);
-      gap += e * e;
-    }
-    if (gap >= lim) continue;
-    const int f = gl_pf[a], n = gl_pc[a];
-    for (int jj = 0; jj < n; ++jj) {
-      const int64_t j = f + jj;
-      const double d0 = x[0] - pts[j], d1 = x[1] - pts[N + j], d2 = x[2] - pts[2 * N + j];
+  for (int q = dstart[g]; q < dstart[g + 1]; ++q) {
+    const int2 rg = drange[q];
+    for (int jj = 0; jj < rg.y; ++jj) {
+      const int64_t j = rg.x + jj;
+      const double d0 = x0 - pts[j], d1 = x1 - pts[N + j], d2 = x2 - pts[2 * N + j];
       if (j != i && d0 * d0 + d1 * d1 + d2 * d2 < a2x4) {
         if (FILL)
           cpair[w++] = make_int2((int)i, (int)j);
@@ -533,15 +583,12 @@ __global__ void k_close_find_u(const double* pts, int64_t N, const int* pleaf, c
 int adapt_close_find(const dfmm_plan* pl, dfmm_tree* t, bool fill, int* cnt, const int* cstart, int2* cpair,
                      hipStream_t st) {
   const double a2x4 = 4.0 * pl->prm.core_a * pl->prm.core_a;
-  const double* lo = pl->prm.box_lo;
   if (fill)
-    k_close_find_u<true><<<nbk(t->N, 128), 128, 0, st>>>(t->pts, t->N, t->pleaf, t->gl_cell, t->gl_pf, t->gl_pc,
-                                                         t->gkey, t->glev, t->ustart, t->usrc, lo[0], lo[1], lo[2],
-                                                         pl->prm.box_size, a2x4, nullptr, cstart, cpair);
+    k_close_find_u<true><<<nbk(t->N, 128), 128, 0, st>>>(t->pts, t->N, t->pleaf, t->dstart, t->drange, a2x4,
+                                                         nullptr, cstart, cpair);
   else
-    k_close_find_u<false><<<nbk(t->N, 128), 128, 0, st>>>(t->pts, t->N, t->pleaf, t->gl_cell, t->gl_pf, t->gl_pc,
-                                                          t->gkey, t->glev, t->ustart, t->usrc, lo[0], lo[1], lo[2],
-                                                          pl->prm.box_size, a2x4, cnt, nullptr, nullptr);
+    k_close_find_u<false><<<nbk(t->N, 128), 128, 0, st>>>(t->pts, t->N, t->pleaf, t->dstart, t->drange, a2x4, cnt,
+                                                          nullptr, nullptr);
   DFMM_LAUNCH_CHECK();
   return DFMM_OK;
 }
@@ -593,16 +640,17 @@ __device__ __forceinline__ void cell_origin(uint32_t key, int level, const doubl
 // lanes per target splitting its sources (as the uniform near field).
 // (the loop below: c0 steps over the targets, S lanes per target in a pass)
 
-// U lists: one wave per leaf; the direct sum over the points of its U leaves.
+// Direct sums: one wave per leaf, over its direct source ranges (the U
+// leaves, and the W/X pairs with few points on the finer side).
 // Single precision leaves pairs closer than 2a to the double-precision
 // close-pair pass and accumulates with compensation.  Writes sig.
 template <typename T, bool MIXED, bool ISO>
 __global__ void __launch_bounds__(64) k_leaf_u(const double* pts, int64_t N, const int* gl_pf, const int* gl_pc,
-                                               const int* ustart, const int* usrc, Med<T> m, double a2x4,
+                                               const int* dstart, const int2* drange, Med<T> m, double a2x4,
                                                double* sig) {
   const int leaf = blockIdx.x, lane = threadIdx.x;
   const int t0 = gl_pf[leaf], nt = gl_pc[leaf];
-  const int u0 = ustart[leaf], nu = ustart[leaf + 1] - u0;
+  const int u0 = dstart[leaf], nu = dstart[leaf + 1] - u0;
   __shared__ int nb_first[64], nb_cnt[64];
   for (int c0 = 0, per = 64; c0 < nt; c0 += per) {
     const int rem = nt - c0;
@@ -621,9 +669,9 @@ __global__ void __launch_bounds__(64) k_leaf_u(const double* pts, int64_t N, con
       const int nq = min(64, nu - q0);
       __syncthreads();
       if (lane < nq) {
-        const int a = usrc[u0 + q0 + lane];
-        nb_first[lane] = gl_pf[a];
-        nb_cnt[lane] = gl_pc[a];
+        const int2 rg = drange[u0 + q0 + lane];
+        nb_first[lane] = rg.x;
+        nb_cnt[lane] = rg.y;
       }
       __syncthreads();
       for (int q = 0; q < nq; ++q) {
@@ -673,8 +721,9 @@ __global__ void __launch_bounds__(64) k_leaf_u(const double* pts, int64_t N, con
 template <typename T, bool ISO>
 __global__ void __launch_bounds__(64) k_m2p(const double* pts, int64_t N, const int* wleaves, const int* gl_pf,
                                             const int* gl_pc, const int* wstart, const int* wsrc,
-                                            const uint32_t* gkey, const unsigned char* glev, const T* W, Med<T> m,
-                                            double lo0, double lo1, double lo2, double L, int p, double* sig) {
+                                            const uint32_t* gkey, const unsigned char* glev, const int* gsn,
+                                            const T* W, Med<T> m, double lo0, double lo1, double lo2, double L,
+                                            int p, double* sig) {
   const int leaf = wleaves[blockIdx.x], lane = threadIdx.x;
   const int t0 = gl_pf[leaf], nt = gl_pc[leaf];
   const int p3 = p * p * p;
@@ -693,6 +742,7 @@ __global__ void __launch_bounds__(64) k_m2p(const double* pts, int64_t N, const 
     if (act) {
       for (int e = wstart[leaf]; e < wstart[leaf + 1]; ++e) {
         const int c = wsrc[e];
+        if (gsn[c] <= p3) continue;  // summed directly with the leaf's other sources
         double o[3], s;
         cell_origin(gkey[c], glev[c], lo, L, o, &s);
         const T* Wc = W + (int64_t)c * 9 * p3;
@@ -831,15 +881,15 @@ int adapt_near(const dfmm_plan* pl, dfmm_tree* t, hipStream_t st) {
   const unsigned g = (unsigned)t->nleaf;
   if constexpr (std::is_same<T, float>::value) {
     if (pl->iso)
-      k_leaf_u<T, true, true><<<g, 64, 0, st>>>(t->pts, t->N, t->gl_pf, t->gl_pc, t->ustart, t->usrc, m, a2x4, t->sig);
+      k_leaf_u<T, true, true><<<g, 64, 0, st>>>(t->pts, t->N, t->gl_pf, t->gl_pc, t->dstart, t->drange, m, a2x4, t->sig);
     else
-      k_leaf_u<T, true, false><<<g, 64, 0, st>>>(t->pts, t->N, t->gl_pf, t->gl_pc, t->ustart, t->usrc, m, a2x4, t->sig);
+      k_leaf_u<T, true, false><<<g, 64, 0, st>>>(t->pts, t->N, t->gl_pf, t->gl_pc, t->dstart, t->drange, m, a2x4, t->sig);
   } else {
     if (pl->iso)
-      k_leaf_u<T, false, true><<<g, 64, 0, st>>>(t->pts, t->N, t->gl_pf, t->gl_pc, t->ustart, t->usrc, m, a2x4, t->sig);
+      k_leaf_u<T, false, true><<<g, 64, 0, st>>>(t->pts, t->N, t->gl_pf, t->gl_pc, t->dstart, t->drange, m, a2x4, t->sig);
     else
-      k_leaf_u<T, false, false><<<g, 64, 0, st>>>(t->pts, t->N, t->gl_pf, t->gl_pc, t->ustart, t->usrc, m, a2x4,
-                                                 t->sig);
+      k_leaf_u<T, false, false><<<g, 64, 0, st>>>(t->pts, t->N, t->gl_pf, t->gl_pc, t->dstart, t->drange, m,
+                                                 a2x4, t->sig);
   }
   DFMM_LAUNCH_CHECK();
   return DFMM_OK;
@@ -853,10 +903,10 @@ int adapt_m2p(const dfmm_plan* pl, dfmm_tree* t, const T* W, hipStream_t st) {
   const unsigned g = (unsigned)t->nwleaf;
   if (pl->iso)
     k_m2p<T, true><<<g, 64, 0, st>>>(t->pts, t->N, t->wleaves, t->gl_pf, t->gl_pc, t->wstart, t->wsrc, t->gkey,
-                                     t->glev, W, m, lo[0], lo[1], lo[2], pl->prm.box_size, pl->p, t->sig);
+                                     t->glev, t->gsn, W, m, lo[0], lo[1], lo[2], pl->prm.box_size, pl->p, t->sig);
   else
     k_m2p<T, false><<<g, 64, 0, st>>>(t->pts, t->N, t->wleaves, t->gl_pf, t->gl_pc, t->wstart, t->wsrc, t->gkey,
-                                      t->glev, W, m, lo[0], lo[1], lo[2], pl->prm.box_size, pl->p, t->sig);
+                                      t->glev, t->gsn, W, m, lo[0], lo[1], lo[2], pl->prm.box_size, pl->p, t->sig);
   DFMM_LAUNCH_CHECK();
   return DFMM_OK;
 }

@@ -231,7 +231,7 @@ void dfmm_tree_destroy(dfmm_tree* t) {
   hipFree(t->kexp); hipFree(t->wmax);
   hipFree(t->gl_cell); hipFree(t->gl_pf); hipFree(t->gl_pc); hipFree(t->gkey); hipFree(t->glev); hipFree(t->gord);
   hipFree(t->ustart); hipFree(t->usrc); hipFree(t->wstart); hipFree(t->wsrc); hipFree(t->xstart); hipFree(t->xsrc);
-  hipFree(t->xcells); hipFree(t->wleaves);
+  hipFree(t->xcells); hipFree(t->wleaves); hipFree(t->gsf); hipFree(t->gsn); hipFree(t->dstart); hipFree(t->drange);
   delete t;
 }
 
@@ -516,7 +516,8 @@ int dfmm_tree_info(const dfmm_tree* t, char* json, size_t cap) {
                   std::to_string(t->adaptive) + ", \"leaves\": " +
                   std::to_string(t->adaptive ? t->nleaf : (t->D >= 2 ? t->lv[t->D].n : 0)) +
                   ", \"u_pairs\": " + std::to_string(t->nu) + ", \"w_pairs\": " + std::to_string(t->nw) +
-                  ", \"x_pairs\": " + std::to_string(t->nx) + ", \"freq_chunks\": " + std::to_string(t->fchunks) +
+                  ", \"x_pairs\": " + std::to_string(t->nx) + ", \"direct_ranges\": " + std::to_string(t->nd) +
+                  ", \"freq_chunks\": " + std::to_string(t->fchunks) +
                   ", \"levels\": [";
   for (int l = 2; l <= t->D; ++l) {
     if (l > 2) s += ", ";

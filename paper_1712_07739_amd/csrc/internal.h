@@ -262,8 +262,13 @@ struct dfmm_tree {
   int* xstart = nullptr;         // [ncell_total + 1] X lists: source leaves acting on a cell's nodes
   int* xsrc = nullptr;
   int64_t nx = 0;
-  int* xcells = nullptr;         // cells with a non-empty X list
+  int* xcells = nullptr;         // cells whose X list goes through their nodes (more than p^3 points below)
   int64_t nxcell = 0;
+  int* gsf = nullptr;            // [ncell_total] first sorted point below the cell
+  int* gsn = nullptr;            // [ncell_total] points below the cell
+  int* dstart = nullptr;         // [nleaf + 1] direct sources of a leaf's points: the U leaves, then the
+  int2* drange = nullptr;        //   W cells and (for its ancestors) X leaves of pairs whose finer cell
+  int64_t nd = 0;                //   holds at most p^3 points, as point ranges (first, count)
   int* wleaves = nullptr;        // leaves with a non-empty W list
   int64_t nwleaf = 0;
   // recorded at the end of every call that is not being captured into a

@@ -69,10 +69,13 @@ def test_lists_equal_the_oracle_tree(env, D, leaf_max):
 ])
 def test_forces_match_oracle_adaptive_fmm(env, name, C, p, D, leaf_max, mode):
     """FP64 <= 1e-10, single precision <= 2e-5 and f16 M2L operands within
-    the f16 bar, each against the oracle's adaptive FMM on the same tree."""
+    the f16 bar, each against the oracle's adaptive FMM on the same tree
+    (with the same rule for direct W/X pairs)."""
     seg, b = clustered()
     med = oracle.medium(*C, 1e-3)
-    ref, ref_far, _ = fmm_forces_adaptive(seg, b, med, p, D, BOX_LO, BOX, leaf_max, return_parts=True)
+    # the GPU sums a W or X pair directly when its finer cell holds at most p^3 points
+    ref, ref_far, _ = fmm_forces_adaptive(seg, b, med, p, D, BOX_LO, BOX, leaf_max, return_parts=True,
+                                          direct_max=p ** 3)
     share = float(np.linalg.norm(ref_far) / np.linalg.norm(ref))
     bars = {0: 1e-10, 1: 2e-5, 2: 2e-5 + 2 * F16_U * share}
     for prec, bar in bars.items():
@@ -129,3 +132,21 @@ def test_full_size_adaptive_vs_oracle_samples(env):
           % (info["leaves"], [lv["level"] for lv in info["levels"] if lv["leaves"] > 0], info["u_pairs"],
              info["w_pairs"], info["x_pairs"], err))
     assert err <= 1e-4
+
+
+def test_deep_cells_below_the_core_size(env):
+    """Leaves down to level 10, whose cells (1.1e-3) are narrower than 2a:
+    W/X pairs summed directly then contain near-coincident pairs, which the
+    single-precision path must hand to its FP64 close-pair pass like the U
+    pairs'.  Against the oracle's adaptive FMM (FP64 throughout)."""
+    seg, b = clustered()
+    med = oracle.medium(*CUB, 1e-3)
+    # leaves of at most 3 points: levels 4..10, with 8 near-coincident point
+    # pairs among the W pairs summed directly
+    ref = fmm_forces_adaptive(seg, b, med, 3, 10, BOX_LO, BOX, 3, direct_max=27)
+    for prec, bar in ((0, 1e-10), (1, 2e-5)):
+        f, info, _ = run(env, seg, b, CUB, 3, 10, 3, precision=prec)
+        assert info["depth"] == 10 and info["w_pairs"] > 0
+        err = oracle.rel_err(f, ref)
+        print("deep adaptive tree, precision %d: %.2e vs oracle" % (prec, err))
+        assert err <= bar, prec
