@@ -107,6 +107,8 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true",
                     help="cubic media: skip training the anisotropic-kernel network (it is used where its gate passes)")
     ap.add_argument("--cpu-sample", type=int, default=3, help="target segments timed on the CPU oracle")
+    ap.add_argument("--surrogate-tol", type=float, default=1e-5,
+                    help="residual gate of the anisotropic-kernel network (bins below it use the network)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run 3 plain device copies of MIB MiB (calibrates HBM byte counters) and exit")
     args = ap.parse_args()
@@ -166,7 +168,7 @@ def main():
         # the learned surrogate of the anisotropic kernel: 2M samples, residual gate 1e-5,
         # the exact quadrature wherever a direction bin fails the gate
         t0 = time.perf_counter()
-        sinfo = plan.surrogate_train(n_samples=1 << 21, tol=1e-5, seed=5)
+        sinfo = plan.surrogate_train(n_samples=1 << 21, tol=args.surrogate_tol, seed=5)
         plan.surrogate_use(True)
         torch.cuda.synchronize()
         sur = {k: sinfo[k] for k in ("n_params", "n_samples", "epochs", "bins", "tol", "pass_frac",

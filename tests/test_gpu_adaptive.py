@@ -150,3 +150,20 @@ def test_deep_cells_below_the_core_size(env):
         err = oracle.rel_err(f, ref)
         print("deep adaptive tree, precision %d: %.2e vs oracle" % (prec, err))
         assert err <= bar, prec
+
+
+def test_uniform_tree_lists_equal_a_brute_force_tree(env):
+    """The uniform tree's lists, an integer result, against the oracle's tree
+    built by definition with every cell split down to the depth (leaf_max 0):
+    M2L pairs per level and near-field point pairs, exactly."""
+    seg, b = synth.make_loops(30, 0.01, 0.05, 61)
+    y, _ = oracle.points(seg, b)
+    D = 4
+    T = AdaptiveTree(y, D, BOX_LO, BOX, 0)
+    v_per_level = {l: sum(len(T.V[c]) for c in T.by_level[l]) for l in range(2, D + 1)}
+    near = sum(len(T.pts[c]) * sum(len(T.pts[a]) for a in T.U[c]) for c in range(T.n) if T.leaf[c])
+    _, info, _ = run(env, seg, b, ISO, 3, D, 0)
+    assert info["adaptive"] == 0
+    assert {lv["level"]: lv["m2l_pairs"] for lv in info["levels"]} == v_per_level
+    assert {lv["level"]: lv["cells"] for lv in info["levels"]} == {l: len(T.by_level[l]) for l in range(2, D + 1)}
+    assert info["near_pairs"] == near
