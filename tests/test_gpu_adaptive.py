@@ -167,3 +167,20 @@ def test_uniform_tree_lists_equal_a_brute_force_tree(env):
     assert {lv["level"]: lv["m2l_pairs"] for lv in info["levels"]} == v_per_level
     assert {lv["level"]: lv["cells"] for lv in info["levels"]} == {l: len(T.by_level[l]) for l in range(2, D + 1)}
     assert info["near_pairs"] == near
+
+
+def test_adaptive_tree_with_spectrum_chunks(env):
+    """The adaptive tree's M2L in frequency chunks equals its whole-spectrum
+    result (FP64 1e-13, f16 operands 1e-6)."""
+    torch, pk, dev = env
+    seg, b = clustered()
+    ts, tb = torch.tensor(seg, device=dev), torch.tensor(b, device=dev)
+    for prec, bar in ((0, 1e-13), (2, 1e-6)):
+        out = []
+        for c in (1, 4):
+            plan = pk.Plan(pk.make_params(4, 5, *CUB, 1e-3, BOX_LO, BOX, precision=prec, m2l_mode=1, leaf_max=20,
+                                          freq_chunks=c))
+            tree = pk.Tree(plan, ts)
+            assert tree.info()["freq_chunks"] == (1 if c == 1 else 4) and tree.info()["adaptive"] == 1
+            out.append(pk.fmm_forces(plan, tree, ts, tb).cpu().numpy())
+        assert oracle.rel_err(out[1], out[0]) <= bar, prec
