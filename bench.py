@@ -124,7 +124,7 @@ def main():
         return
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; --gpus %d is not supported "
-              "(the multi-GPU sharding is described in DESIGN.md)" % args.gpus, file=sys.stderr)
+              "(sharding one ensemble over several GPUs is not built)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
