@@ -455,8 +455,7 @@ __global__ void k_sym_expand(const cplx<T>* __restrict__ Kc, const SymEntry* __r
   if (H16) {
     // all 316 offsets: slot 2 id holds o, slot 2 id + 1 holds -o (-conj)
     uint32_t* o32 = reinterpret_cast<uint32_t*>(out);
-    const int64_t e0 = ((int64_t)f * kNumOffsets + 2 * id) * kKOffsetH + (ab / 3) * kKHalfH + (ab % 3) * 9 +
-                       had_slot_of(ab / 3, wr);
+    const int64_t e0 = ((int64_t)f * kNumOffsets + 2 * id) * kKOffsetH + h16_word_of(ab, wr);
     o32[e0] = pack_h2((float)v.re * scale, (float)v.im * scale);
     o32[e0 + kKOffsetH] = pack_h2(-(float)v.re * scale, (float)v.im * scale);
   } else if (sizeof(T) == 4)
@@ -595,12 +594,15 @@ k_hadamard(const cplx<float>* What, const cplx<float>* Khat, const int* lenq, co
 }
 
 // The Hadamard product on f16 operands (DFMM_MIXED_F16): the same blocks,
-// lanes, list walk and slot order as k_hadamard, with every complex value a
-// pair of f16 (real in the low half) and the products done by
-// v_dot2_f32_f16, two multiply-adds with f32 accumulation per instruction:
+// list walk and source loads as k_hadamard, with every complex value a pair
+// of f16 (real in the low half) and the products done by v_dot2_f32_f16, two
+// multiply-adds with f32 accumulation per instruction:
 //   K w:  re = (kr, ki).(wr, -wi),  im = (kr, ki).(wi, wr),
 // the sign of the real part's product taken by the instruction's neg_hi
-// modifier and the imaginary part's operand half-swapped once per pair.
+// modifier and the imaginary part's operand half-swapped once per pair.  A
+// lane multiplies only the five source components it loads (h16_word_of):
+// the two lanes of a target exchange their partial sums once, after the
+// list, instead of source values at every step.
 // LDS holds the spectra of all 316 offsets (the mirrored offset -o as -conj
 // of o), so there is no per-pair mirror handling; a list entry's bits 23..31
 // are the offset's slot 2 id + mirror.  The spectra take 74 KB of LDS per
@@ -634,7 +636,8 @@ k_hadamard16(const uint32_t* What, const uint32_t* Khat, const int* lenq, const 
   const int h = threadIdx.x & 1;
   const int64_t t = order[tt];
   const int len = lenq[tt];
-  float ar[3] = {0.f, 0.f, 0.f}, ai[3] = {0.f, 0.f, 0.f};
+  // accumulator a holds stress row (3h + a) mod 6
+  float ar[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, ai[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   const char* wfb = reinterpret_cast<const char*>(What + (int64_t)f * ncell * 9);
   const char* ilb = reinterpret_cast<const char*>(ilw);
   constexpr uint32_t kStep = kWaveTargets * sizeof(uint32_t);
@@ -653,12 +656,6 @@ k_hadamard16(const uint32_t* What, const uint32_t* Khat, const int* lenq, const 
     v[4] = *reinterpret_cast<const uint32_t*>(wfb + o + 32);
   };
   auto pair = [&](uint32_t j, const uint32_t* v) {
-    uint32_t w[9];
-#pragma unroll
-    for (int k = 0; k < 5; ++k) w[k] = v[k];
-    // the partner lane's four components (quad permutation 1, 0, 3, 2)
-#pragma unroll
-    for (int k = 0; k < 4; ++k) w[5 + k] = (uint32_t)__builtin_amdgcn_mov_dpp((int)v[k], 0xB1, 0xF, 0xF, false);
     const uint4* K4 = reinterpret_cast<const uint4*>(kb + (j >> 23) * (uint32_t)(kKOffsetH * 4));
     uint32_t kk[28];
 #pragma unroll
@@ -669,15 +666,17 @@ k_hadamard16(const uint32_t* What, const uint32_t* Khat, const int* lenq, const 
       kk[4 * i + 2] = x.z;
       kk[4 * i + 3] = x.w;
     }
+    // v[c]: component 4h + c (c < 4), component 8 (c = 4)
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      const half2v q = __builtin_bit_cast(half2v, __builtin_amdgcn_alignbit(w[k], w[k], 16));  // (wi, wr)
+    for (int c = 0; c < 5; ++c) {
+      const half2v q = __builtin_bit_cast(half2v, __builtin_amdgcn_alignbit(v[c], v[c], 16));  // (wi, wr)
 #pragma unroll
-      for (int r = 0; r < 3; ++r) {
+      for (int a = 0; a < (c < 4 ? 6 : 3); ++a) {
+        const uint32_t kv = c < 4 ? kk[4 * a + c] : kk[24 + a];
         // re: (kr, ki).(wr, -wi), the sign taken by the instruction's neg_hi
         // modifier on the source operand
-        asm("v_dot2_f32_f16 %0, %1, %2, %0 neg_hi:[0,1,0]" : "+v"(ar[r]) : "v"(kk[9 * r + k]), "v"(w[k]));
-        ai[r] = __builtin_amdgcn_fdot2(__builtin_bit_cast(half2v, kk[9 * r + k]), q, ai[r], false);
+        asm("v_dot2_f32_f16 %0, %1, %2, %0 neg_hi:[0,1,0]" : "+v"(ar[a]) : "v"(kv), "v"(v[c]));
+        ai[a] = __builtin_amdgcn_fdot2(__builtin_bit_cast(half2v, kv), q, ai[a], false);
       }
     }
   };
@@ -693,9 +692,15 @@ k_hadamard16(const uint32_t* What, const uint32_t* Khat, const int* lenq, const 
       asm volatile("" : "+v"(jo));
     }
   }
+  // rows 3h..3h+2: accumulators 0..2 here, 3..5 in the partner lane (quad
+  // permutation 1, 0, 3, 2)
   cplx<float>* out = Shat + ((int64_t)f * ncell + t) * 6 + 3 * h;
 #pragma unroll
-  for (int r = 0; r < 3; ++r) out[r] = cplx<float>{ar[r], ai[r]};
+  for (int r = 0; r < 3; ++r) {
+    const float pr = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(ar[3 + r]), 0xB1, 0xF, 0xF, false));
+    const float pi = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(ai[3 + r]), 0xB1, 0xF, 0xF, false));
+    out[r] = cplx<float>{ar[r] + pr, ai[r] + pi};
+  }
 }
 
 // The double-precision Hadamard product: the blocks, lanes, list walk and

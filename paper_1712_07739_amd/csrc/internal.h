@@ -43,11 +43,36 @@ constexpr int kMaxDevices = 64;
 // banks (an even one leaves half of them idle and doubles up the rest).
 constexpr int kKHalfF = 28;
 constexpr int kKOffsetF = 2 * kKHalfF + 2;
-// The f16 Hadamard product keeps the same slot order with one 32-bit word
-// (f16 real, f16 imaginary) per complex value: per offset two halves of 28
-// words and 4 pad words, 15 16-byte units (odd, for the same reason).
+// The f16 Hadamard product splits the 6x9 product between a target's two
+// lanes by source component instead, so that no source value crosses lanes:
+// lane h takes components 4h..4h+3 for all six stress rows and component 8
+// for rows 3h..3h+2, and keeps row R in accumulator (R - 3h) mod 6; the rows
+// a lane writes (3h..3h+2, accumulators 0..2) then receive the partner's
+// accumulators 3..5 once per target.  One 32-bit word (f16 real, f16
+// imaginary) per complex value; lane h's 27 words, in the order it reads
+// them (accumulator-major for components 4h..4h+3, then component 8), start
+// at word 28 h; per offset two halves of 28 words and 4 pad words, 15
+// 16-byte units (odd, for the same reason).
 constexpr int kKHalfH = 28;
 constexpr int kKOffsetH = 2 * kKHalfH + 4;
+// Word of stress row R (0..5), source component C (0..8) in an offset's
+// f16 spectra.
+__host__ __device__ constexpr int h16_word_of(int R, int C) {
+  return C == 8 ? kKHalfH * (R / 3) + 24 + R % 3
+                : kKHalfH * (C >> 2) + 4 * ((R - 3 * (C >> 2) + 6) % 6) + (C & 3);
+}
+// every (row, component) has its own word, the first 27 of a half
+constexpr bool h16_layout_ok() {
+  bool seen[kKOffsetH] = {};
+  for (int R = 0; R < 6; ++R)
+    for (int C = 0; C < 9; ++C) {
+      const int w = h16_word_of(R, C);
+      if (w < 0 || w >= 2 * kKHalfH || w % kKHalfH >= 27 || seen[w]) return false;
+      seen[w] = true;
+    }
+  return true;
+}
+static_assert(h16_layout_ok(), "f16 spectrum words");
 // Double precision: one complex value per 16-byte LDS unit, the two halves of
 // 27 values back to back and one pad unit, 55 units per offset (odd).
 constexpr int kKHalfD = 27;
