@@ -467,6 +467,12 @@ __global__ void k_sym_expand(const cplx<T>* __restrict__ Kc, const SymEntry* __r
 constexpr int kHadThreads = 2 * kM2LWindowF;
 static_assert(kM2LWindowF % kWaveTargets == 0 && 2 * kWaveTargets == 64,
               "a wave holds kWaveTargets targets, two lanes each");
+// Dynamic LDS of the M2L kernels: one frequency's spectra (f32: 158 offsets,
+// f16: 316, double: 158).
+constexpr int kHadLdsF = (int)sizeof(cplx<float>) * kNumCanon * kKOffsetF;
+constexpr int kHadLdsH = (int)sizeof(uint32_t) * kNumOffsets * kKOffsetH;
+constexpr int kHadLdsD = (int)sizeof(cplx<double>) * kNumCanon * kKOffsetD;
+static_assert(2 * kHadLdsF <= 160 * 1024 && 2 * kHadLdsH <= 160 * 1024 && kHadLdsD <= 160 * 1024, "blocks per CU");
 
 __global__ void __launch_bounds__(kHadThreads) __attribute__((amdgpu_waves_per_eu(6, 6)))
 k_hadamard(const cplx<float>* What, const cplx<float>* Khat, const int* lenq, const int* wbase, const uint32_t* ilw,
@@ -489,7 +495,8 @@ k_hadamard(const cplx<float>* What, const cplx<float>* Khat, const int* lenq, co
   const float4* kf = reinterpret_cast<const float4*>(Khat + (int64_t)f * kNumCanon * kKOffsetF);
   for (int e = threadIdx.x; e < kNumCanon * kKOffsetF / 2; e += blockDim.x) Ks4[e] = kf[e];
   __syncthreads();
-  const int64_t tt = (int64_t)win * kM2LWindowF + threadIdx.x / 2;
+  // lane pair -> target: the 8 targets of an LDS pass are consecutive
+  const int64_t tt = (int64_t)win * kM2LWindowF + (threadIdx.x >> 6) * kWaveTargets + pass_target((threadIdx.x & 63) >> 1);
   if (tt >= ncell) return;  // both lanes of a target leave together
   const int h = threadIdx.x & 1;
   const int64_t t = order[tt];
@@ -631,7 +638,8 @@ k_hadamard16(const uint32_t* What, const uint32_t* Khat, const int* lenq, const 
   const uint4* kf = reinterpret_cast<const uint4*>(Khat + (int64_t)f * kNumOffsets * kKOffsetH);
   for (int e = threadIdx.x; e < kNumOffsets * kKOffsetH / 4; e += blockDim.x) Ks4[e] = kf[e];
   __syncthreads();
-  const int64_t tt = (int64_t)win * kM2LWindowF + threadIdx.x / 2;
+  // lane pair -> target: the 8 targets of an LDS pass are consecutive
+  const int64_t tt = (int64_t)win * kM2LWindowF + (threadIdx.x >> 6) * kWaveTargets + pass_target((threadIdx.x & 63) >> 1);
   if (tt >= ncell) return;  // both lanes of a target leave together
   const int h = threadIdx.x & 1;
   const int64_t t = order[tt];
@@ -680,17 +688,28 @@ k_hadamard16(const uint32_t* What, const uint32_t* Khat, const int* lenq, const 
       }
     }
   };
+  // A step's source values are loaded one step ahead and its list entry two
+  // steps ahead (the entries after a list's end are the zero padding of the
+  // wave's block, kIlwPad steps), so neither load waits at its use; two steps
+  // per iteration alternate between two source buffers.
   if (len > 0) {
     uint32_t eb = kStep * (uint32_t)wbase[tt / kWaveTargets] + sizeof(uint32_t) * (uint32_t)(tt % kWaveTargets);
-    uint32_t jo = entry(eb);
-    for (int e = 0; e < len; ++e, eb += kStep) {
-      const uint32_t jn = entry(eb + kStep);
-      uint32_t v[5];
-      load_src(jo, v);
-      pair(jo, v);
-      jo = jn;
-      asm volatile("" : "+v"(jo));
+    uint32_t jo = entry(eb), jn = entry(eb + kStep);
+    uint32_t va[5], vb[5];
+    load_src(jo, va);
+    int e = 0;
+    for (; e + 1 < len; e += 2, eb += 2 * kStep) {
+      const uint32_t j2 = entry(eb + 2 * kStep);
+      load_src(jn, vb);
+      pair(jo, va);
+      const uint32_t j3 = entry(eb + 3 * kStep);
+      load_src(j2, va);
+      pair(jn, vb);
+      jo = j2;
+      jn = j3;
+      asm volatile("" : "+v"(jn));
     }
+    if (e < len) pair(jo, va);
   }
   // rows 3h..3h+2: accumulators 0..2 here, 3..5 in the partner lane (quad
   // permutation 1, 0, 3, 2)
@@ -714,6 +733,7 @@ k_hadamard16(const uint32_t* What, const uint32_t* Khat, const int* lenq, const 
 // between LDS and L2, made the kernel 2.5 times slower: the rows are 144-byte
 // reads at random offsets.)
 constexpr int kHadThreadsD = 2 * kM2LWindowD;
+static_assert(kM2LWindowD % kWaveTargets == 0, "whole waves per window");
 __global__ void __launch_bounds__(kHadThreadsD)
 k_hadamard64(const cplx<double>* What, const cplx<double>* Khat, const int* lenq, const int* wbase, const uint32_t* ilw,
              const uint32_t* order, int64_t ncell, int nf, int nwin, int remap, cplx<double>* Shat) {
@@ -736,7 +756,8 @@ k_hadamard64(const cplx<double>* What, const cplx<double>* Khat, const int* lenq
   double2* Ks2 = reinterpret_cast<double2*>(Ks);
   for (int e = threadIdx.x; e < kNumCanon * kKOffsetD; e += blockDim.x) Ks2[e] = kf[e];
   __syncthreads();
-  const int64_t tt = (int64_t)win * kM2LWindowD + threadIdx.x / 2;
+  // lane pair -> target: the 8 targets of an LDS pass are consecutive
+  const int64_t tt = (int64_t)win * kM2LWindowD + (threadIdx.x >> 6) * kWaveTargets + pass_target((threadIdx.x & 63) >> 1);
   if (tt >= ncell) return;  // both lanes of a target leave together
   const int h = threadIdx.x & 1;
   const int64_t t = order[tt];
@@ -795,8 +816,10 @@ k_hadamard64(const cplx<double>* What, const cplx<double>* Khat, const int* lenq
       ai[r] += ci;
     }
   };
-  // next entry one step ahead, as in k_hadamard; the two lanes of a target
-  // run the same iterations
+  // next entry one step ahead, as in k_hadamard (prefetching the source
+  // values too, as k_hadamard16 does, was 2% slower here: this kernel is
+  // bound by its LDS reads); the two lanes of a target run the same
+  // iterations
   if (len > 0) {
     uint32_t eb = kStep * (uint32_t)wbase[tt / kWaveTargets] + sizeof(uint32_t) * (uint32_t)(tt % kWaveTargets);
     uint32_t jo = entry(eb);
@@ -1817,15 +1840,15 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
       dim3 g(remap ? 8 * ((nwin + 7) / 8) : nwin, nfc);
       STAGE(2, dft<T>(p, true, (unsigned)Lv.n, W + Lv.off * 9 * p3, Lv.n, tb.tw, What, wm, 1.f, fa, fb, 0, st));
       if (h16)
-        STAGE(3, (k_hadamard16<<<g, kHadThreads, sizeof(uint32_t) * kNumOffsets * kKOffsetH, st>>>(
+        STAGE(3, (k_hadamard16<<<g, kHadThreads, kHadLdsH, st>>>(
                      (const uint32_t*)What, (const uint32_t*)kh + fbase * kNumOffsets * kKOffsetH, Lv.lenq,
                      Lv.wbase, Lv.ilw, Lv.order, Lv.n, nfc, nwin, remap, (cplx<float>*)Shat)));
       else if constexpr (std::is_same<T, float>::value)
-        STAGE(3, (k_hadamard<<<g, kHadThreads, sizeof(cplx<float>) * kNumCanon * kKOffsetF, st>>>(
+        STAGE(3, (k_hadamard<<<g, kHadThreads, kHadLdsF, st>>>(
                      What, kh + fbase * kNumCanon * kKOffsetF, Lv.lenq, Lv.wbase, Lv.ilw, Lv.order, Lv.n, nfc,
                      nwin, remap, Shat)));
       else
-        STAGE(3, (k_hadamard64<<<g, kHadThreadsD, sizeof(cplx<double>) * kNumCanon * kKOffsetD, st>>>(
+        STAGE(3, (k_hadamard64<<<g, kHadThreadsD, kHadLdsD, st>>>(
                      What, kh + fbase * kNumCanon * kKOffsetD, Lv.lenq, Lv.wbase, Lv.ilw, Lv.order, Lv.n, nfc, nwin,
                      remap, Shat)));
       STAGE(4, dft<T>(p, false, (unsigned)Lv.n, Shat, Lv.n, tb.tw, s + Lv.off * 6 * p3, wm, ksc, fa, fb, fa > 0, st));
@@ -1872,9 +1895,9 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
 template <typename T>
 static void set_lds_attrs_once() {
   const int mx = 160 * 1024;
-  hipFuncSetAttribute((const void*)k_hadamard, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-  hipFuncSetAttribute((const void*)k_hadamard16, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-  hipFuncSetAttribute((const void*)k_hadamard64, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+  hipFuncSetAttribute((const void*)k_hadamard, hipFuncAttributeMaxDynamicSharedMemorySize, kHadLdsF);
+  hipFuncSetAttribute((const void*)k_hadamard16, hipFuncAttributeMaxDynamicSharedMemorySize, kHadLdsH);
+  hipFuncSetAttribute((const void*)k_hadamard64, hipFuncAttributeMaxDynamicSharedMemorySize, kHadLdsD);
   hipFuncSetAttribute((const void*)k_leaf_sym<T, sizeof(T) == 4, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                       mx);
   dft_lds_attrs<T>(std::make_integer_sequence<int, kMaxOrder - 1>{});

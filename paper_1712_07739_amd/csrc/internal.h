@@ -20,6 +20,9 @@ constexpr int kNumOffsets = 316;  // M2L offsets in [-3,3]^3 outside [-1,1]^3
 // per target: 768 threads in single precision (two blocks per CU), 1024 in
 // double, whose spectra (139 KB) leave room for one block per CU.  Both are
 // whole multiples of four waves, so a CU's four SIMDs get equal shares.
+// (Windows four times as large, whose waves take 32 targets at a time from a
+// counter, made the product 8-18% slower: sorted by list length, a larger
+// window's waves draw their sources from further apart.)
 constexpr int kM2LWindowF = 384;
 constexpr int kM2LWindowD = 512;
 inline int m2l_window(bool mixed) { return mixed ? kM2LWindowF : kM2LWindowD; }
@@ -88,7 +91,33 @@ __host__ __device__ constexpr int had_slot_of(int h, int k) {
 constexpr int kSymMaxLeaf = 1024;  // single precision
 constexpr int kSymMaxLeafD = 768;  // double precision
 constexpr int kWaveTargets = 32;
-constexpr int kIlwPad = 1;
+constexpr int kIlwPad = 2;  // the f16 product reads entries two steps ahead
+// Target (0..31 within the wave) of lane pair lp (lanes 2 lp, 2 lp + 1) in
+// the M2L kernels.  LDS has 64 four-byte banks and serves a wave's 16-byte
+// read in four passes of 16 lanes, which are not runs of consecutive lanes:
+// one-wave reads counted with SQ_LDS_BANK_CONFLICT put lanes 0-3, 12-15 and
+// 20-27 in one pass and 4-11, 16-19, 28-31 in another (the same again for
+// lanes 32-63), i.e. lane l's pass is 2 (l >> 5) plus the parity of bits
+// 2..5 of l.  This map gives the 8 lane pairs of pass k the consecutive
+// targets 8k..8k+7, so the lists' bank-aware order (tree build), which packs
+// the bank groups of 8 consecutive targets, packs each pass.
+__host__ __device__ constexpr int pass_target(int lp) {
+  const int par = ((lp >> 1) ^ (lp >> 2) ^ (lp >> 3) ^ (lp >> 4)) & 1;
+  return (lp & 16) | (par << 3) | ((lp >> 1) & 6) | (lp & 1);
+}
+constexpr bool pass_target_ok() {
+  bool seen[32] = {};
+  for (int lp = 0; lp < 32; ++lp) {
+    const int t = pass_target(lp);
+    if (t < 0 || t >= 32 || seen[t]) return false;
+    seen[t] = true;
+  }
+  // lanes 0-3, 12-15, 20-27 (pairs 0, 1, 6, 7, 10..13) hold targets 0..7
+  return pass_target(0) == 0 && pass_target(1) == 1 && pass_target(6) == 2 && pass_target(7) == 3 &&
+         pass_target(10) == 4 && pass_target(13) == 7 && pass_target(2) == 8 && pass_target(18) == 16 &&
+         pass_target(16) == 24;
+}
+static_assert(pass_target_ok(), "lane pair -> target map");
 
 struct Quad {
   double u[kMaxQuad], w[kMaxQuad];

@@ -358,8 +358,9 @@ __global__ void k_il_wave(const uint32_t* order, const int* il_start, const int2
 
 // Order of the entries inside each list, for the LDS banks of the M2L kernel.
 // A 16-byte LDS read is served 16 lanes at a time, and in the kernel those
-// lanes are the two lanes of each of 8 consecutive targets of a wave, which at
-// one step read the spectra of 8 unrelated offsets: lane h of a target with
+// lanes are the two lanes of each of 8 consecutive targets of a wave (the
+// kernels' lane pair -> target map, pass_target), which at one step read the
+// spectra of 8 unrelated offsets: lane h of a target with
 // offset id c reads 16-byte unit 29 c + 14 h + i (29 units per offset, lane 1
 // from unit 14), bank group (29 c + 14 h + i) mod 16.  Reads of one address are a broadcast; reads of different
 // addresses in one bank group are served one after another.  So step by step,
