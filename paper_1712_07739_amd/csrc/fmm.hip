@@ -248,12 +248,22 @@ __device__ __forceinline__ float h16_wscale(const unsigned* wmax, int p3) {
 }
 
 // Largest |x| over the n floats of one level's weights into *out (float
-// bits; non-negative floats order as unsigned integers): one atomic per block.
+// bits; non-negative floats order as unsigned integers): 16-byte loads over
+// the aligned body (a level's weights start on a 4-byte boundary; the first
+// block takes the unaligned head and the tail), one atomic per block.
 __global__ void __launch_bounds__(256) k_wmax(const float* x, int64_t n, unsigned* out) {
   __shared__ float sh[256];
+  int64_t head = (int64_t)(((16u - ((uintptr_t)x & 15u)) & 15u) / 4u);
+  if (head > n) head = n;
+  const int64_t nb4 = (n - head) / 4, tail0 = head + 4 * nb4;
   float m = 0.f;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
-    m = fmaxf(m, fabsf(x[i]));
+  if (blockIdx.x == 0 && threadIdx.x < head) m = fabsf(x[threadIdx.x]);
+  if (blockIdx.x == 0 && threadIdx.x < n - tail0) m = fmaxf(m, fabsf(x[tail0 + threadIdx.x]));
+  const float4* x4 = reinterpret_cast<const float4*>(x + head);
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nb4; i += (int64_t)gridDim.x * 256) {
+    const float4 v = x4[i];
+    m = fmaxf(m, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
+  }
   sh[threadIdx.x] = m;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
@@ -1807,7 +1817,7 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
       const auto& Lv = t->lv[l];
       const int64_t nw = Lv.n * 9 * p3;
       if (nw > 0)
-        STAGE(2, (k_wmax<<<(unsigned)std::min<int64_t>(2048, (nw + 255) / 256), 256, 0, st>>>(
+        STAGE(2, (k_wmax<<<(unsigned)std::min<int64_t>(8192, (nw / 4 + 255) / 256 + 1), 256, 0, st>>>(
                      (const float*)(W + Lv.off * 9 * p3), nw, t->wmax + l)));
     }
   }
