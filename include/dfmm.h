@@ -168,6 +168,15 @@ int dfmm_build_tree(dfmm_plan* plan, const double* seg, int64_t n_seg, void* str
 int dfmm_fmm_forces(const dfmm_plan* plan, dfmm_tree* tree, const double* seg,
                     const double* burgers, double* forces, void* stream);
 
+/* Debug check for the condition dfmm_fmm_forces relies on: seg (device,
+ * [n_seg][2][3], the tree's n_seg) holds the positions the tree was built
+ * from.  Every quadrature point is formed again as the force call forms it
+ * (Sec. 2: x1 + (1 + u_k)/2 dS) and compared bit for bit with the copy the
+ * build kept.  Synchronises the stream.  Errors: DFMM_E_STATE if any point
+ * differs (the message gives the count and the first segment) or the tree is
+ * from another plan; DFMM_E_ARG, DFMM_E_HIP. */
+int dfmm_tree_check_positions(const dfmm_plan* plan, dfmm_tree* tree, const double* seg, void* stream);
+
 /* Direct O(N^2) forces on the target segments targets[0..n_targets)
  * (device int64 indices into seg; NULL = all segments, then n_targets must
  * equal n_seg) from every quadrature point of every segment, Eq. stress3.

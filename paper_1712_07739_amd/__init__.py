@@ -37,6 +37,7 @@ ENTRY_POINTS = (
     "dfmm_batch_latencies", "dfmm_batch_destroy", "dfmm_autotune_depth",
     "dfmm_direct_forces_noalloc", "dfmm_direct_noalloc_bytes", "dfmm_surrogate_get_gate",
     "dfmm_surrogate_save", "dfmm_surrogate_load", "dfmm_forces_batched", "dfmm_autotune_batch_lanes",
+    "dfmm_tree_check_positions",
 )
 NOALLOC_SCRATCH_BYTES = 64 << 20
 
@@ -95,6 +96,7 @@ def lib():
     L.dfmm_tree_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)]
     L.dfmm_plan_info.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t]
     L.dfmm_tree_info.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t]
+    L.dfmm_tree_check_positions.argtypes = [vp, vp, vp, vp]
     L.dfmm_tree_destroy.argtypes = [vp]
     L.dfmm_plan_destroy.argtypes = [vp]
     L.dfmm_status_string.argtypes = [i32]
@@ -323,6 +325,14 @@ def fmm_forces(plan: Plan, tree: Tree, seg, burgers, out=None, stream=None):
                                  ctypes.c_void_p(burgers.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                                  _stream(stream)))
     return out
+
+
+def tree_check_positions(plan: Plan, tree: Tree, seg, stream=None):
+    """Raise DfmmError (DFMM_E_STATE) unless `seg` holds, bit for bit, the
+    positions `tree` was built from (synchronises the stream)."""
+    seg = _dev_f64(seg, (tree.n_seg, 2, 3), "seg")
+    _check(lib().dfmm_tree_check_positions(plan.handle, tree.handle, ctypes.c_void_p(seg.data_ptr()),
+                                           _stream(stream)))
 
 
 def direct_forces(plan: Plan, seg, burgers, targets=None, fp32=False, out=None, stream=None, noalloc=False):

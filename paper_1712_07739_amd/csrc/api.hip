@@ -227,6 +227,7 @@ void dfmm_tree_destroy(dfmm_tree* t) {
     hipFree(L.ilw); hipFree(L.wbase); hipFree(L.lenq);
   }
   hipFree(t->cstart); hipFree(t->cpair); hipFree(t->cval); hipFree(t->part); hipFree(t->cuni); hipFree(t->bigp);
+  hipFree(t->pos0); hipFree(t->chk);
   hipFree(t->pts); hipFree(t->pleaf); hipFree(t->W); hipFree(t->s); hipFree(t->What); hipFree(t->Shat); hipFree(t->sig);
   hipFree(t->kexp); hipFree(t->wmax);
   hipFree(t->gl_cell); hipFree(t->gl_pf); hipFree(t->gl_pc); hipFree(t->gkey); hipFree(t->glev); hipFree(t->gord);
@@ -240,6 +241,12 @@ int dfmm_fmm_forces(const dfmm_plan* plan, dfmm_tree* tree, const double* seg, c
   if (!plan || !tree || !seg || !burgers || !forces) { set_error("fmm_forces: null argument"); return DFMM_E_ARG; }
   if (tree->plan != plan) { set_error("fmm_forces: tree was built with another plan"); return DFMM_E_STATE; }
   return fmm_forces_impl(plan, tree, seg, burgers, forces, (hipStream_t)stream);
+}
+
+int dfmm_tree_check_positions(const dfmm_plan* plan, dfmm_tree* tree, const double* seg, void* stream) {
+  if (!plan || !tree || !seg) { set_error("tree_check_positions: null argument"); return DFMM_E_ARG; }
+  if (tree->plan != plan) { set_error("tree_check_positions: tree was built with another plan"); return DFMM_E_STATE; }
+  return check_positions_impl(plan, tree, seg, (hipStream_t)stream);
 }
 
 int dfmm_direct_forces(const dfmm_plan* plan, const double* seg, const double* burgers, int64_t n_seg,

@@ -266,6 +266,8 @@ struct dfmm_tree {
   int max_leaf_pts = 0;
   // workspaces
   double* pts = nullptr;    // sorted point data [9][N]: x, y, z, bx, by, bz, tx, ty, tz
+  double* pos0 = nullptr;   // [3][N] the sorted points' positions at build time
+  unsigned long long* chk = nullptr;  // [2] position check: mismatches, first mismatching segment
   void* W = nullptr;        // [ncell_total][9][p^3]  (float or double)
   void* s = nullptr;        // [ncell_total][6][p^3]
   int fchunk = 0;           // first frequency indices per chunk of the spectra (n: whole)
@@ -362,6 +364,7 @@ int surrogate_forward(const dfmm_plan* pl, const float* X, int64_t n, float* You
 int scan_excl(const int* in, int* out, int64_t n, hipStream_t st, int64_t* total);
 // Stable LSD radix sort of (keys, vals) (n >= 1) by the low `bits` bits of keys.
 int radix_sort(uint32_t* keys, uint32_t* vals, int64_t n, int bits, hipStream_t st);
+int check_positions_impl(const dfmm_plan* plan, dfmm_tree* t, const double* seg, hipStream_t st);
 int build_tree_impl(dfmm_plan* plan, const double* seg, int64_t nseg, hipStream_t st, dfmm_tree* t,
                     bool workspaces = true);
 

@@ -10,6 +10,7 @@
 // 189) of every level >= 2 are found by binary search in the sorted keys.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 
 #include "internal.h"
 #include "morton.h"
@@ -434,6 +435,46 @@ __global__ void k_gather_pos(const double* seg, const uint32_t* perm, Quad qd, i
   for (int d = 0; d < 3; ++d) pts[d * N + i] = x[d];
 }
 
+// Debug check that seg holds the positions a tree was built from: every
+// sorted point formed again as the force call's gather forms it, compared bit
+// for bit with the build's copy; chk[0] counts the points that differ, chk[1]
+// keeps the smallest segment index among them.
+__global__ void k_pos_check(const double* seg, const uint32_t* perm, Quad qd, int64_t N, const double* pos0,
+                            unsigned long long* chk) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const uint32_t j = perm[i];
+  const int64_t s = j / qd.n;
+  double x[3], t[3];
+  quad_point(seg, s, (int)(j - s * qd.n), qd, x, t);
+  bool bad = false;
+  for (int d = 0; d < 3; ++d) bad |= __double_as_longlong(x[d]) != __double_as_longlong(pos0[d * N + i]);
+  if (bad) {
+    atomicAdd(&chk[0], 1ull);
+    atomicMin(&chk[1], (unsigned long long)s);
+  }
+}
+
+int check_positions_impl(const dfmm_plan* pl, dfmm_tree* t, const double* seg, hipStream_t st) {
+  const int64_t N = t->N;
+  const unsigned long long init[2] = {0ull, ~0ull};
+  DFMM_HIP(hipMemcpyAsync(t->chk, init, sizeof(init), hipMemcpyHostToDevice, st));
+  k_pos_check<<<(unsigned)((N + 255) / 256), 256, 0, st>>>(seg, t->perm, pl->quad, N, t->pos0, t->chk);
+  DFMM_LAUNCH_CHECK();
+  unsigned long long h[2];
+  DFMM_D2H(h, t->chk, sizeof(h), st);
+  if (h[0] > 0) {
+    char msg[200];
+    std::snprintf(msg, sizeof(msg),
+                  "tree_check_positions: %llu of %lld quadrature points differ from the positions the tree was "
+                  "built from (first at segment %llu)",
+                  h[0], (long long)N, h[1]);
+    set_error(msg);
+    return DFMM_E_STATE;
+  }
+  return DFMM_OK;
+}
+
 // Near-coincident pairs of each sorted target point: the sources closer than
 // 2a in its leaf's 27 neighbour leaves (the point itself excluded: its own
 // term is zero), in the order the near field visits them (neighbour by
@@ -749,6 +790,11 @@ int build_tree_impl(dfmm_plan* pl, const double* seg, int64_t nseg, hipStream_t 
   DFMM_HIP(hipEventCreateWithFlags(&t->join, hipEventDisableTiming));
   DFMM_HIP(hipEventCreateWithFlags(&t->done, hipEventDisableTiming));
   DFMM_HIP(hipMalloc(&t->pts, sizeof(double) * 9 * N));
+  // the build's positions, for dfmm_tree_check_positions
+  DFMM_HIP(hipMalloc(&t->pos0, sizeof(double) * 3 * N));
+  DFMM_HIP(hipMalloc(&t->chk, 2 * sizeof(unsigned long long)));
+  k_gather_pos<<<nb(N, 256), 256, 0, st>>>(seg, t->perm, pl->quad, N, t->pos0);
+  DFMM_LAUNCH_CHECK();
   if (!t->adaptive) {
     DFMM_HIP(hipMalloc(&t->pleaf, sizeof(int) * N));
     k_point_leaf<<<(unsigned)LD.n, 64, 0, st>>>(LD.first, LD.count, (int)LD.n, t->pleaf);
@@ -839,7 +885,7 @@ int build_tree_impl(dfmm_plan* pl, const double* seg, int64_t nseg, hipStream_t 
       DFMM_HIP(hipMemsetAsync(t->cval, 0, sizeof(double) * 6 * t->nclose, st));
     }
   }
-  t->bytes = sizeof(double) * 15 * N + sizeof(int) * N + bW + bS + bWh + bSh +
+  t->bytes = sizeof(double) * 18 * N + sizeof(int) * N + bW + bS + bWh + bSh +
              (sizeof(int2) + 6 * sizeof(double)) * t->nclose + sizeof(int2) * t->nuni +
              (t->cstart ? sizeof(int) * (N + 1) : 0) +
              (t->part ? part_es * 27 * 6 * N : 0) + sizeof(int) * t->nbig + bKx +

@@ -67,6 +67,7 @@ def test_null_arguments_and_status_strings(L):
     assert L.dfmm_plan_info(None, None, 0) == -1
     assert L.dfmm_tree_set_timing(None, 1) == -1
     assert L.dfmm_fmm_forces(None, None, None, None, None, None) == -1
+    assert L.dfmm_tree_check_positions(None, None, None, None) == -1
     L.dfmm_tree_destroy(None)
     L.dfmm_plan_destroy(None)
     for s, txt in ((0, b"ok"), (-4, b"point outside the root cube"), (-5, b"non-finite coordinate")):

@@ -244,6 +244,32 @@ def test_errors_for_bad_coordinates(env):
     assert e.value.status == -1
 
 
+@pytest.mark.parametrize("precision,leaf_max", [(0, 0), (2, 0), (1, 8)])
+def test_tree_check_positions(env, precision, leaf_max):
+    """dfmm_tree_check_positions accepts the segments a tree was built from
+    and rejects, with the first segment named, endpoints moved by 1e-9 in one
+    coordinate (uniform and adaptive trees, FP64 and single)."""
+    torch, pk, dev = env
+    seg, b = synth.loops.make_loops(12, 0.01, 0.05, seed=31)
+    prm = pk.make_params(4, 4, *CUB, 1e-3, BOX_LO, BOX, precision=precision, leaf_max=leaf_max)
+    plan = pk.Plan(prm)
+    ts = torch.tensor(seg, device=dev)
+    tree = pk.Tree(plan, ts)
+    pk.tree_check_positions(plan, tree, ts)
+    moved = seg.copy()
+    moved[37, 0, 2] += 1e-9
+    moved[200, 1, 0] -= 1e-9
+    with pytest.raises(pk.DfmmError) as e:
+        pk.tree_check_positions(plan, tree, torch.tensor(moved, device=dev))
+    assert e.value.status == -6 and "first at segment 37" in str(e.value)
+    pk.tree_check_positions(plan, tree, ts)  # the counters start again at zero
+    pk.fmm_forces(plan, tree, ts, torch.tensor(b, device=dev))
+    pk.tree_check_positions(plan, tree, ts)  # a force call leaves the build's copy alone
+    with pytest.raises(pk.DfmmError) as e:
+        pk.tree_check_positions(pk.Plan(prm), tree, ts)
+    assert e.value.status == -6
+
+
 def test_maximum_depth(env):
     """Depth 10, the deepest the 30-bit Morton keys allow (2^30 leaves in
     the key space), on a small input: against the oracle's FMM."""
