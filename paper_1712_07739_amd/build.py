@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdfmm.so")
 SOURCES = ["api.hip", "setup.hip", "tree.hip", "adaptive.hip", "fmm.hip", "mlp.hip", "batch.hip"]
-PROBE = "probe_lds_passes.hip"
+PROBES = ["probe_lds_passes.hip", "probe_valu_rates.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -30,18 +30,19 @@ def build(verbose: bool = False) -> str:
         subprocess.run(cmd, check=True)
         return obj
 
-    def probe():
-        # the LDS pass probe behind the M2L kernels' lane map: a program of
-        # its own, not part of the library
-        cmd = [hipcc, *FLAGS, os.path.join(CSRC, PROBE), "-o", os.path.join(bdir, PROBE.replace(".hip", ""))]
+    def probe(src):
+        # the measurement programs behind the M2L kernels' lane map and the
+        # VALU rooflines: programs of their own, not part of the library
+        cmd = [hipcc, *FLAGS, os.path.join(CSRC, src), "-o", os.path.join(bdir, src.replace(".hip", ""))]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
 
-    with ThreadPoolExecutor(max_workers=len(SOURCES) + 1) as ex:
-        fp = ex.submit(probe)
+    with ThreadPoolExecutor(max_workers=len(SOURCES) + len(PROBES)) as ex:
+        fps = [ex.submit(probe, src) for src in PROBES]
         objs = list(ex.map(compile_one, SOURCES))
-        fp.result()
+        for fp in fps:
+            fp.result()
     tmp = LIB + ".tmp%d" % os.getpid()
     subprocess.run([hipcc, "--offload-arch=gfx950", "-shared", "-o", tmp, *objs], check=True)
     os.replace(tmp, LIB)
