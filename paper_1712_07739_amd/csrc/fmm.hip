@@ -741,10 +741,13 @@ k_hadamard16(const uint32_t* What, const uint32_t* Khat, const int* lenq, const 
 // LDS) for 108 double multiply-adds: LDS reads are this kernel's limit.
 // (Reading one of the three rows from memory instead, to share the load
 // between LDS and L2, made the kernel 2.5 times slower: the rows are 144-byte
-// reads at random offsets.)
+// reads at random offsets.)  The LDS allows four waves per SIMD, and the
+// kernel says so (amdgpu_waves_per_eu): left to target eight, the compiler
+// fits it into 64 registers by issuing its 27 spectrum reads one at a time,
+// each waited for before its four multiply-adds (455 -> 375 ms on 1M segments).
 constexpr int kHadThreadsD = 2 * kM2LWindowD;
 static_assert(kM2LWindowD % kWaveTargets == 0, "whole waves per window");
-__global__ void __launch_bounds__(kHadThreadsD)
+__global__ void __launch_bounds__(kHadThreadsD) __attribute__((amdgpu_waves_per_eu(4, 4)))
 k_hadamard64(const cplx<double>* What, const cplx<double>* Khat, const int* lenq, const int* wbase, const uint32_t* ilw,
              const uint32_t* order, int64_t ncell, int nf, int nwin, int remap, cplx<double>* Shat) {
   extern __shared__ __align__(16) unsigned char shraw[];
