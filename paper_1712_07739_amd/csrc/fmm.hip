@@ -471,7 +471,7 @@ __global__ void k_sym_expand(const cplx<T>* __restrict__ Kc, const SymEntry* __r
   } else if (sizeof(T) == 4)
     out[((int64_t)f * kNumCanon + id) * kKOffsetF + (ab / 3) * kKHalfF + (ab % 3) * 9 + had_slot_of(ab / 3, wr)] = v;
   else
-    out[((int64_t)f * kNumCanon + id) * kKOffsetD + (ab / 3) * kKHalfD + (ab % 3) * 9 + had_slot_of(ab / 3, wr)] = v;
+    out[((int64_t)f * kNumCanon + id) * kKOffsetD + d_unit_of(ab, wr)] = v;
 }
 
 constexpr int kHadThreads = 2 * kM2LWindowF;
@@ -732,19 +732,22 @@ k_hadamard16(const uint32_t* What, const uint32_t* Khat, const int* lenq, const 
   }
 }
 
-// The double-precision Hadamard product: the blocks, lanes, list walk and
-// source split of k_hadamard, with one 16-byte complex per LDS unit.  The
-// spectra of a frequency are stored in the lanes' slot order (half h = stress
-// rows 3h..3h+2 of offset c at unit 55 c + 27 h), and a block copies them into
-// LDS as they are: 139 KB, so one block of 1024 threads (four waves per SIMD)
-// runs per CU.  Per step a lane reads 27 complex spectrum values (432 B of
-// LDS) for 108 double multiply-adds: LDS reads are this kernel's limit.
-// (Reading one of the three rows from memory instead, to share the load
-// between LDS and L2, made the kernel 2.5 times slower: the rows are 144-byte
-// reads at random offsets.)  The LDS allows four waves per SIMD, and the
-// kernel says so (amdgpu_waves_per_eu): left to target eight, the compiler
-// fits it into 64 registers by issuing its 27 spectrum reads one at a time,
-// each waited for before its four multiply-adds (455 -> 375 ms on 1M segments).
+// The double-precision Hadamard product: the blocks, list walk and source
+// loads of k_hadamard, with one 16-byte complex per LDS unit, and the 6x9
+// product split between a target's two lanes by source component as in
+// k_hadamard16 (d_unit_of): no source value crosses lanes, and the partial
+// sums of the rows a lane writes are exchanged once per target.  The spectra
+// of a frequency are stored in the lanes' reading order (lane h's 27 values of
+// offset c at unit 55 c + 27 h), and a block copies them into LDS as they
+// are: 139 KB, so one block of 1024 threads (four waves per SIMD) runs per
+// CU.  Per step a lane reads 27 complex spectrum values (432 B of LDS) for
+// 108 double multiply-adds.  (Reading one of the three rows from memory
+// instead, to share the load between LDS and L2, made the kernel 2.5 times
+// slower: the rows are 144-byte reads at random offsets.)  The LDS allows
+// four waves per SIMD, and the kernel says so (amdgpu_waves_per_eu): left to
+// target eight, the compiler fits it into 64 registers by issuing its 27
+// spectrum reads one at a time, each waited for before its multiply-adds
+// (455 -> 375 ms on 1M segments).
 constexpr int kHadThreadsD = 2 * kM2LWindowD;
 static_assert(kM2LWindowD % kWaveTargets == 0, "whole waves per window");
 __global__ void __launch_bounds__(kHadThreadsD) __attribute__((amdgpu_waves_per_eu(4, 4)))
@@ -775,7 +778,8 @@ k_hadamard64(const cplx<double>* What, const cplx<double>* Khat, const int* lenq
   const int h = threadIdx.x & 1;
   const int64_t t = order[tt];
   const int len = lenq[tt];
-  double ar[3] = {0.0, 0.0, 0.0}, ai[3] = {0.0, 0.0, 0.0};
+  // accumulator a holds stress row (3h + a) mod 6
+  double ar[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, ai[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   // list entries as in k_hadamard: source cell in bits 0..22, canonical
   // offset in bits 23..30, mirror flag in bit 31
   const char* wfb = reinterpret_cast<const char*>(What + (int64_t)f * ncell * 9);
@@ -792,42 +796,28 @@ k_hadamard64(const cplx<double>* What, const cplx<double>* Khat, const int* lenq
     v[4] = *reinterpret_cast<const double2*>(wfb + o + 128);
   };
   auto pair = [&](uint32_t j, const double2* v) {
-    // mirrored offset: conjugate the source values and negate the real part
-    // of the result
-    const uint32_t sgb = j & 0x80000000u;
-    const double sg = __hiloint2double((int)(0x3ff00000u | sgb), 0);
-    double wr[9], wi[9];
+    // a mirrored offset's spectrum is -conj(K) of the canonical K, and
+    // -conj(K) w = Kr (-wr) - Ki wi + i (Ki wr + Kr (-wi)): the real parts of
+    // K meet sign-flipped source values, with no fix-up per row
+    const int sgb = (int)(j & 0x80000000u);
+    double nr[5], ni[5];
 #pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      wr[k] = v[k].x;
-      wi[k] = __hiloint2double(__double2hiint(v[k].y) ^ (int)sgb, __double2loint(v[k].y));
-    }
-    // swap halves with the neighbouring lane (quad permutation 1, 0, 3, 2)
-    auto swap = [](double x) {
-      const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), 0xB1, 0xF, 0xF, false);
-      const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), 0xB1, 0xF, 0xF, false);
-      return __hiloint2double(hi, lo);
-    };
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      wr[5 + k] = swap(wr[k]);
-      wi[5 + k] = swap(wi[k]);
+    for (int c = 0; c < 5; ++c) {
+      nr[c] = __hiloint2double(__double2hiint(v[c].x) ^ sgb, __double2loint(v[c].x));
+      ni[c] = __hiloint2double(__double2hiint(v[c].y) ^ sgb, __double2loint(v[c].y));
     }
     const cplx<double>* K = kb + ((j >> 23) & 0xFFu) * (uint32_t)kKOffsetD;
+    // v[c]: component 4h + c (c < 4), component 8 (c = 4)
 #pragma unroll
-    for (int r = 0; r < 3; ++r) {
-      double cr = 0.0, ci = 0.0;
+    for (int c = 0; c < 5; ++c)
 #pragma unroll
-      for (int s = 0; s < 9; ++s) {
-        const double2 q = *reinterpret_cast<const double2*>(K + 9 * r + s);
-        cr = fma(q.x, wr[s], cr);
-        cr = fma(-q.y, wi[s], cr);
-        ci = fma(q.x, wi[s], ci);
-        ci = fma(q.y, wr[s], ci);
+      for (int a = 0; a < (c < 4 ? 6 : 3); ++a) {
+        const double2 q = *reinterpret_cast<const double2*>(K + (c < 4 ? 4 * a + c : 24 + a));
+        ar[a] = fma(q.x, nr[c], ar[a]);
+        ar[a] = fma(-q.y, v[c].y, ar[a]);
+        ai[a] = fma(q.y, v[c].x, ai[a]);
+        ai[a] = fma(q.x, ni[c], ai[a]);
       }
-      ar[r] = fma(sg, cr, ar[r]);
-      ai[r] += ci;
-    }
   };
   // next entry one step ahead, as in k_hadamard (prefetching the source
   // values too, as k_hadamard16 does, was 2% slower here: this kernel is
@@ -845,9 +835,16 @@ k_hadamard64(const cplx<double>* What, const cplx<double>* Khat, const int* lenq
       asm volatile("" : "+v"(jo));
     }
   }
+  // rows 3h..3h+2: accumulators 0..2 here, 3..5 in the partner lane (quad
+  // permutation 1, 0, 3, 2)
+  auto partner = [](double x) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), 0xB1, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), 0xB1, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+  };
   cplx<double>* out = Shat + ((int64_t)f * ncell + t) * 6 + 3 * h;
 #pragma unroll
-  for (int r = 0; r < 3; ++r) out[r] = cplx<double>{ar[r], ai[r]};
+  for (int r = 0; r < 3; ++r) out[r] = cplx<double>{ar[r] + partner(ar[3 + r]), ai[r] + partner(ai[3 + r])};
 }
 
 // ------------------------------------------------------------ inverse DFT

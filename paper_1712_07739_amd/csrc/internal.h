@@ -80,6 +80,26 @@ static_assert(h16_layout_ok(), "f16 spectrum words");
 // 27 values back to back and one pad unit, 55 units per offset (odd).
 constexpr int kKHalfD = 27;
 constexpr int kKOffsetD = 2 * kKHalfD + 1;
+// The double product splits the 6x9 product between a target's two lanes by
+// source component as the f16 product does: lane h's 27 values (components
+// 4h..4h+3 for accumulators a = 0..5, stress row (3h + a) mod 6, then
+// component 8 for rows 3h..3h+2) start at unit 27 h.  Unit of stress row R
+// (0..5), source component C (0..8) in an offset's double spectra:
+__host__ __device__ constexpr int d_unit_of(int R, int C) {
+  return C == 8 ? kKHalfD * (R / 3) + 24 + R % 3
+                : kKHalfD * (C >> 2) + 4 * ((R - 3 * (C >> 2) + 6) % 6) + (C & 3);
+}
+constexpr bool d_layout_ok() {
+  bool seen[kKOffsetD] = {};
+  for (int R = 0; R < 6; ++R)
+    for (int C = 0; C < 9; ++C) {
+      const int w = d_unit_of(R, C);
+      if (w < 0 || w >= 2 * kKHalfD || seen[w]) return false;
+      seen[w] = true;
+    }
+  return true;
+}
+static_assert(d_layout_ok(), "double spectrum units");
 __host__ __device__ constexpr int had_slot_of(int h, int k) {
   return k == 8 ? 4 : ((k >> 2) == h ? k - 4 * h : 5 + k - 4 * (1 - h));
 }
