@@ -409,25 +409,27 @@ constexpr size_t lds_fdft_t(int G, size_t es) {
 // f).  The spectra of the 158 canonical offsets at frequency f sit in LDS;
 // the spectrum of a mirrored offset -o is -conj of that of o, so its
 // contribution -conj(K) w = -conj(K conj(w)) is folded into the same loop
-// with a sign.  Two lanes share a target, each owning three of its six stress
-// rows, and walk the target's interaction list:
+// with a sign.  Two lanes share a target and walk its interaction list:
 //   Shat[f][T][r] = sum_{(J, o) in I(T)} sum_k Khat_o(f)[r][k] What[f][J][k].
 // The load of the source's nine values is one of the kernel's limits (with
 // the LDS reads of the spectra and the multiply-adds), so the two lanes of a
-// target split it: lane h loads components 4h..4h+3 and component 8, and the
-// four-value halves are swapped between neighbouring lanes with a DPP move.
-// Each lane then holds the nine components in its own slot order, the order
-// in which the spectra are stored (had_slot_of), and the block's copy of them
-// into LDS is a straight copy.  With many windows, blocks are remapped so that
+// target split it: lane h loads components 4h..4h+3 and component 8 and
+// multiplies only those (the split by component described with f_unit_of),
+// and the two lanes exchange partial sums once per target.  The spectra are
+// stored in the lanes' reading order, so the block's copy of them into LDS
+// is a straight copy.  With many windows, blocks are remapped so that
 // each of the 8 XCDs (blocks are dispatched round-robin over them) works
 // through a contiguous range of windows at one frequency at a time:
 // neighbouring windows share sources in that XCD's L2.
 // The spectra take 73.3 KB of LDS per block, so two blocks (384 targets,
-// twelve waves each) share a CU: six waves per SIMD.
+// twelve waves each) share a CU: six waves per SIMD.  (Splitting by component
+// rather than by stress row, which removed the per-step exchange of four
+// source values: 137 -> 127 VALU operations per lane and step, 202.5 ->
+// 198.5 ms on 1M segments.)
 // Symmetry-reduced store: one level's spectra of the 158 canonical offsets,
 // expanded from the 16 class spectra Kc [nf][16][54] into the layout the
-// Hadamard kernels read (float: slot order, kKOffsetF per offset; double:
-// row-major 6 x 9), in a workspace of the tree, before the level's product.
+// Hadamard kernels read (the lanes' reading order: f_unit_of, d_unit_of,
+// h16_word_of), in a workspace of the tree, before the level's product.
 // With o = R o_c,
 //   Khat_o(f)[a b w r] = det(R) s_a s_b s_w s_r Khat_{o_c}(R^T f)[pi(a) pi(b) pi(w) pi(r)],
 // where (R^T f)_{pi(i)} = s_i f_i (mod n) and the half spectrum supplies g
@@ -469,7 +471,7 @@ __global__ void k_sym_expand(const cplx<T>* __restrict__ Kc, const SymEntry* __r
     o32[e0] = pack_h2((float)v.re * scale, (float)v.im * scale);
     o32[e0 + kKOffsetH] = pack_h2(-(float)v.re * scale, (float)v.im * scale);
   } else if (sizeof(T) == 4)
-    out[((int64_t)f * kNumCanon + id) * kKOffsetF + (ab / 3) * kKHalfF + (ab % 3) * 9 + had_slot_of(ab / 3, wr)] = v;
+    out[((int64_t)f * kNumCanon + id) * kKOffsetF + f_unit_of(ab, wr)] = v;
   else
     out[((int64_t)f * kNumCanon + id) * kKOffsetD + d_unit_of(ab, wr)] = v;
 }
@@ -511,7 +513,8 @@ k_hadamard(const cplx<float>* What, const cplx<float>* Khat, const int* lenq, co
   const int h = threadIdx.x & 1;
   const int64_t t = order[tt];
   const int len = lenq[tt];
-  float ar[3] = {0.f, 0.f, 0.f}, ai[3] = {0.f, 0.f, 0.f};
+  // accumulator a holds stress row (3h + a) mod 6
+  float ar[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, ai[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   // A list entry is one 32-bit word: the source cell in bits 0..22, the
   // canonical offset in bits 23..30 and the mirror flag in bit 31 (the host
   // checks that a level's cells and its slice of the source spectra fit).  The
@@ -538,21 +541,15 @@ k_hadamard(const cplx<float>* What, const cplx<float>* Khat, const int* lenq, co
     v[4] = {z.x, z.y};
   };
   auto pair = [&](uint32_t j, const cplx<float>* v) {
-    // mirrored offset: conjugate the source values (sign bit of the imaginary
-    // parts) and negate the real part of the result
+    // a mirrored offset's spectrum is -conj(K) of the canonical K, and
+    // -conj(K) w = Kr (-wr) - Ki wi + i (Ki wr + Kr (-wi)): the real parts of
+    // K meet sign-flipped source values, with no fix-up per row
     const uint32_t sgb = j & 0x80000000u;
-    const float sg = __uint_as_float(0x3f800000u | sgb);
-    float wr[9], wi[9];
+    float nr[5], ni[5];
 #pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      wr[k] = v[k].re;
-      wi[k] = __uint_as_float(__float_as_uint(v[k].im) ^ sgb);
-    }
-    // swap halves with the neighbouring lane (quad permutation 1, 0, 3, 2)
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      wr[5 + k] = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(wr[k]), 0xB1, 0xF, 0xF, false));
-      wi[5 + k] = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(wi[k]), 0xB1, 0xF, 0xF, false));
+    for (int c = 0; c < 5; ++c) {
+      nr[c] = __uint_as_float(__float_as_uint(v[c].re) ^ sgb);
+      ni[c] = __uint_as_float(__float_as_uint(v[c].im) ^ sgb);
     }
     // the lane's 27 complex spectrum entries: 13 float4 and one float2
     const float4* K4 = reinterpret_cast<const float4*>(kb + ((j >> 23) & 0xFFu) * (uint32_t)(kKOffsetF * 8));
@@ -570,20 +567,18 @@ k_hadamard(const cplx<float>* What, const cplx<float>* Khat, const int* lenq, co
       kk[52] = q.x;
       kk[53] = q.y;
     }
+    // v[c]: component 4h + c (c < 4), component 8 (c = 4)
 #pragma unroll
-    for (int r = 0; r < 3; ++r) {
-      float cr = 0.f, ci = 0.f;
+    for (int c = 0; c < 5; ++c)
 #pragma unroll
-      for (int s = 0; s < 9; ++s) {
-        const float kr = kk[2 * (9 * r + s)], ki = kk[2 * (9 * r + s) + 1];
-        cr = fma(kr, wr[s], cr);
-        cr = fma(-ki, wi[s], cr);
-        ci = fma(kr, wi[s], ci);
-        ci = fma(ki, wr[s], ci);
+      for (int a = 0; a < (c < 4 ? 6 : 3); ++a) {
+        const int e = c < 4 ? 4 * a + c : 24 + a;
+        const float kr = kk[2 * e], ki = kk[2 * e + 1];
+        ar[a] = fma(kr, nr[c], ar[a]);
+        ar[a] = fma(-ki, v[c].im, ar[a]);
+        ai[a] = fma(ki, v[c].re, ai[a]);
+        ai[a] = fma(kr, ni[c], ai[a]);
       }
-      ar[r] = fma(sg, cr, ar[r]);
-      ai[r] += ci;
-    }
   };
   // The next list entry is loaded one step ahead (carried through an empty
   // asm statement, which keeps the compiler from turning it back into a load
@@ -605,9 +600,15 @@ k_hadamard(const cplx<float>* What, const cplx<float>* Khat, const int* lenq, co
       asm volatile("" : "+v"(jo));
     }
   }
+  // rows 3h..3h+2: accumulators 0..2 here, 3..5 in the partner lane (quad
+  // permutation 1, 0, 3, 2)
   cplx<float>* out = Shat + ((int64_t)f * ncell + t) * 6 + 3 * h;
 #pragma unroll
-  for (int r = 0; r < 3; ++r) out[r] = cplx<float>{ar[r], ai[r]};
+  for (int r = 0; r < 3; ++r) {
+    const float pr = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(ar[3 + r]), 0xB1, 0xF, 0xF, false));
+    const float pi = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(ai[3 + r]), 0xB1, 0xF, 0xF, false));
+    out[r] = cplx<float>{ar[r] + pr, ai[r] + pi};
+  }
 }
 
 // The Hadamard product on f16 operands (DFMM_MIXED_F16): the same blocks,

@@ -34,28 +34,46 @@ constexpr int kNumFar = 189;      // interaction-list size of an interior cell
 constexpr long long kScratchBytes = DFMM_NOALLOC_SCRATCH_BYTES;
 constexpr int kMaxDevices = 64;
 
-// Single-precision spectra are stored in the order in which the M2L Hadamard
-// kernel reads them.  Two lanes share a target; lane h owns stress rows
-// 3h..3h+2 and loads source components 4h..4h+3 and 8, then receives the
-// partner's four components by a lane swap.  Its nine slots hold components
-//   slot 0..3: 4h..4h+3,  slot 4: 8,  slot 5..8: 4(1-h)..4(1-h)+3.
-// Per frequency and canonical offset: [2 halves][3 rows][9 slots] complex,
-// each half padded to kKHalfF entries (16-byte aligned; the pads are zero).
-// An offset takes 29 16-byte units: lanes read the spectra of unrelated
-// offsets at once, and an odd stride spreads those reads evenly over the LDS
-// banks (an even one leaves half of them idle and doubles up the rest).
+// The M2L Hadamard kernels split a target's 6x9 product between its two
+// lanes by source component, so that no source value crosses lanes: lane h
+// loads components 4h..4h+3 and 8 of the source and takes components
+// 4h..4h+3 for all six stress rows and component 8 for rows 3h..3h+2 (27
+// complex multiply-adds each), keeping row R in accumulator (R - 3h) mod 6;
+// the rows a lane writes (3h..3h+2, its accumulators 0..2) receive the
+// partner's accumulators 3..5 once per target.  The spectra are stored in
+// the order in which a lane reads them: per frequency and offset, lane h's 27
+// entries (f_unit_of, d_unit_of, h16_word_of) start a half of its own.
+// Single precision: two halves of kKHalfF complex entries (16-byte aligned;
+// the pads are zero), 29 16-byte units per offset: lanes read the spectra of
+// unrelated offsets at once, and an odd stride spreads those reads evenly
+// over the LDS banks (an even one leaves half of them idle and doubles up the
+// rest).
 constexpr int kKHalfF = 28;
 constexpr int kKOffsetF = 2 * kKHalfF + 2;
-// The f16 Hadamard product splits the 6x9 product between a target's two
-// lanes by source component instead, so that no source value crosses lanes:
-// lane h takes components 4h..4h+3 for all six stress rows and component 8
-// for rows 3h..3h+2, and keeps row R in accumulator (R - 3h) mod 6; the rows
-// a lane writes (3h..3h+2, accumulators 0..2) then receive the partner's
-// accumulators 3..5 once per target.  One 32-bit word (f16 real, f16
-// imaginary) per complex value; lane h's 27 words, in the order it reads
-// them (accumulator-major for components 4h..4h+3, then component 8), start
-// at word 28 h; per offset two halves of 28 words and 4 pad words, 15
-// 16-byte units (odd, for the same reason).
+// Entry of stress row R (0..5), source component C (0..8) in an offset's
+// single-precision spectra: lane h's 27 entries (components 4h..4h+3 for
+// accumulators a = 0..5, then component 8 for rows 3h..3h+2) start at entry
+// 28 h.
+__host__ __device__ constexpr int f_unit_of(int R, int C) {
+  return C == 8 ? kKHalfF * (R / 3) + 24 + R % 3
+                : kKHalfF * (C >> 2) + 4 * ((R - 3 * (C >> 2) + 6) % 6) + (C & 3);
+}
+constexpr bool f_layout_ok() {
+  bool seen[kKOffsetF] = {};
+  for (int R = 0; R < 6; ++R)
+    for (int C = 0; C < 9; ++C) {
+      const int w = f_unit_of(R, C);
+      if (w < 0 || w >= 2 * kKHalfF || w % kKHalfF >= 27 || seen[w]) return false;
+      seen[w] = true;
+    }
+  return true;
+}
+static_assert(f_layout_ok(), "single-precision spectrum entries");
+// The f16 product: one 32-bit word (f16 real, f16 imaginary) per complex
+// value; lane h's 27 words, in the order it reads them (accumulator-major for
+// components 4h..4h+3, then component 8), start at word 28 h; per offset two
+// halves of 28 words and 4 pad words, 15 16-byte units (odd, for the same
+// reason).
 constexpr int kKHalfH = 28;
 constexpr int kKOffsetH = 2 * kKHalfH + 4;
 // Word of stress row R (0..5), source component C (0..8) in an offset's
@@ -100,9 +118,6 @@ constexpr bool d_layout_ok() {
   return true;
 }
 static_assert(d_layout_ok(), "double spectrum units");
-__host__ __device__ constexpr int had_slot_of(int h, int k) {
-  return k == 8 ? 4 : ((k >> 2) == h ? k - 4 * h : 5 + k - 4 * (1 - h));
-}
 // The single-precision M2L kernel walks the lists of 32 consecutive targets
 // of the processing order in one wave; their entries are stored step-major per
 // wave (see Level::ilw), and the entry after a list's end is read.
@@ -196,7 +211,7 @@ struct LevelTables {
   void* khat = nullptr;  // DFT of the circulant embedding of each stored offset's
                          // generator.  DFMM_M2L_FFT: the 158 canonical offsets,
                          // double [nf][158][54] complex (row-major 6 x 9), float
-                         // [nf][158][kKOffsetF] complex in slot order (DFMM_MIXED_F16:
+                         // [nf][158][kKOffsetF] complex in reading order (DFMM_MIXED_F16:
                          // [nf][158][kKOffsetH] f16 pairs, scaled by kscale).
                          // DFMM_M2L_FFT_SYM: the 16 symmetry classes, [nf][16][54]
                          // complex (row-major 6 x 9) in the plan's precision.
