@@ -1306,6 +1306,163 @@ __global__ void __launch_bounds__((sym_threads<T, BIG>()), sym_min_waves<T>())
             (T)((double)accB[jj * 6 + c] - (double)cmpB[jj * 6 + c]);
 }
 
+// The same symmetric near field for the leaf pairs with at most 64 points on
+// each side, one wave per leaf A over all its pairs {A, A + o} (slots q =
+// 13..26) as one run of point pairs: rounds of 64 pairs run across the
+// pairs' boundaries, so only the run's last round is partly empty (one wave
+// per leaf pair left most rounds partly empty: the 66 self pairs of a
+// 12-point leaf took two rounds of 64).  Every target sums the same terms in
+// the same order as with one wave per leaf pair, and a leaf pair's partials
+// are written when its last pair has been summed.
+template <typename T, bool MIXED>
+__global__ void __launch_bounds__(64, sizeof(T) == 4 ? 4 : 1)
+    k_leaf_sym_run(const double* pts, int64_t N, const int* first, const int* count, const int* nbr, Med<T> m,
+                   double a2x4, T* part) {
+  constexpr int NT = 64;
+  __shared__ T accA[64 * 6], cmpA[64 * 6], accB[64 * 6], cmpB[64 * 6], vij[NT * 6], vji[NT * 6];
+  __shared__ int sB[14], sq[14], sstart[15], snseg;
+  const int A = blockIdx.x, lane = threadIdx.x;
+  const int fa = first[A], na = count[A];
+  if (na > 64) return;  // all of A's pairs go to the large-leaf kernel
+  if (lane == 0) {
+    int ns = 0, tot = 0;
+    for (int q = 13; q < 27; ++q) {
+      const int B = nbr[(int64_t)A * 27 + q];
+      if (B < 0 || count[B] > 64) continue;
+      sB[ns] = B;
+      sq[ns] = q;
+      sstart[ns] = tot;
+      tot += q == 13 ? na * (na - 1) / 2 : na * count[B];
+      ++ns;
+    }
+    sstart[ns] = tot;
+    snseg = ns;
+  }
+  for (int e = lane; e < 64 * 6; e += NT) accA[e] = cmpA[e] = accB[e] = cmpB[e] = T(0);
+  __syncthreads();
+  const int nseg = snseg, total = sstart[nseg];
+  // the self pairs (slot 13, when present) come first; row i of them holds
+  // (i, i+1 .. na-1) and starts at pair row0(i)
+  const bool has_self = nseg > 0 && sq[0] == 13;
+  const int nself = has_self ? sstart[1] : 0;
+  auto row0 = [&](int i) { return i * na - i * (i + 1) / 2; };
+  int ic = 0, rlo = 0, rhi = 0;
+  int sflush = 0;  // segments before sflush have been written
+  // writes segment s's partials (the lanes own the same items as in the sums)
+  // and clears the sums for the next segment
+  auto flush = [&](int s) {
+    const int q = sq[s], B = sB[s], fb = first[B], nb = count[B];
+    const bool self = q == 13;
+    for (int w = lane; w < na * 6; w += NT) {
+      double v = (double)accA[w] - (double)cmpA[w];
+      if (self) v += (double)accB[w] - (double)cmpB[w];
+      part[((int64_t)(fa + w / 6) * 27 + q) * 6 + w % 6] = (T)v;
+      accA[w] = cmpA[w] = T(0);
+      if (self) accB[w] = cmpB[w] = T(0);
+    }
+    if (!self)
+      for (int w = lane; w < nb * 6; w += NT) {
+        part[((int64_t)(fb + w / 6) * 27 + (26 - q)) * 6 + w % 6] = (T)((double)accB[w] - (double)cmpB[w]);
+        accB[w] = cmpB[w] = T(0);
+      }
+  };
+  for (int p0 = 0; p0 < total; p0 += NT) {
+    const int p = p0 + lane, pend = min(p0 + NT, total);
+    T fi[6] = {0, 0, 0, 0, 0, 0}, fj[6] = {0, 0, 0, 0, 0, 0};
+    if (p < total) {
+      int s = 0;
+      while (s + 1 < nseg && sstart[s + 1] <= p) ++s;
+      const int pl = p - sstart[s];
+      int i, j, fb;
+      if (sq[s] == 13) {
+        while (ic + 1 < na && row0(ic + 1) <= pl) ++ic;
+        i = ic;
+        j = i + 1 + (pl - row0(i));
+        fb = fa;
+      } else {
+        const int nb = count[sB[s]];
+        i = pl / nb;
+        j = pl - i * nb;
+        fb = first[sB[s]];
+      }
+      const int64_t gi = fa + i, gj = fb + j;
+      const double d0 = pts[gi] - pts[gj], d1 = pts[N + gi] - pts[N + gj], d2 = pts[2 * N + gi] - pts[2 * N + gj];
+      if (!MIXED || d0 * d0 + d1 * d1 + d2 * d2 >= a2x4) {
+        T D[27], bj[3], tj[3], bi[3], ti[3];
+        for (int c = 0; c < 3; ++c) {
+          bj[c] = (T)pts[(3 + c) * N + gj], tj[c] = (T)pts[(6 + c) * N + gj];
+          bi[c] = (T)pts[(3 + c) * N + gi], ti[c] = (T)pts[(6 + c) * N + gi];
+        }
+        dg_medium_t<T, false>((T)d0, (T)d1, (T)d2, m, D);
+        contract_b_t<T>(D, m.c12, m.c44, m.hh, bj, tj, fi);
+        contract_b_t<T>(D, m.c12, m.c44, m.hh, bi, ti, fj);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      vij[lane * 6 + c] = fi[c];
+      vji[lane * 6 + c] = -fj[c];  // dG(x_j - x_i) = -dG(x_i - x_j)
+    }
+    // rows of the round's first and last self pairs
+    if (p0 < nself) {
+      while (rlo + 1 < na && row0(rlo + 1) <= p0) ++rlo;
+      const int plast = min(pend, nself) - 1;
+      while (rhi + 1 < na && row0(rhi + 1) <= plast) ++rhi;
+    }
+    __syncthreads();
+    // each segment met by the round: its sums as with one wave per leaf pair
+    // (pair indices local to the segment), then its partials once it ends
+    for (int s = sflush; s < nseg && sstart[s] < pend; ++s) {
+      const int q = sq[s], s0 = sstart[s], s1 = sstart[s + 1];
+      const int lo = max(p0, s0) - s0, hi = min(pend, s1) - s0;  // local pairs of this round
+      const int off = s0 - p0;                                    // local pair r is vij[(r + off) * 6]
+      const bool self = q == 13;
+      const int nb = self ? na : count[sB[s]];
+      for (int w = lane; w < na * 6; w += NT) {  // A's target ii: one run of consecutive pairs
+        const int ii = w / 6, c = w - ii * 6;
+        const int r0 = self ? row0(ii) : ii * nb, len = self ? na - 1 - ii : nb;
+        const int a = max(r0, lo), b = min(r0 + len, hi);
+        if (a >= b) continue;
+        T sa = accA[w], ca = cmpA[w];
+        for (int r = a; r < b; ++r) kadd(sa, ca, vij[(r + off) * 6 + c]);
+        accA[w] = sa;
+        cmpA[w] = ca;
+      }
+      if (self) {
+        for (int w = lane; w < na * 6; w += NT) {  // B's target jj: pairs (i, jj), i < jj, in order of i
+          const int jj = w / 6, c = w - jj * 6;
+          const int iend = min(rhi, jj - 1);
+          if (rlo > iend) continue;
+          T sb = accB[w], cb = cmpB[w];
+          for (int i = rlo; i <= iend; ++i) {
+            const int r = row0(i) + jj - i - 1;
+            if (r >= lo && r < hi) kadd(sb, cb, vji[(r + off) * 6 + c]);
+          }
+          accB[w] = sb;
+          cmpB[w] = cb;
+        }
+      } else {
+        for (int w = lane; w < nb * 6; w += NT) {  // B's target jj: local pairs r with r % nb == jj, in order
+          const int jj = w / 6, c = w - jj * 6;
+          const int r0 = lo + ((jj - lo % nb) % nb + nb) % nb;
+          if (r0 >= hi) continue;
+          T sb = accB[w], cb = cmpB[w];
+          for (int r = r0; r < hi; r += nb) kadd(sb, cb, vji[(r + off) * 6 + c]);
+          accB[w] = sb;
+          cmpB[w] = cb;
+        }
+      }
+      if (s1 <= pend) {
+        flush(s);
+        sflush = s + 1;
+      }
+    }
+    __syncthreads();
+  }
+  // segments without pairs (the self pairs of a leaf with one point)
+  for (int s = sflush; s < nseg; ++s) flush(s);
+}
+
 // Near-field stress of each point: its 27 neighbour-slot partials in slot
 // order (slots of absent neighbour leaves are skipped).
 template <typename T>
@@ -1742,8 +1899,8 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
         STAGE(6, (k_leaf<T, true, true><<<(unsigned)LD.n, 64, 0, nst>>>(LEAF_ARGS)));
       else if (t->part) {
         const double a2x4 = 4.0 * m64.a * m64.a;
-        STAGE(6, (k_leaf_sym<T, true, false><<<dim3((unsigned)LD.n, 14), sym_threads<T, false>(), sym_lds<T, false>(64), nst>>>(
-                     t->pts, N, LD.first, LD.count, t->nbr, m, a2x4, 64, (T*)t->part, nullptr)));
+        STAGE(6, (k_leaf_sym_run<T, true><<<(unsigned)LD.n, 64, 0, nst>>>(t->pts, N, LD.first, LD.count, t->nbr, m,
+                                                                         a2x4, (T*)t->part)));
         if (t->nbig > 0)
           STAGE(6, (k_leaf_sym<T, true, true><<<(unsigned)t->nbig, sym_threads<T, true>(), sym_lds<T, true>(t->max_leaf_pts), nst>>>(
                        t->pts, N, LD.first, LD.count, t->nbr, m, a2x4, t->max_leaf_pts, (T*)t->part, t->bigp)));
@@ -1767,8 +1924,8 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
       } else if (pl->iso) {
         STAGE(6, (k_leaf<T, false, true><<<(unsigned)LD.n, 64, 0, nst>>>(LEAF_ARGS)));
       } else if (t->part) {
-        STAGE(6, (k_leaf_sym<T, false, false><<<dim3((unsigned)LD.n, 14), sym_threads<T, false>(), sym_lds<T, false>(64), nst>>>(
-                     t->pts, N, LD.first, LD.count, t->nbr, m, 0.0, 64, (T*)t->part, nullptr)));
+        STAGE(6, (k_leaf_sym_run<T, false><<<(unsigned)LD.n, 64, 0, nst>>>(t->pts, N, LD.first, LD.count, t->nbr, m,
+                                                                          0.0, (T*)t->part)));
         if (t->nbig > 0)
           STAGE(6, (k_leaf_sym<T, false, true><<<(unsigned)t->nbig, sym_threads<T, true>(), sym_lds<T, true>(t->max_leaf_pts), nst>>>(
                        t->pts, N, LD.first, LD.count, t->nbr, m, 0.0, t->max_leaf_pts, (T*)t->part, t->bigp)));
