@@ -330,29 +330,35 @@ __device__ __forceinline__ void dft_line_pairs(const cplx<T>* x, const T* c, con
 }
 
 // Only the frequencies with first index f1 in [fa, fb) are stored, at f - fa n P
-// (the spectrum in chunks along the first axis, for large trees).
-template <typename T, int P, bool H16>
-__global__ void __launch_bounds__(kDftThreads) k_fdft(const T* __restrict__ W, int64_t ncell, int G,
-                                              const T* __restrict__ twg, cplx<T>* __restrict__ What,
-                                              const unsigned* __restrict__ wmax, int fa, int fb) {
+// (the spectrum in chunks along the first axis, for large trees).  A block
+// takes CPB consecutive cells (CPB threads per 512): the rows of one frequency
+// of neighbouring cells are neighbours in What, so the last pass writes CPB
+// rows in one piece.
+template <typename T, int P, bool H16, int CPB>
+__global__ void __launch_bounds__(kDftThreads * CPB) k_fdft(const T* __restrict__ W, int64_t ncell, int G,
+                                                    const T* __restrict__ twg, cplx<T>* __restrict__ What,
+                                                    const unsigned* __restrict__ wmax, int fa, int fb) {
   constexpr int n = 2 * P - 1, p3 = P * P * P;
   extern __shared__ __align__(16) unsigned char shraw[];
-  cplx<T>* X1 = (cplx<T>*)shraw;  // [G][P][P][P]  (g, m1, m2, f3)
-  cplx<T>* X2 = X1 + G * p3;      // [G][P][n][P]  (g, m1, f2, f3)
+  cplx<T>* X1 = (cplx<T>*)shraw;       // [CPB][G][P][P][P]  (q, g, m1, m2, f3)
+  cplx<T>* X2 = X1 + CPB * G * p3;     // [CPB][G][P][n][P]  (q, g, m1, f2, f3)
   T c[n], s[n];
 #pragma unroll
   for (int k = 0; k < n; ++k) {
     c[k] = twg[2 * k];
     s[k] = twg[2 * k + 1];
   }
-  const int64_t cell = xcd_block(blockIdx.x, ncell);
+  const int64_t cell0 = CPB * xcd_block(blockIdx.x, (ncell + CPB - 1) / CPB);
+  const int nq = (int)min<int64_t>(CPB, ncell - cell0);  // cells of this block
+  const int L1 = G * P * P, L3 = G * n * P;           // lines per cell of passes 1-2 and 3
   for (int c0 = 0; c0 < 9; c0 += G) {
-    const T* src = W + (cell * 9 + c0) * p3;
     // along the last axis: P real values -> P half-spectrum values
-    for (int it = threadIdx.x; it < G * P * P; it += blockDim.x) {
+    for (int it = threadIdx.x; it < nq * L1; it += blockDim.x) {
+      const int q = it / L1, l = it % L1;
+      const T* src = W + ((cell0 + q) * 9 + c0) * p3 + l * P;
       T x[P];
 #pragma unroll
-      for (int m = 0; m < P; ++m) x[m] = src[it * P + m];
+      for (int m = 0; m < P; ++m) x[m] = src[m];
 #pragma unroll
       for (int f = 0; f < P; ++f) {
         T re = 0, im = 0;
@@ -366,8 +372,8 @@ __global__ void __launch_bounds__(kDftThreads) k_fdft(const T* __restrict__ W, i
     }
     __syncthreads();
     // along the middle axis: P -> n
-    for (int it = threadIdx.x; it < G * P * P; it += blockDim.x) {
-      const int f3 = it % P, gm = it / P;
+    for (int it = threadIdx.x; it < nq * L1; it += blockDim.x) {
+      const int f3 = it % P, gm = it / P;  // gm = (q G + g) P + m1
       cplx<T> x[P];
 #pragma unroll
       for (int m = 0; m < P; ++m) x[m] = X1[(gm * P + m) * P + f3];
@@ -375,12 +381,15 @@ __global__ void __launch_bounds__(kDftThreads) k_fdft(const T* __restrict__ W, i
     }
     __syncthreads();
     // along the first axis: P -> n, into What (the G components of a
-    // frequency are neighbours in memory, so they are neighbouring lanes)
-    for (int it = threadIdx.x; it < G * n * P; it += blockDim.x) {
-      const int g = it % G, r = it / G;  // r = f2 P + f3
+    // frequency, then the cells, are neighbours in memory, so they are
+    // neighbouring lanes)
+    for (int it = threadIdx.x; it < nq * L3; it += blockDim.x) {
+      const int g = it % G, q = (it / G) % nq, r = it / (G * nq);  // r = f2 P + f3
+      const cplx<T>* x2 = X2 + (q * G + g) * P * n * P + r;
+      const int64_t cell = cell0 + q;
       cplx<T> x[P];
 #pragma unroll
-      for (int m = 0; m < P; ++m) x[m] = X2[(g * P + m) * n * P + r];
+      for (int m = 0; m < P; ++m) x[m] = x2[m * n * P];
       if constexpr (H16) {
         const float sw = h16_wscale(wmax, p3);
         uint32_t* W16 = reinterpret_cast<uint32_t*>(What);
@@ -402,6 +411,11 @@ __global__ void __launch_bounds__(kDftThreads) k_fdft(const T* __restrict__ W, i
 template <int P>
 constexpr size_t lds_fdft_t(int G, size_t es) {
   return 2 * es * (size_t)G * (P * P * P + P * (2 * P - 1) * P);
+}
+// cells per block of the forward DFT: two where their LDS fits (G = 9)
+template <typename T, int P>
+constexpr int fdft_cpb() {
+  return 2 * lds_fdft_t<P>(9, sizeof(T)) <= 160 * 1024 ? 2 : 1;
 }
 
 // ------------------------------------------------------ Hadamard product
@@ -1722,12 +1736,14 @@ template <typename T, int P>
 static void dft_launch(bool fwd, unsigned blocks, const void* in, int64_t ncell, const T* tw, void* out,
                        const unsigned* wmax, float kscale, int fa, int fb, int acc, hipStream_t st) {
   const int G = dft_groups<T, P>(fwd);
+  constexpr int C = fdft_cpb<T, P>();
+  const unsigned fblocks = (unsigned)((blocks + C - 1) / C);
   if (fwd && wmax)
-    k_fdft<T, P, true><<<blocks, kDftThreads, lds_fdft_t<P>(G, sizeof(T)), st>>>((const T*)in, ncell, G, tw,
-                                                                               (cplx<T>*)out, wmax, fa, fb);
+    k_fdft<T, P, true, C><<<fblocks, kDftThreads * C, C * lds_fdft_t<P>(G, sizeof(T)), st>>>(
+        (const T*)in, ncell, G, tw, (cplx<T>*)out, wmax, fa, fb);
   else if (fwd)
-    k_fdft<T, P, false><<<blocks, kDftThreads, lds_fdft_t<P>(G, sizeof(T)), st>>>((const T*)in, ncell, G, tw,
-                                                                                (cplx<T>*)out, nullptr, fa, fb);
+    k_fdft<T, P, false, C><<<fblocks, kDftThreads * C, C * lds_fdft_t<P>(G, sizeof(T)), st>>>(
+        (const T*)in, ncell, G, tw, (cplx<T>*)out, nullptr, fa, fb);
   else
     k_idft<T, P><<<blocks, kDftThreads, lds_idft_t<P>(sizeof(T)), st>>>((const cplx<T>*)in, ncell, tw, (T*)out,
                                                                          wmax, kscale, fa, fb, acc);
@@ -1794,8 +1810,10 @@ static void project(int p, unsigned blocks, T* data, int ncomp, const T* Pm, hip
 template <typename T, int... Ps>
 static void dft_lds_attrs(std::integer_sequence<int, Ps...>) {
   const int mx = 160 * 1024;
-  ((void)hipFuncSetAttribute((const void*)k_fdft<T, Ps + 2, false>, hipFuncAttributeMaxDynamicSharedMemorySize, mx), ...);
-  ((void)hipFuncSetAttribute((const void*)k_fdft<T, Ps + 2, true>, hipFuncAttributeMaxDynamicSharedMemorySize, mx), ...);
+  ((void)hipFuncSetAttribute((const void*)k_fdft<T, Ps + 2, false, fdft_cpb<T, Ps + 2>()>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, mx), ...);
+  ((void)hipFuncSetAttribute((const void*)k_fdft<T, Ps + 2, true, fdft_cpb<T, Ps + 2>()>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, mx), ...);
   ((void)hipFuncSetAttribute((const void*)k_idft<T, Ps + 2>, hipFuncAttributeMaxDynamicSharedMemorySize, mx), ...);
   ((void)hipFuncSetAttribute((const void*)k_m2m<T, Ps + 2>, hipFuncAttributeMaxDynamicSharedMemorySize, mx), ...);
   ((void)hipFuncSetAttribute((const void*)k_l2l<T, Ps + 2>, hipFuncAttributeMaxDynamicSharedMemorySize, mx), ...);
