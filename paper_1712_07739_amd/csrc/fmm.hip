@@ -902,41 +902,41 @@ __device__ __forceinline__ void idft_line_pairs(const cplx<T>* x, const T* c, co
 // the Hadamard product's stores land together, which gains more than these
 // reads cost).  The last pass uses the Hermitian symmetry of the last axis
 // (f3 = 0 once, f3 > 0 twice, real part).
-template <typename T, int P>
-// With the spectrum in chunks: Shat holds the frequencies with first index
-// f1 in [fa, fb) (the others count as zero, the transform being linear), and
-// acc adds the result to s instead of writing it.
-__global__ void __launch_bounds__(kDftThreads) k_idft(const cplx<T>* __restrict__ Shat, int64_t ncell,
-                                              const T* __restrict__ twg, T* __restrict__ s,
-                                              const unsigned* __restrict__ wmax, float kscale, int fa, int fb,
-                                              int acc_out) {
+template <typename T, int P, int CPB>
+__global__ void __launch_bounds__(kDftThreads * CPB) k_idft(const cplx<T>* __restrict__ Shat, int64_t ncell,
+                                                    const T* __restrict__ twg, T* __restrict__ s,
+                                                    const unsigned* __restrict__ wmax, float kscale, int fa, int fb,
+                                                    int acc_out) {
   constexpr int n = 2 * P - 1, p3 = P * P * P, nf = n * n * P;
   extern __shared__ __align__(16) unsigned char shraw[];
-  cplx<T>* Y1 = (cplx<T>*)shraw;     // [6][n(f2)][P(f3)][P(l1)]
-  cplx<T>* Y2 = Y1 + 6 * n * P * P;  // [6][P(f3)][P(l1)][P(l2)]
+  cplx<T>* Y1 = (cplx<T>*)shraw;           // [CPB][6][n(f2)][P(f3)][P(l1)]
+  cplx<T>* Y2 = Y1 + CPB * 6 * n * P * P;  // [CPB][6][P(f3)][P(l1)][P(l2)]
   T c[n], sn[n];  // exp(+2 pi i k / n) = c[k] + i sn[k]
 #pragma unroll
   for (int k = 0; k < n; ++k) {
     c[k] = twg[2 * k];
     sn[k] = -twg[2 * k + 1];
   }
-  const int64_t cell = xcd_block(blockIdx.x, ncell);
+  const int64_t cell0 = CPB * xcd_block(blockIdx.x, (ncell + CPB - 1) / CPB);
+  const int nq = (int)min<int64_t>(CPB, ncell - cell0);  // cells of this block
   // the f16 product's spectra carry the operator and source scales
   const T scale = wmax ? T(1) / (T(n * n * n) * (T)kscale * (T)h16_wscale(wmax, p3)) : T(1) / T(n * n * n);
-  const cplx<T>* src = Shat + cell * 6;
-  // along the first axis: n -> P
-  for (int it = threadIdx.x; it < 6 * n * P; it += blockDim.x) {
-    const int g = it % 6, r = it / 6;  // r = f2 P + f3
+  const cplx<T>* src = Shat + cell0 * 6;
+  // along the first axis: n -> P (lanes over component, then cell, then
+  // line: the rows of one frequency of neighbouring cells are neighbours)
+  for (int it = threadIdx.x; it < nq * 6 * n * P; it += blockDim.x) {
+    const int g = it % 6, q = (it / 6) % nq, r = it / (6 * nq);  // r = f2 P + f3
     cplx<T> x[n];
 #pragma unroll
     for (int f = 0; f < n; ++f)
-      x[f] = (f >= fa && f < fb) ? src[(int64_t)((f - fa) * n * P + r) * ncell * 6 + g] : cplx<T>{T(0), T(0)};
-    idft_line_pairs<T, P>(x, c, sn, [&](int l, cplx<T> v) { Y1[(g * n * P + r) * P + l] = v; });
+      x[f] = (f >= fa && f < fb) ? src[(int64_t)((f - fa) * n * P + r) * ncell * 6 + 6 * q + g]
+                                 : cplx<T>{T(0), T(0)};
+    idft_line_pairs<T, P>(x, c, sn, [&](int l, cplx<T> v) { Y1[((q * 6 + g) * n * P + r) * P + l] = v; });
   }
   __syncthreads();
   // along the middle axis: n -> P
-  for (int it = threadIdx.x; it < 6 * P * P; it += blockDim.x) {
-    const int l1 = it % P, f3 = (it / P) % P, g = it / (P * P);
+  for (int it = threadIdx.x; it < nq * 6 * P * P; it += blockDim.x) {
+    const int l1 = it % P, f3 = (it / P) % P, g = it / (P * P);  // g = q 6 + component
     cplx<T> x[n];
 #pragma unroll
     for (int f = 0; f < n; ++f) x[f] = Y1[((g * n + f) * P + f3) * P + l1];
@@ -944,12 +944,12 @@ __global__ void __launch_bounds__(kDftThreads) k_idft(const cplx<T>* __restrict_
   }
   __syncthreads();
   // along the last axis: half spectrum (P) -> P real outputs
-  for (int it = threadIdx.x; it < 6 * P * P; it += blockDim.x) {
-    const int l2 = it % P, l1 = (it / P) % P, g = it / (P * P);
+  for (int it = threadIdx.x; it < nq * 6 * P * P; it += blockDim.x) {
+    const int l2 = it % P, l1 = (it / P) % P, g = it / (P * P);  // g = q 6 + component
     cplx<T> x[P];
 #pragma unroll
     for (int f = 0; f < P; ++f) x[f] = Y2[((g * P + f) * P + l1) * P + l2];
-    T* out = s + (cell * 6 + g) * p3 + (l1 * P + l2) * P;
+    T* out = s + (cell0 * 6 + g) * p3 + (l1 * P + l2) * P;
 #pragma unroll
     for (int l = 0; l < P; ++l) {
       T acc = 0;
@@ -964,6 +964,11 @@ __global__ void __launch_bounds__(kDftThreads) k_idft(const cplx<T>* __restrict_
 template <int P>
 constexpr size_t lds_idft_t(size_t es) {
   return 2 * es * ((size_t)6 * (2 * P - 1) * P * P + (size_t)6 * P * P * P);
+}
+// cells per block of the inverse DFT
+template <typename T, int P>
+constexpr int idft_cpb() {
+  return 2 * lds_idft_t<P>(sizeof(T)) <= 160 * 1024 ? 2 : 1;
 }
 
 // ------------------------------------------------ near field + L2P (leaf)
@@ -1745,8 +1750,11 @@ static void dft_launch(bool fwd, unsigned blocks, const void* in, int64_t ncell,
     k_fdft<T, P, false, C><<<fblocks, kDftThreads * C, C * lds_fdft_t<P>(G, sizeof(T)), st>>>(
         (const T*)in, ncell, G, tw, (cplx<T>*)out, nullptr, fa, fb);
   else
-    k_idft<T, P><<<blocks, kDftThreads, lds_idft_t<P>(sizeof(T)), st>>>((const cplx<T>*)in, ncell, tw, (T*)out,
-                                                                         wmax, kscale, fa, fb, acc);
+  {
+    constexpr int C = idft_cpb<T, P>();
+    k_idft<T, P, C><<<(unsigned)((blocks + C - 1) / C), kDftThreads * C, C * lds_idft_t<P>(sizeof(T)), st>>>(
+        (const cplx<T>*)in, ncell, tw, (T*)out, wmax, kscale, fa, fb, acc);
+  }
 }
 
 // fa, fb: the chunk of first frequency indices (0, n for the whole
@@ -1814,7 +1822,8 @@ static void dft_lds_attrs(std::integer_sequence<int, Ps...>) {
                              hipFuncAttributeMaxDynamicSharedMemorySize, mx), ...);
   ((void)hipFuncSetAttribute((const void*)k_fdft<T, Ps + 2, true, fdft_cpb<T, Ps + 2>()>,
                              hipFuncAttributeMaxDynamicSharedMemorySize, mx), ...);
-  ((void)hipFuncSetAttribute((const void*)k_idft<T, Ps + 2>, hipFuncAttributeMaxDynamicSharedMemorySize, mx), ...);
+  ((void)hipFuncSetAttribute((const void*)k_idft<T, Ps + 2, idft_cpb<T, Ps + 2>()>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, mx), ...);
   ((void)hipFuncSetAttribute((const void*)k_m2m<T, Ps + 2>, hipFuncAttributeMaxDynamicSharedMemorySize, mx), ...);
   ((void)hipFuncSetAttribute((const void*)k_l2l<T, Ps + 2>, hipFuncAttributeMaxDynamicSharedMemorySize, mx), ...);
   ((void)hipFuncSetAttribute((const void*)k_project<T, Ps + 2>, hipFuncAttributeMaxDynamicSharedMemorySize, mx), ...);
