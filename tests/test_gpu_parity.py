@@ -469,6 +469,25 @@ def test_fmm_f16_m2l_matches_oracle_fmm(env, name, C, nloops, p, D, mode):
     assert np.array_equal(f16, pk.fmm_forces(plan, tree, ts, tb).cpu().numpy())
 
 
+@pytest.mark.parametrize("name,C,nloops,seed", [("iso", ISO, 10, 17), ("cubic", CUB, 6, 19)])
+def test_single_precision_dfts_on_levels_of_both_parities(env, name, C, nloops, seed):
+    """In single precision the forward and inverse DFTs take two consecutive
+    cells per block, so on a level with an odd number of cells the last block
+    holds one.  These trees (p = 7, depth 3) have levels of both parities
+    (checked), and the f32 and f16 paths match the oracle's FMM on them at the
+    bars of the tests above."""
+    seg, b = synth.make_loops(nloops, 0.01, 0.05, seed)
+    med = oracle.medium(*C, 1e-3)
+    ref, ref_far, _ = oracle.fmm_forces(seg, b, med, 7, 3, BOX_LO, BOX, return_parts=True)
+    share = float(np.linalg.norm(ref_far) / np.linalg.norm(ref))
+    f32, _, tree = run_fmm(env, seg, b, C, 7, 3, precision=1)
+    cells = [lv["cells"] for lv in tree.info()["levels"]]
+    assert {n % 2 for n in cells} == {0, 1}, cells
+    assert oracle.rel_err(f32, ref) <= 2e-5, name
+    f16, _, _ = run_fmm(env, seg, b, C, 7, 3, precision=2)
+    assert oracle.rel_err(f16, ref) <= 2e-5 + 2 * F16_U * share, name
+
+
 def test_full_size_f16_m2l_vs_oracle_samples(env):
     """The 1M-segment cubic workload with f16 operands in the M2L at p = 7:
     the force error against the oracle's direct sum on the 64 golden
