@@ -157,8 +157,9 @@ __device__ __forceinline__ void pass_axis(const T* in, T* out, const T* __restri
 
 // M2M: one block per parent cell; the children's W (next finer level) are
 // anterpolated onto the parent's nodes one child at a time.
+constexpr int kM2mThreads = 512;  // 9 P^2 lines a pass: one round up to P = 7
 template <typename T, int P>
-__global__ void k_m2m(const int* first, const int* count, const uint32_t* ckey, const T* Wc, T* Wp,
+__global__ void __launch_bounds__(kM2mThreads) k_m2m(const int* first, const int* count, const uint32_t* ckey, const T* Wc, T* Wp,
                       const T* __restrict__ Sg) {
   extern __shared__ unsigned char shraw[];
   constexpr int p3 = P * P * P;
@@ -168,10 +169,27 @@ __global__ void k_m2m(const int* first, const int* count, const uint32_t* ckey, 
   for (int e = threadIdx.x; e < 9 * p3; e += blockDim.x) C[e] = T(0);
   const int par = blockIdx.x;
   const int c0 = first[par], nc = count[par];
+  // a thread's share of a child's 9 P^3 values, the next child's loaded while
+  // the current one is transformed
+  constexpr int kM2mVals = (9 * p3 + kM2mThreads - 1) / kM2mThreads;
+  T nx[kM2mVals];
+  auto load = [&](int c) {
+    const T* src = Wc + (int64_t)c * 9 * p3;
+#pragma unroll
+    for (int k = 0; k < kM2mVals; ++k) {
+      const int e = threadIdx.x + k * kM2mThreads;
+      if (e < 9 * p3) nx[k] = src[e];
+    }
+  };
+  if (nc > 0) load(c0);
   for (int c = c0; c < c0 + nc; ++c) {
     const uint32_t bits = ckey[c] & 7;
-    const T* src = Wc + (int64_t)c * 9 * p3;
-    for (int e = threadIdx.x; e < 9 * p3; e += blockDim.x) A[e] = src[e];
+#pragma unroll
+    for (int k = 0; k < kM2mVals; ++k) {
+      const int e = threadIdx.x + k * kM2mThreads;
+      if (e < 9 * p3) A[e] = nx[k];
+    }
+    if (c + 1 < c0 + nc) load(c + 1);
     __syncthreads();
     pass_axis<T, false, false, P, 2>(A, B, Sg, bits & 1, 9);
     __syncthreads();
@@ -1780,7 +1798,7 @@ template <typename T, int P>
 static void tree_pass_p(bool up, unsigned blocks, size_t shm, const int* a, const int* b, const uint32_t* key,
                         const T* in, T* out, const T* S, hipStream_t st) {
   if (up)
-    k_m2m<T, P><<<blocks, 512, shm, st>>>(a, b, key, in, out, S);  // 9 P^2 lines a pass: one round up to P = 7
+    k_m2m<T, P><<<blocks, kM2mThreads, shm, st>>>(a, b, key, in, out, S);
   else
     k_l2l<T, P><<<blocks, 256, shm, st>>>(a, key, in, out, S);
 }
