@@ -75,12 +75,33 @@ __device__ __forceinline__ void cell_lo(uint32_t key, double lo0, double lo1, do
   }
 }
 
+// The largest |v| over a block's threads folded into *wmax (the bits of a
+// non-negative float, whose order as unsigned integers is the float order);
+// every thread of the block calls it.  The running value is read first and
+// the atomic issued only above it: it only grows, so a stale read costs at
+// most a needless atomic, and the blocks of a level do not all queue on one
+// address.
+__device__ __forceinline__ void block_absmax(float m, unsigned* wmax) {
+  __shared__ float red[16];
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float r = red[0];
+    for (int w = 1; w < (int)((blockDim.x + 63) >> 6); ++w) r = fmaxf(r, red[w]);
+    const unsigned u = __float_as_uint(r);
+    if (u > __hip_atomic_load(wmax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(wmax, u);
+  }
+}
+
 // ------------------------------------------------------------------- P2M
 // One block per leaf; thread = node m.  Points are staged in LDS in chunks of
-// 64 with their 1D basis values and 9-component strengths b (x) t.
+// 64 with their 1D basis values and 9-component strengths b (x) t.  wmax
+// (f16 path, or null): the level's largest |W| is folded in.
 template <typename T>
 __global__ void k_p2m(const double* pts, int64_t N, const int* first, const int* count, const uint32_t* key,
-                      double lo0, double lo1, double lo2, double sD, int p, T* W, const int* cell) {
+                      double lo0, double lo1, double lo2, double sD, int p, T* W, const int* cell,
+                      unsigned* wmax) {
   extern __shared__ unsigned char shraw[];
   T* Lb = (T*)shraw;          // [64][3][p]
   T* qs = Lb + 64 * 3 * p;    // [64][9]
@@ -117,11 +138,16 @@ __global__ void k_p2m(const double* pts, int64_t N, const int* first, const int*
     }
     __syncthreads();
   }
+  float am = 0.f;
   if (tid < p3) {
     T* out = W + (int64_t)leaf * 9 * p3;
 #pragma unroll
-    for (int c = 0; c < 9; ++c) out[c * p3 + tid] = acc[c];
+    for (int c = 0; c < 9; ++c) {
+      out[c * p3 + tid] = acc[c];
+      am = fmaxf(am, fabsf((float)acc[c]));
+    }
   }
+  if (wmax) block_absmax(am, wmax);
 }
 
 // ------------------------------------------------------- separable passes
@@ -156,11 +182,12 @@ __device__ __forceinline__ void pass_axis(const T* in, T* out, const T* __restri
 }
 
 // M2M: one block per parent cell; the children's W (next finer level) are
-// anterpolated onto the parent's nodes one child at a time.
+// anterpolated onto the parent's nodes one child at a time.  wmax (f16 path,
+// or null): the parent level's largest |W| is folded in.
 constexpr int kM2mThreads = 512;  // 9 P^2 lines a pass: one round up to P = 7
 template <typename T, int P>
 __global__ void __launch_bounds__(kM2mThreads) k_m2m(const int* first, const int* count, const uint32_t* ckey, const T* Wc, T* Wp,
-                      const T* __restrict__ Sg) {
+                      const T* __restrict__ Sg, unsigned* wmax) {
   extern __shared__ unsigned char shraw[];
   constexpr int p3 = P * P * P;
   T* A = (T*)shraw;
@@ -199,7 +226,12 @@ __global__ void __launch_bounds__(kM2mThreads) k_m2m(const int* first, const int
     __syncthreads();
   }
   T* dst = Wp + (int64_t)par * 9 * p3;
-  for (int e = threadIdx.x; e < 9 * p3; e += blockDim.x) dst[e] = C[e];
+  float am = 0.f;
+  for (int e = threadIdx.x; e < 9 * p3; e += blockDim.x) {
+    dst[e] = C[e];
+    am = fmaxf(am, fabsf((float)C[e]));
+  }
+  if (wmax) block_absmax(am, wmax);
 }
 
 // L2L: one block per child cell; adds the parent's interpolated local values.
@@ -1796,24 +1828,24 @@ static void dft(int p, bool fwd, unsigned blocks, const void* in, int64_t ncell,
 // index of each child (b unused).
 template <typename T, int P>
 static void tree_pass_p(bool up, unsigned blocks, size_t shm, const int* a, const int* b, const uint32_t* key,
-                        const T* in, T* out, const T* S, hipStream_t st) {
+                        const T* in, T* out, const T* S, unsigned* wmax, hipStream_t st) {
   if (up)
-    k_m2m<T, P><<<blocks, kM2mThreads, shm, st>>>(a, b, key, in, out, S);
+    k_m2m<T, P><<<blocks, kM2mThreads, shm, st>>>(a, b, key, in, out, S, wmax);
   else
     k_l2l<T, P><<<blocks, 256, shm, st>>>(a, key, in, out, S);
 }
 
 template <typename T>
 static void tree_pass(int p, bool up, unsigned blocks, size_t shm, const int* a, const int* b, const uint32_t* key,
-                      const T* in, T* out, const T* S, hipStream_t st) {
+                      const T* in, T* out, const T* S, unsigned* wmax, hipStream_t st) {
   switch (p) {
-    case 2: tree_pass_p<T, 2>(up, blocks, shm, a, b, key, in, out, S, st); break;
-    case 3: tree_pass_p<T, 3>(up, blocks, shm, a, b, key, in, out, S, st); break;
-    case 4: tree_pass_p<T, 4>(up, blocks, shm, a, b, key, in, out, S, st); break;
-    case 5: tree_pass_p<T, 5>(up, blocks, shm, a, b, key, in, out, S, st); break;
-    case 6: tree_pass_p<T, 6>(up, blocks, shm, a, b, key, in, out, S, st); break;
-    case 7: tree_pass_p<T, 7>(up, blocks, shm, a, b, key, in, out, S, st); break;
-    default: tree_pass_p<T, 8>(up, blocks, shm, a, b, key, in, out, S, st); break;
+    case 2: tree_pass_p<T, 2>(up, blocks, shm, a, b, key, in, out, S, wmax, st); break;
+    case 3: tree_pass_p<T, 3>(up, blocks, shm, a, b, key, in, out, S, wmax, st); break;
+    case 4: tree_pass_p<T, 4>(up, blocks, shm, a, b, key, in, out, S, wmax, st); break;
+    case 5: tree_pass_p<T, 5>(up, blocks, shm, a, b, key, in, out, S, wmax, st); break;
+    case 6: tree_pass_p<T, 6>(up, blocks, shm, a, b, key, in, out, S, wmax, st); break;
+    case 7: tree_pass_p<T, 7>(up, blocks, shm, a, b, key, in, out, S, wmax, st); break;
+    default: tree_pass_p<T, 8>(up, blocks, shm, a, b, key, in, out, S, wmax, st); break;
   }
 }
 
@@ -1842,7 +1874,9 @@ static void dft_lds_attrs(std::integer_sequence<int, Ps...>) {
                              hipFuncAttributeMaxDynamicSharedMemorySize, mx), ...);
   ((void)hipFuncSetAttribute((const void*)k_idft<T, Ps + 2, idft_cpb<T, Ps + 2>()>,
                              hipFuncAttributeMaxDynamicSharedMemorySize, mx), ...);
-  ((void)hipFuncSetAttribute((const void*)k_m2m<T, Ps + 2>, hipFuncAttributeMaxDynamicSharedMemorySize, mx), ...);
+  // k_m2m: its three buffers (it also has a small static array)
+  ((void)hipFuncSetAttribute((const void*)k_m2m<T, Ps + 2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)(sizeof(T) * 27 * (Ps + 2) * (Ps + 2) * (Ps + 2))), ...);
   ((void)hipFuncSetAttribute((const void*)k_l2l<T, Ps + 2>, hipFuncAttributeMaxDynamicSharedMemorySize, mx), ...);
   ((void)hipFuncSetAttribute((const void*)k_project<T, Ps + 2>, hipFuncAttributeMaxDynamicSharedMemorySize, mx), ...);
 }
@@ -1981,6 +2015,13 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
     }
 #undef LEAF_ARGS
   }
+  // DFMM_MIXED_F16: each level's largest |W|, for the f16 scale of its
+  // spectra, folded in by the kernels that write W (P2M, M2M); when the
+  // projection below changes W afterwards, taken by k_wmax once it has
+  const bool h16 = std::is_same<T, float>::value && pl->h16;
+  const bool wfuse = h16 && pl->lsq == 0;
+  if (wfuse) STAGE(0, (k_fill_uint<<<1, 64, 0, st>>>(t->wmax, D + 1, 0u)));
+  auto wm_of = [&](int l) { return wfuse ? t->wmax + l : nullptr; };
   const int p2m_bs = std::max(64, ((p3 + 63) / 64) * 64);
   const size_t p2m_shm = es * (64 * 3 * p + 64 * 9);
   // P2M of the leaves of level l of an adaptive tree (after that level's M2M,
@@ -1989,21 +2030,21 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
     if (t->leaf_n[l] > 0)
       k_p2m<T><<<(unsigned)t->leaf_n[l], p2m_bs, p2m_shm, st>>>(
           t->pts, N, t->gl_pf + t->leaf_off[l], t->gl_pc + t->leaf_off[l], t->gkey, lo[0], lo[1], lo[2],
-          L / std::ldexp(1.0, l), p, W, t->gl_cell + t->leaf_off[l]);
+          L / std::ldexp(1.0, l), p, W, t->gl_cell + t->leaf_off[l], wm_of(l));
   };
   if (t->adaptive)
     STAGE(0, p2m_level(D));
   else
     STAGE(0, (k_p2m<T><<<(unsigned)LD.n, p2m_bs, p2m_shm, st>>>(t->pts, N, LD.first, LD.count, LD.key, lo[0],
                                                                   lo[1], lo[2], sD, p, W + LD.off * 9 * p3,
-                                                                  nullptr)));
+                                                                  nullptr, wm_of(D))));
   {
     size_t shm = es * 27 * p3;
     for (int l = D - 1; l >= 2; --l) {
       const auto& Lc = t->lv[l + 1];
       const auto& Lp = t->lv[l];
       STAGE(1, tree_pass<T>(p, true, (unsigned)Lp.n, shm, Lp.first, Lp.count, Lc.key, W + Lc.off * 9 * p3,
-                               W + Lp.off * 9 * p3, tb.S, st));
+                               W + Lp.off * 9 * p3, tb.S, wm_of(l), st));
       if (t->adaptive) STAGE(1, p2m_level(l));
     }
   }
@@ -2012,9 +2053,7 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
   if (pl->lsq > 0)
     for (int l = 2; l <= D; ++l)
       if (t->lv[l].n > 0) STAGE(1, project<T>(p, (unsigned)t->lv[l].n, W + t->lv[l].off * 9 * p3, 9, tb.Pm, st));
-  // DFMM_MIXED_F16: each level's largest weight, for the f16 scale of its spectra
-  const bool h16 = std::is_same<T, float>::value && pl->h16;
-  if (h16) {
+  if (h16 && !wfuse) {
     STAGE(2, (k_fill_uint<<<1, 64, 0, st>>>(t->wmax, D + 1, 0u)));
     for (int l = 2; l <= D; ++l) {
       const auto& Lv = t->lv[l];
@@ -2080,7 +2119,7 @@ static int run_fmm(const dfmm_plan* pl, dfmm_tree* t, const double* seg, const d
       const auto& Lv = t->lv[l];
       const auto& Lp = t->lv[l - 1];
       STAGE(5, tree_pass<T>(p, false, (unsigned)Lv.n, shm, Lv.parent, nullptr, Lv.key, s + Lp.off * 6 * p3,
-                               s + Lv.off * 6 * p3, tb.S, st));
+                               s + Lv.off * 6 * p3, tb.S, nullptr, st));
       if (pl->lsq > 0 && Lv.n > 0) STAGE(5, project<T>(p, (unsigned)Lv.n, s + Lv.off * 6 * p3, 6, tb.Pm, st));
     }
   }
@@ -2114,7 +2153,10 @@ static void set_lds_attrs_once() {
   hipFuncSetAttribute((const void*)k_leaf_sym<T, sizeof(T) == 4, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                       mx);
   dft_lds_attrs<T>(std::make_integer_sequence<int, kMaxOrder - 1>{});
-  hipFuncSetAttribute((const void*)k_p2m<T>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+  // k_p2m: 64 points' basis values and strengths at the largest order (it
+  // also has a small static array)
+  hipFuncSetAttribute((const void*)k_p2m<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)(sizeof(T) * 64 * (3 * kMaxOrder + 9)));
   hipFuncSetAttribute((const void*)k_leaf_sur, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
 }
 
