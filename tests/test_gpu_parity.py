@@ -310,8 +310,8 @@ def _golden(name):
 BAR_ORDER = {"iso200k": 6, "cubic100k": 6, "cubic1m": 7}
 
 
-@pytest.mark.parametrize("name,precision", [("iso200k", 0), ("iso200k", 1), ("cubic100k", 1),
-                                            ("cubic1m", 1)])
+@pytest.mark.parametrize("name,precision", [("iso200k", 0), ("iso200k", 1), ("cubic100k", 0), ("cubic100k", 1),
+                                            ("cubic1m", 0), ("cubic1m", 1)])
 def test_full_size_fmm_vs_oracle_samples(env, name, precision):
     """The launch configuration the benchmark times, at the full size, against
     the oracle's direct sum on sampled segments (values written by
