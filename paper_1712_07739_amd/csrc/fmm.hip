@@ -953,7 +953,7 @@ __device__ __forceinline__ void idft_line_pairs(const cplx<T>* x, const T* c, co
 // reads cost).  The last pass uses the Hermitian symmetry of the last axis
 // (f3 = 0 once, f3 > 0 twice, real part).
 template <typename T, int P, int CPB>
-__global__ void __launch_bounds__(kDftThreads * CPB) k_idft(const cplx<T>* __restrict__ Shat, int64_t ncell,
+__global__ void __launch_bounds__(CPB > 1 ? 1024 : kDftThreads) k_idft(const cplx<T>* __restrict__ Shat, int64_t ncell,
                                                     const T* __restrict__ twg, T* __restrict__ s,
                                                     const unsigned* __restrict__ wmax, float kscale, int fa, int fb,
                                                     int acc_out) {
@@ -1015,10 +1015,11 @@ template <int P>
 constexpr size_t lds_idft_t(size_t es) {
   return 2 * es * ((size_t)6 * (2 * P - 1) * P * P + (size_t)6 * P * P * P);
 }
-// cells per block of the inverse DFT
+// cells per block of the inverse DFT (1024 threads for more than one): three
+// at the larger orders where their LDS fits, else two where that fits
 template <typename T, int P>
 constexpr int idft_cpb() {
-  return 2 * lds_idft_t<P>(sizeof(T)) <= 160 * 1024 ? 2 : 1;
+  return P >= 6 && 3 * lds_idft_t<P>(sizeof(T)) <= 160 * 1024 ? 3 : 2 * lds_idft_t<P>(sizeof(T)) <= 160 * 1024 ? 2 : 1;
 }
 
 // ------------------------------------------------ near field + L2P (leaf)
@@ -1802,7 +1803,7 @@ static void dft_launch(bool fwd, unsigned blocks, const void* in, int64_t ncell,
   else
   {
     constexpr int C = idft_cpb<T, P>();
-    k_idft<T, P, C><<<(unsigned)((blocks + C - 1) / C), kDftThreads * C, C * lds_idft_t<P>(sizeof(T)), st>>>(
+    k_idft<T, P, C><<<(unsigned)((blocks + C - 1) / C), C > 1 ? 1024 : kDftThreads, C * lds_idft_t<P>(sizeof(T)), st>>>(
         (const cplx<T>*)in, ncell, tw, (T*)out, wmax, kscale, fa, fb, acc);
   }
 }
