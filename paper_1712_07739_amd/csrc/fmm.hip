@@ -1385,11 +1385,27 @@ __global__ void __launch_bounds__((sym_threads<T, BIG>()), sym_min_waves<T>())
 // the same order as with one wave per leaf pair, and a leaf pair's partials
 // are written when its last pair has been summed.
 template <typename T, bool MIXED>
-__global__ void __launch_bounds__(64, sizeof(T) == 4 ? 4 : 1)
+__global__ void __launch_bounds__(64, sizeof(T) == 4 ? 4 : 3)
     k_leaf_sym_run(const double* pts, int64_t N, const int* first, const int* count, const int* nbr, Med<T> m,
                    double a2x4, T* part) {
   constexpr int NT = 64;
-  __shared__ T accA[64 * 6], cmpA[64 * 6], accB[64 * 6], cmpB[64 * 6], vij[NT * 6], vji[NT * 6];
+  // Single-precision sums are compensated; double-precision ones need not
+  // be, and without the two compensation arrays (12 KB of LDS a wave) three
+  // waves share a SIMD, where 18 KB allowed two.
+  constexpr bool KC = sizeof(T) == 4;
+  __shared__ T accA[64 * 6], cmpA[KC ? 64 * 6 : 1], accB[64 * 6], cmpB[KC ? 64 * 6 : 1], vij[NT * 6], vji[NT * 6];
+  auto cmp_of = [&](const T* c, int w) -> double {
+    if constexpr (KC) return (double)c[w];
+    else return 0.0;
+  };
+  auto clear = [&](T* acc, T* c, int w) {
+    acc[w] = T(0);
+    if constexpr (KC) c[w] = T(0);
+  };
+  auto add = [&](T& s, T& c, T x) {
+    if constexpr (KC) kadd(s, c, x);
+    else s += x;
+  };
   __shared__ int sB[14], sq[14], sstart[15], snseg;
   const int A = blockIdx.x, lane = threadIdx.x;
   const int fa = first[A], na = count[A];
@@ -1408,7 +1424,10 @@ __global__ void __launch_bounds__(64, sizeof(T) == 4 ? 4 : 1)
     sstart[ns] = tot;
     snseg = ns;
   }
-  for (int e = lane; e < 64 * 6; e += NT) accA[e] = cmpA[e] = accB[e] = cmpB[e] = T(0);
+  for (int e = lane; e < 64 * 6; e += NT) {
+    clear(accA, cmpA, e);
+    clear(accB, cmpB, e);
+  }
   __syncthreads();
   const int nseg = snseg, total = sstart[nseg];
   // the self pairs (slot 13, when present) come first; row i of them holds
@@ -1424,16 +1443,16 @@ __global__ void __launch_bounds__(64, sizeof(T) == 4 ? 4 : 1)
     const int q = sq[s], B = sB[s], fb = first[B], nb = count[B];
     const bool self = q == 13;
     for (int w = lane; w < na * 6; w += NT) {
-      double v = (double)accA[w] - (double)cmpA[w];
-      if (self) v += (double)accB[w] - (double)cmpB[w];
+      double v = (double)accA[w] - cmp_of(cmpA, w);
+      if (self) v += (double)accB[w] - cmp_of(cmpB, w);
       part[((int64_t)(fa + w / 6) * 27 + q) * 6 + w % 6] = (T)v;
-      accA[w] = cmpA[w] = T(0);
-      if (self) accB[w] = cmpB[w] = T(0);
+      clear(accA, cmpA, w);
+      if (self) clear(accB, cmpB, w);
     }
     if (!self)
       for (int w = lane; w < nb * 6; w += NT) {
-        part[((int64_t)(fb + w / 6) * 27 + (26 - q)) * 6 + w % 6] = (T)((double)accB[w] - (double)cmpB[w]);
-        accB[w] = cmpB[w] = T(0);
+        part[((int64_t)(fb + w / 6) * 27 + (26 - q)) * 6 + w % 6] = (T)((double)accB[w] - cmp_of(cmpB, w));
+        clear(accB, cmpB, w);
       }
   };
   for (int p0 = 0; p0 < total; p0 += NT) {
@@ -1493,33 +1512,33 @@ __global__ void __launch_bounds__(64, sizeof(T) == 4 ? 4 : 1)
         const int r0 = self ? row0(ii) : ii * nb, len = self ? na - 1 - ii : nb;
         const int a = max(r0, lo), b = min(r0 + len, hi);
         if (a >= b) continue;
-        T sa = accA[w], ca = cmpA[w];
-        for (int r = a; r < b; ++r) kadd(sa, ca, vij[(r + off) * 6 + c]);
+        T sa = accA[w], ca = (T)cmp_of(cmpA, w);
+        for (int r = a; r < b; ++r) add(sa, ca, vij[(r + off) * 6 + c]);
         accA[w] = sa;
-        cmpA[w] = ca;
+        if constexpr (KC) cmpA[w] = ca;
       }
       if (self) {
         for (int w = lane; w < na * 6; w += NT) {  // B's target jj: pairs (i, jj), i < jj, in order of i
           const int jj = w / 6, c = w - jj * 6;
           const int iend = min(rhi, jj - 1);
           if (rlo > iend) continue;
-          T sb = accB[w], cb = cmpB[w];
+          T sb = accB[w], cb = (T)cmp_of(cmpB, w);
           for (int i = rlo; i <= iend; ++i) {
             const int r = row0(i) + jj - i - 1;
-            if (r >= lo && r < hi) kadd(sb, cb, vji[(r + off) * 6 + c]);
+            if (r >= lo && r < hi) add(sb, cb, vji[(r + off) * 6 + c]);
           }
           accB[w] = sb;
-          cmpB[w] = cb;
+          if constexpr (KC) cmpB[w] = cb;
         }
       } else {
         for (int w = lane; w < nb * 6; w += NT) {  // B's target jj: local pairs r with r % nb == jj, in order
           const int jj = w / 6, c = w - jj * 6;
           const int r0 = lo + ((jj - lo % nb) % nb + nb) % nb;
           if (r0 >= hi) continue;
-          T sb = accB[w], cb = cmpB[w];
-          for (int r = r0; r < hi; r += nb) kadd(sb, cb, vji[(r + off) * 6 + c]);
+          T sb = accB[w], cb = (T)cmp_of(cmpB, w);
+          for (int r = r0; r < hi; r += nb) add(sb, cb, vji[(r + off) * 6 + c]);
           accB[w] = sb;
-          cmpB[w] = cb;
+          if constexpr (KC) cmpB[w] = cb;
         }
       }
       if (s1 <= pend) {
