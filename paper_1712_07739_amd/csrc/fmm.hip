@@ -1249,16 +1249,19 @@ __device__ __forceinline__ void kadd(T& s, T& c, T x) {
 // for 64 accumulators per side, so LDS does not limit occupancy); BIG = true
 // takes the others, with accumulators for the largest leaf (lmax).
 // Threads of a block: leaf pairs with more than 64 points on a side take
-// rounds of 256 point pairs in single precision (four waves share one set of
-// LDS sums, which would otherwise limit a CU to two waves per SIMD), 64 else.
+// rounds of 256 point pairs (four waves share one set of LDS sums, which
+// would otherwise limit a CU to two waves per SIMD in single precision, and
+// to about one wave per CU in FP64), 64 else.  Single-precision sums are
+// compensated; FP64 ones are plain (no compensation arrays: 12 FP64 values
+// of LDS per point where 24 left large leaves one block per CU).
 template <typename T, bool BIG>
 constexpr int sym_threads() {
-  return BIG && sizeof(T) == 4 ? 256 : 64;
+  return BIG ? 256 : 64;
 }
 
 template <typename T>
 constexpr int sym_min_waves() {
-  return sizeof(T) == 4 ? 3 : 1;
+  return 3;
 }
 
 template <typename T, bool MIXED, bool BIG>
@@ -1277,13 +1280,25 @@ __global__ void __launch_bounds__((sym_threads<T, BIG>()), sym_min_waves<T>())
   const int fa = first[A], na = count[A], fb = first[B], nb = count[B];
   if ((na > 64 || nb > 64) != BIG) return;
   if (!BIG) lmax = 64;
-  T* accA = symsh;              // [lmax][6]
-  T* cmpA = accA + lmax * 6;
+  constexpr bool KC = sizeof(T) == 4;  // compensated sums
+  T* accA = symsh;                      // [lmax][6]
+  T* cmpA = accA + (KC ? lmax * 6 : 0);  // [lmax][6] (single precision)
   T* accB = cmpA + lmax * 6;
-  T* cmpB = accB + lmax * 6;
-  T* vij = cmpB + lmax * 6;     // [NT][6] contributions to A's targets
-  T* vji = vij + NT * 6;        // [NT][6] contributions to B's targets
-  for (int e = lane; e < lmax * 6; e += NT) accA[e] = cmpA[e] = accB[e] = cmpB[e] = T(0);
+  T* cmpB = accB + (KC ? lmax * 6 : 0);
+  T* vij = cmpB + lmax * 6;             // [NT][6] contributions to A's targets
+  T* vji = vij + NT * 6;                // [NT][6] contributions to B's targets
+  auto cmp_of = [&](const T* c, int w) -> double {
+    if constexpr (KC) return (double)c[w];
+    else return 0.0;
+  };
+  auto add = [&](T& s, T& c, T x) {
+    if constexpr (KC) kadd(s, c, x);
+    else s += x;
+  };
+  for (int e = lane; e < lmax * 6; e += NT) {
+    accA[e] = accB[e] = T(0);
+    if constexpr (KC) cmpA[e] = cmpB[e] = T(0);
+  }
   __syncthreads();
   // With the leaf itself only the pairs i < j are enumerated, row by row:
   // row i holds (i, i+1 .. na-1) and starts at pair row0(i).
@@ -1333,39 +1348,39 @@ __global__ void __launch_bounds__((sym_threads<T, BIG>()), sym_min_waves<T>())
       const int s0 = self ? row0(ii) : ii * nb, len = self ? na - 1 - ii : nb;
       const int lo = max(s0, p0), hi = min(s0 + len, pend);
       if (lo >= hi) continue;
-      T sa = accA[w], ca = cmpA[w];
-      for (int r = lo; r < hi; ++r) kadd(sa, ca, vij[(r - p0) * 6 + c]);
+      T sa = accA[w], ca = (T)cmp_of(cmpA, w);
+      for (int r = lo; r < hi; ++r) add(sa, ca, vij[(r - p0) * 6 + c]);
       accA[w] = sa;
-      cmpA[w] = ca;
+      if constexpr (KC) cmpA[w] = ca;
     }
     for (int w = lane; self && w < nb * 6; w += NT) {  // B's target jj: pairs (i, jj), i < jj, in order of i
       const int jj = w / 6, c = w - jj * 6;
       const int iend = min(rhi, jj - 1);
       if (rlo > iend) continue;
-      T sb = accB[w], cb = cmpB[w];
+      T sb = accB[w], cb = (T)cmp_of(cmpB, w);
       for (int i = rlo; i <= iend; ++i) {
         const int r = row0(i) + jj - i - 1;
-        if (r >= p0 && r < pend) kadd(sb, cb, vji[(r - p0) * 6 + c]);
+        if (r >= p0 && r < pend) add(sb, cb, vji[(r - p0) * 6 + c]);
       }
       accB[w] = sb;
-      cmpB[w] = cb;
+      if constexpr (KC) cmpB[w] = cb;
     }
     for (int w = lane; !self && w < nb * 6; w += NT) {  // B's target jj: lanes with p % nb == jj, in order
       const int jj = w / 6, c = w - jj * 6;
       const int r0 = p0 + ((jj - p0 % nb) % nb + nb) % nb;
       if (r0 >= pend) continue;
-      T sb = accB[w], cb = cmpB[w];
-      for (int r = r0; r < pend; r += nb) kadd(sb, cb, vji[(r - p0) * 6 + c]);
+      T sb = accB[w], cb = (T)cmp_of(cmpB, w);
+      for (int r = r0; r < pend; r += nb) add(sb, cb, vji[(r - p0) * 6 + c]);
       accB[w] = sb;
-      cmpB[w] = cb;
+      if constexpr (KC) cmpB[w] = cb;
     }
     __syncthreads();
   }
   for (int ii = lane; ii < na; ii += NT)
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
-      double v = (double)accA[ii * 6 + c] - (double)cmpA[ii * 6 + c];
-      if (self) v += (double)accB[ii * 6 + c] - (double)cmpB[ii * 6 + c];
+      double v = (double)accA[ii * 6 + c] - cmp_of(cmpA, ii * 6 + c);
+      if (self) v += (double)accB[ii * 6 + c] - cmp_of(cmpB, ii * 6 + c);
       part[((int64_t)(fa + ii) * 27 + q) * 6 + c] = (T)v;
     }
   if (!self)
@@ -1373,7 +1388,7 @@ __global__ void __launch_bounds__((sym_threads<T, BIG>()), sym_min_waves<T>())
 #pragma unroll
       for (int c = 0; c < 6; ++c)
         part[((int64_t)(fb + jj) * 27 + (26 - q)) * 6 + c] =
-            (T)((double)accB[jj * 6 + c] - (double)cmpB[jj * 6 + c]);
+            (T)((double)accB[jj * 6 + c] - cmp_of(cmpB, jj * 6 + c));
 }
 
 // The same symmetric near field for the leaf pairs with at most 64 points on
@@ -1569,7 +1584,9 @@ __global__ void k_near_sum(const T* part, int64_t N, const int* pleaf, const int
 }
 
 template <typename T, bool BIG>
-inline size_t sym_lds(int lmax) { return sizeof(T) * (24 * (size_t)lmax + 2 * (size_t)sym_threads<T, BIG>() * 6); }
+inline size_t sym_lds(int lmax) {
+  return sizeof(T) * ((sizeof(T) == 4 ? 24 : 12) * (size_t)lmax + 2 * (size_t)sym_threads<T, BIG>() * 6);
+}
 
 // The near-coincident pairs (closer than 2a) that the single-precision near
 // field skips, in double precision.  The tree holds them per target point, in

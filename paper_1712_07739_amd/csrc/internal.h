@@ -122,7 +122,8 @@ static_assert(d_layout_ok(), "double spectrum units");
 // of the processing order in one wave; their entries are stored step-major per
 // wave (see Level::ilw), and the entry after a list's end is read.
 // Largest leaf (points) for the symmetric near field (its LDS holds four
-// accumulators per point); trees with larger leaves use the one-sided kernel.
+// accumulators per point in single precision, two in FP64); trees with larger
+// leaves use the one-sided kernel.
 constexpr int kSymMaxLeaf = 1024;  // single precision
 constexpr int kSymMaxLeafD = 768;  // double precision
 constexpr int kWaveTargets = 32;
