@@ -354,7 +354,10 @@ int dfmm_autotune_depth(const dfmm_params* prm, const double* seg, const double*
                         int d_min, int d_max, void* stream, int* best, double* pred_ms, double* meas_ms);
 
 /* JSON descriptions: parameters, M2L operator memory (Eq. mem_unif and the
- * stored spectra), precompute time / tree sizes per level, pair counts. */
+ * stored spectra), precompute time / tree sizes per level, pair counts, and
+ * for a tree whether its near field takes one kernel evaluation per
+ * unordered pair ("symmetric_near": cubic media, uniform tree, leaves of at
+ * most 1024 points) or one per ordered pair. */
 int dfmm_plan_info(const dfmm_plan* plan, char* json, size_t cap);
 int dfmm_tree_info(const dfmm_tree* tree, char* json, size_t cap);
 

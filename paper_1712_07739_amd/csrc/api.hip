@@ -519,6 +519,7 @@ int dfmm_tree_info(const dfmm_tree* t, char* json, size_t cap) {
                   ", \"depth\": " + std::to_string(t->D) + ", \"m2l_pairs\": " + std::to_string(t->npairs) +
                   ", \"near_pairs\": " + std::to_string(t->near_pairs) +
                   ", \"max_leaf_points\": " + std::to_string(t->max_leaf_pts) +
+                  ", \"symmetric_near\": " + std::to_string(t->part != nullptr ? 1 : 0) +
                   ", \"workspace_bytes\": " + std::to_string(t->bytes) + ", \"adaptive\": " +
                   std::to_string(t->adaptive) + ", \"leaves\": " +
                   std::to_string(t->adaptive ? t->nleaf : (t->D >= 2 ? t->lv[t->D].n : 0)) +

@@ -1587,6 +1587,9 @@ template <typename T, bool BIG>
 inline size_t sym_lds(int lmax) {
   return sizeof(T) * ((sizeof(T) == 4 ? 24 : 12) * (size_t)lmax + 2 * (size_t)sym_threads<T, BIG>() * 6);
 }
+static_assert(sizeof(float) * (24 * kSymMaxLeaf + 2 * 256 * 6) <= 160 * 1024 &&
+                  sizeof(double) * (12 * kSymMaxLeaf + 2 * 256 * 6) <= 160 * 1024,
+              "the large-leaf near field's LDS at the largest symmetric leaf");
 
 // The near-coincident pairs (closer than 2a) that the single-precision near
 // field skips, in double precision.  The tree holds them per target point, in

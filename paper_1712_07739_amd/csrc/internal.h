@@ -121,11 +121,10 @@ static_assert(d_layout_ok(), "double spectrum units");
 // The single-precision M2L kernel walks the lists of 32 consecutive targets
 // of the processing order in one wave; their entries are stored step-major per
 // wave (see Level::ilw), and the entry after a list's end is read.
-// Largest leaf (points) for the symmetric near field (its LDS holds four
-// accumulators per point in single precision, two in FP64); trees with larger
-// leaves use the one-sided kernel.
-constexpr int kSymMaxLeaf = 1024;  // single precision
-constexpr int kSymMaxLeafD = 768;  // double precision
+// Largest leaf (points) for the symmetric near field, both precisions (its
+// LDS holds four accumulators per point in single precision, two in FP64);
+// trees with larger leaves use the one-sided kernel.
+constexpr int kSymMaxLeaf = 1024;
 constexpr int kWaveTargets = 32;
 constexpr int kIlwPad = 2;  // the f16 product reads entries two steps ahead
 // Target (0..31 within the wave) of lane pair lp (lanes 2 lp, 2 lp + 1) in

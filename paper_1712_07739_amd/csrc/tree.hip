@@ -813,7 +813,7 @@ int build_tree_impl(dfmm_plan* pl, const double* seg, int64_t nseg, hipStream_t 
   }
   if (pl->h16) DFMM_HIP(hipMalloc(&t->wmax, sizeof(unsigned) * (D + 1)));
   const size_t part_es = pl->mixed ? sizeof(float) : sizeof(double);
-  if (!t->adaptive && !pl->iso && t->max_leaf_pts <= (pl->mixed ? kSymMaxLeaf : kSymMaxLeafD)) {
+  if (!t->adaptive && !pl->iso && t->max_leaf_pts <= kSymMaxLeaf) {
     DFMM_HIP(hipMalloc(&t->part, part_es * 27 * 6 * N));
     if (!hbig.empty()) {
       t->nbig = (int64_t)hbig.size();

@@ -169,26 +169,30 @@ def test_symmetric_near_field_small_and_large_leaves(env):
     ref = oracle.fmm_forces(seg, b, med, 4, 3, BOX_LO, BOX)
     assert oracle.rel_err(f32, ref) <= 2e-5
     f64, _, tree64 = run_fmm(env, seg, b, CUB, 4, 3, precision=0)
-    assert tree64.info()["max_leaf_points"] <= 768
+    assert tree.info()["symmetric_near"] == 1 and tree64.info()["symmetric_near"] == 1
     assert oracle.rel_err(f64, ref) <= 1e-10
     assert oracle.rel_err(f32, f64) <= 2e-5
 
 
-def test_near_field_leaf_beyond_the_fp64_symmetric_limit(env):
-    """One leaf of 768 < n <= 1024 points (seven loops shrunk into it) beside
-    small leaves: single precision keeps the symmetric launch for large
-    leaves, the FP64 path, whose large-leaf LDS allows at most 768 points,
-    falls back to the one-sided near field; both must match the oracle's FMM."""
-    s1, b1 = synth.make_loops(7, 0.01, 0.04, 31)
+@pytest.mark.parametrize("nloops,symmetric", [(7, 1), (9, 0)])
+def test_near_field_leaves_around_the_symmetric_limit(env, nloops, symmetric):
+    """One leaf of 840 points (seven loops shrunk into it) or 1080 points
+    (nine) beside small leaves.  Up to 1024 points both precisions take the
+    symmetric near field, its large-leaf launch included; beyond, the
+    one-sided near field.  Both must match the oracle's FMM."""
+    s1, b1 = synth.make_loops(nloops, 0.01, 0.04, 31)
     s1 = 0.635 + 0.2 * (s1 - s1.reshape(-1, 3).mean(axis=0))
     s2, b2 = synth.make_loops(6, 0.01, 0.04, 32)
     seg, b = np.concatenate([s1, s2]), np.concatenate([b1, b2])
     med = oracle.medium(*CUB, 1e-3)
     ref = oracle.fmm_forces(seg, b, med, 4, 2, BOX_LO, BOX)
     f64, _, tree = run_fmm(env, seg, b, CUB, 4, 2, precision=0)
-    assert 768 < tree.info()["max_leaf_points"] <= 1024
+    info = tree.info()
+    assert (768 < info["max_leaf_points"] <= 1024) if symmetric else info["max_leaf_points"] > 1024
+    assert info["symmetric_near"] == symmetric
     assert oracle.rel_err(f64, ref) <= 1e-10
-    f32, _, _ = run_fmm(env, seg, b, CUB, 4, 2, precision=1)
+    f32, _, tree32 = run_fmm(env, seg, b, CUB, 4, 2, precision=1)
+    assert tree32.info()["symmetric_near"] == symmetric
     assert oracle.rel_err(f32, ref) <= 2e-5
 
 
