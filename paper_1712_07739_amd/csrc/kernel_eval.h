@@ -41,6 +41,18 @@ template <>
 __device__ __forceinline__ float fast_rcp<float>(float x) {
   return __builtin_amdgcn_rcpf(x);  // 1 ulp: ample for the float evaluation
 }
+// double: the hardware estimate refined by two Newton-Raphson steps
+// r <- r + r (1 - x r) (each squares the relative error), within an ulp or
+// two of 1/x, not correctly rounded; every argument here is a positive
+// normal number (2 (1 - nu), the determinant of a positive definite matrix)
+template <>
+__device__ __forceinline__ double fast_rcp<double>(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
 template <typename T>
 __device__ __forceinline__ T fast_rsqrt(T x) {
   return T(1) / sqrt(x);
