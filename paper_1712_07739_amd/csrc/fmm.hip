@@ -334,8 +334,9 @@ __device__ __forceinline__ uint32_t pack_h2(float re, float im) {
 }
 
 // ------------------------------------------------------------ forward DFT
-constexpr int kDftThreads = 512;  // threads per block of the DFT kernels
-// One block per cell of a level: W[cell][9][P^3] (real, zero-padded to n^3,
+constexpr int kDftThreads = 512;  // threads per cell of a DFT block (at most 1024 a block)
+// One block per cell of a level (or per CPB consecutive cells, below):
+// W[cell][9][P^3] (real, zero-padded to n^3,
 // n = 2P - 1) -> What[f][cell][9], f = (f1 n + f2) P + f3, the half spectrum
 // in the last axis (the input is real).  Three passes of length-P to
 // length-n (or P) DFTs, G components at a time.  A thread takes one input
@@ -381,7 +382,7 @@ __device__ __forceinline__ void dft_line_pairs(const cplx<T>* x, const T* c, con
 
 // Only the frequencies with first index f1 in [fa, fb) are stored, at f - fa n P
 // (the spectrum in chunks along the first axis, for large trees).  A block
-// takes CPB consecutive cells (CPB threads per 512): the rows of one frequency
+// takes CPB consecutive cells (512 threads per cell): the rows of one frequency
 // of neighbouring cells are neighbours in What, so the last pass writes CPB
 // rows in one piece.
 template <typename T, int P, bool H16, int CPB>
@@ -940,7 +941,9 @@ __device__ __forceinline__ void idft_line_pairs(const cplx<T>* x, const T* c, co
   }
 }
 
-// One block per cell: Shat[f][cell][6] -> s[cell][6][P^3] (overwrites): the
+// One block per CPB consecutive cells (1024 threads when CPB > 1), whose
+// rows of one frequency the first pass reads in one piece:
+// Shat[f][cell][6] -> s[cell][6][P^3] (overwrites): the
 // inverse transform of the half spectrum of a real circular convolution, of
 // which only the outputs l < P are needed (the rest is the wrap-around of the
 // embedding).  As in the forward transform, a thread takes one line of a
